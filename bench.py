@@ -1,0 +1,182 @@
+"""Benchmark of the wavelet-collocation vortex step on one MI355X.
+
+Workload: the Fujiwhara pair at Re = 5000 on a 512 x 512 finest grid
+(J = 9), 4-point DD, threshold 1e-4, Krylov dimension 20, dt = 0.01; a batch
+of 8 solves whose radii and separations are drawn from seeds 1000..1007.
+One step = one exponential Rosenbrock-Euler step of every solve of the batch
+(residual, 20 Jacobian-vector products, Arnoldi, phi_1, update and FP64
+regrid), launched together through solve_batch and replayed as a HIP graph.
+
+Metric: active-point residual evaluations per second, summed over the batch
+((1 + m_eff) N_a per solve and step, counted on the device).  Also reported:
+the roofline fraction of the dominant kernel (HIP events on the launching
+stream) and the FP64 CPU oracle timed on a bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec mixed|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SEEDS = list(range(1000, 1008))
+METRIC = "active-pt RHS evals/s"
+
+
+def kernel_bytes(name: str, N: int, na: int, tiles_active_frac: float, nbatch: int, esz: int) -> float:
+    """Algorithmic HBM bytes of one launch of a step kernel for the batch."""
+    nf = N * N
+    if name == "jvp":
+        # psi_v, v~, w~, u, v, nu_e on active tiles + rank map; J v out (FP64)
+        per = (6 * esz + 4) * nf * tiles_active_frac + 8 * na
+    elif name == "rhs":
+        per = (2 * esz + 4) * nf + 3 * esz * nf + 8 * na
+    elif name in ("fft_rows", "fft_rows_inv"):
+        per = esz * nf + 2 * esz * (N // 2 + 1) * N
+    elif name == "fft_cols":
+        per = 2 * (2 * esz * (N // 2 + 1) * N)
+    elif name == "prolong_finest":
+        lev = 3 * nf // 4
+        per = lev * (1 + esz)          # mask byte + written value (inputs are re-read coarse values)
+    elif name == "forward":
+        per = nf * (8 + 8)
+    else:
+        raise KeyError(name)
+    return per * nbatch
+
+
+def cpu_baseline(steps: int) -> dict:
+    """The FP64 oracle on one solve of the batch, single-threaded, timed here."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               NUMEXPR_NUM_THREADS="1")
+    code = (
+        "import json,sys,time; sys.path.insert(0, %r)\n"
+        "import workloads as W\n"
+        "from oracle import krylov as ok, ops as oo\n"
+        "pb = W.fujiwhara_pair(%d)\n"
+        "g = ok.Grid(J=pb.J, p=pb.p, eps=pb.eps); fl = oo.Flow(nu0=pb.nu0, cs=pb.cs)\n"
+        "st = ok.init_state(W.initial_field(pb), g)\n"
+        "ev = 0; t0 = time.perf_counter()\n"
+        "for _ in range(%d):\n"
+        "    na = st.omega_M.size; st = ok.step(st, g, fl, pb.m, pb.dt); ev += (1 + st.last_m_eff) * na\n"
+        "dt = time.perf_counter() - t0\n"
+        "print(json.dumps({'evals': ev, 'sec': dt}))\n" % (ROOT, SEEDS[0], steps))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": r["evals"] / r["sec"], "unit": "active-pt RHS evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of one 512^2 Fujiwhara solve (seed {SEEDS[0]}), FP64 NumPy/SciPy, "
+                      f"{r['sec']:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--batch", type=int, default=len(SEEDS))
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel", default="jvp")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        return 2
+
+    import torch
+    import paper_1604_08159_amd as m
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    prec = m.MRA_MIXED if args.prec == "mixed" else m.MRA_FP64
+    stream = torch.cuda.Stream(device=dev)
+    seeds = [SEEDS[i % len(SEEDS)] + 100 * (i // len(SEEDS)) for i in range(args.batch)]
+    pbs = [W.fujiwhara_pair(s) for s in seeds]
+    solves = []
+    with torch.cuda.stream(stream):
+        for pb in pbs:
+            w0 = torch.from_numpy(W.initial_field(pb)).to(dev)
+            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m,
+                                  pb.dt, w0, stream=stream))
+    n = len(solves)
+    m.solve_batch(solves, [args.warmup] * n, stream=stream)
+    stream.synchronize()
+    ev0 = sum(s.scalars()["evals"] for s in solves)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.solve_batch(solves, [args.steps] * n, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev1 = sum(s.scalars()["evals"] for s in solves)
+    value = (ev1 - ev0) / wall
+
+    # state after the timed region
+    nas = []
+    for s in solves:
+        _, diag = s.read(dense=False, stream=stream)
+        nas.append(int(diag["n_active"]))
+        if diag["status"] != 0:
+            print(json.dumps({"error": f"solve reported status {diag['status']}"}))
+            return 1
+    N = 1 << pbs[0].J
+    esz = 4 if prec == m.MRA_MIXED else 8
+
+    # dominant kernel: HIP events around back-to-back launches of the same
+    # launch configuration, on the stream the step runs on
+    reps = 50
+    k_ms = m.time_kernel(solves, args.kernel, reps, stream=stream)
+    # fraction of stencil tiles holding an active node (the stencil skips the rest)
+    ts = 32
+    act_tiles = []
+    for s in solves:
+        _, mask, ip, fi = s.active_set()
+        f = fi.long()
+        t = ((f // N) // ts) * (N // ts) + (f % N) // ts
+        act_tiles.append(torch.unique(t).numel() / (N // ts) ** 2)
+    frac_t = sum(act_tiles) / len(act_tiles)
+    nbytes = kernel_bytes(args.kernel, N, int(sum(nas) / len(nas)), frac_t, n, esz)
+    achieved = nbytes / (k_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "active-pt RHS evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == m.MRA_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Fujiwhara pair Re=5000, finest 512^2 (J=9), 4-point DD, eps=1e-4, m=20, "
+                               f"dt=0.01; batch of {n} seeded solves",
+                   "batch": n, "finest_points": N * N, "mean_active_points": sum(nas) / len(nas),
+                   "precision": args.prec, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "kernel": args.kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": k_ms, "algorithmic_bytes_per_launch": nbytes,
+                     "active_tile_fraction": frac_t},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    for s in solves:
+        s.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,210 @@
+/*
+ * mra.h -- C-ABI of the MI355X (gfx950) wavelet-collocation vortex library.
+ *
+ * The library evaluates, on one GPU, the hot path of the weighted-residual
+ * collocation method of Walsh & Alam (arXiv:1604.08159) for the barotropic
+ * vorticity-streamfunction equations on the periodic square [0, L)^2:
+ *
+ *   laplacian(psi) = -omega,  u = d psi/dy,  v = -d psi/dx,
+ *   d omega/dt = -div(u omega) + eddy diffusion (Smagorinsky, eq. (5)).
+ *
+ * Grid: N = 2^J nodes per side, h = L/N, arrays f[y][x] row-major (x fastest).
+ * Multiresolution (Section 2.4, eq. (6)): nested meshes G^{j0} .. G^J, the
+ * order-2p Deslauriers-Dubuc (DD) prediction, details d = u - P(u|G^{l-1}),
+ * an active set M of nodes whose detail is significant (plus an adjacent zone
+ * and the coarsest mesh); the unknowns are the nodal values at M.
+ * Derivatives (Section 2.5): collocation first derivative with the DD filter
+ * phi'(n); the second derivative is the (2p+1)-point Lagrange rule.
+ * Time step: exponential Rosenbrock-Euler in a Krylov subspace (the paper's
+ * Krylov projection, abstract and Section 2.1).
+ *
+ * Packed pyramid layout (N*N entries): the 2^j0 x 2^j0 coarse values at
+ * offset 0, then for l = j0+1..J three bands of 2^(l-1) x 2^(l-1) entries,
+ * row-major [b][a], at offsets 4^(l-1) (X: node ((2a+1)s, 2bs)),
+ * 2*4^(l-1) (Y: node (2as, (2b+1)s)) and 3*4^(l-1) (XY: ((2a+1)s, (2b+1)s)),
+ * s = 2^(J-l).  The mask and index_packed use packed positions; index_fine
+ * holds y*N + x of the same nodes, both ascending in packed order.
+ *
+ * Conventions
+ *   - Every pointer argument named *_dev, and every array argument unless
+ *     stated otherwise, is DEVICE memory owned by the caller.  The library
+ *     never allocates or frees device memory; it keeps only small constant
+ *     tables in module memory (set up by mra_init) and, per solve handle, a
+ *     small host object plus captured HIP graphs.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Every call is
+ *     asynchronous on it except mra_solve_read, which synchronises it.
+ *   - Argument and size errors are returned before anything is launched.
+ *     Device-side conditions (non-finite values) go to the solve's status
+ *     word, read back by mra_solve_read.  No C++ exception crosses the ABI.
+ *   - Sizes that change on the device (the active count N_a) live in device
+ *     memory so that captured graphs stay valid.
+ *   - Distinct solves on distinct streams are independent; calls that share
+ *     a workspace or a solve must not overlap.
+ */
+#ifndef MRA_H
+#define MRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MRA_OK = 0,
+  MRA_E_ARG = 1,          /* bad argument (null pointer, unknown enum)          */
+  MRA_E_SIZE = 2,         /* grid, order, Krylov size or buffer size unsupported */
+  MRA_E_NOMEM = 3,        /* arena / workspace smaller than required             */
+  MRA_E_DEVICE = 4,       /* a HIP call failed                                   */
+  MRA_E_NONFINITE = 5,    /* a non-finite value was met (status word only)       */
+  MRA_E_UNSUPPORTED = 6
+};
+
+enum { MRA_FP64 = 0, MRA_FP32 = 1, MRA_MIXED = 2 };   /* MIXED: FP32 bulk fields,
+                                                         FP64 Krylov / regrid      */
+enum { MRA_FORWARD = 1, MRA_INVERSE = -1, MRA_PROLONG = 2 };
+
+/* Grid: J in [j0+1, 11]; p in {2, 3} (4- and 6-point DD); j0 must equal
+ * ceil(log2(2p)) (2 for p = 2, 3 for p = 3); length > 0 is the side of the
+ * periodic square; eps >= 0 the relative threshold (tau = eps * max|u|);
+ * adjacent_zone 0/1. */
+typedef struct {
+  int32_t J, j0, p, adjacent_zone;
+  double length, eps;
+} mra_grid_desc;
+
+/* Flow: nu0 >= 0 molecular/base viscosity; cs Smagorinsky constant; s0 the
+ * a-priori |S| of smag_mode 1; mu >= 0 linear friction; smag_mode 0 (nu0
+ * only), 1 (nu0 + (cs h)^2 s0) or 2 (nu0 + (cs h)^2 |S| from the resolved
+ * strain).  Eq. (5) with Delta = h. */
+typedef struct {
+  double nu0, cs, s0, mu;
+  int32_t smag_mode, reserved;
+} mra_flow_desc;
+
+typedef struct mra_solve_s* mra_solve;
+
+/* Device pointers into a solve's arena (for inspection by tests/tools). */
+typedef struct {
+  double* omega_active;      /* [N*N] FP64, first N_a valid                     */
+  uint8_t* mask;             /* [N*N] packed layout, 1 = active                  */
+  int32_t* index_packed;     /* [N*N], first N_a valid                           */
+  int32_t* index_fine;       /* [N*N], first N_a valid                           */
+  int64_t* n_active;         /* device scalar                                    */
+  double* krylov_V;          /* [(m+1)][N*N] FP64 Arnoldi basis                  */
+  double* hessenberg;        /* [(m+1)][m] FP64                                  */
+  double* scalars;           /* [16] FP64: [0] beta, [2] ||A v_last||, [4] t,
+                                [5] active-point residual evaluations so far
+                                (sum over steps of (1 + m_eff) N_a), [6] steps */
+  int32_t* control;          /* [16] int: m_eff, done, status, ...               */
+} mra_solve_ptrs;
+
+const char* mra_status_str(int32_t status);
+int32_t mra_abi_version(void);
+
+/* Set up the library's constant tables (FFT twiddles) on the CURRENT device.
+ * Idempotent per device; called implicitly by the other entry points. */
+int32_t mra_init(void);
+
+/* ------------------------------------------------------------------------
+ * mra_transform -- DD multiresolution transform (Section 2.4, eq. (6)).
+ *
+ * prec selects the element type of the dense / packed arrays: MRA_FP64 ->
+ * double, MRA_FP32 or MRA_MIXED -> float.  Active values are always double.
+ *
+ * MRA_FORWARD: in = dense [N][N]; out = packed pyramid [N*N] (coarse values,
+ *   then details d = u - P(u|G^{l-1}) of every level, the 2-D prediction
+ *   being the tensor-product DD rule applied along y, then x).  If mask is
+ *   non-NULL the active set is also built: tau = eps * max|in|,
+ *   S = {non-coarse nodes with |d| >= tau}, M = G^{j0} + S + adjacent zone
+ *   (nodes of G^{min(l+1,J)} within periodic Chebyshev distance 2^(J-l) of a
+ *   node of S at level l); mask [N*N] (packed), index_packed / index_fine
+ *   [N*N capacity] and *n_active (device int64) are written.  In FP64 the
+ *   details are computed with one rounding per operation and no fused
+ *   multiply-add, so they and the active set are reproducible bit for bit.
+ * MRA_INVERSE: in = packed pyramid, out = dense: u = d + P(u|G^{l-1}),
+ *   coarse to fine.
+ * MRA_PROLONG (nodal inverse transform Pi): in = active values (double,
+ *   n_active entries in index_fine order); mask and index_fine describe M;
+ *   out = dense [N][N]: active nodes keep their value, an inactive node of
+ *   level l gets the DD prediction from the final level-(l-1) values.
+ *
+ * ws: device workspace of at least mra_transform_ws_bytes bytes.
+ * ------------------------------------------------------------------------ */
+int32_t mra_transform_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes);
+int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir,
+                      const void* in, void* out,
+                      uint8_t* mask, int32_t* index_packed, int32_t* index_fine,
+                      int64_t* n_active, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * collocation_rhs -- residual F(omega) or the Jacobian-vector product J v at
+ * the active nodes (Sections 2.3 and 2.5; vorticity-streamfunction form):
+ *
+ *   w~ = Pi(omega), psi = -L^{-1} w~ (k = 0 mode dropped), u = D1_y psi,
+ *   v = -D1_x psi, nu_e from eq. (5),
+ *   F = -[D1_x(u w~) + D1_y(v w~)] + 1/2[L(nu_e w~) + nu_e L w~ - w~ L nu_e]
+ *       - mu w~,
+ *   J v (nu_e frozen at omega): with v~ = Pi(v), psi_v = -L^{-1} v~,
+ *   -[D1_x(u_v w~ + u v~) + D1_y(v_v w~ + v v~)]
+ *       + 1/2[L(nu_e v~) + nu_e L v~ - v~ L nu_e] - mu v~.
+ *
+ * mask / index_fine / n_active: the active set (as from mra_transform).
+ * omega_active, v_active (NULL -> F), out_active: double [n_active].
+ * psi_dense_or_null: if non-NULL receives psi [N][N] (element type of prec).
+ * prec: element type of the dense fields (FP64, or FP32 for FP32/MIXED).
+ * ------------------------------------------------------------------------ */
+int32_t mra_rhs_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes);
+int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec,
+                        const uint8_t* mask, const int32_t* index_fine,
+                        const int64_t* n_active, const double* omega_active,
+                        const double* v_active, double* out_active,
+                        void* psi_dense_or_null, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Solves.  A solve keeps its whole state in a caller-owned device arena of
+ * mra_solve_footprint bytes: active values (FP64), active set, Krylov basis
+ * V [(m+1) x N*N] FP64, Hessenberg matrix, dense work fields and FFT
+ * spectra.  1 <= m <= 47.
+ *
+ * mra_solve_init: omega0_dense (device, double [N][N]) is transformed and
+ *   thresholded to the first active set; the host handle is written to *out.
+ * krylov_step: nsteps exponential Rosenbrock-Euler steps
+ *   omega_M <- omega_M + dt beta V_m phi_1(dt H_m) e_1, with Arnoldi (CGS2,
+ *   happy breakdown h_{j+1,j} <= 1e-13 ||A v_j||, beta = 0 -> no update) and
+ *   an FP64 regrid (Pi, forward transform, threshold, gather) after each
+ *   step.  The first call captures one step into a HIP graph on `stream`;
+ *   later calls replay it.
+ * solve_batch: advances solves[i] by nsteps[i] steps; solves of equal
+ *   (J, p, precision, m) share every kernel launch.  Results are bit for bit
+ *   those of krylov_step on each solve alone.
+ * mra_solve_read: synchronises `stream`; omega_dense_out (device double
+ *   [N][N], may be NULL) receives Pi(omega_M); diag_out (HOST double[8],
+ *   may be NULL) receives t, energy, enstrophy, palinstrophy, circulation,
+ *   max|omega|, N_a, status (Sections 3.3 and 3.4).
+ * ------------------------------------------------------------------------ */
+int32_t mra_solve_footprint(const mra_grid_desc* g, int32_t prec, int32_t m, size_t* bytes);
+int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec,
+                       int32_t m, double dt, const double* omega0_dense,
+                       void* arena, size_t arena_bytes, void* stream, mra_solve* out);
+int32_t krylov_step(mra_solve s, int32_t nsteps, void* stream);
+int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* stream);
+int32_t mra_solve_read(mra_solve s, double* omega_dense_out, double* diag_out, void* stream);
+int32_t mra_solve_ptrs_get(mra_solve s, mra_solve_ptrs* out);
+int32_t mra_solve_destroy(mra_solve s);
+
+/* Profiling hook: times `reps` back-to-back launches of one kernel of the
+ * step, launched exactly as the step launches it for the batch `solves`
+ * (n solves of equal J, p, precision and m): 0 Jacobian-vector stencil,
+ * 1/2/3 Poisson FFT passes (rows, columns, inverse rows), 4 prolongation of
+ * the finest level, 5 forward transform (FP64 regrid), 6 residual stencil.
+ * HIP events on `stream`; *avg_ms receives the mean launch duration.  Only
+ * work buffers are overwritten: call it between steps. */
+int32_t mra_time_kernel(mra_solve* solves, int32_t n, int32_t which, int32_t reps, void* stream,
+                        float* avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRA_H */

@@ -1,0 +1,219 @@
+"""MI355X (gfx950) wavelet-collocation vortex solver: Python binding.
+
+A thin layer over the C-ABI of ``libmra.so`` (declared in include/mra.h):
+PyTorch provides device memory and streams, every step of the method runs
+in the library's HIP kernels.  The names follow the C entry points:
+
+  mra_transform      DD forward / inverse transform, threshold, prolongation
+  collocation_rhs    residual F(omega) or Jacobian-vector product at the active nodes
+  Solve              one solve (arena, init, krylov_step, read)
+  solve_batch        advance several solves with shared launches
+
+Method: Walsh & Alam, "Fujiwhara interaction of tropical cyclone scale
+vortices using a weighted residual collocation method" (arXiv:1604.08159),
+Sections 2.3-2.5 (Smagorinsky closure, DD multiresolution, collocation) and
+its Krylov-projected time integration.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import (FlowDesc, GridDesc, MraError, SolvePtrs, MRA_FORWARD, MRA_INVERSE, MRA_PROLONG,
+                   MRA_FP64, MRA_FP32, MRA_MIXED, MRA_OK, MRA_E_NONFINITE)
+
+_LIB: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it is missing (no fallback path exists)."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _lib.load()
+    return _LIB
+
+
+def _check(fn: str, st: int) -> None:
+    if st != MRA_OK:
+        raise MraError(fn, st, lib().mra_status_str(st).decode())
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def coarsest_level(p: int) -> int:
+    return int(math.ceil(math.log2(2 * p)))
+
+
+def grid_desc(J: int, p: int, eps: float, length: float = 2.0 * math.pi, adjacent_zone: int = 1,
+              j0: Optional[int] = None) -> GridDesc:
+    return GridDesc(J, coarsest_level(p) if j0 is None else j0, p, adjacent_zone, length, eps)
+
+
+def flow_desc(nu0: float, cs: float = 0.17, s0: float = 0.0, mu: float = 0.0, smag_mode: int = 2) -> FlowDesc:
+    return FlowDesc(nu0, cs, s0, mu, smag_mode, 0)
+
+
+def bulk_dtype(prec: int) -> torch.dtype:
+    return torch.float64 if prec == MRA_FP64 else torch.float32
+
+
+def _alloc(nbytes: int, device) -> torch.Tensor:
+    # 256-byte alignment: over-allocate and slice
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw[off: off + nbytes]
+
+
+def transform_ws_bytes(g: GridDesc, prec: int) -> int:
+    n = C.c_size_t()
+    _check("mra_transform_ws_bytes", lib().mra_transform_ws_bytes(C.byref(g), prec, C.byref(n)))
+    return n.value
+
+
+def mra_transform(g: GridDesc, prec: int, direction: int, inp: torch.Tensor, out: torch.Tensor,
+                  mask: Optional[torch.Tensor] = None, index_packed: Optional[torch.Tensor] = None,
+                  index_fine: Optional[torch.Tensor] = None, n_active: Optional[torch.Tensor] = None,
+                  ws: Optional[torch.Tensor] = None, stream=None) -> None:
+    if ws is None:
+        ws = _alloc(transform_ws_bytes(g, prec), inp.device)
+    st = lib().mra_transform(C.byref(g), prec, direction, _ptr(inp), _ptr(out), _ptr(mask),
+                             _ptr(index_packed), _ptr(index_fine), _ptr(n_active), _ptr(ws),
+                             ws.numel(), _stream(stream))
+    _check("mra_transform", st)
+
+
+def rhs_ws_bytes(g: GridDesc, prec: int) -> int:
+    n = C.c_size_t()
+    _check("mra_rhs_ws_bytes", lib().mra_rhs_ws_bytes(C.byref(g), prec, C.byref(n)))
+    return n.value
+
+
+def collocation_rhs(g: GridDesc, f: FlowDesc, prec: int, mask: torch.Tensor, index_fine: torch.Tensor,
+                    n_active: torch.Tensor, omega_active: torch.Tensor, v_active: Optional[torch.Tensor],
+                    out_active: torch.Tensor, psi: Optional[torch.Tensor] = None,
+                    ws: Optional[torch.Tensor] = None, stream=None) -> None:
+    if ws is None:
+        ws = _alloc(rhs_ws_bytes(g, prec), omega_active.device)
+    st = lib().collocation_rhs(C.byref(g), C.byref(f), prec, _ptr(mask), _ptr(index_fine), _ptr(n_active),
+                               _ptr(omega_active), _ptr(v_active), _ptr(out_active), _ptr(psi), _ptr(ws),
+                               ws.numel(), _stream(stream))
+    _check("collocation_rhs", st)
+
+
+def solve_footprint(g: GridDesc, prec: int, m: int) -> int:
+    n = C.c_size_t()
+    _check("mra_solve_footprint", lib().mra_solve_footprint(C.byref(g), prec, m, C.byref(n)))
+    return n.value
+
+
+DIAG_KEYS = ("t", "energy", "enstrophy", "palinstrophy", "gamma", "max_abs", "n_active", "status")
+
+
+class Solve:
+    """One solve whose whole state lives in a torch-allocated device arena."""
+
+    def __init__(self, g: GridDesc, f: FlowDesc, prec: int, m: int, dt: float, omega0: torch.Tensor,
+                 stream=None, arena: Optional[torch.Tensor] = None):
+        N = 1 << g.J
+        if omega0.dtype != torch.float64 or tuple(omega0.shape) != (N, N):
+            raise ValueError("omega0 must be a float64 [N, N] device tensor")
+        self.g, self.f, self.prec, self.m, self.dt = g, f, prec, m, dt
+        self.N = N
+        self.nbytes = solve_footprint(g, prec, m)
+        self.arena = arena if arena is not None else _alloc(self.nbytes, omega0.device)
+        h = C.c_void_p()
+        st = lib().mra_solve_init(C.byref(g), C.byref(f), prec, m, dt, _ptr(omega0.contiguous()),
+                                  _ptr(self.arena), self.arena.numel(), _stream(stream), C.byref(h))
+        _check("mra_solve_init", st)
+        self.handle = h
+
+    def step(self, nsteps: int = 1, stream=None) -> None:
+        _check("krylov_step", lib().krylov_step(self.handle, nsteps, _stream(stream)))
+
+    def read(self, dense: bool = True, stream=None) -> Tuple[Optional[torch.Tensor], Dict[str, float]]:
+        out = torch.empty((self.N, self.N), dtype=torch.float64, device=self.arena.device) if dense else None
+        diag = (C.c_double * 8)()
+        st = lib().mra_solve_read(self.handle, _ptr(out), diag, _stream(stream))
+        if st not in (MRA_OK, MRA_E_NONFINITE):
+            _check("mra_solve_read", st)
+        return out, dict(zip(DIAG_KEYS, list(diag)))
+
+    def ptrs(self) -> SolvePtrs:
+        p = SolvePtrs()
+        _check("mra_solve_ptrs_get", lib().mra_solve_ptrs_get(self.handle, C.byref(p)))
+        return p
+
+    def _arena_view(self, addr: int, n: int, dtype: torch.dtype) -> torch.Tensor:
+        """View of n elements at device address addr inside this solve's arena."""
+        esz = torch.empty((), dtype=dtype).element_size()
+        off = addr - self.arena.data_ptr()
+        if off < 0 or off + n * esz > self.arena.numel():
+            raise ValueError("address outside the arena")
+        return self.arena[off: off + n * esz].view(dtype)
+
+    def active_set(self) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor, torch.Tensor]:
+        """(omega_M, mask, index_packed, index_fine) copied out of the arena."""
+        p = self.ptrs()
+        torch.cuda.synchronize(self.arena.device)
+        na = int(self._arena_view(p.n_active, 1, torch.int64).item())
+        nf = self.N * self.N
+        return (self._arena_view(p.omega_active, na, torch.float64).clone(),
+                self._arena_view(p.mask, nf, torch.uint8).clone(),
+                self._arena_view(p.index_packed, na, torch.int32).clone(),
+                self._arena_view(p.index_fine, na, torch.int32).clone())
+
+    def scalars(self) -> Dict[str, float]:
+        """t, steps and the active-point residual evaluations counted on the device."""
+        p = self.ptrs()
+        torch.cuda.synchronize(self.arena.device)
+        v = self._arena_view(p.scalars, 16, torch.float64).cpu().tolist()
+        return {"t": v[4], "evals": v[5], "steps": v[6], "beta": v[0]}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().mra_solve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+KERNELS = {"jvp": 0, "fft_rows": 1, "fft_cols": 2, "fft_rows_inv": 3, "prolong_finest": 4,
+           "forward": 5, "rhs": 6}
+
+
+def time_kernel(solves: Sequence[Solve], which: str, reps: int, stream=None) -> float:
+    """Mean duration [ms] of one launch of a step kernel for this batch (HIP events)."""
+    n = len(solves)
+    hs = (C.c_void_p * n)(*[s.handle for s in solves])
+    ms = C.c_float()
+    _check("mra_time_kernel", lib().mra_time_kernel(hs, n, KERNELS[which], reps, _stream(stream), C.byref(ms)))
+    return ms.value
+
+
+def solve_batch(solves: Sequence[Solve], nsteps: Sequence[int], stream=None) -> None:
+    n = len(solves)
+    hs = (C.c_void_p * n)(*[s.handle for s in solves])
+    ns = (C.c_int32 * n)(*[int(k) for k in nsteps])
+    _check("solve_batch", lib().solve_batch(hs, n, ns, _stream(stream)))

@@ -1,0 +1,312 @@
+// Collocation stencils of the residual and of its Jacobian-vector product,
+// and the diagnostics, on tiles of the dense finest grid staged in LDS.
+//
+// Section 2.5: first derivatives at a node use the DD collocation filter
+// (D1 f)[k] = (1/h) sum_{n=1}^{2p-2} a_n (f[k+n] - f[k-n]), a_n = -phi'(n):
+//   p = 2: (2/3, -1/12);  p = 3: (272/365, -53/365, 16/1095, 1/2920).
+// Second derivatives use the (2p+1)-point Lagrange rule
+//   p = 2: (-5/2; 4/3, -1/12)/h^2;  p = 3: (-49/18; 3/2, -3/20, 1/90)/h^2.
+// Section 2.3, eq. (5): Smagorinsky eddy viscosity nu_e = nu0 + (Cs h)^2 |S|,
+// |S| = sqrt(2 S_ij S_ij) from the resolved strain of u = D1_y psi,
+// v = -D1_x psi.
+// Residual (flux form, symmetric conservative diffusion):
+//   F = -[D1_x(u w) + D1_y(v w)] + 1/2 [L(nu w) + nu L w - w L nu] - mu w,
+// evaluated only at the active nodes of a tile (written to their position in
+// the active list through the dense rank map); tiles without an active node
+// skip the residual.  The residual kernel also stores u, v, nu_e on the whole
+// grid: the Jacobian-vector products of the step reuse them with nu_e frozen.
+#include "mra_internal.hpp"
+
+namespace mra {
+
+template <int P, typename T> __device__ inline T d1c(int n) {
+  if constexpr (P == 2) return n == 1 ? T(2.0 / 3.0) : T(-1.0 / 12.0);
+  else return n == 1 ? T(272.0 / 365.0) : n == 2 ? T(-53.0 / 365.0) : n == 3 ? T(16.0 / 1095.0) : T(1.0 / 2920.0);
+}
+template <int P, typename T> __device__ inline T d2c(int n) {
+  if constexpr (P == 2) return n == 0 ? T(-2.5) : n == 1 ? T(4.0 / 3.0) : T(-1.0 / 12.0);
+  else return n == 0 ? T(-49.0 / 18.0) : n == 1 ? T(1.5) : n == 2 ? T(-0.15) : T(1.0 / 90.0);
+}
+
+// D1 along x / y at (r, c) of an LDS array with pitch W (times 1/h outside)
+template <int P, typename T> __device__ inline T dx1(const T* a, int W, int r, int c) {
+  T s = T(0);
+#pragma unroll
+  for (int n = 1; n <= 2 * P - 2; ++n) s += d1c<P, T>(n) * (a[r * W + c + n] - a[r * W + c - n]);
+  return s;
+}
+template <int P, typename T> __device__ inline T dy1(const T* a, int W, int r, int c) {
+  T s = T(0);
+#pragma unroll
+  for (int n = 1; n <= 2 * P - 2; ++n) s += d1c<P, T>(n) * (a[(r + n) * W + c] - a[(r - n) * W + c]);
+  return s;
+}
+// L = D2_x + D2_y (times 1/h^2 outside)
+template <int P, typename T> __device__ inline T lap5(const T* a, int W, int r, int c) {
+  T s = T(2) * d2c<P, T>(0) * a[r * W + c];
+#pragma unroll
+  for (int n = 1; n <= P; ++n)
+    s += d2c<P, T>(n) * ((a[r * W + c + n] + a[r * W + c - n]) + (a[(r + n) * W + c] + a[(r - n) * W + c]));
+  return s;
+}
+
+template <typename T>
+__device__ inline void load_region(T* dst, const T* __restrict__ src, int x0, int y0, int W, int N) {
+  const int nm = N - 1;
+  for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+    const int r = q / W, c = q - r * W;
+    dst[q] = src[((y0 + r) & nm) * N + ((x0 + c) & nm)];
+  }
+}
+
+__device__ inline int tile_of_block(int bid, int ntiles) {
+  // XCD-aware: consecutive blocks are dealt round-robin to the 8 XCDs; give
+  // each XCD a contiguous run of tiles so that shared halos stay in its L2.
+  if ((ntiles & 7) != 0) return bid;
+  return (bid & 7) * (ntiles >> 3) + (bid >> 3);
+}
+
+template <int P> struct Geo {
+  static constexpr int R1 = 2 * P - 2;   // D1 reach
+  static constexpr int HP = 5 * P - 4;   // psi halo for the residual
+  static constexpr int HU = 3 * P - 2;   // u, v halo for the residual
+};
+
+template <int P, typename T>
+__host__ __device__ inline size_t rhs_lds_elems(int TS) {
+  using G = Geo<P>;
+  const size_t Wp = TS + 2 * G::HP, Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
+  return Wp * Wp + 2 * Wu * Wu + Wn * Wn + Ww * Ww;
+}
+template <int P, typename T>
+__host__ __device__ inline size_t jvp_lds_elems(int TS) {
+  using G = Geo<P>;
+  const size_t Wpv = TS + 4 * G::R1, Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
+  return Wpv * Wpv + 3 * Ww * Ww + Wn * Wn;
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_rhs(Batch b) {
+  using G = Geo<P>;
+  extern __shared__ unsigned char smem[];
+  const SolveDev& s = *b.s[blockIdx.y];
+  const int N = s.N, TS = s.tile, ntx = s.ntx;
+  const int tile = tile_of_block(blockIdx.x, ntx * ntx);
+  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
+  const int Wp = TS + 2 * G::HP, Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
+  T* psi = reinterpret_cast<T*>(smem);
+  T* uu = psi + Wp * Wp;
+  T* vv = uu + Wu * Wu;
+  T* nu = vv + Wu * Wu;
+  T* ww = nu + Wn * Wn;
+  const T* gpsi = reinterpret_cast<const T*>(s.psi);
+  const T* gw = reinterpret_cast<const T*>(s.wt);
+  load_region(psi, gpsi, x0 - G::HP, y0 - G::HP, Wp, N);
+  load_region(ww, gw, x0 - G::R1, y0 - G::R1, Ww, N);
+  __syncthreads();
+  const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
+  // u = D1_y psi, v = -D1_x psi on the Wu region
+  for (int q = threadIdx.x; q < Wu * Wu; q += blockDim.x) {
+    const int r = q / Wu, c = q - r * Wu;
+    uu[q] = ih * dy1<P, T>(psi, Wp, r + G::R1, c + G::R1);
+    vv[q] = -ih * dx1<P, T>(psi, Wp, r + G::R1, c + G::R1);
+  }
+  __syncthreads();
+  // nu_e on the Wn region
+  const T cs2 = T((s.cs * s.h) * (s.cs * s.h));
+  const T nu0 = T(s.nu0);
+  const T nuc = T(s.nu0 + (s.cs * s.h) * (s.cs * s.h) * s.s0);
+  for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
+    const int r = q / Wn, c = q - r * Wn;
+    T val;
+    if (s.smag_mode == 2) {
+      const int ru = r + G::R1, cu = c + G::R1;
+      const T s11 = ih * dx1<P, T>(uu, Wu, ru, cu);
+      const T s22 = ih * dy1<P, T>(vv, Wu, ru, cu);
+      const T s12 = T(0.5) * ih * (dy1<P, T>(uu, Wu, ru, cu) + dx1<P, T>(vv, Wu, ru, cu));
+      val = nu0 + cs2 * sqrt(T(2) * (s11 * s11 + s22 * s22 + T(2) * s12 * s12));
+    } else {
+      val = s.smag_mode == 1 ? nuc : nu0;
+    }
+    nu[q] = val;
+  }
+  __syncthreads();
+  // store the base fields of the tile for the Jacobian-vector products
+  T* gu = reinterpret_cast<T*>(s.u);
+  T* gv = reinterpret_cast<T*>(s.v);
+  T* gn = reinterpret_cast<T*>(s.nu);
+  for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+    const int r = q / TS, c = q - r * TS;
+    const int f = (y0 + r) * N + x0 + c;
+    gu[f] = uu[(r + G::HU) * Wu + c + G::HU];
+    gv[f] = vv[(r + G::HU) * Wu + c + G::HU];
+    gn[f] = nu[(r + P) * Wn + c + P];
+  }
+  if (!s.tile_flag[tile]) return;
+  __syncthreads();
+  // fluxes u w, v w on the Ww region (in place of u, v), nu w on the Wn region
+  const int ou = G::HU - G::R1;   // = P
+  for (int q = threadIdx.x; q < Ww * Ww; q += blockDim.x) {
+    const int r = q / Ww, c = q - r * Ww;
+    const T wv = ww[q];
+    uu[(r + ou) * Wu + c + ou] *= wv;
+    vv[(r + ou) * Wu + c + ou] *= wv;
+  }
+  T* cn = psi;   // psi is dead: nu w with pitch Wn
+  const int on = G::R1 - P;
+  for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
+    const int r = q / Wn, c = q - r * Wn;
+    cn[q] = nu[q] * ww[(r + on) * Ww + c + on];
+  }
+  __syncthreads();
+  const int* rank = s.rank;
+  const T mu = T(s.mu);
+  double* out = s.out_rhs;
+  for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+    const int r = q / TS, c = q - r * TS;
+    const int k = rank[(y0 + r) * N + x0 + c];
+    if (k < 0) continue;
+    const int ra = r + G::HU, ca = c + G::HU;
+    const T adv = -ih * (dx1<P, T>(uu, Wu, ra, ca) + dy1<P, T>(vv, Wu, ra, ca));
+    const int rw = r + G::R1, cw = c + G::R1, rn = r + P, cn_ = c + P;
+    const T wv = ww[rw * Ww + cw];
+    const T nv = nu[rn * Wn + cn_];
+    const T diff = T(0.5) * ih2 * (lap5<P, T>(cn, Wn, rn, cn_) + nv * lap5<P, T>(ww, Ww, rw, cw) -
+                                   wv * lap5<P, T>(nu, Wn, rn, cn_));
+    out[k] = (double)(adv + diff - mu * wv);
+  }
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_jvp(Batch b) {
+  using G = Geo<P>;
+  extern __shared__ unsigned char smem[];
+  const SolveDev& s = *b.s[blockIdx.y];
+  if (s.ctrl[C_DONE]) return;
+  const int N = s.N, TS = s.tile, ntx = s.ntx, nm = N - 1;
+  const int tile = tile_of_block(blockIdx.x, ntx * ntx);
+  if (!s.tile_flag[tile]) return;
+  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
+  const int Wpv = TS + 4 * G::R1, Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
+  T* pv = reinterpret_cast<T*>(smem);
+  T* vt = pv + Wpv * Wpv;
+  T* fa = vt + Ww * Ww;
+  T* fb = fa + Ww * Ww;
+  T* nu = fb + Ww * Ww;
+  load_region(pv, reinterpret_cast<const T*>(s.psiv), x0 - 2 * G::R1, y0 - 2 * G::R1, Wpv, N);
+  load_region(vt, reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, Ww, N);
+  load_region(nu, reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, Wn, N);
+  __syncthreads();
+  const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
+  const T* gu = reinterpret_cast<const T*>(s.u);
+  const T* gv = reinterpret_cast<const T*>(s.v);
+  const T* gw = reinterpret_cast<const T*>(s.wt);
+  // fluxes of the linearised advection on the Ww region
+  for (int q = threadIdx.x; q < Ww * Ww; q += blockDim.x) {
+    const int r = q / Ww, c = q - r * Ww;
+    const int f = ((y0 - G::R1 + r) & nm) * N + ((x0 - G::R1 + c) & nm);
+    const T uv = ih * dy1<P, T>(pv, Wpv, r + G::R1, c + G::R1);
+    const T vv = -ih * dx1<P, T>(pv, Wpv, r + G::R1, c + G::R1);
+    const T wv = gw[f], vtv = vt[q];
+    fa[q] = uv * wv + gu[f] * vtv;
+    fb[q] = vv * wv + gv[f] * vtv;
+  }
+  __syncthreads();
+  T* cn = pv;   // psi_v is dead: nu v~ with pitch Wn
+  const int on = G::R1 - P;
+  for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
+    const int r = q / Wn, c = q - r * Wn;
+    cn[q] = nu[q] * vt[(r + on) * Ww + c + on];
+  }
+  __syncthreads();
+  const int* rank = s.rank;
+  const T mu = T(s.mu);
+  double* out = s.out_jvp;
+  for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+    const int r = q / TS, c = q - r * TS;
+    const int k = rank[(y0 + r) * N + x0 + c];
+    if (k < 0) continue;
+    const int ra = r + G::R1, ca = c + G::R1, rn = r + P, cn_ = c + P;
+    const T adv = -ih * (dx1<P, T>(fa, Ww, ra, ca) + dy1<P, T>(fb, Ww, ra, ca));
+    const T vv = vt[ra * Ww + ca];
+    const T nv = nu[rn * Wn + cn_];
+    const T diff = T(0.5) * ih2 * (lap5<P, T>(cn, Wn, rn, cn_) + nv * lap5<P, T>(vt, Ww, ra, ca) -
+                                   vv * lap5<P, T>(nu, Wn, rn, cn_));
+    out[k] = (double)(adv + diff - mu * vv);
+  }
+}
+
+template <int P, typename T>
+static hipError_t rhs_t(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {
+  const int N = 1 << c.J;
+  const int TS = tile_edge(c.J, c.p, c.prec);
+  const int nt = (N / TS) * (N / TS);
+  if (!jvp) {
+    const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
+    hipLaunchKernelGGL((k_rhs<P, T>), dim3(nt, b.n), dim3(256), lds, st, b);
+  } else {
+    const size_t lds = jvp_lds_elems<P, T>(TS) * sizeof(T);
+    hipLaunchKernelGGL((k_jvp<P, T>), dim3(nt, b.n), dim3(256), lds, st, b);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t rhs_dispatch(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {
+  if (c.prec == 0) return c.p == 2 ? rhs_t<2, double>(b, c, jvp, st) : rhs_t<3, double>(b, c, jvp, st);
+  return c.p == 2 ? rhs_t<2, float>(b, c, jvp, st) : rhs_t<3, float>(b, c, jvp, st);
+}
+
+hipError_t launch_rhs(const Batch& b, const LaunchCfg& c, hipStream_t st) { return rhs_dispatch(b, c, false, st); }
+hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st) { return rhs_dispatch(b, c, true, st); }
+
+// ------------------------------------------------------------- diagnostics
+// One block per row y of the FP64 field dense64 and its FP64 streamfunction
+// psi: row sums of w, u^2 + v^2, w^2, |grad w|^2 and the row max of |w|
+// (Sections 3.3, 3.4).  The host adds the rows in order.
+template <int P>
+__global__ void __launch_bounds__(256) k_diag(Batch b) {
+  const SolveDev& s = *b.s[blockIdx.y];
+  const int N = s.N, nm = N - 1, y = blockIdx.x;
+  const double* w = s.dense64;
+  const double* ps = reinterpret_cast<const double*>(s.psi);
+  const double ih = 1.0 / s.h;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+  for (int x = threadIdx.x; x < N; x += blockDim.x) {
+    double u = 0, v = 0, gx = 0, gy = 0;
+    for (int n = 1; n <= 2 * P - 2; ++n) {
+      const double cn = d1c<P, double>(n);
+      u += cn * (ps[((y + n) & nm) * N + x] - ps[((y - n) & nm) * N + x]);
+      v -= cn * (ps[y * N + ((x + n) & nm)] - ps[y * N + ((x - n) & nm)]);
+      gy += cn * (w[((y + n) & nm) * N + x] - w[((y - n) & nm) * N + x]);
+      gx += cn * (w[y * N + ((x + n) & nm)] - w[y * N + ((x - n) & nm)]);
+    }
+    u *= ih; v *= ih; gx *= ih; gy *= ih;
+    const double wv = w[y * N + x];
+    a0 += wv;
+    a1 += u * u + v * v;
+    a2 += wv * wv;
+    a3 += gx * gx + gy * gy;
+    a4 = fmax(a4, fabs(wv));
+  }
+  __shared__ double red[5][256];
+  red[0][threadIdx.x] = a0; red[1][threadIdx.x] = a1; red[2][threadIdx.x] = a2;
+  red[3][threadIdx.x] = a3; red[4][threadIdx.x] = a4;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) s.diag[y * 5 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_diag(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  const int N = 1 << c.J;
+  if (c.p == 2) hipLaunchKernelGGL(k_diag<2>, dim3(N, b.n), dim3(256), 0, st, b);
+  else hipLaunchKernelGGL(k_diag<3>, dim3(N, b.n), dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+}  // namespace mra

@@ -1,0 +1,640 @@
+// C-ABI of the library: argument checks, workspace / arena layouts, the
+// sequence of launches of one exponential step, HIP-graph capture of that
+// step, batching of solves, read-back and diagnostics.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/mra.h"
+#include "mra_internal.hpp"
+
+using namespace mra;
+
+struct mra_solve_s {
+  SolveDev host;          // pointers into the arena
+  SolveDev* dev = nullptr;
+  LaunchCfg cfg{};
+  int device = 0;
+  hipGraphExec_t graph = nullptr;
+  hipGraph_t graph_def = nullptr;
+  hipStream_t graph_stream = nullptr;
+  std::vector<double> diag_rows;
+};
+
+namespace {
+
+std::mutex g_mu;
+bool g_init[64] = {};
+
+#define MRA_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return MRA_E_DEVICE;          \
+  } while (0)
+
+int32_t ensure_init() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MRA_E_DEVICE;
+  if (dev < 0 || dev >= 64) return MRA_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_init[dev]) return MRA_OK;
+  MRA_TRY(fft_init_tables(nullptr));
+  MRA_TRY(hipDeviceSynchronize());
+  g_init[dev] = true;
+  return MRA_OK;
+}
+
+int32_t check_grid(const mra_grid_desc* g) {
+  if (!g) return MRA_E_ARG;
+  if (g->p != 2 && g->p != 3) return MRA_E_SIZE;
+  const int j0 = g->p == 2 ? 2 : 3;
+  if (g->j0 != j0) return MRA_E_SIZE;
+  if (g->J < j0 + 1 || g->J > kMaxJ) return MRA_E_SIZE;
+  if (!(g->length > 0.0) || !(g->eps >= 0.0) || !std::isfinite(g->eps)) return MRA_E_ARG;
+  if (g->adjacent_zone != 0 && g->adjacent_zone != 1) return MRA_E_ARG;
+  return MRA_OK;
+}
+
+int32_t check_flow(const mra_flow_desc* f) {
+  if (!f) return MRA_E_ARG;
+  if (!(f->nu0 >= 0.0) || !(f->mu >= 0.0) || !(f->cs >= 0.0) || !(f->s0 >= 0.0)) return MRA_E_ARG;
+  if (f->smag_mode < 0 || f->smag_mode > 2) return MRA_E_ARG;
+  return MRA_OK;
+}
+
+int prec_bulk(int32_t prec) { return prec == MRA_FP64 ? 0 : 1; }
+
+// Simple bump allocator over a caller buffer (null base = size query).
+struct Layout {
+  char* base;
+  size_t off = 0;
+  explicit Layout(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+void fill_geometry(SolveDev& s, const mra_grid_desc* g, int32_t prec) {
+  std::memset(&s, 0, sizeof(s));
+  s.J = g->J;
+  s.j0 = g->j0;
+  s.p = g->p;
+  s.N = 1 << g->J;
+  s.prec = prec_bulk(prec);
+  s.adjacent_zone = g->adjacent_zone;
+  s.tile = tile_edge(s.J, s.p, s.prec);
+  s.ntx = s.N / s.tile;
+  s.length = g->length;
+  s.h = g->length / s.N;
+  s.eps = g->eps;
+}
+
+void fill_flow(SolveDev& s, const mra_flow_desc* f) {
+  s.nu0 = f->nu0;
+  s.cs = f->cs;
+  s.s0 = f->s0;
+  s.mu = f->mu;
+  s.smag_mode = f->smag_mode;
+}
+
+int nscan_of(int J) {
+  const int nf = 1 << (2 * J);
+  return (nf + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
+}
+
+// Workspace of the stand-alone transform.
+void transform_layout(Layout& L, SolveDev& s) {
+  const size_t Nf = (size_t)s.N * s.N;
+  (void)L.take<SolveDev>(1);
+  s.umax = L.take<unsigned long long>(1);
+  s.ctrl = L.take<int>(C_NCTRL);
+  s.scal = L.take<double>(S_NSCAL);
+  s.block_off = L.take<int32_t>(nscan_of(s.J));
+  s.rank = L.take<int32_t>(Nf);
+  s.tile_flag = L.take<uint8_t>((size_t)s.ntx * s.ntx);
+}
+
+// Workspace of the stand-alone residual / JVP.
+void rhs_layout(Layout& L, SolveDev& s) {
+  const size_t Nf = (size_t)s.N * s.N;
+  const size_t esz = s.prec == 0 ? 8 : 4;
+  (void)L.take<SolveDev>(1);
+  s.ctrl = L.take<int>(C_NCTRL);
+  s.scal = L.take<double>(S_NSCAL);
+  s.rank = L.take<int32_t>(Nf);
+  s.tile_flag = L.take<uint8_t>((size_t)s.ntx * s.ntx);
+  s.wt = L.take<char>(Nf * esz);
+  s.psi = L.take<char>(Nf * esz);
+  s.u = L.take<char>(Nf * esz);
+  s.v = L.take<char>(Nf * esz);
+  s.nu = L.take<char>(Nf * esz);
+  s.vt = L.take<char>(Nf * esz);
+  s.psiv = L.take<char>(Nf * esz);
+  s.spec = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 2 * esz);
+  s.out_rhs = L.take<double>(Nf);
+}
+
+// Arena of a solve.
+void solve_layout(Layout& L, SolveDev& s) {
+  const size_t Nf = (size_t)s.N * s.N;
+  const size_t esz = s.prec == 0 ? 8 : 4;
+  (void)L.take<SolveDev>(1);
+  s.ctrl = L.take<int>(C_NCTRL);
+  s.scal = L.take<double>(S_NSCAL);
+  s.umax = L.take<unsigned long long>(1);
+  s.n_active = L.take<int64_t>(1);
+  s.mask = L.take<uint8_t>(Nf);
+  s.index_packed = L.take<int32_t>(Nf);
+  s.index_fine = L.take<int32_t>(Nf);
+  s.rank = L.take<int32_t>(Nf);
+  s.tile_flag = L.take<uint8_t>((size_t)s.ntx * s.ntx);
+  s.block_off = L.take<int32_t>(nscan_of(s.J));
+  s.omega = L.take<double>(Nf);
+  s.V = L.take<double>((size_t)(s.m + 1) * Nf);
+  s.w = L.take<double>(Nf);
+  s.H = L.take<double>((size_t)(s.m + 1) * s.m);
+  s.hpart = L.take<double>(2 * (kMaxM + 1));
+  s.y = L.take<double>(kMaxM + 1);
+  s.partials = L.take<double>((size_t)kRedBlocks * (kMaxM + 2));
+  s.wt = L.take<char>(Nf * esz);
+  s.psi = L.take<char>(Nf * 8);      // FP64 for the diagnostics
+  s.u = L.take<char>(Nf * esz);
+  s.v = L.take<char>(Nf * esz);
+  s.nu = L.take<char>(Nf * esz);
+  s.vt = L.take<char>(Nf * esz);
+  s.psiv = L.take<char>(Nf * esz);
+  s.spec = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 16);
+  s.dense64 = L.take<double>(Nf);
+  s.packed64 = L.take<double>(Nf);
+  s.diag = L.take<double>((size_t)s.N * 5);
+  s.out_rhs = s.w;
+  s.out_jvp = s.w;
+}
+
+Batch one(const SolveDev* d) {
+  Batch b;
+  std::memset(&b, 0, sizeof(b));
+  b.s[0] = d;
+  b.n = 1;
+  return b;
+}
+
+// One exponential Rosenbrock-Euler step with regrid for every solve of b.
+hipError_t enqueue_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  const int dbl = c.prec == 0;
+  hipError_t e;
+  // residual F at omega
+  if ((e = launch_scatter(b, c, 0, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_prolong(b, c, 0, dbl, st)) != hipSuccess) return e;
+  if ((e = launch_poisson(b, c, 0, st)) != hipSuccess) return e;
+  if ((e = launch_rhs(b, c, st)) != hipSuccess) return e;
+  if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
+  // Arnoldi
+  for (int j = 0; j < c.m; ++j) {
+    if ((e = launch_scatter(b, c, 1, 1, j, st)) != hipSuccess) return e;
+    if ((e = launch_prolong(b, c, 1, dbl, st)) != hipSuccess) return e;
+    if ((e = launch_poisson(b, c, 1, st)) != hipSuccess) return e;
+    if ((e = launch_jvp(b, c, st)) != hipSuccess) return e;
+    if ((e = launch_arnoldi(b, c, j, st)) != hipSuccess) return e;
+  }
+  if ((e = launch_phi1(b, c, st)) != hipSuccess) return e;
+  if ((e = launch_update(b, c, st)) != hipSuccess) return e;
+  // FP64 regrid: Pi on the old set, forward transform, threshold, gather
+  if ((e = launch_scatter(b, c, 0, 2, 0, st)) != hipSuccess) return e;
+  if ((e = launch_prolong(b, c, 2, 1, st)) != hipSuccess) return e;
+  if ((e = launch_reset_max(b, st)) != hipSuccess) return e;
+  if ((e = launch_forward(b, c, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_threshold(b, c, 1, st)) != hipSuccess) return e;
+  return launch_gather(b, c, st);
+}
+
+bool graphs_enabled() {
+  const char* v = std::getenv("MRA_NO_GRAPH");
+  return !(v && v[0] == '1');
+}
+
+struct GraphEntry {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+};
+std::map<std::pair<std::vector<const void*>, hipStream_t>, GraphEntry> g_batch_graphs;
+
+void drop_batch_graphs() {
+  for (auto& kv : g_batch_graphs) {
+    if (kv.second.x) (void)hipGraphExecDestroy(kv.second.x);
+    if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+  }
+  g_batch_graphs.clear();
+}
+
+hipError_t capture(const Batch& b, const LaunchCfg& c, hipStream_t st, hipGraph_t* g, hipGraphExec_t* x) {
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t e1 = enqueue_step(b, c, st);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(st, &graph);
+  if (e1 != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return e1; }
+  if (e2 != hipSuccess) return e2;
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) { (void)hipGraphDestroy(graph); return e; }
+  *g = graph;
+  *x = exec;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mra_status_str(int32_t st) {
+  switch (st) {
+    case MRA_OK: return "ok";
+    case MRA_E_ARG: return "invalid argument";
+    case MRA_E_SIZE: return "unsupported size";
+    case MRA_E_NOMEM: return "buffer too small";
+    case MRA_E_DEVICE: return "HIP error";
+    case MRA_E_NONFINITE: return "non-finite value";
+    case MRA_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+int32_t mra_abi_version(void) { return 1; }
+
+int32_t mra_init(void) { return ensure_init(); }
+
+int32_t mra_transform_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes) {
+  int32_t r = check_grid(g);
+  if (r != MRA_OK) return r;
+  if (!bytes || prec < 0 || prec > 2) return MRA_E_ARG;
+  SolveDev s;
+  fill_geometry(s, g, prec);
+  Layout L(nullptr);
+  transform_layout(L, s);
+  *bytes = L.off + 256;
+  return MRA_OK;
+}
+
+int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const void* in, void* out,
+                      uint8_t* mask, int32_t* index_packed, int32_t* index_fine, int64_t* n_active,
+                      void* ws, size_t ws_bytes, void* stream) {
+  int32_t r = check_grid(g);
+  if (r != MRA_OK) return r;
+  if (prec < 0 || prec > 2 || !in || !out || !ws) return MRA_E_ARG;
+  if (dir != MRA_FORWARD && dir != MRA_INVERSE && dir != MRA_PROLONG) return MRA_E_ARG;
+  if (dir == MRA_FORWARD && mask && (!index_packed || !index_fine || !n_active)) return MRA_E_ARG;
+  if (dir == MRA_PROLONG && (!mask || !index_fine || !n_active)) return MRA_E_ARG;
+  size_t need = 0;
+  mra_transform_ws_bytes(g, prec, &need);
+  if (ws_bytes < need) return MRA_E_NOMEM;
+  if ((r = ensure_init()) != MRA_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SolveDev s;
+  fill_geometry(s, g, prec);
+  Layout L(ws);
+  transform_layout(L, s);
+  SolveDev* dev = reinterpret_cast<SolveDev*>(ws);
+  const bool dbl = s.prec == 0;
+  LaunchCfg c{s.J, s.p, s.prec, 0};
+  s.mask = mask;
+  s.index_packed = index_packed;
+  s.index_fine = index_fine;
+  s.n_active = n_active;
+  if (dir == MRA_FORWARD) {
+    if (dbl) { s.dense64 = (double*)in; s.packed64 = (double*)out; }
+    else { s.wt = const_cast<void*>(in); s.spec = out; }
+    MRA_TRY(launch_write_desc(dev, s, st));
+    Batch b = one(dev);
+    MRA_TRY(launch_reset_max(b, st));
+    MRA_TRY(launch_forward(b, c, dbl ? 0 : 1, dbl ? 0 : 1, st));
+    if (mask) MRA_TRY(launch_threshold(b, c, dbl ? 1 : 0, st));
+  } else if (dir == MRA_INVERSE) {
+    s.spec = const_cast<void*>(in);
+    s.wt = out;
+    MRA_TRY(launch_write_desc(dev, s, st));
+    MRA_TRY(launch_inverse(one(dev), c, st));
+  } else {
+    s.omega = (double*)in;
+    if (dbl) s.dense64 = (double*)out;
+    else s.wt = out;
+    MRA_TRY(launch_write_desc(dev, s, st));
+    Batch b = one(dev);
+    MRA_TRY(launch_scatter(b, c, 0, dbl ? 2 : 0, 0, st));
+    MRA_TRY(launch_prolong(b, c, dbl ? 2 : 0, dbl ? 1 : 0, st));
+  }
+  return MRA_OK;
+}
+
+int32_t mra_rhs_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes) {
+  int32_t r = check_grid(g);
+  if (r != MRA_OK) return r;
+  if (!bytes || prec < 0 || prec > 2) return MRA_E_ARG;
+  SolveDev s;
+  fill_geometry(s, g, prec);
+  Layout L(nullptr);
+  rhs_layout(L, s);
+  *bytes = L.off + 256;
+  return MRA_OK;
+}
+
+int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, const uint8_t* mask,
+                        const int32_t* index_fine, const int64_t* n_active, const double* omega_active,
+                        const double* v_active, double* out_active, void* psi_dense_or_null, void* ws,
+                        size_t ws_bytes, void* stream) {
+  int32_t r = check_grid(g);
+  if (r != MRA_OK) return r;
+  if ((r = check_flow(f)) != MRA_OK) return r;
+  if (prec < 0 || prec > 2 || !mask || !index_fine || !n_active || !omega_active || !out_active || !ws)
+    return MRA_E_ARG;
+  size_t need = 0;
+  mra_rhs_ws_bytes(g, prec, &need);
+  if (ws_bytes < need) return MRA_E_NOMEM;
+  if ((r = ensure_init()) != MRA_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SolveDev s;
+  fill_geometry(s, g, prec);
+  fill_flow(s, f);
+  Layout L(ws);
+  rhs_layout(L, s);
+  SolveDev* dev = reinterpret_cast<SolveDev*>(ws);
+  s.mask = const_cast<uint8_t*>(mask);
+  s.index_fine = const_cast<int32_t*>(index_fine);
+  s.n_active = const_cast<int64_t*>(n_active);
+  s.omega = const_cast<double*>(omega_active);
+  if (psi_dense_or_null) s.psi = psi_dense_or_null;
+  if (v_active) {
+    s.out_jvp = out_active;
+    s.vin = v_active;
+  } else {
+    s.out_rhs = out_active;
+  }
+  const int dbl = s.prec == 0;
+  LaunchCfg c{s.J, s.p, s.prec, 0};
+  MRA_TRY(launch_write_desc(dev, s, st));
+  Batch b = one(dev);
+  MRA_TRY(launch_reset_ctrl(b, st));
+  MRA_TRY(launch_rank_from_index(b, c, st));
+  MRA_TRY(launch_scatter(b, c, 0, 0, 0, st));
+  MRA_TRY(launch_prolong(b, c, 0, dbl, st));
+  MRA_TRY(launch_poisson(b, c, 0, st));
+  MRA_TRY(launch_rhs(b, c, st));
+  if (v_active) {
+    MRA_TRY(launch_scatter(b, c, 2, 1, 0, st));
+    MRA_TRY(launch_prolong(b, c, 1, dbl, st));
+    MRA_TRY(launch_poisson(b, c, 1, st));
+    MRA_TRY(launch_jvp(b, c, st));
+  }
+  return MRA_OK;
+}
+
+int32_t mra_solve_footprint(const mra_grid_desc* g, int32_t prec, int32_t m, size_t* bytes) {
+  int32_t r = check_grid(g);
+  if (r != MRA_OK) return r;
+  if (!bytes || prec < 0 || prec > 2) return MRA_E_ARG;
+  if (m < 1 || m > kMaxM) return MRA_E_SIZE;
+  SolveDev s;
+  fill_geometry(s, g, prec);
+  s.m = m;
+  Layout L(nullptr);
+  solve_layout(L, s);
+  *bytes = L.off + 256;
+  return MRA_OK;
+}
+
+int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, int32_t m, double dt,
+                       const double* omega0_dense, void* arena, size_t arena_bytes, void* stream,
+                       mra_solve* out) {
+  int32_t r = check_grid(g);
+  if (r != MRA_OK) return r;
+  if ((r = check_flow(f)) != MRA_OK) return r;
+  if (!omega0_dense || !arena || !out || prec < 0 || prec > 2) return MRA_E_ARG;
+  if (m < 1 || m > kMaxM) return MRA_E_SIZE;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return MRA_E_ARG;
+  if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return MRA_E_ARG;
+  size_t need = 0;
+  mra_solve_footprint(g, prec, m, &need);
+  if (arena_bytes < need) return MRA_E_NOMEM;
+  if ((r = ensure_init()) != MRA_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  mra_solve_s* h = new (std::nothrow) mra_solve_s();
+  if (!h) return MRA_E_NOMEM;
+  SolveDev& s = h->host;
+  fill_geometry(s, g, prec);
+  fill_flow(s, f);
+  s.m = m;
+  s.dt = dt;
+  Layout L(arena);
+  solve_layout(L, s);
+  h->dev = reinterpret_cast<SolveDev*>(arena);
+  h->cfg = LaunchCfg{s.J, s.p, s.prec, m};
+  (void)hipGetDevice(&h->device);
+  h->diag_rows.resize((size_t)s.N * 5);
+  const size_t Nf = (size_t)s.N * s.N;
+  Batch b = one(h->dev);
+  hipError_t e;
+  if ((e = launch_write_desc(h->dev, s, st)) != hipSuccess ||
+      (e = launch_reset_ctrl(b, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.dense64, omega0_dense, Nf * sizeof(double), hipMemcpyDeviceToDevice, st)) !=
+          hipSuccess ||
+      (e = launch_reset_max(b, st)) != hipSuccess || (e = launch_forward(b, h->cfg, 0, 0, st)) != hipSuccess ||
+      (e = launch_threshold(b, h->cfg, 1, st)) != hipSuccess || (e = launch_gather(b, h->cfg, st)) != hipSuccess) {
+    delete h;
+    return MRA_E_DEVICE;
+  }
+  *out = h;
+  return MRA_OK;
+}
+
+int32_t krylov_step(mra_solve h, int32_t nsteps, void* stream) {
+  if (!h || nsteps < 0) return MRA_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Batch b = one(h->dev);
+  if (nsteps == 0) return MRA_OK;
+  if (!st || !graphs_enabled()) {
+    for (int i = 0; i < nsteps; ++i) MRA_TRY(enqueue_step(b, h->cfg, st));
+    return MRA_OK;
+  }
+  if (!h->graph || h->graph_stream != st) {
+    if (h->graph) { (void)hipGraphExecDestroy(h->graph); h->graph = nullptr; }
+    if (h->graph_def) { (void)hipGraphDestroy(h->graph_def); h->graph_def = nullptr; }
+    MRA_TRY(capture(b, h->cfg, st, &h->graph_def, &h->graph));
+    h->graph_stream = st;
+  }
+  for (int i = 0; i < nsteps; ++i) MRA_TRY(hipGraphLaunch(h->graph, st));
+  return MRA_OK;
+}
+
+int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* stream) {
+  if (!solves || !nsteps || n < 0) return MRA_E_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!solves[i] || nsteps[i] < 0) return MRA_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int maxs = 0;
+  for (int i = 0; i < n; ++i) maxs = std::max(maxs, nsteps[i]);
+  const bool use_graph = st && graphs_enabled();
+  for (int t = 0; t < maxs; ++t) {
+    // group the solves still running by launch configuration
+    std::map<std::tuple<int, int, int, int>, std::vector<mra_solve>> groups;
+    for (int i = 0; i < n; ++i)
+      if (nsteps[i] > t) {
+        const LaunchCfg& c = solves[i]->cfg;
+        groups[std::make_tuple(c.J, c.p, c.prec, c.m)].push_back(solves[i]);
+      }
+    for (auto& kv : groups) {
+      auto& v = kv.second;
+      for (size_t o = 0; o < v.size(); o += kMaxBatch) {
+        Batch b;
+        std::memset(&b, 0, sizeof(b));
+        b.n = (int)std::min<size_t>(kMaxBatch, v.size() - o);
+        std::vector<const void*> key;
+        for (int k = 0; k < b.n; ++k) {
+          b.s[k] = v[o + k]->dev;
+          key.push_back(v[o + k]);
+        }
+        const LaunchCfg& c = v[o]->cfg;
+        if (!use_graph) {
+          MRA_TRY(enqueue_step(b, c, st));
+          continue;
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_batch_graphs.find({key, st});
+        if (it == g_batch_graphs.end()) {
+          GraphEntry ge;
+          MRA_TRY(capture(b, c, st, &ge.g, &ge.x));
+          it = g_batch_graphs.emplace(std::make_pair(key, st), ge).first;
+        }
+        MRA_TRY(hipGraphLaunch(it->second.x, st));
+      }
+    }
+  }
+  return MRA_OK;
+}
+
+int32_t mra_solve_read(mra_solve h, double* omega_dense_out, double* diag_out, void* stream) {
+  if (!h) return MRA_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const SolveDev& s = h->host;
+  const size_t Nf = (size_t)s.N * s.N;
+  Batch b = one(h->dev);
+  LaunchCfg c = h->cfg;
+  MRA_TRY(launch_scatter(b, c, 0, 2, 0, st));
+  MRA_TRY(launch_prolong(b, c, 2, 1, st));
+  if (omega_dense_out)
+    MRA_TRY(hipMemcpyAsync(omega_dense_out, s.dense64, Nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+  int64_t na = 0;
+  int ctrl[C_NCTRL];
+  double scal[S_NSCAL];
+  if (diag_out) {
+    MRA_TRY(launch_poisson(b, c, 2, st));
+    MRA_TRY(launch_diag(b, c, st));
+    MRA_TRY(hipMemcpyAsync(h->diag_rows.data(), s.diag, (size_t)s.N * 5 * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+  }
+  MRA_TRY(hipMemcpyAsync(&na, s.n_active, sizeof(na), hipMemcpyDeviceToHost, st));
+  MRA_TRY(hipMemcpyAsync(ctrl, s.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, st));
+  MRA_TRY(hipMemcpyAsync(scal, s.scal, sizeof(scal), hipMemcpyDeviceToHost, st));
+  MRA_TRY(hipStreamSynchronize(st));
+  if (diag_out) {
+    double sw = 0, suv = 0, sw2 = 0, sg = 0, mx = 0;
+    for (int y = 0; y < s.N; ++y) {
+      const double* r = &h->diag_rows[(size_t)y * 5];
+      sw += r[0]; suv += r[1]; sw2 += r[2]; sg += r[3]; mx = std::max(mx, r[4]);
+    }
+    const double h2 = s.h * s.h;
+    diag_out[0] = scal[S_T];
+    diag_out[1] = 0.5 * h2 * suv;
+    diag_out[2] = 0.5 * h2 * sw2;
+    diag_out[3] = 0.5 * h2 * sg;
+    diag_out[4] = h2 * sw;
+    diag_out[5] = mx;
+    diag_out[6] = (double)na;
+    diag_out[7] = (double)ctrl[C_STATUS];
+  }
+  return ctrl[C_STATUS] == 0 ? MRA_OK : MRA_E_NONFINITE;
+}
+
+int32_t mra_solve_ptrs_get(mra_solve h, mra_solve_ptrs* out) {
+  if (!h || !out) return MRA_E_ARG;
+  const SolveDev& s = h->host;
+  out->omega_active = s.omega;
+  out->mask = s.mask;
+  out->index_packed = s.index_packed;
+  out->index_fine = s.index_fine;
+  out->n_active = s.n_active;
+  out->krylov_V = s.V;
+  out->hessenberg = s.H;
+  out->scalars = s.scal;
+  out->control = s.ctrl;
+  return MRA_OK;
+}
+
+int32_t mra_solve_destroy(mra_solve h) {
+  if (!h) return MRA_E_ARG;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    drop_batch_graphs();
+  }
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->graph_def) (void)hipGraphDestroy(h->graph_def);
+  delete h;
+  return MRA_OK;
+}
+
+int32_t mra_time_kernel(mra_solve* solves, int32_t n, int32_t which, int32_t reps, void* stream,
+                        float* avg_ms) {
+  if (!solves || n < 1 || n > kMaxBatch || !avg_ms || reps < 1) return MRA_E_ARG;
+  if (which < 0 || which > 6) return MRA_E_ARG;
+  Batch b;
+  std::memset(&b, 0, sizeof(b));
+  b.n = n;
+  for (int i = 0; i < n; ++i) {
+    if (!solves[i]) return MRA_E_ARG;
+    const LaunchCfg& c0 = solves[0]->cfg;
+    const LaunchCfg& ci = solves[i]->cfg;
+    if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m) return MRA_E_ARG;
+    b.s[i] = solves[i]->dev;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const LaunchCfg& c = solves[0]->cfg;
+  // the end of a step leaves the Arnoldi flag set; clear it so that the
+  // timed Jacobian-vector stencil does its work (the next step resets it)
+  MRA_TRY(launch_clear_done(b, st));
+  hipEvent_t e0, e1;
+  MRA_TRY(hipEventCreate(&e0));
+  MRA_TRY(hipEventCreate(&e1));
+  MRA_TRY(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i) {
+    hipError_t e = hipSuccess;
+    switch (which) {
+      case 0: e = launch_jvp(b, c, st); break;
+      case 1: e = launch_poisson_pass(b, c, 1, 0, st); break;
+      case 2: e = launch_poisson_pass(b, c, 1, 1, st); break;
+      case 3: e = launch_poisson_pass(b, c, 1, 2, st); break;
+      case 4: e = launch_prolong_level(b, c, 1, c.prec == 0, c.J, st); break;
+      case 5: e = launch_forward(b, c, 0, 0, st); break;
+      case 6: e = launch_rhs(b, c, st); break;
+      default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return MRA_E_DEVICE;
+  }
+  MRA_TRY(hipEventRecord(e1, st));
+  MRA_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  MRA_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return MRA_OK;
+}
+
+}  // extern "C"

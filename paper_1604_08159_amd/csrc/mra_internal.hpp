@@ -1,0 +1,232 @@
+// Internal declarations of the gfx950 wavelet-collocation library.
+//
+// Every kernel works on a batch of solves of equal (J, p, precision): the
+// solve index is blockIdx.y and its buffers are described by a SolveDev
+// record that lives in device memory (in the solve's arena, or in the
+// workspace of a stand-alone call).  Sizes that change on the device (the
+// active count) are read from device memory, so launch shapes depend only on
+// (J, p, m) and a captured step stays valid.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mra {
+
+constexpr int kMaxJ = 11;
+constexpr int kMaxM = 47;           // Krylov dimension cap (augmented size <= 48)
+constexpr int kMaxBatch = 64;       // solves per launch
+constexpr int kTile = 32;           // stencil tile edge (clamped to N)
+constexpr int kRedBlocks = 256;     // blocks of the Krylov reductions
+constexpr int kScanItems = 4;       // packed entries per thread in compaction
+constexpr int kScanBlock = 256;     // threads per compaction block
+constexpr int kCoarseLevels = 6;    // levels <= this are prolonged by one block
+constexpr int kTwN = 2048;          // twiddle table size (largest FFT length)
+
+// Control words (int) and scalars (double) of a solve.
+enum Ctrl : int { C_MEFF = 0, C_DONE = 1, C_STATUS = 2, C_CNT0 = 4, C_CNT1 = 5, C_CNT2 = 6,
+                  C_CNT3 = 7, C_NCTRL = 16 };
+enum Scal : int { S_BETA = 0, S_INV = 1, S_NRMAV = 2, S_UMAX = 3, S_T = 4, S_EVALS = 5, S_STEPS = 6,
+                  S_NSCAL = 16 };
+
+struct SolveDev {
+  // geometry / numbers
+  int J, j0, p, N;
+  int prec;                 // 0 -> double bulk fields, 1 -> float bulk fields
+  int m;                    // Krylov dimension
+  int adjacent_zone;
+  int smag_mode;
+  int tile, ntx;            // stencil tile edge and tiles per side
+  double h, length, eps, dt;
+  double nu0, cs, s0, mu;
+  // active set
+  uint8_t* mask;            // [Nf] packed
+  int32_t* index_packed;    // [Nf]
+  int32_t* index_fine;      // [Nf]
+  int32_t* rank;            // [Nf] dense: active position or -1
+  uint8_t* tile_flag;       // [ntiles]
+  int64_t* n_active;        // device scalar
+  int32_t* block_off;       // [nscan] compaction block counts -> offsets
+  unsigned long long* umax; // bits of max|u| (non-negative doubles order as integers)
+  // Krylov (FP64)
+  double* omega;            // [Nf] active values
+  double* V;                // [(m+1)][Nf]
+  double* w;                // [Nf]
+  double* H;                // [(m+1)][m]
+  double* hpart;            // [3][kMaxM+1] Gram-Schmidt coefficients of the current column
+  double* y;                // [kMaxM + 1]
+  double* partials;         // [kRedBlocks][kMaxM + 2]
+  double* scal;             // [S_NSCAL]
+  int* ctrl;                // [C_NCTRL]
+  // dense fields (element type by prec)
+  void* wt;                 // Pi(omega)
+  void* psi;
+  void* u;
+  void* v;
+  void* nu;
+  void* vt;                 // Pi(v)
+  void* psiv;
+  void* spec;               // complex half spectrum [(N/2+1)][N]
+  double* dense64;          // FP64 regrid field [Nf]
+  double* packed64;         // FP64 packed pyramid [Nf]
+  double* out_rhs;          // residual at the active nodes [Nf]
+  double* out_jvp;          // J v at the active nodes [Nf]
+  const double* vin;        // active vector scattered by src 2 of the scatter
+  double* diag;             // [N][4] per-row diagnostic partial sums
+};
+
+struct Batch {
+  const SolveDev* s[kMaxBatch];
+  int n;
+};
+
+// ------------------------------------------------------------------ helpers
+__host__ __device__ inline int ilog2(unsigned v) { return 31 - __builtin_clz(v); }
+__host__ __device__ inline int ntz(unsigned v) { return __builtin_ctz(v); }
+
+// packed index -> fine index y*N + x (also returns level).
+__device__ inline int packed_to_fine(int i, int J, int j0, int* level) {
+  int N = 1 << J;
+  int n0 = 1 << j0;
+  if (i < n0 * n0) {
+    int s0 = 1 << (J - j0);
+    if (level) *level = j0;
+    return (i >> j0) * s0 * N + (i & (n0 - 1)) * s0;
+  }
+  int l = (ilog2((unsigned)i) >> 1) + 1;
+  int lb = l - 1;
+  int n2 = 1 << (2 * lb);
+  int band = (i >> (2 * lb)) - 1;
+  int r = i - (band + 1) * n2;
+  int b = r >> lb, a = r & ((1 << lb) - 1);
+  int s = 1 << (J - l);
+  int x = (2 * a + (band != 1 ? 1 : 0)) * s;
+  int y = (2 * b + (band != 0 ? 1 : 0)) * s;
+  if (level) *level = l;
+  return y * N + x;
+}
+
+// fine (x, y) -> level.
+__device__ inline int level_of(int x, int y, int J, int j0) {
+  unsigned t = (unsigned)(x | y);
+  int tz = t == 0 ? J : ntz(t);
+  int l = J - tz;
+  return l < j0 ? j0 : l;
+}
+
+// fine (x, y) of level l > j0 -> packed index.
+__device__ inline int fine_to_packed(int x, int y, int l, int J, int j0) {
+  if (l <= j0) {
+    int s0 = 1 << (J - j0);
+    return (y / s0) * (1 << j0) + x / s0;
+  }
+  int s = J - l;
+  int xs = x >> s, ys = y >> s;
+  int band = (xs & 1) ? ((ys & 1) ? 2 : 0) : 1;
+  int lb = l - 1;
+  return ((band + 1) << (2 * lb)) + ((ys >> 1) << lb) + (xs >> 1);
+}
+
+// Order-2p DD midpoint prediction from c[0..2P-1] = coarse values at offsets
+// -P+1 .. P; one rounding per operation, pairs nearest first.
+template <int P, typename T>
+__device__ inline T dd_pred(const T* c) {
+#pragma clang fp contract(off)
+  if constexpr (P == 2) {
+    T s = T(0.5625) * (c[1] + c[2]);
+    s = s + T(-0.0625) * (c[0] + c[3]);
+    return s;
+  } else {
+    T s = T(0.5859375) * (c[2] + c[3]);
+    s = s + T(-0.09765625) * (c[1] + c[4]);
+    s = s + T(0.01171875) * (c[0] + c[5]);
+    return s;
+  }
+}
+
+// Prediction of a non-coarse node (x, y) of level l from the level-(l-1)
+// values of the dense field f (coarse stride S = 2^(J-l+1)).
+template <int P, typename T>
+__device__ inline T predict_node(const T* __restrict__ f, int x, int y, int l, int J) {
+  const int N = 1 << J;
+  const int s = 1 << (J - l);
+  const int S = 2 * s;
+  const int nm = N - 1;
+  const bool ox = (x & s) != 0, oy = (y & s) != 0;
+  T c[2 * P];
+  if (ox && !oy) {
+    const int row = y * N;
+    const int x0 = x - s - (P - 1) * S;
+#pragma unroll
+    for (int o = 0; o < 2 * P; ++o) c[o] = f[row + ((x0 + o * S) & nm)];
+    return dd_pred<P, T>(c);
+  } else if (oy && !ox) {
+    const int y0 = y - s - (P - 1) * S;
+#pragma unroll
+    for (int o = 0; o < 2 * P; ++o) c[o] = f[((y0 + o * S) & nm) * N + x];
+    return dd_pred<P, T>(c);
+  } else {
+    T py[2 * P];
+    const int x0 = x - s - (P - 1) * S;
+    const int y0 = y - s - (P - 1) * S;
+#pragma unroll
+    for (int ox2 = 0; ox2 < 2 * P; ++ox2) {
+      const int xx = (x0 + ox2 * S) & nm;
+#pragma unroll
+      for (int o = 0; o < 2 * P; ++o) c[o] = f[((y0 + o * S) & nm) * N + xx];
+      py[ox2] = dd_pred<P, T>(c);
+    }
+    return dd_pred<P, T>(py);
+  }
+}
+
+// Stencil tile edge: 32, or 16 where a 32-tile would need more than 64 KB of
+// LDS (FP64 with the 6-point rule); never more than N.
+__host__ __device__ inline int tile_edge(int J, int p, int prec) {
+  const int t = (prec == 0 && p == 3) ? 16 : kTile;
+  const int N = 1 << J;
+  return N < t ? N : t;
+}
+
+// ------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.  `nb` solves in `b`.
+struct LaunchCfg {
+  int J, p, prec, m;
+};
+
+hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);
+
+// transforms
+hipError_t launch_scatter(const Batch& b, const LaunchCfg& c, int src /*0 omega,1 w*scale->V[j]*/,
+                          int target /*0 wt,1 vt,2 dense64*/, int j, hipStream_t st);
+hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as_double, hipStream_t st);
+hipError_t launch_prolong_level(const Batch& b, const LaunchCfg& c, int target, int as_double, int level,
+                                hipStream_t st);
+hipError_t launch_forward(const Batch& b, const LaunchCfg& c, int src /*0 dense64 (fp64), 1 wt*/,
+                          int dst /*0 packed64, 1 spec-as-packed (T)*/, hipStream_t st);
+hipError_t launch_inverse(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_threshold(const Batch& b, const LaunchCfg& c, int packed_is_double, hipStream_t st);
+hipError_t launch_gather(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_rank_from_index(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_reset_max(const Batch& b, hipStream_t st);
+
+// Poisson
+hipError_t fft_init_tables(hipStream_t st);
+hipError_t launch_poisson(const Batch& b, const LaunchCfg& c, int src /*0 wt->psi, 1 vt->psiv, 2 dense64->psi(fp64)*/,
+                          hipStream_t st);
+hipError_t launch_poisson_pass(const Batch& b, const LaunchCfg& c, int src, int pass, hipStream_t st);
+
+// stencils
+hipError_t launch_rhs(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_diag(const Batch& b, const LaunchCfg& c, hipStream_t st);
+
+// Krylov
+hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st);
+hipError_t launch_phi1(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_update(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_reset_ctrl(const Batch& b, hipStream_t st);
+hipError_t launch_clear_done(const Batch& b, hipStream_t st);
+
+}  // namespace mra
