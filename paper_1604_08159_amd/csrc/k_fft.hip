@@ -8,10 +8,8 @@
 // Three passes over HBM, each a batch of 1-D FFTs staged in LDS:
 //   A  rows: real-to-complex FFT of length N (complex FFT of length N/2 on
 //      the packed even/odd samples), written transposed as spec[kx][y];
-//   B  columns (contiguous rows of spec): forward FFT (decimation in
-//      frequency, natural -> bit-reversed), multiply by -1/lambda / N^2 in
-//      bit-reversed order, inverse FFT (decimation in time,
-//      bit-reversed -> natural);
+//   B  columns (contiguous rows of spec): forward FFT, multiply by
+//      -1/lambda / N^2, inverse FFT;
 //   C  rows: complex-to-real inverse, read transposed.
 // Twiddles come from one table of exp(-2 pi i k / 2048) set up once.
 #include "mra_internal.hpp"
@@ -53,50 +51,105 @@ template <typename V> __device__ inline V cmulc(V a, V b) {   // a * conj(b)
 }
 template <typename V> __device__ inline V cconj(V a) { return V{a.x, -a.y}; }
 
-__device__ inline int brev(int k, int bits) { return (int)(__brev((unsigned)k) >> (32 - bits)); }
+// ------------------------------------------------------------ FFT core
+// Stockham autosort FFT (natural order in and out) of nfft vectors of length
+// L = 2^lg held in LDS at stride L, by a block of 256 threads.  Passes of
+// radix 8 (the last one of radix 2, 4 or 8 to complete L): every thread keeps
+// 8 complex values in registers per pass, so a pass is one LDS read phase,
+// one barrier, the small DFTs and twiddles in registers, one LDS write phase.
+// The block handles nfft * L <= 2048 points.  S = -1 forward, +1 inverse
+// (unnormalised).
+constexpr int kFftThreads = 256;
+constexpr int kFftPoints = 2048;
 
-// nvec vectors of length M = 2^lm in LDS (stride M).
-// forward, decimation in frequency: natural in, bit-reversed out.
-template <typename T>
-__device__ void fft_dif(typename C2<T>::t* buf, int nvec, int lm) {
+template <int S, typename V> __device__ inline V mul_i(V a) {   // (S i) * a
+  return S < 0 ? V{a.y, -a.x} : V{-a.y, a.x};
+}
+
+template <int R, int S, typename T>
+__device__ inline void small_dft(typename C2<T>::t* v) {
   using V = typename C2<T>::t;
-  const int M = 1 << lm, half = M >> 1;
-  const int nb = nvec * half;
-  for (int lh = lm - 1; lh >= 0; --lh) {
-    const int hs = 1 << lh;
-    const int tws = kTwN >> (lh + 1);
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-      const int v = q >> (lm - 1), r = q & (half - 1);
-      const int pos = r & (hs - 1);
-      const int i0 = v * M + ((r >> lh) << (lh + 1)) + pos;
-      const V a = buf[i0], b = buf[i0 + hs];
-      buf[i0] = cadd(a, b);
-      buf[i0 + hs] = cmul(csub(a, b), C2<T>::tw(pos * tws));
-    }
-    __syncthreads();
+  if constexpr (R == 2) {
+    const V a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    const V t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const V t2 = cadd(v[1], v[3]), t3 = mul_i<S>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  } else {
+    V e[4] = {v[0], v[2], v[4], v[6]};
+    V o[4] = {v[1], v[3], v[5], v[7]};
+    small_dft<4, S, T>(e);
+    small_dft<4, S, T>(o);
+    const T c = T(0.70710678118654752440);
+    const V w1 = V{c * (o[1].x - S * o[1].y), c * (o[1].y + S * o[1].x)};   // e^{S i pi/4} o1
+    const V w2 = mul_i<S>(o[2]);
+    const V w3 = V{c * (-o[3].x - S * o[3].y), c * (-o[3].y + S * o[3].x)}; // e^{S 3i pi/4} o3
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], w1);
+    v[5] = csub(e[1], w1);
+    v[2] = cadd(e[2], w2);
+    v[6] = csub(e[2], w2);
+    v[3] = cadd(e[3], w3);
+    v[7] = csub(e[3], w3);
   }
 }
 
-// inverse (conjugate twiddles), decimation in time: bit-reversed in, natural
-// out, unnormalised.
-template <typename T>
-__device__ void ifft_dit(typename C2<T>::t* buf, int nvec, int lm) {
+template <int R, int S, typename T>
+__device__ inline void stockham_pass(typename C2<T>::t* buf, int L, int nfft, int Ns) {
   using V = typename C2<T>::t;
-  const int M = 1 << lm, half = M >> 1;
-  const int nb = nvec * half;
-  for (int lh = 0; lh < lm; ++lh) {
-    const int hs = 1 << lh;
-    const int tws = kTwN >> (lh + 1);
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-      const int v = q >> (lm - 1), r = q & (half - 1);
-      const int pos = r & (hs - 1);
-      const int i0 = v * M + ((r >> lh) << (lh + 1)) + pos;
-      const V a = buf[i0];
-      const V b = cmulc(buf[i0 + hs], C2<T>::tw(pos * tws));
-      buf[i0] = cadd(a, b);
-      buf[i0 + hs] = csub(a, b);
+  constexpr int IPT = 8 / R;               // work items per thread
+  const int per = L / R;
+  const int total = nfft * per;
+  const int twstep = kTwN / (Ns * R);
+  V v[IPT][R];
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const int q = threadIdx.x + it * kFftThreads;
+    if (q < total) {
+      const int f = q / per, j = q - f * per;
+      const int k = j & (Ns - 1);
+      const V* src = buf + f * L + j;
+      v[it][0] = src[0];
+      // twiddles w^r, w = exp(-2 pi i k / (Ns R)): one table load, then powers
+      const V w1 = C2<T>::tw(k * twstep);
+      V wr = w1;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const V x = src[r * per];
+        v[it][r] = S < 0 ? cmul(x, wr) : cmulc(x, wr);
+        wr = cmul(wr, w1);
+      }
     }
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const int q = threadIdx.x + it * kFftThreads;
+    if (q < total) {
+      const int f = q / per, j = q - f * per;
+      const int k = j & (Ns - 1);
+      small_dft<R, S, T>(v[it]);
+      V* dst = buf + f * L + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int S, typename T>
+__device__ void fft_block(typename C2<T>::t* buf, int L, int nfft) {
+  for (int Ns = 1; Ns < L;) {
+    const int rem = L / Ns;
+    if (rem >= 8) { stockham_pass<8, S, T>(buf, L, nfft, Ns); Ns *= 8; }
+    else if (rem == 4) { stockham_pass<4, S, T>(buf, L, nfft, Ns); Ns *= 4; }
+    else { stockham_pass<2, S, T>(buf, L, nfft, Ns); Ns *= 2; }
   }
 }
 
@@ -111,29 +164,26 @@ __device__ inline T* poisson_dst(const SolveDev& s, int src) {
   return reinterpret_cast<T*>(src == 1 ? s.psiv : s.psi);
 }
 
-// pass A: rows -> spec[kx][y], R rows per block
+// pass A: rows -> spec[kx][y], R rows per block (R * N/2 <= 2048)
 template <typename T>
-__global__ void __launch_bounds__(256) k_fft_rows_fwd(Batch b, int src, int R) {
+__global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src, int R) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
-  const SolveDev& s = *b.s[blockIdx.y];
-  const int J = s.J, N = s.N, M = N >> 1, lm = J - 1;
-  const int y0 = blockIdx.x * R;
+  const SolveDev& s = MRA_SOLVE(b);
+  const int N = s.N, M = N >> 1;
+  const int y0 = MRA_BX(b) * R;
   const V* in = reinterpret_cast<const V*>(poisson_src<T>(s, src));
-  for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
-    const int r = q / M, n = q - r * M;
-    buf[q] = in[(size_t)(y0 + r) * M + n];
-  }
+  for (int q = threadIdx.x; q < R * M; q += blockDim.x) buf[q] = in[(size_t)y0 * M + q];
   __syncthreads();
-  fft_dif<T>(buf, R, lm);
+  fft_block<-1, T>(buf, M, R);
   V* spec = reinterpret_cast<V*>(s.spec);
   const int twN = kTwN / N;
   for (int q = threadIdx.x; q < (M + 1) * R; q += blockDim.x) {
     const int k = q / R, r = q - k * R;
     const V* row = buf + r * M;
-    const V zk = row[brev(k & (M - 1), lm)];
-    const V zc = cconj(row[brev((M - k) & (M - 1), lm)]);
+    const V zk = row[k & (M - 1)];
+    const V zc = cconj(row[(M - k) & (M - 1)]);
     const V e = cmul(csub(zk, zc), C2<T>::tw(k * twN));
     V x;
     x.x = T(0.5) * (zk.x + zc.x + e.y);
@@ -156,43 +206,45 @@ __device__ inline double d2_sigma(int k, int N) {
   }
 }
 
-// pass B: C spectrum rows (fixed kx) per block
+// pass B: C spectrum rows (fixed kx) per block (C * N <= 2048)
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_fft_cols(Batch b, int C) {
+__global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b, int C) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const int J = s.J, N = s.N, M = N >> 1;
-  const int k0 = blockIdx.x * C;
+  const int k0 = MRA_BX(b) * C;
   const int nr = (M + 1 - k0) < C ? (M + 1 - k0) : C;
   V* spec = reinterpret_cast<V*>(s.spec);
+  double* sig = reinterpret_cast<double*>(buf + C * N);    // sigma_2 of every ky
   for (int q = threadIdx.x; q < nr * N; q += blockDim.x) buf[q] = spec[(size_t)k0 * N + q];
+  for (int k = threadIdx.x; k < N; k += blockDim.x) sig[k] = d2_sigma<P>(k, N);
   __syncthreads();
-  fft_dif<T>(buf, nr, J);
+  fft_block<-1, T>(buf, N, nr);
   const double h2n = s.h * s.h / ((double)N * (double)N);
   for (int q = threadIdx.x; q < nr * N; q += blockDim.x) {
-    const int r = q >> J, j = q & (N - 1);
-    const int kx = k0 + r, ky = brev(j, J);
-    const double den = d2_sigma<P>(kx, N) + d2_sigma<P>(ky, N);
+    const int r = q >> J, ky = q & (N - 1);
+    const int kx = k0 + r;
+    const double den = sig[kx] + sig[ky];
     const T g = (kx == 0 && ky == 0) ? T(0) : (T)(-h2n / den);
     buf[q].x *= g;
     buf[q].y *= g;
   }
   __syncthreads();
-  ifft_dit<T>(buf, nr, J);
+  fft_block<1, T>(buf, N, nr);
   for (int q = threadIdx.x; q < nr * N; q += blockDim.x) spec[(size_t)k0 * N + q] = buf[q];
 }
 
-// pass C: spec[kx][y] -> real rows
+// pass C: spec[kx][y] -> real rows, R rows per block (R * N/2 <= 2048)
 template <typename T>
-__global__ void __launch_bounds__(256) k_fft_rows_inv(Batch b, int src, int R) {
+__global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src, int R) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
-  const SolveDev& s = *b.s[blockIdx.y];
-  const int J = s.J, N = s.N, M = N >> 1, lm = J - 1;
-  const int y0 = blockIdx.x * R;
+  const SolveDev& s = MRA_SOLVE(b);
+  const int N = s.N, M = N >> 1;
+  const int y0 = MRA_BX(b) * R;
   const V* spec = reinterpret_cast<const V*>(s.spec);
   const int twN = kTwN / N;
   for (int q = threadIdx.x; q < M * R; q += blockDim.x) {
@@ -203,51 +255,41 @@ __global__ void __launch_bounds__(256) k_fft_rows_inv(Batch b, int src, int R) {
     V z;
     z.x = xk.x + xc.x - e.y;
     z.y = xk.y + xc.y + e.x;
-    buf[r * M + brev(k, lm)] = z;
+    buf[r * M + k] = z;
   }
   __syncthreads();
-  ifft_dit<T>(buf, R, lm);
+  fft_block<1, T>(buf, M, R);
   V* out = reinterpret_cast<V*>(poisson_dst<T>(s, src));
-  for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
-    const int r = q / M, n = q - r * M;
-    out[(size_t)(y0 + r) * M + n] = buf[q];
-  }
+  for (int q = threadIdx.x; q < R * M; q += blockDim.x) out[(size_t)y0 * M + q] = buf[q];
 }
 
-static int rows_per_block(int N, size_t elem) {
-  const size_t budget = 64 * 1024;
-  size_t per = (size_t)(N / 2) * elem;
-  int r = (int)(budget / per);
-  if (r > 32) r = 32;
-  if (r > N) r = N;
-  if (r < 1) r = 1;
-  int p2 = 1;
-  while (p2 * 2 <= r) p2 *= 2;
-  return p2;
+static int rows_per_block(int N) {
+  int r = kFftPoints / (N / 2);
+  return r < N ? r : N;
 }
-static int cols_per_block(int N, size_t elem) {
-  const size_t budget = 64 * 1024;
-  int c = (int)(budget / ((size_t)N * elem));
-  if (c > 16) c = 16;
-  if (c < 1) c = 1;
-  return c;
+static int cols_per_block(int N) {
+  int c = kFftPoints / N;
+  return c < N / 2 + 1 ? c : N / 2 + 1;
 }
 
 template <typename T>
 static hipError_t poisson_t(const Batch& b, const LaunchCfg& c, int src, int pass, hipStream_t st) {
   using V = typename C2<T>::t;
   const int N = 1 << c.J, M = N / 2;
-  const int R = rows_per_block(N, sizeof(V));
-  const int C = cols_per_block(N, sizeof(V));
+  const int R = rows_per_block(N);
+  const int C = cols_per_block(N);
   if (pass < 0 || pass == 0)
-    hipLaunchKernelGGL(k_fft_rows_fwd<T>, dim3(N / R, b.n), dim3(256), (size_t)R * M * sizeof(V), st, b, src, R);
+    hipLaunchKernelGGL(k_fft_rows_fwd<T>, dim3((N / R) * b.n), dim3(kFftThreads), (size_t)R * M * sizeof(V), st, b,
+                       src, R);
   if (pass < 0 || pass == 1) {
-    dim3 g((M + 1 + C - 1) / C, b.n);
-    if (c.p == 2) hipLaunchKernelGGL((k_fft_cols<2, T>), g, dim3(256), (size_t)C * N * sizeof(V), st, b, C);
-    else hipLaunchKernelGGL((k_fft_cols<3, T>), g, dim3(256), (size_t)C * N * sizeof(V), st, b, C);
+    dim3 g(((M + 1 + C - 1) / C) * b.n);
+    const size_t lds = (size_t)C * N * sizeof(V) + (size_t)N * sizeof(double);
+    if (c.p == 2) hipLaunchKernelGGL((k_fft_cols<2, T>), g, dim3(kFftThreads), lds, st, b, C);
+    else hipLaunchKernelGGL((k_fft_cols<3, T>), g, dim3(kFftThreads), lds, st, b, C);
   }
   if (pass < 0 || pass == 2)
-    hipLaunchKernelGGL(k_fft_rows_inv<T>, dim3(N / R, b.n), dim3(256), (size_t)R * M * sizeof(V), st, b, src, R);
+    hipLaunchKernelGGL(k_fft_rows_inv<T>, dim3((N / R) * b.n), dim3(kFftThreads), (size_t)R * M * sizeof(V), st, b,
+                       src, R);
   return hipGetLastError();
 }
 

@@ -7,201 +7,140 @@
 // subspace (abstract; Section 2.1); the exponential Euler step with the
 // Jacobian at frozen eddy viscosity is the reading implemented here.
 //
-// Reductions over the active nodes are deterministic: the active list is cut
-// into the same fixed chunks in every kernel of a step (the chunk count
-// depends only on N_a), every block reduces its chunk in a fixed order, and
-// the last block to finish (device-scope counter) adds the block partials in
-// block order.
+// Reductions over the active nodes are deterministic and need no cross-block
+// signalling: the active list is cut into the same fixed chunks in every
+// kernel of a step (the chunk count depends only on N_a), one wavefront per
+// basis vector reduces a chunk in a fixed order into a per-chunk partial, and
+// every block of the NEXT kernel adds the partials in the same fixed order
+// (the kernel boundary orders the writes before the reads).
 #include "mra_internal.hpp"
 
 namespace mra {
 
-constexpr double kBreakdown = 1e-13;
-constexpr int kChunkMin = 2048;
-
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-struct Chunk {
-  int nb, lo, hi;
-};
-__device__ inline Chunk chunk_of(int na) {
-  int nb = (na + kChunkMin - 1) / kChunkMin;
-  if (nb < 1) nb = 1;
-  if (nb > kRedBlocks) nb = kRedBlocks;
-  const int per = (na + nb - 1) / nb;
-  Chunk c;
-  c.nb = nb;
-  c.lo = blockIdx.x * per;
-  c.hi = c.lo + per < na ? c.lo + per : na;
-  return c;
-}
-
-// Per block: partial sums of cnt values written to partials[blk][0..cnt).
-// Returns true in exactly one block (the last to finish), after a device
-// fence, with every block's partials visible.
-__device__ bool publish_partials(const SolveDev& s, int nb, int cnt, double* red /*[4][kMaxM+2]*/,
-                                 int counter) {
-  __syncthreads();
-  const int stride = kMaxM + 2;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    double t = red[i] + red[stride + i];
-    t += red[2 * stride + i];
-    t += red[3 * stride + i];
-    s.partials[blockIdx.x * stride + i] = t;
-  }
-  __threadfence();
-  __syncthreads();
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    const int prev = atomicAdd(&s.ctrl[counter], 1);
-    last = prev == nb - 1;
-    if (last) s.ctrl[counter] = 0;
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
-// In the last block: totals[i] = sum over blocks (in block order) of the
-// partials, i < cnt.  One wave per value, lanes stride the blocks.
-__device__ void reduce_partials(const SolveDev& s, int nb, int cnt, double* totals) {
-  const int stride = kMaxM + 2;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = wid; i < cnt; i += nw) {
-    double t = 0.0;
-    for (int b = lane; b < nb; b += 64) t += __hip_atomic_load(&s.partials[b * stride + i], __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT);
-    t = wave_sum(t);
-    if (lane == 0) totals[i] = t;
-  }
-  __syncthreads();
-}
-
-// ||w||^2 over a chunk, stored in red[wave][slot]
-__device__ inline void chunk_dot(const double* a, const double* b, int lo, int hi, double* red, int slot) {
-  double t = 0.0;
-  for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) t += a[k] * b[k];
-  t = wave_sum(t);
-  if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * (kMaxM + 2) + slot] = t;
-}
-
-// beta = ||F||; v_1 scaling, flags.
-__global__ void __launch_bounds__(256) k_norm0(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
-  const int na = (int)*s.n_active;
-  const Chunk c = chunk_of(na);
-  if ((int)blockIdx.x >= c.nb) return;
-  __shared__ double red[4 * (kMaxM + 2)];
-  __shared__ double tot[kMaxM + 2];
-  chunk_dot(s.w, s.w, c.lo, c.hi, red, 0);
-  if (!publish_partials(s, c.nb, 1, red, C_CNT0)) return;
-  reduce_partials(s, c.nb, 1, tot);
-  if (threadIdx.x == 0) {
-    const double beta = sqrt(tot[0]);
-    s.scal[S_BETA] = beta;
-    const bool ok = isfinite(beta);
-    if (!ok) s.ctrl[C_STATUS] = 5;
-    const bool zero = !(beta > 0.0) || !ok;
-    s.ctrl[C_DONE] = zero ? 1 : 0;
-    s.ctrl[C_MEFF] = zero ? 0 : s.m;
-    s.scal[S_INV] = zero ? 0.0 : 1.0 / beta;
-  }
-}
-
-// Stage 1: h1 = V_j^T w, ||w||^2 (= ||A v_j||^2).
-__global__ void __launch_bounds__(256) k_gs_dot(Batch b, int j) {
-  const SolveDev& s = *b.s[blockIdx.y];
-  if (s.ctrl[C_DONE]) return;
-  const int na = (int)*s.n_active;
-  const Chunk c = chunk_of(na);
-  if ((int)blockIdx.x >= c.nb) return;
+// Chunk parts of V_i . w for i <= j and, if with_norm, of w . w (slot j+1):
+// each wavefront reduces its own elements and writes buf[(ch*4+wave)][.].
+// Four basis vectors per pass keep many independent loads in flight.
+__device__ inline void chunk_dots(const SolveDev& s, int j, int lo, int hi, bool with_norm, double* buf,
+                                  int ch) {
   const size_t Nf = (size_t)s.N * s.N;
-  __shared__ double red[4 * (kMaxM + 2)];
-  __shared__ double tot[kMaxM + 2];
-  for (int i = 0; i <= j; ++i) chunk_dot(s.V + i * Nf, s.w, c.lo, c.hi, red, i);
-  chunk_dot(s.w, s.w, c.lo, c.hi, red, j + 1);
-  if (!publish_partials(s, c.nb, j + 2, red, C_CNT1)) return;
-  reduce_partials(s, c.nb, j + 2, tot);
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) s.hpart[i] = tot[i];
-  if (threadIdx.x == 0) s.scal[S_NRMAV] = sqrt(tot[j + 1]);
-}
-
-// Stage 2: w -= V_j h1; h2 = V_j^T w.
-__global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
-  const SolveDev& s = *b.s[blockIdx.y];
-  if (s.ctrl[C_DONE]) return;
-  const int na = (int)*s.n_active;
-  const Chunk c = chunk_of(na);
-  if ((int)blockIdx.x >= c.nb) return;
-  const size_t Nf = (size_t)s.N * s.N;
-  __shared__ double red[4 * (kMaxM + 2)];
-  __shared__ double tot[kMaxM + 2];
-  __shared__ double h[kMaxM + 1];
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) h[i] = s.hpart[i];
-  __syncthreads();
-  for (int k = c.lo + threadIdx.x; k < c.hi; k += blockDim.x) {
-    double t = s.w[k];
-    for (int i = 0; i <= j; ++i) t -= h[i] * s.V[i * Nf + k];
-    s.w[k] = t;
-  }
-  __syncthreads();
-  for (int i = 0; i <= j; ++i) chunk_dot(s.V + i * Nf, s.w, c.lo, c.hi, red, i);
-  if (!publish_partials(s, c.nb, j + 1, red, C_CNT2)) return;
-  reduce_partials(s, c.nb, j + 1, tot);
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) s.hpart[(kMaxM + 1) + i] = tot[i];
-}
-
-// Stage 3: w -= V_j h2; H[:, j] = h1 + h2, H[j+1, j] = ||w||; breakdown test.
-__global__ void __launch_bounds__(256) k_gs_axpy_norm(Batch b, int j) {
-  const SolveDev& s = *b.s[blockIdx.y];
-  if (s.ctrl[C_DONE]) return;
-  const int na = (int)*s.n_active;
-  const Chunk c = chunk_of(na);
-  if ((int)blockIdx.x >= c.nb) return;
-  const size_t Nf = (size_t)s.N * s.N;
-  __shared__ double red[4 * (kMaxM + 2)];
-  __shared__ double tot[kMaxM + 2];
-  __shared__ double h[kMaxM + 1];
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) h[i] = s.hpart[(kMaxM + 1) + i];
-  __syncthreads();
-  for (int k = c.lo + threadIdx.x; k < c.hi; k += blockDim.x) {
-    double t = s.w[k];
-    for (int i = 0; i <= j; ++i) t -= h[i] * s.V[i * Nf + k];
-    s.w[k] = t;
-  }
-  __syncthreads();
-  chunk_dot(s.w, s.w, c.lo, c.hi, red, 0);
-  if (!publish_partials(s, c.nb, 1, red, C_CNT3)) return;
-  reduce_partials(s, c.nb, 1, tot);
-  const int m = s.m;
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) s.H[i * m + j] = s.hpart[i] + h[i];
-  if (threadIdx.x == 0) {
-    const double hn = sqrt(tot[0]);
-    s.H[(j + 1) * m + j] = hn;
-    const double nav = s.scal[S_NRMAV];
-    if (!isfinite(hn) || !isfinite(nav)) {
-      s.ctrl[C_STATUS] = 5;
-      s.ctrl[C_DONE] = 1;
-      s.ctrl[C_MEFF] = 0;
-    } else if (hn <= kBreakdown * nav || j + 1 == m) {
-      s.ctrl[C_DONE] = 1;
-      s.ctrl[C_MEFF] = j + 1;
-    } else {
-      s.scal[S_INV] = 1.0 / hn;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double* out = buf + (size_t)(ch * kWavesPerBlock + wid) * (kMaxM + 2);
+  const double* w = s.w;
+  const int top = with_norm ? j + 1 : j;
+  for (int i0 = 0; i0 <= top; i0 += 4) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u;
+      a[u] = i <= j ? s.V + i * Nf : w;
+    }
+    for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) {
+      const double wk = w[k];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u <= top) t[u] += a[u][k] * wk;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u > top) break;
+      const double r = wave_sum(t[u]);
+      if (lane == 0) out[i0 + u] = r;
     }
   }
 }
 
+// w -= V_j h over the chunk
+__device__ inline void chunk_axpy(const SolveDev& s, int j, int lo, int hi, const double* h) {
+  const size_t Nf = (size_t)s.N * s.N;
+  for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+    double t = s.w[k];
+    for (int i = 0; i <= j; ++i) t -= h[i] * s.V[i * Nf + k];
+    s.w[k] = t;
+  }
+  __syncthreads();
+}
+
+// ||F||^2 partials (buffer B).
+__global__ void __launch_bounds__(256) k_norm0(Batch b) {
+  const SolveDev& s = MRA_SOLVE(b);
+  const int na = (int)*s.n_active;
+  const int nb = nchunks(na);
+  for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
+    const Chunk c = chunk_of(na, ch);
+    chunk_dots(s, -1, c.lo, c.hi, true, part_buf(s, 1), ch);
+  }
+}
+
+// Stage 1: h1 = V_j^T w, ||w||^2 (= ||A v_j||^2) partials (buffer A).
+__global__ void __launch_bounds__(256) k_gs_dot(Batch b, int j) {
+  const SolveDev& s = MRA_SOLVE(b);
+  if (s.ctrl[C_DONE]) return;
+  const int na = (int)*s.n_active;
+  const int nb = nchunks(na);
+  for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
+    const Chunk c = chunk_of(na, ch);
+    chunk_dots(s, j, c.lo, c.hi, true, part_buf(s, 0), ch);
+  }
+}
+
+// Stage 2: h1 from A; w -= V_j h1; h2 = V_j^T w partials (buffer B).
+__global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
+  const SolveDev& s = MRA_SOLVE(b);
+  if (s.ctrl[C_DONE]) return;
+  const int na = (int)*s.n_active;
+  const int nb = nchunks(na);
+  if ((int)MRA_BX(b) >= nb) return;
+  __shared__ double h[kMaxM + 2];
+  reduce_partials(part_buf(s, 0), nb, j + 2, h);
+  if (MRA_BX(b) == 0) {
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) s.hpart[i] = h[i];
+    if (threadIdx.x == 0) s.scal[S_NRMAV] = sqrt(h[j + 1]);
+  }
+  for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
+    const Chunk c = chunk_of(na, ch);
+    chunk_axpy(s, j, c.lo, c.hi, h);
+    chunk_dots(s, j, c.lo, c.hi, false, part_buf(s, 1), ch);
+  }
+}
+
+// Stage 3: h2 from B; w -= V_j h2; H[:j+1, j] = h1 + h2; ||w||^2 partials
+// (buffer A), consumed by the next scaling (next_scale) or by phi_1.
+__global__ void __launch_bounds__(256) k_gs_axpy_norm(Batch b, int j) {
+  const SolveDev& s = MRA_SOLVE(b);
+  if (s.ctrl[C_DONE]) return;
+  const int na = (int)*s.n_active;
+  const int nb = nchunks(na);
+  if ((int)MRA_BX(b) >= nb) return;
+  __shared__ double h[kMaxM + 2];
+  reduce_partials(part_buf(s, 1), nb, j + 1, h);
+  if (MRA_BX(b) == 0)
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) s.H[i * s.m + j] = s.hpart[i] + h[i];
+  for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
+    const Chunk c = chunk_of(na, ch);
+    chunk_axpy(s, j, c.lo, c.hi, h);
+    double t = 0.0;
+    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) t += s.w[k] * s.w[k];
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) part_buf(s, 0)[(size_t)(ch * kWavesPerBlock + (threadIdx.x >> 6)) * (kMaxM + 2)] = t;
+  }
+}
+
+// Grid of the reductions: enough blocks for the largest possible active set
+// of the grid, at most 256 per solve (blocks loop over chunks).
+static int red_grid(int J) {
+  const int nf = 1 << (2 * J);
+  int g = (nf + kChunkMin - 1) / kChunkMin;
+  return g < 256 ? g : 256;
+}
+
 hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_norm0, dim3(kRedBlocks, b.n), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_norm0, dim3((red_grid(c.J)) * b.n), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
 hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st) {
-  dim3 g(kRedBlocks, b.n);
+  dim3 g((red_grid(c.J)) * b.n);
   hipLaunchKernelGGL(k_gs_dot, g, dim3(256), 0, st, b, j);
   hipLaunchKernelGGL(k_gs_axpy_dot, g, dim3(256), 0, st, b, j);
   hipLaunchKernelGGL(k_gs_axpy_norm, g, dim3(256), 0, st, b, j);
@@ -225,7 +164,17 @@ __device__ void mat_mul(const double* A, const double* B, double* C, int K) {
 }
 
 __global__ void __launch_bounds__(256) k_phi1(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
+  // the last column's norm (partials of stage 3): only its finiteness matters
+  if (!s.ctrl[C_DONE]) {
+    __shared__ double tot[2];
+    reduce_partials(part_buf(s, 0), nchunks((int)*s.n_active), 1, tot);
+    if (threadIdx.x == 0 && !isfinite(tot[0])) {
+      s.ctrl[C_STATUS] = 5;
+      s.ctrl[C_MEFF] = 0;
+    }
+    __syncthreads();
+  }
   const int k = s.ctrl[C_MEFF];
   if (k <= 0) return;
   const int K = k + 1, m = s.m;
@@ -283,16 +232,16 @@ __global__ void __launch_bounds__(256) k_phi1(Batch b) {
 }
 
 hipError_t launch_phi1(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_phi1, dim3(1, b.n), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_phi1, dim3((1) * b.n), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
 // omega_M += dt beta V_k y; the time advances.
 __global__ void __launch_bounds__(256) k_update(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const int k = s.ctrl[C_MEFF];
   const int na = (int)*s.n_active;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (MRA_BX(b) == 0 && threadIdx.x == 0) {
     s.scal[S_T] += s.dt;
     s.scal[S_STEPS] += 1.0;
     // active-point residual evaluations of this step: F and k products J v
@@ -305,7 +254,7 @@ __global__ void __launch_bounds__(256) k_update(Batch b) {
   for (int i = threadIdx.x; i < k; i += blockDim.x) yy[i] = f * s.y[i];
   __syncthreads();
   bool bad = false;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < na; q += gridDim.x * blockDim.x) {
+  for (int q = MRA_BX(b) * blockDim.x + threadIdx.x; q < na; q += MRA_GX(b) * blockDim.x) {
     double t = 0.0;
     for (int i = 0; i < k; ++i) t += yy[i] * s.V[i * Nf + q];
     const double nv = s.omega[q] + t;
@@ -319,27 +268,27 @@ hipError_t launch_update(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   const int nf = 1 << (2 * c.J);
   int nb = (nf + 255) / 256;
   if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(k_update, dim3(nb, b.n), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_update, dim3((nb) * b.n), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
 __global__ void k_reset_ctrl(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   for (int i = threadIdx.x; i < C_NCTRL; i += blockDim.x) s.ctrl[i] = 0;
   for (int i = threadIdx.x; i < S_NSCAL; i += blockDim.x) s.scal[i] = 0.0;
 }
 
 __global__ void k_clear_done(Batch b) {
-  if (threadIdx.x == 0) b.s[blockIdx.y]->ctrl[C_DONE] = 0;
+  if (threadIdx.x == 0) MRA_SOLVE(b).ctrl[C_DONE] = 0;
 }
 
 hipError_t launch_clear_done(const Batch& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_clear_done, dim3(1, b.n), dim3(64), 0, st, b);
+  hipLaunchKernelGGL(k_clear_done, dim3((1) * b.n), dim3(64), 0, st, b);
   return hipGetLastError();
 }
 
 hipError_t launch_reset_ctrl(const Batch& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_ctrl, dim3(1, b.n), dim3(64), 0, st, b);
+  hipLaunchKernelGGL(k_reset_ctrl, dim3((1) * b.n), dim3(64), 0, st, b);
   return hipGetLastError();
 }
 

@@ -50,8 +50,8 @@ template <int P, typename T> __device__ inline T lap5(const T* a, int W, int r, 
   return s;
 }
 
-template <typename T>
-__device__ inline void load_region(T* dst, const T* __restrict__ src, int x0, int y0, int W, int N) {
+template <int W, typename T>
+__device__ inline void load_region(T* dst, const T* __restrict__ src, int x0, int y0, int N) {
   const int nm = N - 1;
   for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
     const int r = q / W, c = q - r * W;
@@ -85,15 +85,15 @@ __host__ __device__ inline size_t jvp_lds_elems(int TS) {
   return Wpv * Wpv + 3 * Ww * Ww + Wn * Wn;
 }
 
-template <int P, typename T>
+template <int P, typename T, int TS>
 __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   using G = Geo<P>;
   extern __shared__ unsigned char smem[];
-  const SolveDev& s = *b.s[blockIdx.y];
-  const int N = s.N, TS = s.tile, ntx = s.ntx;
-  const int tile = tile_of_block(blockIdx.x, ntx * ntx);
+  const SolveDev& s = MRA_SOLVE(b);
+  const int N = s.N, ntx = s.ntx;
+  const int tile = tile_of_block(MRA_BX(b), ntx * ntx);
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
-  const int Wp = TS + 2 * G::HP, Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
+  constexpr int Wp = TS + 2 * G::HP, Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
   T* psi = reinterpret_cast<T*>(smem);
   T* uu = psi + Wp * Wp;
   T* vv = uu + Wu * Wu;
@@ -101,8 +101,8 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   T* ww = nu + Wn * Wn;
   const T* gpsi = reinterpret_cast<const T*>(s.psi);
   const T* gw = reinterpret_cast<const T*>(s.wt);
-  load_region(psi, gpsi, x0 - G::HP, y0 - G::HP, Wp, N);
-  load_region(ww, gw, x0 - G::R1, y0 - G::R1, Ww, N);
+  load_region<Wp>(psi, gpsi, x0 - G::HP, y0 - G::HP, N);
+  load_region<Ww>(ww, gw, x0 - G::R1, y0 - G::R1, N);
   __syncthreads();
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
   // u = D1_y psi, v = -D1_x psi on the Wu region
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
     gv[f] = vv[(r + G::HU) * Wu + c + G::HU];
     gn[f] = nu[(r + P) * Wn + c + P];
   }
-  if (!s.tile_flag[tile]) return;
+  if (s.tile_count[tile] == 0) return;
   __syncthreads();
   // fluxes u w, v w on the Ww region (in place of u, v), nu w on the Wn region
   const int ou = G::HU - G::R1;   // = P
@@ -177,25 +177,25 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   }
 }
 
-template <int P, typename T>
+template <int P, typename T, int TS>
 __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   using G = Geo<P>;
   extern __shared__ unsigned char smem[];
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
-  const int N = s.N, TS = s.tile, ntx = s.ntx, nm = N - 1;
-  const int tile = tile_of_block(blockIdx.x, ntx * ntx);
-  if (!s.tile_flag[tile]) return;
+  const int N = s.N, ntx = s.ntx, nm = N - 1;
+  const int tile = tile_of_block(MRA_BX(b), ntx * ntx);
+  if (s.tile_count[tile] == 0) return;
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
-  const int Wpv = TS + 4 * G::R1, Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
+  constexpr int Wpv = TS + 4 * G::R1, Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
   T* pv = reinterpret_cast<T*>(smem);
   T* vt = pv + Wpv * Wpv;
   T* fa = vt + Ww * Ww;
   T* fb = fa + Ww * Ww;
   T* nu = fb + Ww * Ww;
-  load_region(pv, reinterpret_cast<const T*>(s.psiv), x0 - 2 * G::R1, y0 - 2 * G::R1, Wpv, N);
-  load_region(vt, reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, Ww, N);
-  load_region(nu, reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, Wn, N);
+  load_region<Wpv>(pv, reinterpret_cast<const T*>(s.psiv), x0 - 2 * G::R1, y0 - 2 * G::R1, N);
+  load_region<Ww>(vt, reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, N);
+  load_region<Wn>(nu, reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, N);
   __syncthreads();
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
   const T* gu = reinterpret_cast<const T*>(s.u);
@@ -236,19 +236,26 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   }
 }
 
+template <int P, typename T, int TS>
+static hipError_t rhs_ts(const Batch& b, int N, bool jvp, hipStream_t st) {
+  const int nt = (N / TS) * (N / TS);
+  if (!jvp) {
+    const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
+    hipLaunchKernelGGL((k_rhs<P, T, TS>), dim3((nt) * b.n), dim3(256), lds, st, b);
+  } else {
+    const size_t lds = jvp_lds_elems<P, T>(TS) * sizeof(T);
+    hipLaunchKernelGGL((k_jvp<P, T, TS>), dim3((nt) * b.n), dim3(256), lds, st, b);
+  }
+  return hipGetLastError();
+}
+
 template <int P, typename T>
 static hipError_t rhs_t(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {
   const int N = 1 << c.J;
   const int TS = tile_edge(c.J, c.p, c.prec);
-  const int nt = (N / TS) * (N / TS);
-  if (!jvp) {
-    const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
-    hipLaunchKernelGGL((k_rhs<P, T>), dim3(nt, b.n), dim3(256), lds, st, b);
-  } else {
-    const size_t lds = jvp_lds_elems<P, T>(TS) * sizeof(T);
-    hipLaunchKernelGGL((k_jvp<P, T>), dim3(nt, b.n), dim3(256), lds, st, b);
-  }
-  return hipGetLastError();
+  if (TS == 32) return rhs_ts<P, T, 32>(b, N, jvp, st);
+  if (TS == 16) return rhs_ts<P, T, 16>(b, N, jvp, st);
+  return rhs_ts<P, T, 8>(b, N, jvp, st);
 }
 
 static hipError_t rhs_dispatch(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {
@@ -265,8 +272,8 @@ hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st) { retu
 // (Sections 3.3, 3.4).  The host adds the rows in order.
 template <int P>
 __global__ void __launch_bounds__(256) k_diag(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
-  const int N = s.N, nm = N - 1, y = blockIdx.x;
+  const SolveDev& s = MRA_SOLVE(b);
+  const int N = s.N, nm = N - 1, y = MRA_BX(b);
   const double* w = s.dense64;
   const double* ps = reinterpret_cast<const double*>(s.psi);
   const double ih = 1.0 / s.h;
@@ -304,8 +311,8 @@ __global__ void __launch_bounds__(256) k_diag(Batch b) {
 
 hipError_t launch_diag(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   const int N = 1 << c.J;
-  if (c.p == 2) hipLaunchKernelGGL(k_diag<2>, dim3(N, b.n), dim3(256), 0, st, b);
-  else hipLaunchKernelGGL(k_diag<3>, dim3(N, b.n), dim3(256), 0, st, b);
+  if (c.p == 2) hipLaunchKernelGGL(k_diag<2>, dim3((N) * b.n), dim3(256), 0, st, b);
+  else hipLaunchKernelGGL(k_diag<3>, dim3((N) * b.n), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

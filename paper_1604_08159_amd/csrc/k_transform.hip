@@ -33,25 +33,25 @@ __device__ inline T* dense_target(const SolveDev& s, int target) {
 // src 0: omega; src 1: V[j] = w * inv (stored), then scattered; src 2: vin.
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter(Batch b, int src, int target, int j) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const int na = (int)*s.n_active;
   const int Nf = s.N * s.N;
   T* dense = dense_target<T>(s, target);
   const int* fi = s.index_fine;
   if (src == 0) {
     const double* om = s.omega;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x)
+    for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x)
       dense[fi[k]] = (T)om[k];
   } else if (src == 2) {
     const double* vin = s.vin;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x)
+    for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x)
       dense[fi[k]] = (T)vin[k];
   } else {
-    const bool done = s.ctrl[C_DONE] != 0;
-    const double inv = s.scal[S_INV];
+    const double inv = next_scale(s, j, MRA_BX(b));
+    const bool done = inv == 0.0;
     double* Vj = s.V + (size_t)j * Nf;
     const double* w = s.w;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x) {
+    for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x) {
       double val = 0.0;
       if (!done) {
         val = w[k] * inv;
@@ -69,7 +69,7 @@ static int scatter_blocks(int J) {
 }
 
 hipError_t launch_scatter(const Batch& b, const LaunchCfg& c, int src, int target, int j, hipStream_t st) {
-  dim3 g(scatter_blocks(c.J), b.n);
+  dim3 g((scatter_blocks(c.J)) * b.n);
   if (target == 2 || c.prec == 0)
     hipLaunchKernelGGL(k_scatter<double>, g, dim3(256), 0, st, b, src, target, j);
   else
@@ -93,35 +93,64 @@ __device__ inline void prolong_node(T* __restrict__ f, const uint8_t* __restrict
   f[fi] = mode == 0 ? pr : packed[i] + pr;
 }
 
+// Levels j0+1 .. Lc (Lc = min(J, kCoarseLevels)) for one solve per block: the
+// 2^Lc x 2^Lc sub-grid of stride 2^(J-Lc) is gathered into LDS (active
+// values from the dense field, through the contiguous coarse part of the
+// packed mask), every coarse level is swept in LDS with the same arithmetic
+// as the fine levels, and the predicted nodes are written back.
+// mode 1 (inverse transform) adds the details of the packed input instead.
 template <int P, typename T>
 __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, int lmax, int mode) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   T* f = dense_target<T>(s, target);
   const T* packed = mode == 1 ? reinterpret_cast<const T*>(s.spec) : nullptr;
   const int J = s.J, j0 = s.j0;
-  const int top = lmax < J ? lmax : J;
-  for (int l = j0 + 1; l <= top; ++l) {
+  const int Lc = lmax < J ? lmax : J;
+  const int n = 1 << Lc, S = 1 << (J - Lc);
+  const int cnt = 1 << (2 * Lc);
+  __shared__ T val[1 << (2 * kCoarseLevels)];
+  __shared__ uint8_t act[1 << (2 * kCoarseLevels)];
+  const int n0sq = 1 << (2 * j0);
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int fi = packed_to_fine(i, J, j0, nullptr);
+    const int sub = ((fi >> J) / S) * n + (fi & (s.N - 1)) / S;
+    const bool a = mode == 0 ? s.mask[i] != 0 : i < n0sq;
+    act[sub] = a;
+    if (a) val[sub] = f[fi];
+  }
+  __syncthreads();
+  for (int l = j0 + 1; l <= Lc; ++l) {
     const int lo = 1 << (2 * (l - 1)), hi = 1 << (2 * l);
-    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
-      prolong_node<P, T>(f, s.mask, packed, i, l, J, j0, mode);
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      int lv;
+      const int sf = packed_to_fine(i, Lc, j0, &lv);   // node of the sub-grid
+      if (act[sf]) continue;
+      const T pr = predict_node<P, T>(val, sf & (n - 1), sf >> Lc, l, Lc);
+      val[sf] = mode == 0 ? pr : packed[i] + pr;
+    }
     __syncthreads();
+  }
+  for (int i = n0sq + threadIdx.x; i < cnt; i += blockDim.x) {
+    const int fi = packed_to_fine(i, J, j0, nullptr);
+    const int sub = ((fi >> J) / S) * n + (fi & (s.N - 1)) / S;
+    if (!act[sub]) f[fi] = val[sub];
   }
 }
 
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_prolong_level(Batch b, int target, int l, int mode) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   T* f = dense_target<T>(s, target);
   const T* packed = mode == 1 ? reinterpret_cast<const T*>(s.spec) : nullptr;
   const int lo = 1 << (2 * (l - 1)), hi = 1 << (2 * l);
-  const int i = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = lo + MRA_BX(b) * blockDim.x + threadIdx.x;
   if (i < hi) prolong_node<P, T>(f, s.mask, packed, i, l, s.J, s.j0, mode);
 }
 
 // coarse copy for the inverse transform: dense(coarse node) = packed[i]
 template <typename T>
 __global__ void k_inverse_coarse(Batch b, int target) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   T* f = dense_target<T>(s, target);
   const T* packed = reinterpret_cast<const T*>(s.spec);
   const int n0 = 1 << s.j0;
@@ -131,7 +160,7 @@ __global__ void k_inverse_coarse(Batch b, int target) {
 template <typename T>
 static hipError_t prolong_t(const Batch& b, const LaunchCfg& c, int target, int mode, hipStream_t st) {
   const int j0 = c.p == 2 ? 2 : 3;
-  dim3 g1(1, b.n);
+  dim3 g1((1) * b.n);
   if (mode == 1) hipLaunchKernelGGL(k_inverse_coarse<T>, g1, dim3(256), 0, st, b, target);
   if (c.p == 2)
     hipLaunchKernelGGL((k_prolong_coarse<2, T>), g1, dim3(1024), 0, st, b, target, kCoarseLevels, mode);
@@ -139,7 +168,7 @@ static hipError_t prolong_t(const Batch& b, const LaunchCfg& c, int target, int 
     hipLaunchKernelGGL((k_prolong_coarse<3, T>), g1, dim3(1024), 0, st, b, target, kCoarseLevels, mode);
   for (int l = (kCoarseLevels > j0 ? kCoarseLevels : j0) + 1; l <= c.J; ++l) {
     const int cnt = 3 << (2 * (l - 1));
-    dim3 g((cnt + 255) / 256, b.n);
+    dim3 g(((cnt + 255) / 256) * b.n);
     if (c.p == 2)
       hipLaunchKernelGGL((k_prolong_level<2, T>), g, dim3(256), 0, st, b, target, l, mode);
     else
@@ -156,7 +185,7 @@ hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as
 hipError_t launch_prolong_level(const Batch& b, const LaunchCfg& c, int target, int as_double, int l,
                                 hipStream_t st) {
   const int cnt = 3 << (2 * (l - 1));
-  dim3 g((cnt + 255) / 256, b.n);
+  dim3 g(((cnt + 255) / 256) * b.n);
   if (as_double) {
     if (c.p == 2) hipLaunchKernelGGL((k_prolong_level<2, double>), g, dim3(256), 0, st, b, target, l, 0);
     else hipLaunchKernelGGL((k_prolong_level<3, double>), g, dim3(256), 0, st, b, target, l, 0);
@@ -180,11 +209,11 @@ __device__ inline double warp_max(double v) {
 }
 
 __global__ void k_reset_max(Batch b) {
-  if (threadIdx.x == 0) *b.s[blockIdx.y]->umax = 0ull;
+  if (threadIdx.x == 0) *MRA_SOLVE(b).umax = 0ull;
 }
 
 hipError_t launch_reset_max(const Batch& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_max, dim3(1, b.n), dim3(64), 0, st, b);
+  hipLaunchKernelGGL(k_reset_max, dim3((1) * b.n), dim3(64), 0, st, b);
   return hipGetLastError();
 }
 
@@ -193,12 +222,12 @@ hipError_t launch_reset_max(const Batch& b, hipStream_t st) {
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_forward(Batch b, int src, int dst) {
 #pragma clang fp contract(off)
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const T* f = src == 0 ? reinterpret_cast<const T*>(s.dense64) : reinterpret_cast<const T*>(s.wt);
   T* out = dst == 0 ? reinterpret_cast<T*>(s.packed64) : reinterpret_cast<T*>(s.spec);
   const int J = s.J, j0 = s.j0, N = s.N;
   const int Nf = N * N;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = MRA_BX(b) * blockDim.x + threadIdx.x;
   double am = 0.0;
   if (i < Nf) {
     int l;
@@ -219,7 +248,7 @@ __global__ void __launch_bounds__(256) k_forward(Batch b, int src, int dst) {
 
 hipError_t launch_forward(const Batch& b, const LaunchCfg& c, int src, int dst, hipStream_t st) {
   const int nf = 1 << (2 * c.J);
-  dim3 g((nf + 255) / 256, b.n);
+  dim3 g(((nf + 255) / 256) * b.n);
   const bool dbl = src == 0 || c.prec == 0;
   if (dbl) {
     if (c.p == 2) hipLaunchKernelGGL((k_forward<2, double>), g, dim3(256), 0, st, b, src, dst);
@@ -268,11 +297,11 @@ __device__ inline bool is_active(const TP* __restrict__ d, int i, int J, int j0,
 
 template <typename TP>
 __global__ void __launch_bounds__(kScanBlock) k_mask_count(Batch b, int packed_is_double) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const TP* d = packed_is_double ? reinterpret_cast<const TP*>(s.packed64) : reinterpret_cast<const TP*>(s.spec);
   const int Nf = s.N * s.N;
   const double tau = s.eps * __longlong_as_double((long long)*s.umax);
-  const int base = blockIdx.x * (kScanBlock * kScanItems) + threadIdx.x * kScanItems;
+  const int base = MRA_BX(b) * (kScanBlock * kScanItems) + threadIdx.x * kScanItems;
   int cnt = 0;
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
@@ -290,7 +319,7 @@ __global__ void __launch_bounds__(kScanBlock) k_mask_count(Batch b, int packed_i
   if (threadIdx.x == 0) {
     int t = 0;
     for (int w = 0; w < kScanBlock / 64; ++w) t += red[w];
-    s.block_off[blockIdx.x] = t;
+    s.block_off[MRA_BX(b)] = t;
   }
 }
 
@@ -317,7 +346,7 @@ __device__ inline int block_exclusive_scan(int v, int* sh, int* total) {
 }
 
 __global__ void __launch_bounds__(1024) k_scan(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const int Nf = s.N * s.N;
   const int nblk = (Nf + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
   const int per = (nblk + blockDim.x - 1) / blockDim.x;
@@ -338,14 +367,14 @@ __global__ void __launch_bounds__(1024) k_scan(Batch b) {
   }
   if (threadIdx.x == 0) *s.n_active = total;
   const int ntiles = s.ntx * s.ntx;
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) s.tile_flag[t] = 0;
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) s.tile_count[t] = 0;
 }
 
 __global__ void __launch_bounds__(kScanBlock) k_compact(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const int Nf = s.N * s.N;
   const int J = s.J, j0 = s.j0, N = s.N, T = s.tile, ntx = s.ntx;
-  const int base = blockIdx.x * (kScanBlock * kScanItems) + threadIdx.x * kScanItems;
+  const int base = MRA_BX(b) * (kScanBlock * kScanItems) + threadIdx.x * kScanItems;
   int m[kScanItems];
   int cnt = 0;
 #pragma unroll
@@ -356,7 +385,7 @@ __global__ void __launch_bounds__(kScanBlock) k_compact(Batch b) {
   }
   __shared__ int sh[kScanBlock / 64 + 1];
   int total;
-  int pos = s.block_off[blockIdx.x] + block_exclusive_scan(cnt, sh, &total);
+  int pos = s.block_off[MRA_BX(b)] + block_exclusive_scan(cnt, sh, &total);
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
     const int i = base + q;
@@ -367,7 +396,7 @@ __global__ void __launch_bounds__(kScanBlock) k_compact(Batch b) {
       s.index_fine[pos] = f;
       s.rank[f] = pos;
       const int x = f & (N - 1), y = f >> J;
-      s.tile_flag[(y / T) * ntx + x / T] = 1;
+      atomicAdd(&s.tile_count[(y / T) * ntx + x / T], 1);
       ++pos;
     } else {
       s.rank[f] = -1;
@@ -378,52 +407,52 @@ __global__ void __launch_bounds__(kScanBlock) k_compact(Batch b) {
 hipError_t launch_threshold(const Batch& b, const LaunchCfg& c, int packed_is_double, hipStream_t st) {
   const int nf = 1 << (2 * c.J);
   const int nblk = (nf + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
-  dim3 g(nblk, b.n);
+  dim3 g((nblk) * b.n);
   if (packed_is_double || c.prec == 0)
     hipLaunchKernelGGL(k_mask_count<double>, g, dim3(kScanBlock), 0, st, b, packed_is_double);
   else
     hipLaunchKernelGGL(k_mask_count<float>, g, dim3(kScanBlock), 0, st, b, packed_is_double);
-  hipLaunchKernelGGL(k_scan, dim3(1, b.n), dim3(1024), 0, st, b);
+  hipLaunchKernelGGL(k_scan, dim3((1) * b.n), dim3(1024), 0, st, b);
   hipLaunchKernelGGL(k_compact, g, dim3(kScanBlock), 0, st, b);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- gather
 __global__ void __launch_bounds__(256) k_gather(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const int na = (int)*s.n_active;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x)
+  for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x)
     s.omega[k] = s.dense64[s.index_fine[k]];
 }
 
 hipError_t launch_gather(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3(scatter_blocks(c.J), b.n), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_gather, dim3((scatter_blocks(c.J)) * b.n), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
 // rank map and tile flags from a caller-given index list
 __global__ void __launch_bounds__(256) k_rank_clear(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const int Nf = s.N * s.N;
-  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < Nf; f += gridDim.x * blockDim.x) s.rank[f] = -1;
+  for (int f = MRA_BX(b) * blockDim.x + threadIdx.x; f < Nf; f += MRA_GX(b) * blockDim.x) s.rank[f] = -1;
   const int ntiles = s.ntx * s.ntx;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x)
-    s.tile_flag[t] = 0;
+  for (int t = MRA_BX(b) * blockDim.x + threadIdx.x; t < ntiles; t += MRA_GX(b) * blockDim.x)
+    s.tile_count[t] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_rank_scatter(Batch b) {
-  const SolveDev& s = *b.s[blockIdx.y];
+  const SolveDev& s = MRA_SOLVE(b);
   const int na = (int)*s.n_active;
   const int J = s.J, N = s.N, T = s.tile, ntx = s.ntx;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x) {
+  for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x) {
     const int f = s.index_fine[k];
     s.rank[f] = k;
-    s.tile_flag[((f >> J) / T) * ntx + (f & (N - 1)) / T] = 1;
+    atomicAdd(&s.tile_count[((f >> J) / T) * ntx + (f & (N - 1)) / T], 1);
   }
 }
 
 hipError_t launch_rank_from_index(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  dim3 g(scatter_blocks(c.J), b.n);
+  dim3 g((scatter_blocks(c.J)) * b.n);
   hipLaunchKernelGGL(k_rank_clear, g, dim3(256), 0, st, b);
   hipLaunchKernelGGL(k_rank_scatter, g, dim3(256), 0, st, b);
   return hipGetLastError();

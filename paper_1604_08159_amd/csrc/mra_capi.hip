@@ -120,7 +120,7 @@ void transform_layout(Layout& L, SolveDev& s) {
   s.scal = L.take<double>(S_NSCAL);
   s.block_off = L.take<int32_t>(nscan_of(s.J));
   s.rank = L.take<int32_t>(Nf);
-  s.tile_flag = L.take<uint8_t>((size_t)s.ntx * s.ntx);
+  s.tile_count = L.take<int32_t>((size_t)s.ntx * s.ntx);
 }
 
 // Workspace of the stand-alone residual / JVP.
@@ -131,7 +131,7 @@ void rhs_layout(Layout& L, SolveDev& s) {
   s.ctrl = L.take<int>(C_NCTRL);
   s.scal = L.take<double>(S_NSCAL);
   s.rank = L.take<int32_t>(Nf);
-  s.tile_flag = L.take<uint8_t>((size_t)s.ntx * s.ntx);
+  s.tile_count = L.take<int32_t>((size_t)s.ntx * s.ntx);
   s.wt = L.take<char>(Nf * esz);
   s.psi = L.take<char>(Nf * esz);
   s.u = L.take<char>(Nf * esz);
@@ -156,7 +156,7 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.index_packed = L.take<int32_t>(Nf);
   s.index_fine = L.take<int32_t>(Nf);
   s.rank = L.take<int32_t>(Nf);
-  s.tile_flag = L.take<uint8_t>((size_t)s.ntx * s.ntx);
+  s.tile_count = L.take<int32_t>((size_t)s.ntx * s.ntx);
   s.block_off = L.take<int32_t>(nscan_of(s.J));
   s.omega = L.take<double>(Nf);
   s.V = L.take<double>((size_t)(s.m + 1) * Nf);
@@ -164,7 +164,7 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.H = L.take<double>((size_t)(s.m + 1) * s.m);
   s.hpart = L.take<double>(2 * (kMaxM + 1));
   s.y = L.take<double>(kMaxM + 1);
-  s.partials = L.take<double>((size_t)kRedBlocks * (kMaxM + 2));
+  s.partials = L.take<double>((size_t)2 * kPartSlots * (kMaxM + 2));
   s.wt = L.take<char>(Nf * esz);
   s.psi = L.take<char>(Nf * 8);      // FP64 for the diagnostics
   s.u = L.take<char>(Nf * esz);

@@ -1,8 +1,8 @@
 // Internal declarations of the gfx950 wavelet-collocation library.
 //
-// Every kernel works on a batch of solves of equal (J, p, precision): the
-// solve index is blockIdx.y and its buffers are described by a SolveDev
-// record that lives in device memory (in the solve's arena, or in the
+// Every kernel works on a batch of solves of equal (J, p, precision): each
+// block works for one solve (see MRA_SOLVE) whose buffers are described by a
+// SolveDev record that lives in device memory (in the solve's arena, or in the
 // workspace of a stand-alone call).  Sizes that change on the device (the
 // active count) are read from device memory, so launch shapes depend only on
 // (J, p, m) and a captured step stays valid.
@@ -17,7 +17,7 @@ constexpr int kMaxJ = 11;
 constexpr int kMaxM = 47;           // Krylov dimension cap (augmented size <= 48)
 constexpr int kMaxBatch = 64;       // solves per launch
 constexpr int kTile = 32;           // stencil tile edge (clamped to N)
-constexpr int kRedBlocks = 256;     // blocks of the Krylov reductions
+constexpr int kRedBlocks = 256;     // max chunks per solve of the Krylov reductions
 constexpr int kScanItems = 4;       // packed entries per thread in compaction
 constexpr int kScanBlock = 256;     // threads per compaction block
 constexpr int kCoarseLevels = 6;    // levels <= this are prolonged by one block
@@ -44,7 +44,7 @@ struct SolveDev {
   int32_t* index_packed;    // [Nf]
   int32_t* index_fine;      // [Nf]
   int32_t* rank;            // [Nf] dense: active position or -1
-  uint8_t* tile_flag;       // [ntiles]
+  int32_t* tile_count;      // [ntiles] active nodes per stencil tile
   int64_t* n_active;        // device scalar
   int32_t* block_off;       // [nscan] compaction block counts -> offsets
   unsigned long long* umax; // bits of max|u| (non-negative doubles order as integers)
@@ -55,7 +55,7 @@ struct SolveDev {
   double* H;                // [(m+1)][m]
   double* hpart;            // [3][kMaxM+1] Gram-Schmidt coefficients of the current column
   double* y;                // [kMaxM + 1]
-  double* partials;         // [kRedBlocks][kMaxM + 2]
+  double* partials;         // [2][kRedBlocks * 4][kMaxM + 2]
   double* scal;             // [S_NSCAL]
   int* ctrl;                // [C_NCTRL]
   // dense fields (element type by prec)
@@ -79,6 +79,15 @@ struct Batch {
   const SolveDev* s[kMaxBatch];
   int n;
 };
+
+// Launch geometry of a batch: a 1-D grid of n * gx blocks in which block
+// L works for solve L % n as its block L / n.  Workgroups are dealt to the 8
+// XCDs round-robin by linear id, so (for n dividing 8 or a multiple of 8) all
+// blocks of one solve run on the same XCD(s) and consecutive kernels of that
+// solve meet its data in the same L2.
+#define MRA_SOLVE(b) (*(b).s[blockIdx.x % (b).n])
+#define MRA_BX(b) ((int)(blockIdx.x / (b).n))
+#define MRA_GX(b) ((int)(gridDim.x / (b).n))
 
 // ------------------------------------------------------------------ helpers
 __host__ __device__ inline int ilog2(unsigned v) { return 31 - __builtin_clz(v); }
@@ -186,6 +195,100 @@ __host__ __device__ inline int tile_edge(int J, int p, int prec) {
   const int t = (prec == 0 && p == 3) ? 16 : kTile;
   const int N = 1 << J;
   return N < t ? N : t;
+}
+
+// ------------------------------------------------- Krylov reductions
+constexpr double kBreakdown = 1e-13;
+constexpr int kChunkMin = 512;
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+struct Chunk {
+  int lo, hi;
+};
+__device__ inline int nchunks(int na) {
+  int nb = (na + kChunkMin - 1) / kChunkMin;
+  if (nb < 1) nb = 1;
+  return nb > kRedBlocks ? kRedBlocks : nb;
+}
+__device__ inline Chunk chunk_of(int na, int ch) {
+  const int nb = nchunks(na);
+  const int per = (na + nb - 1) / nb;
+  Chunk c;
+  c.lo = ch * per;
+  c.hi = c.lo + per < na ? c.lo + per : na;
+  return c;
+}
+
+// Partial-sum buffers: stage 1 and 3 write A, the residual norm and stage 2
+// write B, so that a kernel never overwrites partials another block of the
+// same kernel is still reading.  One slot per (chunk, wavefront).
+constexpr int kWavesPerBlock = 4;
+constexpr int kPartSlots = kRedBlocks * kWavesPerBlock;
+__device__ inline double* part_buf(const SolveDev& s, int which) {
+  return s.partials + (size_t)which * kPartSlots * (kMaxM + 2);
+}
+
+// totals[i] = sum over the nb * 4 slots of buf[slot][i], i < cnt, in a fixed
+// order (lanes stride the slots, then a fixed butterfly): every block that
+// calls this gets bit-identical totals.
+__device__ inline void reduce_partials(const double* buf, int nb, int cnt, double* totals) {
+  const int stride = kMaxM + 2;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nslots = nb * kWavesPerBlock;
+  for (int i = wid; i < cnt; i += nw) {
+    double t = 0.0;
+    for (int q = lane; q < nslots; q += 64) t += buf[q * stride + i];
+    t = wave_sum(t);
+    if (lane == 0) totals[i] = t;
+  }
+  __syncthreads();
+}
+
+// The scaling of the next basis vector, from the partials of the previous
+// kernel.  j = 0: beta = ||F|| (buffer B); j > 0: h_{j,j-1} = ||w|| (buffer A)
+// with the happy-breakdown test.  Every block computes the same values;
+// block 0 records them.  Returns 1 / norm, or 0 when the basis is complete.
+__device__ inline double next_scale(const SolveDev& s, int j, int bx) {
+  __shared__ double tot[2];
+  __shared__ double inv_sh;
+  const int na = (int)*s.n_active;
+  const int nb = nchunks(na);
+  if (j > 0 && s.ctrl[C_DONE]) return 0.0;
+  reduce_partials(part_buf(s, j == 0 ? 1 : 0), nb, 1, tot);
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(tot[0]);
+    const bool rec = bx == 0;
+    double inv = 0.0;
+    if (j == 0) {
+      const bool ok = isfinite(nrm);
+      const bool zero = !(nrm > 0.0) || !ok;
+      inv = zero ? 0.0 : 1.0 / nrm;
+      if (rec) {
+        s.scal[S_BETA] = nrm;
+        if (!ok) s.ctrl[C_STATUS] = 5;
+        s.ctrl[C_DONE] = zero ? 1 : 0;
+        s.ctrl[C_MEFF] = zero ? 0 : s.m;
+      }
+    } else {
+      const double nav = s.scal[S_NRMAV];
+      const bool bad = !isfinite(nrm) || !isfinite(nav);
+      const bool brk = bad || nrm <= kBreakdown * nav;
+      inv = brk ? 0.0 : 1.0 / nrm;
+      if (rec) {
+        s.H[j * s.m + (j - 1)] = nrm;
+        if (bad) { s.ctrl[C_STATUS] = 5; s.ctrl[C_MEFF] = 0; }
+        else if (brk) s.ctrl[C_MEFF] = j;
+        if (brk) s.ctrl[C_DONE] = 1;
+      }
+    }
+    inv_sh = inv;
+  }
+  __syncthreads();
+  return inv_sh;
 }
 
 // ------------------------------------------------------------- launchers
