@@ -29,78 +29,38 @@ __device__ inline T* dense_target(const SolveDev& s, int target) {
   return reinterpret_cast<T*>(s.dense64);
 }
 
-// ---------------------------------------------------------------- scatter
-// src 0: omega; src 1: V[j] = w * inv (stored), then scattered; src 2: vin.
-template <typename T>
-__global__ void __launch_bounds__(256) k_scatter(Batch b, int src, int target, int j) {
-  const SolveDev& s = MRA_SOLVE(b);
-  const int na = (int)*s.n_active;
-  const int Nf = s.N * s.N;
-  T* dense = dense_target<T>(s, target);
-  const int* fi = s.index_fine;
-  if (src == 0) {
-    const double* om = s.omega;
-    for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x)
-      dense[fi[k]] = (T)om[k];
-  } else if (src == 2) {
-    const double* vin = s.vin;
-    for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x)
-      dense[fi[k]] = (T)vin[k];
-  } else {
-    const double inv = next_scale(s, j, MRA_BX(b));
-    const bool done = inv == 0.0;
-    double* Vj = s.V + (size_t)j * Nf;
-    const double* w = s.w;
-    for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x) {
-      double val = 0.0;
-      if (!done) {
-        val = w[k] * inv;
-        Vj[k] = val;
-      }
-      dense[fi[k]] = (T)val;
-    }
-  }
-}
-
-static int scatter_blocks(int J) {
-  int nf = 1 << (2 * J);
-  int nb = (nf + 255) / 256;
-  return nb < 1024 ? nb : 1024;
-}
-
-hipError_t launch_scatter(const Batch& b, const LaunchCfg& c, int src, int target, int j, hipStream_t st) {
-  dim3 g((scatter_blocks(c.J)) * b.n);
-  if (target == 2 || c.prec == 0)
-    hipLaunchKernelGGL(k_scatter<double>, g, dim3(256), 0, st, b, src, target, j);
-  else
-    hipLaunchKernelGGL(k_scatter<float>, g, dim3(256), 0, st, b, src, target, j);
-  return hipGetLastError();
+// ------------------------------------------------------- active values
+// The value of active node k in the prolongation of: src 0 the state omega,
+// src 1 the next Arnoldi vector w * inv (inv = 0: the basis is complete),
+// src 2 a caller vector.
+__device__ inline double active_value(const SolveDev& s, int src, int k, double inv) {
+  if (src == 0) return s.omega[k];
+  if (src == 2) return s.vin[k];
+  return inv == 0.0 ? 0.0 : s.w[k] * inv;
 }
 
 // ---------------------------------------------------------------- prolong
-// mode 0: Pi (inactive nodes predicted, active kept); mode 1: inverse
-// transform (every node = detail + prediction, details from `packed`).
+// mode 0: Pi (inactive nodes predicted, active nodes take their value);
+// mode 1: inverse transform (every node = detail + prediction, details from
+// the packed input in s.spec).
 template <int P, typename T>
-__device__ inline void prolong_node(T* __restrict__ f, const uint8_t* __restrict__ mask,
-                                    const T* __restrict__ packed, int i, int l, int J, int j0,
-                                    int mode) {
+__device__ inline void prolong_node(T* __restrict__ f, const T* __restrict__ packed, int i, int l, int J,
+                                    int j0) {
 #pragma clang fp contract(off)
-  if (mode == 0 && mask[i]) return;
   int lv;
   const int fi = packed_to_fine(i, J, j0, &lv);
   const int N = 1 << J;
   const T pr = predict_node<P, T>(f, fi & (N - 1), fi >> J, l, J);
-  f[fi] = mode == 0 ? pr : packed[i] + pr;
+  f[fi] = packed[i] + pr;
 }
 
-// Levels j0+1 .. Lc (Lc = min(J, kCoarseLevels)) for one solve per block: the
-// 2^Lc x 2^Lc sub-grid of stride 2^(J-Lc) is gathered into LDS (active
-// values from the dense field, through the contiguous coarse part of the
-// packed mask), every coarse level is swept in LDS with the same arithmetic
-// as the fine levels, and the predicted nodes are written back.
-// mode 1 (inverse transform) adds the details of the packed input instead.
+// Inverse transform, levels j0+1 .. Lc (Lc = min(J, kCoarseLevels)), one
+// block per solve: the 2^Lc x 2^Lc sub-grid of stride 2^(J-Lc) is swept in
+// LDS (node = detail + prediction) and written back.  (mode 0, the
+// prolongation of a source vector on the coarse levels, is kept for
+// completeness; the step uses k_prolong_tiles.)
 template <int P, typename T>
-__global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, int lmax, int mode) {
+__global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, int lmax, int mode, int src, int j) {
   const SolveDev& s = MRA_SOLVE(b);
   T* f = dense_target<T>(s, target);
   const T* packed = mode == 1 ? reinterpret_cast<const T*>(s.spec) : nullptr;
@@ -111,12 +71,27 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
   __shared__ T val[1 << (2 * kCoarseLevels)];
   __shared__ uint8_t act[1 << (2 * kCoarseLevels)];
   const int n0sq = 1 << (2 * j0);
+  double inv = 0.0;
+  if (mode == 0 && src == 1) {
+    inv = next_scale(s, j, 0);
+    if (threadIdx.x == 0) s.scal[S_INV] = inv;
+  }
+  double* Vj = s.V + (size_t)j * s.N * s.N;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     const int fi = packed_to_fine(i, J, j0, nullptr);
     const int sub = ((fi >> J) / S) * n + (fi & (s.N - 1)) / S;
     const bool a = mode == 0 ? s.mask[i] != 0 : i < n0sq;
     act[sub] = a;
-    if (a) val[sub] = f[fi];
+    if (a) {
+      if (mode == 0) {
+        const int k = s.rank[fi];
+        const double v = active_value(s, src, k, inv);
+        if (src == 1 && inv != 0.0) Vj[k] = v;
+        val[sub] = (T)v;
+      } else {
+        val[sub] = f[fi];
+      }
+    }
   }
   __syncthreads();
   for (int l = j0 + 1; l <= Lc; ++l) {
@@ -130,21 +105,139 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
     }
     __syncthreads();
   }
-  for (int i = n0sq + threadIdx.x; i < cnt; i += blockDim.x) {
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     const int fi = packed_to_fine(i, J, j0, nullptr);
-    const int sub = ((fi >> J) / S) * n + (fi & (s.N - 1)) / S;
-    if (!act[sub]) f[fi] = val[sub];
+    f[fi] = val[((fi >> J) / S) * n + (fi & (s.N - 1)) / S];
   }
 }
 
+// Lattice of level l held by a fine tile: the G^l nodes within E_l of the
+// tile [x0, x0 + B), E_J = 0, E_{l-1} = E_l + (2p-1) 2^(J-l) (the reach of
+// the level-l prediction); origin o (a multiple of 2^(J-l)) and count n.
+__device__ inline void fine_box(int J, int P, int B, int x0, int l, int* o, int* n) {
+  int E = 0;
+  for (int q = J; q > l; --q) E += (2 * P - 1) << (J - q);
+  const int sh = J - l;
+  const int lo = x0 - E, hi = x0 + B - 1 + E;
+  const int oo = (lo >> sh) << sh;       // floor to the lattice (arithmetic shift)
+  *o = oo;
+  *n = ((hi - oo) >> sh) + 1;
+}
+
+// DD prediction of a level-l node from the level-(l-1) lattice prev (pitch
+// pn) whose origin is (dx, dy) fine units away; sh = J - l.  Same operand
+// order as predict_node.
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_prolong_level(Batch b, int target, int l, int mode) {
+__device__ inline T predict_lattice(const T* prev, int pn, int dx, int dy, int sh, bool oxd, bool oyd) {
+  const int sv = 1 << sh;
+  T c[2 * P];
+  if (oxd && !oyd) {
+    const int r = dy >> (sh + 1), a = ((dx - sv) >> (sh + 1)) - (P - 1);
+#pragma unroll
+    for (int o = 0; o < 2 * P; ++o) c[o] = prev[r * pn + a + o];
+    return dd_pred<P, T>(c);
+  } else if (oyd && !oxd) {
+    const int a = dx >> (sh + 1), bb = ((dy - sv) >> (sh + 1)) - (P - 1);
+#pragma unroll
+    for (int o = 0; o < 2 * P; ++o) c[o] = prev[(bb + o) * pn + a];
+    return dd_pred<P, T>(c);
+  } else {
+    const int a = ((dx - sv) >> (sh + 1)) - (P - 1), bb = ((dy - sv) >> (sh + 1)) - (P - 1);
+    T py[2 * P];
+#pragma unroll
+    for (int o2 = 0; o2 < 2 * P; ++o2) {
+#pragma unroll
+      for (int o = 0; o < 2 * P; ++o) c[o] = prev[(bb + o) * pn + a + o2];
+      py[o2] = dd_pred<P, T>(c);
+    }
+    return dd_pred<P, T>(py);
+  }
+}
+
+// Pi in one launch: one block per B x B tile of the finest grid (B =
+// min(N, 32)) sweeps the lattices of levels j0 .. J in LDS, each a halo wider
+// than the next (the reach of the next level's prediction), and writes the
+// tile.  The level-j0 lattice is all active.  Halo nodes are recomputed by
+// every tile that needs them, with identical arithmetic, so all tiles agree.
+// Active nodes take their value through the rank map; for src 1 every block
+// derives the scale of the new Arnoldi vector from the previous kernel's
+// partial sums (block 0 records it) and the tile that owns a node writes its
+// entry of V_j.
+constexpr int kFineTile = 32;
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int src, int j) {
+#pragma clang fp contract(off)
+  __shared__ T buf[2][kFineTile * kFineTile];
+  const SolveDev& s = MRA_SOLVE(b);
+  const int J = s.J, N = s.N, nm = N - 1, j0 = s.j0;
+  const int B = N < kFineTile ? N : kFineTile;
+  const int ntx = N / B;
+  const int t = MRA_BX(b);
+  const int x0 = (t % ntx) * B, y0 = (t / ntx) * B;
+  T* f = dense_target<T>(s, target);
+  const int* __restrict__ rank = s.rank;
+  const double inv = src == 1 ? next_scale(s, j, t) : 0.0;
+  double* Vj = s.V + (size_t)j * N * N;
+  auto owned = [&](int x, int y) { return x >= x0 && x < x0 + B && y >= y0 && y < y0 + B; };
+  int pox, poy, pn, tmp;
+  fine_box(J, P, B, x0, j0, &pox, &pn);
+  fine_box(J, P, B, y0, j0, &poy, &tmp);
+  {
+    const int sh = J - j0;
+    for (int q = threadIdx.x; q < pn * pn; q += blockDim.x) {
+      const int iy = q / pn, ix = q - iy * pn;
+      const int x = pox + (ix << sh), y = poy + (iy << sh);
+      const int k = rank[(y & nm) * N + (x & nm)];
+      const double a = active_value(s, src, k, inv);
+      if (src == 1 && inv != 0.0 && owned(x, y)) Vj[k] = a;
+      buf[0][q] = (T)a;
+    }
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int l = j0 + 1; l <= J; ++l) {
+    const int sh = J - l, sv = 1 << sh;
+    int ox, oy, n;
+    fine_box(J, P, B, x0, l, &ox, &n);
+    fine_box(J, P, B, y0, l, &oy, &tmp);
+    const T* prev = buf[cur];
+    T* nxt = buf[cur ^ 1];
+    for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
+      const int iy = q / n, ix = q - iy * n;
+      const int x = ox + (ix << sh), y = oy + (iy << sh);
+      T v;
+      if (((x | y) & sv) == 0) {
+        v = prev[((y - poy) >> (sh + 1)) * pn + ((x - pox) >> (sh + 1))];
+      } else {
+        const int k = rank[(y & nm) * N + (x & nm)];
+        if (k >= 0) {
+          const double a = active_value(s, src, k, inv);
+          if (src == 1 && inv != 0.0 && owned(x, y)) Vj[k] = a;
+          v = (T)a;
+        } else {
+          v = predict_lattice<P, T>(prev, pn, x - pox, y - poy, sh, (x & sv) != 0, (y & sv) != 0);
+        }
+      }
+      nxt[q] = v;
+    }
+    __syncthreads();
+    cur ^= 1;
+    pox = ox;
+    poy = oy;
+    pn = n;
+  }
+  for (int q = threadIdx.x; q < B * B; q += blockDim.x) f[(y0 + q / B) * N + x0 + (q % B)] = buf[cur][q];
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_prolong_level(Batch b, int target, int l) {
   const SolveDev& s = MRA_SOLVE(b);
   T* f = dense_target<T>(s, target);
-  const T* packed = mode == 1 ? reinterpret_cast<const T*>(s.spec) : nullptr;
+  const T* packed = reinterpret_cast<const T*>(s.spec);
   const int lo = 1 << (2 * (l - 1)), hi = 1 << (2 * l);
   const int i = lo + MRA_BX(b) * blockDim.x + threadIdx.x;
-  if (i < hi) prolong_node<P, T>(f, s.mask, packed, i, l, s.J, s.j0, mode);
+  if (i < hi) prolong_node<P, T>(f, packed, i, l, s.J, s.j0);
 }
 
 // coarse copy for the inverse transform: dense(coarse node) = packed[i]
@@ -158,48 +251,41 @@ __global__ void k_inverse_coarse(Batch b, int target) {
 }
 
 template <typename T>
-static hipError_t prolong_t(const Batch& b, const LaunchCfg& c, int target, int mode, hipStream_t st) {
-  const int j0 = c.p == 2 ? 2 : 3;
-  dim3 g1((1) * b.n);
-  if (mode == 1) hipLaunchKernelGGL(k_inverse_coarse<T>, g1, dim3(256), 0, st, b, target);
-  if (c.p == 2)
-    hipLaunchKernelGGL((k_prolong_coarse<2, T>), g1, dim3(1024), 0, st, b, target, kCoarseLevels, mode);
-  else
-    hipLaunchKernelGGL((k_prolong_coarse<3, T>), g1, dim3(1024), 0, st, b, target, kCoarseLevels, mode);
-  for (int l = (kCoarseLevels > j0 ? kCoarseLevels : j0) + 1; l <= c.J; ++l) {
+static hipError_t prolong_t(const Batch& b, const LaunchCfg& c, int target, int src, int j, hipStream_t st) {
+  const int N = 1 << c.J;
+  const int B = N < kFineTile ? N : kFineTile;
+  const int nt = (N / B) * (N / B);
+  if (c.p == 2) hipLaunchKernelGGL((k_prolong_tiles<2, T>), dim3(nt * b.n), dim3(256), 0, st, b, target, src, j);
+  else hipLaunchKernelGGL((k_prolong_tiles<3, T>), dim3(nt * b.n), dim3(256), 0, st, b, target, src, j);
+  return hipGetLastError();
+}
+
+// inverse transform: coarse copy, coarse kernel, one launch per finer level
+template <typename T>
+static hipError_t inverse_t(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  dim3 g1(b.n);
+  hipLaunchKernelGGL(k_inverse_coarse<T>, g1, dim3(256), 0, st, b, 0);
+  if (c.p == 2) hipLaunchKernelGGL((k_prolong_coarse<2, T>), g1, dim3(1024), 0, st, b, 0, kCoarseLevels, 1, 0, 0);
+  else hipLaunchKernelGGL((k_prolong_coarse<3, T>), g1, dim3(1024), 0, st, b, 0, kCoarseLevels, 1, 0, 0);
+  for (int l = kCoarseLevels + 1; l <= c.J; ++l) {
     const int cnt = 3 << (2 * (l - 1));
     dim3 g(((cnt + 255) / 256) * b.n);
-    if (c.p == 2)
-      hipLaunchKernelGGL((k_prolong_level<2, T>), g, dim3(256), 0, st, b, target, l, mode);
-    else
-      hipLaunchKernelGGL((k_prolong_level<3, T>), g, dim3(256), 0, st, b, target, l, mode);
+    if (c.p == 2) hipLaunchKernelGGL((k_prolong_level<2, T>), g, dim3(256), 0, st, b, 0, l);
+    else hipLaunchKernelGGL((k_prolong_level<3, T>), g, dim3(256), 0, st, b, 0, l);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as_double, hipStream_t st) {
-  if (as_double) return prolong_t<double>(b, c, target, 0, st);
-  return prolong_t<float>(b, c, target, 0, st);
-}
-
-hipError_t launch_prolong_level(const Batch& b, const LaunchCfg& c, int target, int as_double, int l,
-                                hipStream_t st) {
-  const int cnt = 3 << (2 * (l - 1));
-  dim3 g(((cnt + 255) / 256) * b.n);
-  if (as_double) {
-    if (c.p == 2) hipLaunchKernelGGL((k_prolong_level<2, double>), g, dim3(256), 0, st, b, target, l, 0);
-    else hipLaunchKernelGGL((k_prolong_level<3, double>), g, dim3(256), 0, st, b, target, l, 0);
-  } else {
-    if (c.p == 2) hipLaunchKernelGGL((k_prolong_level<2, float>), g, dim3(256), 0, st, b, target, l, 0);
-    else hipLaunchKernelGGL((k_prolong_level<3, float>), g, dim3(256), 0, st, b, target, l, 0);
-  }
-  return hipGetLastError();
+hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as_double, int src, int j,
+                          hipStream_t st) {
+  if (as_double) return prolong_t<double>(b, c, target, src, j, st);
+  return prolong_t<float>(b, c, target, src, j, st);
 }
 
 // inverse transform: packed input in s.spec (element type of prec), output wt.
 hipError_t launch_inverse(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  if (c.prec == 0) return prolong_t<double>(b, c, 0, 1, st);
-  return prolong_t<float>(b, c, 0, 1, st);
+  if (c.prec == 0) return inverse_t<double>(b, c, st);
+  return inverse_t<float>(b, c, st);
 }
 
 // ---------------------------------------------------------------- forward
@@ -418,6 +504,12 @@ hipError_t launch_threshold(const Batch& b, const LaunchCfg& c, int packed_is_do
 }
 
 // ---------------------------------------------------------------- gather
+static int grid_blocks(int J) {
+  const int nf = 1 << (2 * J);
+  const int nb = (nf + 255) / 256;
+  return nb < 1024 ? nb : 1024;
+}
+
 __global__ void __launch_bounds__(256) k_gather(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
   const int na = (int)*s.n_active;
@@ -426,7 +518,7 @@ __global__ void __launch_bounds__(256) k_gather(Batch b) {
 }
 
 hipError_t launch_gather(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3((scatter_blocks(c.J)) * b.n), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_gather, dim3((grid_blocks(c.J)) * b.n), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
@@ -452,7 +544,7 @@ __global__ void __launch_bounds__(256) k_rank_scatter(Batch b) {
 }
 
 hipError_t launch_rank_from_index(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  dim3 g((scatter_blocks(c.J)) * b.n);
+  dim3 g((grid_blocks(c.J)) * b.n);
   hipLaunchKernelGGL(k_rank_clear, g, dim3(256), 0, st, b);
   hipLaunchKernelGGL(k_rank_scatter, g, dim3(256), 0, st, b);
   return hipGetLastError();

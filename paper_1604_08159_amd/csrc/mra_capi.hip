@@ -193,15 +193,13 @@ hipError_t enqueue_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   const int dbl = c.prec == 0;
   hipError_t e;
   // residual F at omega
-  if ((e = launch_scatter(b, c, 0, 0, 0, st)) != hipSuccess) return e;
-  if ((e = launch_prolong(b, c, 0, dbl, st)) != hipSuccess) return e;
+  if ((e = launch_prolong(b, c, 0, dbl, 0, 0, st)) != hipSuccess) return e;
   if ((e = launch_poisson(b, c, 0, st)) != hipSuccess) return e;
   if ((e = launch_rhs(b, c, st)) != hipSuccess) return e;
   if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
   // Arnoldi
   for (int j = 0; j < c.m; ++j) {
-    if ((e = launch_scatter(b, c, 1, 1, j, st)) != hipSuccess) return e;
-    if ((e = launch_prolong(b, c, 1, dbl, st)) != hipSuccess) return e;
+    if ((e = launch_prolong(b, c, 1, dbl, 1, j, st)) != hipSuccess) return e;
     if ((e = launch_poisson(b, c, 1, st)) != hipSuccess) return e;
     if ((e = launch_jvp(b, c, st)) != hipSuccess) return e;
     if ((e = launch_arnoldi(b, c, j, st)) != hipSuccess) return e;
@@ -209,8 +207,7 @@ hipError_t enqueue_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   if ((e = launch_phi1(b, c, st)) != hipSuccess) return e;
   if ((e = launch_update(b, c, st)) != hipSuccess) return e;
   // FP64 regrid: Pi on the old set, forward transform, threshold, gather
-  if ((e = launch_scatter(b, c, 0, 2, 0, st)) != hipSuccess) return e;
-  if ((e = launch_prolong(b, c, 2, 1, st)) != hipSuccess) return e;
+  if ((e = launch_prolong(b, c, 2, 1, 0, 0, st)) != hipSuccess) return e;
   if ((e = launch_reset_max(b, st)) != hipSuccess) return e;
   if ((e = launch_forward(b, c, 0, 0, st)) != hipSuccess) return e;
   if ((e = launch_threshold(b, c, 1, st)) != hipSuccess) return e;
@@ -329,8 +326,8 @@ int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const v
     else s.wt = out;
     MRA_TRY(launch_write_desc(dev, s, st));
     Batch b = one(dev);
-    MRA_TRY(launch_scatter(b, c, 0, dbl ? 2 : 0, 0, st));
-    MRA_TRY(launch_prolong(b, c, dbl ? 2 : 0, dbl ? 1 : 0, st));
+    MRA_TRY(launch_rank_from_index(b, c, st));
+    MRA_TRY(launch_prolong(b, c, dbl ? 2 : 0, dbl ? 1 : 0, 0, 0, st));
   }
   return MRA_OK;
 }
@@ -384,13 +381,11 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
   Batch b = one(dev);
   MRA_TRY(launch_reset_ctrl(b, st));
   MRA_TRY(launch_rank_from_index(b, c, st));
-  MRA_TRY(launch_scatter(b, c, 0, 0, 0, st));
-  MRA_TRY(launch_prolong(b, c, 0, dbl, st));
+  MRA_TRY(launch_prolong(b, c, 0, dbl, 0, 0, st));
   MRA_TRY(launch_poisson(b, c, 0, st));
   MRA_TRY(launch_rhs(b, c, st));
   if (v_active) {
-    MRA_TRY(launch_scatter(b, c, 2, 1, 0, st));
-    MRA_TRY(launch_prolong(b, c, 1, dbl, st));
+    MRA_TRY(launch_prolong(b, c, 1, dbl, 2, 0, st));
     MRA_TRY(launch_poisson(b, c, 1, st));
     MRA_TRY(launch_jvp(b, c, st));
   }
@@ -527,8 +522,7 @@ int32_t mra_solve_read(mra_solve h, double* omega_dense_out, double* diag_out, v
   const size_t Nf = (size_t)s.N * s.N;
   Batch b = one(h->dev);
   LaunchCfg c = h->cfg;
-  MRA_TRY(launch_scatter(b, c, 0, 2, 0, st));
-  MRA_TRY(launch_prolong(b, c, 2, 1, st));
+  MRA_TRY(launch_prolong(b, c, 2, 1, 0, 0, st));
   if (omega_dense_out)
     MRA_TRY(hipMemcpyAsync(omega_dense_out, s.dense64, Nf * sizeof(double), hipMemcpyDeviceToDevice, st));
   int64_t na = 0;
@@ -620,7 +614,7 @@ int32_t mra_time_kernel(mra_solve* solves, int32_t n, int32_t which, int32_t rep
       case 1: e = launch_poisson_pass(b, c, 1, 0, st); break;
       case 2: e = launch_poisson_pass(b, c, 1, 1, st); break;
       case 3: e = launch_poisson_pass(b, c, 1, 2, st); break;
-      case 4: e = launch_prolong_level(b, c, 1, c.prec == 0, c.J, st); break;
+      case 4: e = launch_prolong(b, c, 1, c.prec == 0, 0, 0, st); break;
       case 5: e = launch_forward(b, c, 0, 0, st); break;
       case 6: e = launch_rhs(b, c, st); break;
       default: e = hipErrorInvalidValue;

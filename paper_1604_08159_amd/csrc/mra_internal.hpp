@@ -300,11 +300,10 @@ struct LaunchCfg {
 hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);
 
 // transforms
-hipError_t launch_scatter(const Batch& b, const LaunchCfg& c, int src /*0 omega,1 w*scale->V[j]*/,
-                          int target /*0 wt,1 vt,2 dense64*/, int j, hipStream_t st);
-hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as_double, hipStream_t st);
-hipError_t launch_prolong_level(const Batch& b, const LaunchCfg& c, int target, int as_double, int level,
-                                hipStream_t st);
+// Pi into target (0 wt, 1 vt, 2 dense64) from src (0 omega, 1 the next
+// Arnoldi vector V_j, 2 vin); as_double selects the element type.
+hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as_double, int src, int j,
+                          hipStream_t st);
 hipError_t launch_forward(const Batch& b, const LaunchCfg& c, int src /*0 dense64 (fp64), 1 wt*/,
                           int dst /*0 packed64, 1 spec-as-packed (T)*/, hipStream_t st);
 hipError_t launch_inverse(const Batch& b, const LaunchCfg& c, hipStream_t st);

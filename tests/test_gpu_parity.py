@@ -103,7 +103,8 @@ def _active_inputs(u, J, p, eps):
     return mask, ip, fi
 
 
-@pytest.mark.parametrize("p,J,eps", [(2, 5, 1e-3), (2, 8, 1e-4), (3, 7, 1e-3), (2, 6, 0.0)])
+@pytest.mark.parametrize("p,J,eps", [(2, 5, 1e-3), (2, 8, 1e-4), (3, 7, 1e-3), (2, 6, 0.0), (2, 9, 1e-4),
+                                     (3, 9, 1e-3), (2, 10, 1e-3), (3, 8, 0.0)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_prolong(M, p, J, eps, prec):
     N = 1 << J
@@ -132,7 +133,8 @@ def _gpu_rhs(M, g, fl, prec, mask, fi, omega, v=None):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("p,J,eps", [(2, 5, 1e-3), (2, 7, 1e-4), (3, 6, 1e-3), (3, 7, 0.0), (2, 4, 0.0)])
+@pytest.mark.parametrize("p,J,eps", [(2, 5, 1e-3), (2, 7, 1e-4), (3, 6, 1e-3), (3, 7, 0.0), (2, 4, 0.0),
+                                     (2, 8, 1e-4)])
 @pytest.mark.parametrize("smag", [2, 0])
 def test_rhs_and_jvp_fp64(M, p, J, eps, smag):
     N = 1 << J
@@ -224,6 +226,19 @@ def test_step_fp64_matches_oracle(M, nsteps):
     assert abs(diag["enstrophy"] - d["enstrophy"]) <= 1e-10 * d["enstrophy"]
     assert abs(diag["t"] - nsteps * pb.dt) < 1e-12
     assert int(diag["n_active"]) == st.omega_M.size
+
+
+def test_step_fp64_fine_levels_matches_oracle(M):
+    # J = 8: the prolongation runs its fused fine-level kernel
+    pb = W.fujiwhara_pair(1003, J=8)
+    s, w0 = _solve_pair(M, pb, M.MRA_FP64, m=12)
+    s.step(2)
+    dense, diag = s.read()
+    st, g = _oracle_run(pb, w0, 2, m=12)
+    ref = om.prolong(st.omega_M, st.index_fine, pb.J, pb.p)
+    _, mask, _, _ = s.active_set()
+    assert np.array_equal(mask.cpu().numpy(), st.mask)
+    assert np.linalg.norm(dense.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
 def test_step_mixed_error_reported(M):
