@@ -29,6 +29,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CALIB_BYTES = 64 << 20          # plain device copy of known size (PMC byte-counter scale)
+KERNEL_SOURCES = {"jvp": "k_stencil.hip", "rhs": "k_stencil.hip", "fft_rows": "k_fft.hip",
+                  "fft_cols": "k_fft.hip", "fft_rows_inv": "k_fft.hip", "prolong_finest": "k_transform.hip",
+                  "forward": "k_transform.hip"}
 SEEDS = list(range(1000, 1008))
 METRIC = "active-pt RHS evals/s"
 
@@ -53,6 +57,43 @@ def kernel_bytes(name: str, N: int, na: int, tiles_active_frac: float, nbatch: i
     else:
         raise KeyError(name)
     return per * nbatch
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs, if they were taken on the current source of the kernel."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1604_08159_amd", "csrc", KERNEL_SOURCES[kernel])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def fp64_per_solve(m, W, dev, steps: int) -> dict:
+    """The same workload, one solve at a time, all bulk fields in FP64."""
+    import torch
+    stream = torch.cuda.Stream(device=dev)
+    pb = W.fujiwhara_pair(SEEDS[0])
+    with torch.cuda.stream(stream):
+        w0 = torch.from_numpy(W.initial_field(pb)).to(dev)
+        s = m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_FP64, pb.m, pb.dt, w0,
+                    stream=stream)
+    s.step(3, stream=stream)
+    stream.synchronize()
+    e0 = s.scalars()["evals"]
+    t0 = time.perf_counter()
+    s.step(steps, stream=stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    e1 = s.scalars()["evals"]
+    s.close()
+    return {"value": (e1 - e0) / wall, "ms_per_step": wall / steps * 1e3, "steps": steps,
+            "solves_per_s_at_2000_steps": 1.0 / (wall / steps * 2000)}
 
 
 def cpu_baseline(steps: int) -> dict:
@@ -81,13 +122,14 @@ def cpu_baseline(steps: int) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--batch", type=int, default=len(SEEDS))
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", default="jvp")
+    ap.add_argument("--no-fp64-compare", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -148,6 +190,16 @@ def main() -> int:
     nbytes = kernel_bytes(args.kernel, N, int(sum(nas) / len(nas)), frac_t, n, esz)
     achieved = nbytes / (k_ms * 1e-3) / 1e9
 
+    # plain copy of known size: the byte-counter scale of profiled runs
+    cal_a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    cal_b = torch.empty_like(cal_a)
+    cal_b.copy_(cal_a)
+    torch.cuda.synchronize()
+    del cal_a, cal_b
+    compare = None
+    if not args.no_fp64_compare and prec == m.MRA_MIXED:
+        compare = fp64_per_solve(m, W, dev, max(10, args.steps // 10))
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -166,10 +218,16 @@ def main() -> int:
                    "batch": n, "finest_points": N * N, "mean_active_points": sum(nas) / len(nas),
                    "precision": args.prec, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "kernel": args.kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.kernel),
                      "avg_launch_ms": k_ms, "algorithmic_bytes_per_launch": nbytes,
                      "active_tile_fraction": frac_t},
     }
+    step_s = wall / args.steps
+    out["ensemble"] = {"solves_per_s_at_2000_steps": n / (step_s * 2000),
+                       "note": "batch solves/s if each solve ran the configuration's 2000 steps"}
+    if compare is not None:
+        out["fp64_per_solve_gpu"] = compare
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     for s in solves:

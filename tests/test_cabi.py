@@ -1,0 +1,78 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/mra.h declares, and its host-side argument checks and size queries
+behave as documented (no kernel is launched by any call here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mra.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\([^;{]*\)\s*;", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1604_08159_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libmra.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("mra_transform", "collocation_rhs", "krylov_step", "solve_batch", "mra_solve_init",
+              "mra_solve_read", "mra_solve_footprint", "mra_status_str"):
+        assert n in names, n
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1604_08159_amd import _lib
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in mra.h but not exported"
+        assert n in _lib.EXPORTS, f"{n} has no binding"
+
+
+def test_status_strings_and_version(lib):
+    assert lib.mra_abi_version() == 1
+    assert lib.mra_status_str(0).decode() == "ok"
+    assert "argument" in lib.mra_status_str(1).decode()
+    assert lib.mra_status_str(99).decode() == "unknown status"
+
+
+def _grid(J, p, eps=1e-3, j0=None):
+    from paper_1604_08159_amd._lib import GridDesc
+    import math
+    return GridDesc(J, (2 if p == 2 else 3) if j0 is None else j0, p, 1, 2 * math.pi, eps)
+
+
+def test_size_queries_and_argument_checks(lib):
+    n = C.c_size_t()
+    assert lib.mra_solve_footprint(C.byref(_grid(9, 2)), 2, 20, C.byref(n)) == 0
+    fp_mixed = n.value
+    assert lib.mra_solve_footprint(C.byref(_grid(9, 2)), 0, 20, C.byref(n)) == 0
+    assert n.value > fp_mixed                                   # FP64 fields are larger
+    # the arena holds at least the Krylov basis (m+1) x N^2 FP64
+    assert fp_mixed > 21 * 512 * 512 * 8
+    assert lib.mra_solve_footprint(C.byref(_grid(12, 2)), 2, 20, C.byref(n)) == 2     # J too large
+    assert lib.mra_solve_footprint(C.byref(_grid(2, 2)), 2, 20, C.byref(n)) == 2      # J <= j0
+    assert lib.mra_solve_footprint(C.byref(_grid(9, 4)), 2, 20, C.byref(n)) == 2      # p unsupported
+    assert lib.mra_solve_footprint(C.byref(_grid(9, 2, j0=3)), 2, 20, C.byref(n)) == 2  # wrong j0
+    assert lib.mra_solve_footprint(C.byref(_grid(9, 2)), 2, 48, C.byref(n)) == 2     # m too large
+    assert lib.mra_solve_footprint(C.byref(_grid(9, 2, eps=-1.0)), 2, 20, C.byref(n)) == 1
+    assert lib.mra_transform_ws_bytes(C.byref(_grid(9, 3)), 0, C.byref(n)) == 0 and n.value > 0
+    assert lib.mra_rhs_ws_bytes(C.byref(_grid(9, 3)), 1, C.byref(n)) == 0 and n.value > 0
+    # null pointers are rejected before anything is launched
+    assert lib.mra_transform(C.byref(_grid(5, 2)), 0, 1, None, None, None, None, None, None, None, 0, None) == 1
+    assert lib.krylov_step(None, 1, None) == 1
+    assert lib.solve_batch(None, 0, None, None) == 1
+    assert lib.mra_solve_destroy(None) == 1
