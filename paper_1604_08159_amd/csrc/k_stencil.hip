@@ -59,11 +59,16 @@ __device__ inline void load_region(T* dst, const T* __restrict__ src, int x0, in
   }
 }
 
-__device__ inline int tile_of_block(int bid, int ntiles) {
-  // XCD-aware: consecutive blocks are dealt round-robin to the 8 XCDs; give
-  // each XCD a contiguous run of tiles so that shared halos stay in its L2.
-  if ((ntiles & 7) != 0) return bid;
-  return (bid & 7) * (ntiles >> 3) + (bid >> 3);
+// XCD-aware tile order.  Block L of a batch of n solves runs on XCD L % 8
+// and serves solve L % n as its block L / n, so one solve's blocks are spread
+// over nx = 8 / gcd(n, 8) XCDs, its block bx landing on XCD group bx % nx.
+// Give each of those XCDs a contiguous run of tiles so that shared halos stay
+// in its L2 (nx = 1: plain order).
+__device__ inline int tile_of_block(int bid, int ntiles, int nbatch) {
+  int g = nbatch & 7;
+  const int nx = g == 0 ? 1 : (g == 4 ? 2 : (g == 2 || g == 6 ? 4 : 8));
+  if (nx == 1 || ntiles % nx != 0) return bid;
+  return (bid % nx) * (ntiles / nx) + bid / nx;
 }
 
 template <int P> struct Geo {
@@ -91,7 +96,7 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   extern __shared__ unsigned char smem[];
   const SolveDev& s = MRA_SOLVE(b);
   const int N = s.N, ntx = s.ntx;
-  const int tile = tile_of_block(MRA_BX(b), ntx * ntx);
+  const int tile = tile_of_block(MRA_BX(b), ntx * ntx, b.n);
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   constexpr int Wp = TS + 2 * G::HP, Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
   T* psi = reinterpret_cast<T*>(smem);
@@ -177,6 +182,9 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   }
 }
 
+// Jacobian-vector product on one tile.  Every global load is issued in one
+// phase: psi_v, v~ and nu_e regions into LDS, u, v, w~ at this thread's flux
+// points and the ranks of its output nodes into registers.
 template <int P, typename T, int TS>
 __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   using G = Geo<P>;
@@ -184,48 +192,72 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
   const int N = s.N, ntx = s.ntx, nm = N - 1;
-  const int tile = tile_of_block(MRA_BX(b), ntx * ntx);
+  const int tile = tile_of_block(MRA_BX(b), ntx * ntx, b.n);
   if (s.tile_count[tile] == 0) return;
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   constexpr int Wpv = TS + 4 * G::R1, Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
+  constexpr int NQ = (Ww * Ww + 255) / 256;       // flux points per thread
+  constexpr int NO = (TS * TS + 255) / 256;       // output nodes per thread
   T* pv = reinterpret_cast<T*>(smem);
   T* vt = pv + Wpv * Wpv;
   T* fa = vt + Ww * Ww;
   T* fb = fa + Ww * Ww;
   T* nu = fb + Ww * Ww;
+  const T* gu = reinterpret_cast<const T*>(s.u);
+  const T* gv = reinterpret_cast<const T*>(s.v);
+  const T* gw = reinterpret_cast<const T*>(s.wt);
+  T ur[NQ], vr[NQ], wr[NQ];
+  int kr[NO];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    if (q < Ww * Ww) {
+      const int r = q / Ww, c = q - r * Ww;
+      const int f = ((y0 - G::R1 + r) & nm) * N + ((x0 - G::R1 + c) & nm);
+      ur[i] = gu[f];
+      vr[i] = gv[f];
+      wr[i] = gw[f];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NO; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    kr[i] = q < TS * TS ? s.rank[(y0 + q / TS) * N + x0 + (q % TS)] : -1;
+  }
   load_region<Wpv>(pv, reinterpret_cast<const T*>(s.psiv), x0 - 2 * G::R1, y0 - 2 * G::R1, N);
   load_region<Ww>(vt, reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, N);
   load_region<Wn>(nu, reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, N);
   __syncthreads();
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
-  const T* gu = reinterpret_cast<const T*>(s.u);
-  const T* gv = reinterpret_cast<const T*>(s.v);
-  const T* gw = reinterpret_cast<const T*>(s.wt);
   // fluxes of the linearised advection on the Ww region
-  for (int q = threadIdx.x; q < Ww * Ww; q += blockDim.x) {
-    const int r = q / Ww, c = q - r * Ww;
-    const int f = ((y0 - G::R1 + r) & nm) * N + ((x0 - G::R1 + c) & nm);
-    const T uv = ih * dy1<P, T>(pv, Wpv, r + G::R1, c + G::R1);
-    const T vv = -ih * dx1<P, T>(pv, Wpv, r + G::R1, c + G::R1);
-    const T wv = gw[f], vtv = vt[q];
-    fa[q] = uv * wv + gu[f] * vtv;
-    fb[q] = vv * wv + gv[f] * vtv;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    if (q < Ww * Ww) {
+      const int r = q / Ww, c = q - r * Ww;
+      const T uv = ih * dy1<P, T>(pv, Wpv, r + G::R1, c + G::R1);
+      const T vv = -ih * dx1<P, T>(pv, Wpv, r + G::R1, c + G::R1);
+      const T vtv = vt[q];
+      fa[q] = uv * wr[i] + ur[i] * vtv;
+      fb[q] = vv * wr[i] + vr[i] * vtv;
+    }
   }
   __syncthreads();
   T* cn = pv;   // psi_v is dead: nu v~ with pitch Wn
-  const int on = G::R1 - P;
+  constexpr int on = G::R1 - P;
   for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
     const int r = q / Wn, c = q - r * Wn;
     cn[q] = nu[q] * vt[(r + on) * Ww + c + on];
   }
   __syncthreads();
-  const int* rank = s.rank;
   const T mu = T(s.mu);
   double* out = s.out_jvp;
-  for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
-    const int r = q / TS, c = q - r * TS;
-    const int k = rank[(y0 + r) * N + x0 + c];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    const int k = kr[i];
     if (k < 0) continue;
+    const int r = q / TS, c = q - r * TS;
     const int ra = r + G::R1, ca = c + G::R1, rn = r + P, cn_ = c + P;
     const T adv = -ih * (dx1<P, T>(fa, Ww, ra, ca) + dy1<P, T>(fb, Ww, ra, ca));
     const T vv = vt[ra * Ww + ca];

@@ -164,6 +164,7 @@ __device__ inline T predict_lattice(const T* prev, int pn, int dx, int dy, int s
 // partial sums (block 0 records it) and the tile that owns a node writes its
 // entry of V_j.
 constexpr int kFineTile = 32;
+constexpr int kLatMax = kFineTile * kFineTile;   // lattice nodes of one level of a tile
 
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int src, int j) {
@@ -250,11 +251,37 @@ __global__ void k_inverse_coarse(Batch b, int target) {
   for (int i = threadIdx.x; i < n0 * n0; i += blockDim.x) f[packed_to_fine(i, s.J, s.j0, nullptr)] = packed[i];
 }
 
+// Host check of k_prolong_tiles' assumptions for a grid, over every tile
+// offset: each level's lattice count is the same for every offset (so the
+// x and y lattices of a tile have equal size) and all lattices fit in LDS.
+static int lattice_count(int J, int P, int B, int x0, int l) {
+  int E = 0;
+  for (int q = J; q > l; --q) E += (2 * P - 1) << (J - q);
+  const int sh = J - l;
+  const int lo = x0 - E, hi = x0 + B - 1 + E;
+  const int oo = (lo >> sh) << sh;
+  return ((hi - oo) >> sh) + 1;
+}
+
+static bool lattice_fits(int J, int P) {
+  const int N = 1 << J, j0 = P == 2 ? 2 : 3;
+  const int B = N < kFineTile ? N : kFineTile;
+  for (int x0 = 0; x0 < N; x0 += B) {
+    for (int l = j0; l <= J; ++l) {
+      const int n = lattice_count(J, P, B, x0, l);
+      if (n != lattice_count(J, P, B, 0, l)) return false;
+      if (n * n > kLatMax) return false;
+    }
+  }
+  return true;
+}
+
 template <typename T>
 static hipError_t prolong_t(const Batch& b, const LaunchCfg& c, int target, int src, int j, hipStream_t st) {
   const int N = 1 << c.J;
   const int B = N < kFineTile ? N : kFineTile;
   const int nt = (N / B) * (N / B);
+  if (!lattice_fits(c.J, c.p)) return hipErrorInvalidValue;
   if (c.p == 2) hipLaunchKernelGGL((k_prolong_tiles<2, T>), dim3(nt * b.n), dim3(256), 0, st, b, target, src, j);
   else hipLaunchKernelGGL((k_prolong_tiles<3, T>), dim3(nt * b.n), dim3(256), 0, st, b, target, src, j);
   return hipGetLastError();

@@ -224,6 +224,7 @@ struct GraphEntry {
   hipGraphExec_t x = nullptr;
 };
 std::map<std::pair<std::vector<const void*>, hipStream_t>, GraphEntry> g_batch_graphs;
+constexpr size_t kMaxCachedGraphs = 32;
 
 void drop_batch_graphs() {
   for (auto& kv : g_batch_graphs) {
@@ -504,6 +505,11 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_batch_graphs.find({key, st});
         if (it == g_batch_graphs.end()) {
+          // bounded cache: a serving loop changes the batch composition often
+          if (g_batch_graphs.size() >= kMaxCachedGraphs) {
+            MRA_TRY(hipStreamSynchronize(st));
+            drop_batch_graphs();
+          }
           GraphEntry ge;
           MRA_TRY(capture(b, c, st, &ge.g, &ge.x));
           it = g_batch_graphs.emplace(std::make_pair(key, st), ge).first;
