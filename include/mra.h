@@ -143,7 +143,8 @@ int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir,
  * the active nodes (Sections 2.3 and 2.5; vorticity-streamfunction form):
  *
  *   w~ = Pi(omega), psi = -L^{-1} w~ (k = 0 mode dropped), u = D1_y psi,
- *   v = -D1_x psi, nu_e from eq. (5),
+ *   v = -D1_x psi (L and D1 are circulant: all three are applied as Fourier
+ *   multipliers of w~), nu_e from eq. (5),
  *   F = -[D1_x(u w~) + D1_y(v w~)] + 1/2[L(nu_e w~) + nu_e L w~ - w~ L nu_e]
  *       - mu w~,
  *   J v (nu_e frozen at omega): with v~ = Pi(v), psi_v = -L^{-1} v~,
@@ -152,7 +153,8 @@ int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir,
  *
  * mask / index_fine / n_active: the active set (as from mra_transform).
  * omega_active, v_active (NULL -> F), out_active: double [n_active].
- * psi_dense_or_null: if non-NULL receives psi [N][N] (element type of prec).
+ * vel_dense_or_null: if non-NULL receives the velocity of w~ as [2][N][N]
+ *   (u then v; element type of prec), caller-owned.
  * prec: element type of the dense fields (FP64, or FP32 for FP32/MIXED).
  * ------------------------------------------------------------------------ */
 int32_t mra_rhs_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes);
@@ -160,7 +162,7 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
                         const uint8_t* mask, const int32_t* index_fine,
                         const int64_t* n_active, const double* omega_active,
                         const double* v_active, double* out_active,
-                        void* psi_dense_or_null, void* ws, size_t ws_bytes, void* stream);
+                        void* vel_dense_or_null, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Solves.  A solve keeps its whole state in a caller-owned device arena of

@@ -108,12 +108,12 @@ def rhs_ws_bytes(g: GridDesc, prec: int) -> int:
 
 def collocation_rhs(g: GridDesc, f: FlowDesc, prec: int, mask: torch.Tensor, index_fine: torch.Tensor,
                     n_active: torch.Tensor, omega_active: torch.Tensor, v_active: Optional[torch.Tensor],
-                    out_active: torch.Tensor, psi: Optional[torch.Tensor] = None,
+                    out_active: torch.Tensor, velocity: Optional[torch.Tensor] = None,
                     ws: Optional[torch.Tensor] = None, stream=None) -> None:
     if ws is None:
         ws = _alloc(rhs_ws_bytes(g, prec), omega_active.device)
     st = lib().collocation_rhs(C.byref(g), C.byref(f), prec, _ptr(mask), _ptr(index_fine), _ptr(n_active),
-                               _ptr(omega_active), _ptr(v_active), _ptr(out_active), _ptr(psi), _ptr(ws),
+                               _ptr(omega_active), _ptr(v_active), _ptr(out_active), _ptr(velocity), _ptr(ws),
                                ws.numel(), _stream(stream))
     _check("collocation_rhs", st)
 

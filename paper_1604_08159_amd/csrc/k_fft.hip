@@ -1,16 +1,21 @@
-// Streamfunction Poisson solve on the periodic grid: psi_hat = -omega_hat /
-// lambda(k) with lambda the exact symbol of the discrete Laplacian
-// L = D2_x + D2_y ((2p+1)-point Lagrange second differences), the k = 0 mode
-// set to zero.  The paper states only that the streamfunction satisfies a
-// Poisson equation (Section 4); the FFT inverse of the discrete L is the
-// solver chosen here.
+// Velocity from vorticity on the periodic grid: psi_hat = -omega_hat /
+// lambda(k), lambda the exact symbol of the discrete Laplacian L = D2_x + D2_y
+// ((2p+1)-point Lagrange second differences), the k = 0 mode set to zero; then
+// u = D1_y psi and v = -D1_x psi with the collocation first derivative of
+// Section 2.5.  D1 and L are circulant on the periodic grid, so both are
+// diagonal in Fourier space: u_hat = i s1(ky) psi_hat, v_hat = -i s1(kx)
+// psi_hat with s1(theta) = (2/h) sum_n a_n sin(n theta).  Applying them as
+// multipliers gives the same discrete operator as differencing psi, with the
+// rounding of the transforms relative to |u| instead of amplified by 1/h.
+// The paper states only that the streamfunction satisfies a Poisson equation
+// (Section 4); the FFT inverse of the discrete L is the solver chosen here.
 //
 // Three passes over HBM, each a batch of 1-D FFTs staged in LDS:
 //   A  rows: real-to-complex FFT of length N (complex FFT of length N/2 on
 //      the packed even/odd samples), written transposed as spec[kx][y];
 //   B  columns (contiguous rows of spec): forward FFT, multiply by
-//      -1/lambda / N^2, inverse FFT;
-//   C  rows: complex-to-real inverse, read transposed.
+//      -1/lambda / N^2, form the u and v spectra, two inverse FFTs;
+//   C  rows: complex-to-real inverse of both, read transposed.
 // Twiddles come from one table of exp(-2 pi i k / 2048) set up once.
 #include "mra_internal.hpp"
 
@@ -159,9 +164,12 @@ __device__ inline const T* poisson_src(const SolveDev& s, int src) {
   if (src == 1) return reinterpret_cast<const T*>(s.vt);
   return reinterpret_cast<const T*>(s.dense64);
 }
+// velocity outputs: src 0 -> (u, v), src 1 -> (u_v, v_v), src 2 -> FP64 pair
 template <typename T>
-__device__ inline T* poisson_dst(const SolveDev& s, int src) {
-  return reinterpret_cast<T*>(src == 1 ? s.psiv : s.psi);
+__device__ inline T* poisson_dst(const SolveDev& s, int src, int comp) {
+  if (src == 0) return reinterpret_cast<T*>(comp == 0 ? s.u : s.v);
+  if (src == 1) return reinterpret_cast<T*>(comp == 0 ? s.uv : s.vv);
+  return reinterpret_cast<T*>(s.vel64 + (size_t)comp * s.N * s.N);
 }
 
 // pass A: rows -> spec[kx][y], R rows per block (R * N/2 <= 2048)
@@ -192,51 +200,79 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src, 
   }
 }
 
-// sigma_2(theta_k) = c0 + 2 sum_n c_n cos(2 pi n k / N), FP64
+// Symbols at theta = 2 pi k / N, FP64: sigma_2 = c0 + 2 sum_n c_n cos(n theta)
+// (h^2 times the eigenvalue of D2) and sigma_1 = 2 sum_n a_n sin(n theta)
+// (h / i times the eigenvalue of D1).  Table entry m: exp(-2 pi i m / 2048).
 template <int P>
-__device__ inline double d2_sigma(int k, int N) {
+__device__ inline void symbols(int k, int N, double* s1, double* s2) {
   const int tws = kTwN / N;
+  double c[4], sn[5];
+#pragma unroll
+  for (int n = 1; n <= 2 * P - 2; ++n) {
+    const double2 t = g_tw64[((n * k) & (N - 1)) * tws];
+    if (n <= P) c[n] = t.x;
+    sn[n] = -t.y;
+  }
   if constexpr (P == 2) {
-    return -2.5 + 2.0 * ((4.0 / 3.0) * g_tw64[((k) & (N - 1)) * tws].x +
-                         (-1.0 / 12.0) * g_tw64[((2 * k) & (N - 1)) * tws].x);
+    *s2 = -2.5 + 2.0 * ((4.0 / 3.0) * c[1] + (-1.0 / 12.0) * c[2]);
+    *s1 = 2.0 * ((2.0 / 3.0) * sn[1] + (-1.0 / 12.0) * sn[2]);
   } else {
-    return -49.0 / 18.0 + 2.0 * (1.5 * g_tw64[((k) & (N - 1)) * tws].x +
-                                 (-0.15) * g_tw64[((2 * k) & (N - 1)) * tws].x +
-                                 (1.0 / 90.0) * g_tw64[((3 * k) & (N - 1)) * tws].x);
+    *s2 = -49.0 / 18.0 + 2.0 * (1.5 * c[1] + (-0.15) * c[2] + (1.0 / 90.0) * c[3]);
+    *s1 = 2.0 * ((272.0 / 365.0) * sn[1] + (-53.0 / 365.0) * sn[2] + (16.0 / 1095.0) * sn[3] +
+                 (1.0 / 2920.0) * sn[4]);
   }
 }
 
-// pass B: C spectrum rows (fixed kx) per block (C * N <= 2048)
+// pass B: C spectrum rows (fixed kx) per block (C * N <= 2048).  LDS: A holds
+// psi_hat, B the u (then the v) spectrum; 2 * 2048 complex values at most.
 template <int P, typename T>
 __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b, int C) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem[];
-  V* buf = reinterpret_cast<V*>(smem);
+  V* A = reinterpret_cast<V*>(smem);
+  V* Bv = A + C * (1 << MRA_SOLVE(b).J);
   const SolveDev& s = MRA_SOLVE(b);
   const int J = s.J, N = s.N, M = N >> 1;
   const int k0 = MRA_BX(b) * C;
   const int nr = (M + 1 - k0) < C ? (M + 1 - k0) : C;
-  V* spec = reinterpret_cast<V*>(s.spec);
-  double* sig = reinterpret_cast<double*>(buf + C * N);    // sigma_2 of every ky
-  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) buf[q] = spec[(size_t)k0 * N + q];
-  for (int k = threadIdx.x; k < N; k += blockDim.x) sig[k] = d2_sigma<P>(k, N);
+  V* specU = reinterpret_cast<V*>(s.spec);
+  V* specV = reinterpret_cast<V*>(s.spec2);
+  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) A[q] = specU[(size_t)k0 * N + q];
   __syncthreads();
-  fft_block<-1, T>(buf, N, nr);
+  fft_block<-1, T>(A, N, nr);
   const double h2n = s.h * s.h / ((double)N * (double)N);
+  const double ih = 1.0 / s.h;
   for (int q = threadIdx.x; q < nr * N; q += blockDim.x) {
     const int r = q >> J, ky = q & (N - 1);
     const int kx = k0 + r;
-    const double den = sig[kx] + sig[ky];
-    const T g = (kx == 0 && ky == 0) ? T(0) : (T)(-h2n / den);
-    buf[q].x *= g;
-    buf[q].y *= g;
+    double s1x, s2x, s1y, s2y;
+    symbols<P>(kx, N, &s1x, &s2x);
+    symbols<P>(ky, N, &s1y, &s2y);
+    const T g = (kx == 0 && ky == 0) ? T(0) : (T)(-h2n / (s2x + s2y));
+    const V z = A[q];
+    const T sy = (T)(s1y * ih);
+    A[q] = V{z.x * g, z.y * g};
+    Bv[q] = V{-sy * (z.y * g), sy * (z.x * g)};          // i s1(ky) psi_hat
   }
   __syncthreads();
-  fft_block<1, T>(buf, N, nr);
-  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) spec[(size_t)k0 * N + q] = buf[q];
+  fft_block<1, T>(Bv, N, nr);
+  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) specU[(size_t)k0 * N + q] = Bv[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) {
+    const int r = q >> J;
+    double s1x, s2x;
+    symbols<P>(k0 + r, N, &s1x, &s2x);
+    const T sx = (T)(s1x * ih);
+    const V z = A[q];
+    Bv[q] = V{sx * z.y, -sx * z.x};                       // -i s1(kx) psi_hat
+  }
+  __syncthreads();
+  fft_block<1, T>(Bv, N, nr);
+  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) specV[(size_t)k0 * N + q] = Bv[q];
 }
 
-// pass C: spec[kx][y] -> real rows, R rows per block (R * N/2 <= 2048)
+// pass C: spec[kx][y] -> real rows, R rows per block (R * N/2 <= 2048), for
+// the u spectrum and then the v spectrum.
 template <typename T>
 __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src, int R) {
   using V = typename C2<T>::t;
@@ -245,22 +281,25 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src, 
   const SolveDev& s = MRA_SOLVE(b);
   const int N = s.N, M = N >> 1;
   const int y0 = MRA_BX(b) * R;
-  const V* spec = reinterpret_cast<const V*>(s.spec);
   const int twN = kTwN / N;
-  for (int q = threadIdx.x; q < M * R; q += blockDim.x) {
-    const int k = q / R, r = q - k * R;
-    const V xk = spec[(size_t)k * N + y0 + r];
-    const V xc = cconj(spec[(size_t)(M - k) * N + y0 + r]);
-    const V e = cmulc(csub(xk, xc), C2<T>::tw(k * twN));
-    V z;
-    z.x = xk.x + xc.x - e.y;
-    z.y = xk.y + xc.y + e.x;
-    buf[r * M + k] = z;
+  for (int comp = 0; comp < 2; ++comp) {
+    const V* spec = reinterpret_cast<const V*>(comp == 0 ? s.spec : s.spec2);
+    for (int q = threadIdx.x; q < M * R; q += blockDim.x) {
+      const int k = q / R, r = q - k * R;
+      const V xk = spec[(size_t)k * N + y0 + r];
+      const V xc = cconj(spec[(size_t)(M - k) * N + y0 + r]);
+      const V e = cmulc(csub(xk, xc), C2<T>::tw(k * twN));
+      V z;
+      z.x = xk.x + xc.x - e.y;
+      z.y = xk.y + xc.y + e.x;
+      buf[r * M + k] = z;
+    }
+    __syncthreads();
+    fft_block<1, T>(buf, M, R);
+    V* out = reinterpret_cast<V*>(poisson_dst<T>(s, src, comp));
+    for (int q = threadIdx.x; q < R * M; q += blockDim.x) out[(size_t)y0 * M + q] = buf[q];
+    __syncthreads();
   }
-  __syncthreads();
-  fft_block<1, T>(buf, M, R);
-  V* out = reinterpret_cast<V*>(poisson_dst<T>(s, src));
-  for (int q = threadIdx.x; q < R * M; q += blockDim.x) out[(size_t)y0 * M + q] = buf[q];
 }
 
 static int rows_per_block(int N) {
@@ -283,7 +322,7 @@ static hipError_t poisson_t(const Batch& b, const LaunchCfg& c, int src, int pas
                        src, R);
   if (pass < 0 || pass == 1) {
     dim3 g(((M + 1 + C - 1) / C) * b.n);
-    const size_t lds = (size_t)C * N * sizeof(V) + (size_t)N * sizeof(double);
+    const size_t lds = 2 * (size_t)C * N * sizeof(V);
     if (c.p == 2) hipLaunchKernelGGL((k_fft_cols<2, T>), g, dim3(kFftThreads), lds, st, b, C);
     else hipLaunchKernelGGL((k_fft_cols<3, T>), g, dim3(kFftThreads), lds, st, b, C);
   }

@@ -7,14 +7,15 @@
 // Second derivatives use the (2p+1)-point Lagrange rule
 //   p = 2: (-5/2; 4/3, -1/12)/h^2;  p = 3: (-49/18; 3/2, -3/20, 1/90)/h^2.
 // Section 2.3, eq. (5): Smagorinsky eddy viscosity nu_e = nu0 + (Cs h)^2 |S|,
-// |S| = sqrt(2 S_ij S_ij) from the resolved strain of u = D1_y psi,
-// v = -D1_x psi.
+// |S| = sqrt(2 S_ij S_ij) from the resolved strain of the velocity
+// u = D1_y psi, v = -D1_x psi (computed by the Fourier pass of the Poisson
+// solve and read here).
 // Residual (flux form, symmetric conservative diffusion):
 //   F = -[D1_x(u w) + D1_y(v w)] + 1/2 [L(nu w) + nu L w - w L nu] - mu w,
 // evaluated only at the active nodes of a tile (written to their position in
 // the active list through the dense rank map); tiles without an active node
-// skip the residual.  The residual kernel also stores u, v, nu_e on the whole
-// grid: the Jacobian-vector products of the step reuse them with nu_e frozen.
+// skip the residual.  The residual kernel also stores nu_e on the whole grid:
+// the Jacobian-vector products of the step reuse it (frozen) with u and v.
 #include "mra_internal.hpp"
 
 namespace mra {
@@ -73,21 +74,20 @@ __device__ inline int tile_of_block(int bid, int ntiles, int nbatch) {
 
 template <int P> struct Geo {
   static constexpr int R1 = 2 * P - 2;   // D1 reach
-  static constexpr int HP = 5 * P - 4;   // psi halo for the residual
   static constexpr int HU = 3 * P - 2;   // u, v halo for the residual
 };
 
 template <int P, typename T>
 __host__ __device__ inline size_t rhs_lds_elems(int TS) {
   using G = Geo<P>;
-  const size_t Wp = TS + 2 * G::HP, Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
-  return Wp * Wp + 2 * Wu * Wu + Wn * Wn + Ww * Ww;
+  const size_t Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
+  return 2 * Wu * Wu + 2 * Wn * Wn + Ww * Ww;
 }
 template <int P, typename T>
 __host__ __device__ inline size_t jvp_lds_elems(int TS) {
   using G = Geo<P>;
-  const size_t Wpv = TS + 4 * G::R1, Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
-  return Wpv * Wpv + 3 * Ww * Ww + Wn * Wn;
+  const size_t Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
+  return 3 * Ww * Ww + 2 * Wn * Wn;
 }
 
 template <int P, typename T, int TS>
@@ -98,25 +98,17 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   const int N = s.N, ntx = s.ntx;
   const int tile = tile_of_block(MRA_BX(b), ntx * ntx, b.n);
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
-  constexpr int Wp = TS + 2 * G::HP, Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
-  T* psi = reinterpret_cast<T*>(smem);
-  T* uu = psi + Wp * Wp;
+  constexpr int Wu = TS + 2 * G::HU, Wn = TS + 2 * P, Ww = TS + 2 * G::R1;
+  T* uu = reinterpret_cast<T*>(smem);
   T* vv = uu + Wu * Wu;
   T* nu = vv + Wu * Wu;
   T* ww = nu + Wn * Wn;
-  const T* gpsi = reinterpret_cast<const T*>(s.psi);
-  const T* gw = reinterpret_cast<const T*>(s.wt);
-  load_region<Wp>(psi, gpsi, x0 - G::HP, y0 - G::HP, N);
-  load_region<Ww>(ww, gw, x0 - G::R1, y0 - G::R1, N);
+  T* cn = ww + Ww * Ww;
+  load_region<Wu>(uu, reinterpret_cast<const T*>(s.u), x0 - G::HU, y0 - G::HU, N);
+  load_region<Wu>(vv, reinterpret_cast<const T*>(s.v), x0 - G::HU, y0 - G::HU, N);
+  load_region<Ww>(ww, reinterpret_cast<const T*>(s.wt), x0 - G::R1, y0 - G::R1, N);
   __syncthreads();
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
-  // u = D1_y psi, v = -D1_x psi on the Wu region
-  for (int q = threadIdx.x; q < Wu * Wu; q += blockDim.x) {
-    const int r = q / Wu, c = q - r * Wu;
-    uu[q] = ih * dy1<P, T>(psi, Wp, r + G::R1, c + G::R1);
-    vv[q] = -ih * dx1<P, T>(psi, Wp, r + G::R1, c + G::R1);
-  }
-  __syncthreads();
   // nu_e on the Wn region
   const T cs2 = T((s.cs * s.h) * (s.cs * s.h));
   const T nu0 = T(s.nu0);
@@ -136,16 +128,11 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
     nu[q] = val;
   }
   __syncthreads();
-  // store the base fields of the tile for the Jacobian-vector products
-  T* gu = reinterpret_cast<T*>(s.u);
-  T* gv = reinterpret_cast<T*>(s.v);
+  // store nu_e of the tile for the Jacobian-vector products
   T* gn = reinterpret_cast<T*>(s.nu);
   for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
     const int r = q / TS, c = q - r * TS;
-    const int f = (y0 + r) * N + x0 + c;
-    gu[f] = uu[(r + G::HU) * Wu + c + G::HU];
-    gv[f] = vv[(r + G::HU) * Wu + c + G::HU];
-    gn[f] = nu[(r + P) * Wn + c + P];
+    gn[(y0 + r) * N + x0 + c] = nu[(r + P) * Wn + c + P];
   }
   if (s.tile_count[tile] == 0) return;
   __syncthreads();
@@ -157,8 +144,7 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
     uu[(r + ou) * Wu + c + ou] *= wv;
     vv[(r + ou) * Wu + c + ou] *= wv;
   }
-  T* cn = psi;   // psi is dead: nu w with pitch Wn
-  const int on = G::R1 - P;
+  const int on = G::R1 - P;   // nu w with pitch Wn
   for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
     const int r = q / Wn, c = q - r * Wn;
     cn[q] = nu[q] * ww[(r + on) * Ww + c + on];
@@ -183,8 +169,8 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
 }
 
 // Jacobian-vector product on one tile.  Every global load is issued in one
-// phase: psi_v, v~ and nu_e regions into LDS, u, v, w~ at this thread's flux
-// points and the ranks of its output nodes into registers.
+// phase: v~ and nu_e regions into LDS; u, v, u_v, v_v, w~ at this thread's
+// flux points and the ranks of its output nodes into registers.
 template <int P, typename T, int TS>
 __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   using G = Geo<P>;
@@ -195,18 +181,20 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   const int tile = tile_of_block(MRA_BX(b), ntx * ntx, b.n);
   if (s.tile_count[tile] == 0) return;
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
-  constexpr int Wpv = TS + 4 * G::R1, Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
+  constexpr int Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
   constexpr int NQ = (Ww * Ww + 255) / 256;       // flux points per thread
   constexpr int NO = (TS * TS + 255) / 256;       // output nodes per thread
-  T* pv = reinterpret_cast<T*>(smem);
-  T* vt = pv + Wpv * Wpv;
+  T* vt = reinterpret_cast<T*>(smem);
   T* fa = vt + Ww * Ww;
   T* fb = fa + Ww * Ww;
   T* nu = fb + Ww * Ww;
+  T* cn = nu + Wn * Wn;
   const T* gu = reinterpret_cast<const T*>(s.u);
   const T* gv = reinterpret_cast<const T*>(s.v);
+  const T* guv = reinterpret_cast<const T*>(s.uv);
+  const T* gvv = reinterpret_cast<const T*>(s.vv);
   const T* gw = reinterpret_cast<const T*>(s.wt);
-  T ur[NQ], vr[NQ], wr[NQ];
+  T ur[NQ], vr[NQ], wr[NQ], uvr[NQ], vvr[NQ];
   int kr[NO];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
@@ -217,6 +205,8 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
       ur[i] = gu[f];
       vr[i] = gv[f];
       wr[i] = gw[f];
+      uvr[i] = guv[f];
+      vvr[i] = gvv[f];
     }
   }
 #pragma unroll
@@ -224,26 +214,20 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
     const int q = threadIdx.x + 256 * i;
     kr[i] = q < TS * TS ? s.rank[(y0 + q / TS) * N + x0 + (q % TS)] : -1;
   }
-  load_region<Wpv>(pv, reinterpret_cast<const T*>(s.psiv), x0 - 2 * G::R1, y0 - 2 * G::R1, N);
   load_region<Ww>(vt, reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, N);
   load_region<Wn>(nu, reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, N);
   __syncthreads();
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
-  // fluxes of the linearised advection on the Ww region
+  // fluxes of the linearised advection on the Ww region, nu v~ on the Wn region
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int q = threadIdx.x + 256 * i;
     if (q < Ww * Ww) {
-      const int r = q / Ww, c = q - r * Ww;
-      const T uv = ih * dy1<P, T>(pv, Wpv, r + G::R1, c + G::R1);
-      const T vv = -ih * dx1<P, T>(pv, Wpv, r + G::R1, c + G::R1);
       const T vtv = vt[q];
-      fa[q] = uv * wr[i] + ur[i] * vtv;
-      fb[q] = vv * wr[i] + vr[i] * vtv;
+      fa[q] = uvr[i] * wr[i] + ur[i] * vtv;
+      fb[q] = vvr[i] * wr[i] + vr[i] * vtv;
     }
   }
-  __syncthreads();
-  T* cn = pv;   // psi_v is dead: nu v~ with pitch Wn
   constexpr int on = G::R1 - P;
   for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
     const int r = q / Wn, c = q - r * Wn;
@@ -299,27 +283,27 @@ hipError_t launch_rhs(const Batch& b, const LaunchCfg& c, hipStream_t st) { retu
 hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st) { return rhs_dispatch(b, c, true, st); }
 
 // ------------------------------------------------------------- diagnostics
-// One block per row y of the FP64 field dense64 and its FP64 streamfunction
-// psi: row sums of w, u^2 + v^2, w^2, |grad w|^2 and the row max of |w|
+// One block per row y of the FP64 field dense64 and its FP64 velocity
+// vel64: row sums of w, u^2 + v^2, w^2, |grad w|^2 and the row max of |w|
 // (Sections 3.3, 3.4).  The host adds the rows in order.
 template <int P>
 __global__ void __launch_bounds__(256) k_diag(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
   const int N = s.N, nm = N - 1, y = MRA_BX(b);
   const double* w = s.dense64;
-  const double* ps = reinterpret_cast<const double*>(s.psi);
+  const double* vu = s.vel64;
+  const double* vv = s.vel64 + (size_t)N * N;
   const double ih = 1.0 / s.h;
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
   for (int x = threadIdx.x; x < N; x += blockDim.x) {
-    double u = 0, v = 0, gx = 0, gy = 0;
+    double gx = 0, gy = 0;
     for (int n = 1; n <= 2 * P - 2; ++n) {
       const double cn = d1c<P, double>(n);
-      u += cn * (ps[((y + n) & nm) * N + x] - ps[((y - n) & nm) * N + x]);
-      v -= cn * (ps[y * N + ((x + n) & nm)] - ps[y * N + ((x - n) & nm)]);
       gy += cn * (w[((y + n) & nm) * N + x] - w[((y - n) & nm) * N + x]);
       gx += cn * (w[y * N + ((x + n) & nm)] - w[y * N + ((x - n) & nm)]);
     }
-    u *= ih; v *= ih; gx *= ih; gy *= ih;
+    gx *= ih; gy *= ih;
+    const double u = vu[y * N + x], v = vv[y * N + x];
     const double wv = w[y * N + x];
     a0 += wv;
     a1 += u * u + v * v;

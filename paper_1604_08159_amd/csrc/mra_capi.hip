@@ -133,13 +133,14 @@ void rhs_layout(Layout& L, SolveDev& s) {
   s.rank = L.take<int32_t>(Nf);
   s.tile_count = L.take<int32_t>((size_t)s.ntx * s.ntx);
   s.wt = L.take<char>(Nf * esz);
-  s.psi = L.take<char>(Nf * esz);
   s.u = L.take<char>(Nf * esz);
   s.v = L.take<char>(Nf * esz);
   s.nu = L.take<char>(Nf * esz);
   s.vt = L.take<char>(Nf * esz);
-  s.psiv = L.take<char>(Nf * esz);
+  s.uv = L.take<char>(Nf * esz);
+  s.vv = L.take<char>(Nf * esz);
   s.spec = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 2 * esz);
+  s.spec2 = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 2 * esz);
   s.out_rhs = L.take<double>(Nf);
 }
 
@@ -166,13 +167,15 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.y = L.take<double>(kMaxM + 1);
   s.partials = L.take<double>((size_t)2 * kPartSlots * (kMaxM + 2));
   s.wt = L.take<char>(Nf * esz);
-  s.psi = L.take<char>(Nf * 8);      // FP64 for the diagnostics
   s.u = L.take<char>(Nf * esz);
   s.v = L.take<char>(Nf * esz);
   s.nu = L.take<char>(Nf * esz);
   s.vt = L.take<char>(Nf * esz);
-  s.psiv = L.take<char>(Nf * esz);
+  s.uv = L.take<char>(Nf * esz);
+  s.vv = L.take<char>(Nf * esz);
+  s.vel64 = L.take<double>(2 * Nf);  // FP64 for the diagnostics
   s.spec = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 16);
+  s.spec2 = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 16);
   s.dense64 = L.take<double>(Nf);
   s.packed64 = L.take<double>(Nf);
   s.diag = L.take<double>((size_t)s.N * 5);
@@ -347,7 +350,7 @@ int32_t mra_rhs_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes) {
 
 int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, const uint8_t* mask,
                         const int32_t* index_fine, const int64_t* n_active, const double* omega_active,
-                        const double* v_active, double* out_active, void* psi_dense_or_null, void* ws,
+                        const double* v_active, double* out_active, void* vel_dense_or_null, void* ws,
                         size_t ws_bytes, void* stream) {
   int32_t r = check_grid(g);
   if (r != MRA_OK) return r;
@@ -369,7 +372,10 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
   s.index_fine = const_cast<int32_t*>(index_fine);
   s.n_active = const_cast<int64_t*>(n_active);
   s.omega = const_cast<double*>(omega_active);
-  if (psi_dense_or_null) s.psi = psi_dense_or_null;
+  if (vel_dense_or_null) {
+    s.u = vel_dense_or_null;
+    s.v = static_cast<char*>(vel_dense_or_null) + (size_t)s.N * s.N * (s.prec == 0 ? 8 : 4);
+  }
   if (v_active) {
     s.out_jvp = out_active;
     s.vin = v_active;
@@ -507,7 +513,7 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
         if (it == g_batch_graphs.end()) {
           // bounded cache: a serving loop changes the batch composition often
           if (g_batch_graphs.size() >= kMaxCachedGraphs) {
-            MRA_TRY(hipStreamSynchronize(st));
+            MRA_TRY(hipDeviceSynchronize());   // cached graphs may be in flight on any stream
             drop_batch_graphs();
           }
           GraphEntry ge;
@@ -582,9 +588,21 @@ int32_t mra_solve_destroy(mra_solve h) {
   if (!h) return MRA_E_ARG;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    drop_batch_graphs();
+    // drop the cached batch graphs that launch this solve
+    bool synced = false;
+    for (auto it = g_batch_graphs.begin(); it != g_batch_graphs.end();) {
+      const auto& key = it->first.first;
+      if (std::find(key.begin(), key.end(), static_cast<const void*>(h)) == key.end()) { ++it; continue; }
+      if (!synced) { (void)hipDeviceSynchronize(); synced = true; }
+      if (it->second.x) (void)hipGraphExecDestroy(it->second.x);
+      if (it->second.g) (void)hipGraphDestroy(it->second.g);
+      it = g_batch_graphs.erase(it);
+    }
   }
-  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->graph) {
+    (void)hipStreamSynchronize(h->graph_stream);
+    (void)hipGraphExecDestroy(h->graph);
+  }
   if (h->graph_def) (void)hipGraphDestroy(h->graph_def);
   delete h;
   return MRA_OK;

@@ -60,13 +60,15 @@ struct SolveDev {
   int* ctrl;                // [C_NCTRL]
   // dense fields (element type by prec)
   void* wt;                 // Pi(omega)
-  void* psi;
-  void* u;
+  void* u;                  // velocity of Pi(omega)
   void* v;
-  void* nu;
+  void* nu;                 // eddy viscosity of Pi(omega)
   void* vt;                 // Pi(v)
-  void* psiv;
-  void* spec;               // complex half spectrum [(N/2+1)][N]
+  void* uv;                 // velocity of Pi(v)
+  void* vv;
+  void* spec;               // complex half spectrum [(N/2+1)][N]: omega, then u
+  void* spec2;              // the v spectrum, same shape
+  double* vel64;            // FP64 velocity [2][Nf] of dense64 (diagnostics)
   double* dense64;          // FP64 regrid field [Nf]
   double* packed64;         // FP64 packed pyramid [Nf]
   double* out_rhs;          // residual at the active nodes [Nf]
@@ -314,7 +316,7 @@ hipError_t launch_reset_max(const Batch& b, hipStream_t st);
 
 // Poisson
 hipError_t fft_init_tables(hipStream_t st);
-hipError_t launch_poisson(const Batch& b, const LaunchCfg& c, int src /*0 wt->psi, 1 vt->psiv, 2 dense64->psi(fp64)*/,
+hipError_t launch_poisson(const Batch& b, const LaunchCfg& c, int src /*0 wt->(u,v), 1 vt->(uv,vv), 2 dense64->vel64 (fp64)*/,
                           hipStream_t st);
 hipError_t launch_poisson_pass(const Batch& b, const LaunchCfg& c, int src, int pass, hipStream_t st);
 

@@ -1,0 +1,189 @@
+"""Continuous batching of vortex solves on one GPU.
+
+Host-side orchestration only: every step of every solve runs in the
+library's kernels through solve_batch.  Requests (initial vortices, grid,
+Reynolds number, step count) arrive over time; a request is admitted as soon
+as its arena fits in the HBM budget (footprint from mra_solve_footprint) and
+stays resident -- active set, Krylov basis, dense work fields -- until its
+last step.  All resident solves advance together in rounds: solves of equal
+(J, p, precision, m) share every kernel launch and a captured step graph,
+and each such group runs on its own stream so that groups overlap on the
+device.  A solve finishes in the round in which its step count is reached;
+its result is read back, its latency recorded and its arena released, which
+may admit waiting requests.
+
+Results do not depend on the mix: kernels and reductions are per solve, so a
+solve gives bit-identical results alone and inside any batch.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import MRA_MIXED, Solve, flow_desc, grid_desc, solve_batch, solve_footprint
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds after the start of the run
+    J: int
+    p: int
+    eps: float
+    nu0: float
+    cs: float
+    m: int
+    dt: float
+    steps: int
+    omega0: object                 # host FP64 [N][N] (numpy)
+
+
+@dataclasses.dataclass
+class Record:
+    rid: int
+    J: int
+    steps: int
+    arrival: float
+    admitted: float = -1.0
+    finished: float = -1.0
+    evals: float = 0.0
+    n_active: int = 0
+    status: int = 0
+    diag: Optional[Dict[str, float]] = None
+    omega: Optional[torch.Tensor] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    """Admission by HBM footprint, resident state, batched rounds of steps."""
+
+    def __init__(self, hbm_budget: int, prec: int = MRA_MIXED, round_steps: int = 20,
+                 device: str = "cuda:0", keep_results: bool = False,
+                 progress: Optional[Callable[[int, int, int], None]] = None):
+        self.budget = int(hbm_budget)
+        self.progress = progress          # called after each round: (done, resident, waiting)
+        self.prec = prec
+        self.round_steps = round_steps
+        self.dev = torch.device(device)
+        self.keep = keep_results
+        self.streams: Dict[Tuple[int, int, int], torch.cuda.Stream] = {}
+        self.used = 0
+        self.live: Dict[int, Tuple[Solve, Request, Record, int]] = {}   # rid -> (solve, req, rec, steps done)
+
+    def footprint(self, r: Request) -> int:
+        return solve_footprint(grid_desc(r.J, r.p, r.eps), self.prec, r.m)
+
+    def _stream(self, r: Request) -> torch.cuda.Stream:
+        key = (r.J, r.p, r.m)
+        if key not in self.streams:
+            self.streams[key] = torch.cuda.Stream(device=self.dev)
+        return self.streams[key]
+
+    def _admit(self, r: Request, rec: Record, now: float) -> None:
+        st = self._stream(r)
+        with torch.cuda.stream(st):
+            w0 = torch.from_numpy(r.omega0).to(self.dev, non_blocking=False)
+            s = Solve(grid_desc(r.J, r.p, r.eps), flow_desc(r.nu0, r.cs), self.prec, r.m, r.dt, w0, stream=st)
+        self.used += s.nbytes
+        rec.admitted = now
+        self.live[r.rid] = (s, r, rec, 0)
+
+    def _retire(self, rid: int, now: float) -> Record:
+        s, r, rec, _ = self.live.pop(rid)
+        st = self._stream(r)
+        dense, diag = s.read(dense=self.keep, stream=st)
+        rec.finished = now
+        rec.diag = diag
+        rec.n_active = int(diag["n_active"])
+        rec.status = int(diag["status"])
+        rec.evals = s.scalars()["evals"]
+        rec.omega = dense
+        self.used -= s.nbytes
+        s.close()
+        return rec
+
+    def run(self, requests: Sequence[Request], realtime: bool = True) -> List[Record]:
+        """Serve the requests (sorted by arrival); returns their records.  A
+        request whose footprint alone exceeds the budget is rejected
+        (status -1) without affecting the others."""
+        records: Dict[int, Record] = {r.rid: Record(r.rid, r.J, r.steps, r.arrival) for r in requests}
+        done: List[Record] = []
+        ok = []
+        for r in requests:
+            if self.footprint(r) > self.budget:
+                rec = records[r.rid]
+                rec.status, rec.admitted, rec.finished = -1, r.arrival, r.arrival
+                done.append(rec)
+            else:
+                ok.append(r)
+        pending = collections.deque(sorted(ok, key=lambda r: r.arrival))
+        t0 = time.perf_counter()
+        clock = (lambda: time.perf_counter() - t0) if realtime else None
+        vclock = 0.0
+        while pending or self.live:
+            now = clock() if realtime else vclock
+            # admission: FIFO, while the head fits in the remaining budget
+            # (realtime=False: arrival times only order the queue)
+            while pending and (not realtime or pending[0].arrival <= now):
+                r = pending[0]
+                if self.used + self.footprint(r) > self.budget and self.live:
+                    break
+                pending.popleft()
+                if not realtime:
+                    vclock = max(vclock, r.arrival)
+                self._admit(r, records[r.rid], now if realtime else vclock)
+            if not self.live:
+                if realtime and pending:
+                    time.sleep(max(0.0, min(0.002, pending[0].arrival - clock())))
+                continue
+            # one round: every group advances together on its own stream
+            groups: Dict[Tuple[int, int, int], List[int]] = collections.defaultdict(list)
+            for rid, (s, r, rec, k) in self.live.items():
+                groups[(r.J, r.p, r.m)].append(rid)
+            for key, rids in groups.items():
+                k = min(self.round_steps, min(self.live[i][1].steps - self.live[i][3] for i in rids))
+                solves = [self.live[i][0] for i in rids]
+                solve_batch(solves, [k] * len(solves), stream=self.streams[key])
+                for i in rids:
+                    s, r, rec, d = self.live[i]
+                    self.live[i] = (s, r, rec, d + k)
+            for st in self.streams.values():
+                st.synchronize()
+            now = clock() if realtime else vclock
+            for rid in [i for i, (s, r, rec, d) in self.live.items() if d >= r.steps]:
+                done.append(self._retire(rid, now))
+            if self.progress:
+                self.progress(len(done), len(self.live), len(pending))
+        return done
+
+
+def summarize(records: Sequence[Record], wall: float) -> Dict[str, float]:
+    served = [r for r in records if r.status >= 0]
+    lat = sorted(r.latency for r in served)
+
+    def pct(q):
+        if not lat:
+            return float("nan")
+        i = min(len(lat) - 1, max(0, int(round(q * (len(lat) - 1)))))
+        return lat[i]
+
+    return {"requests": len(records), "wall_s": wall, "solves_per_s": len(served) / wall if wall > 0 else 0.0,
+            "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "max_latency_s": lat[-1] if lat else 0.0,
+            "active_pt_evals_per_s": sum(r.evals for r in records) / wall if wall > 0 else 0.0,
+            "failed": sum(1 for r in records if r.status > 0),
+            "rejected": sum(1 for r in records if r.status < 0)}
+
+
+def requests_from_problems(timed_problems, omega_fn) -> List[Request]:
+    """Requests from (arrival, workloads.Problem) pairs; omega_fn(problem) -> host field."""
+    out = []
+    for i, (t, pb) in enumerate(timed_problems):
+        out.append(Request(i, t, pb.J, pb.p, pb.eps, pb.nu0, pb.cs, pb.m, pb.dt, pb.steps, omega_fn(pb)))
+    return out
