@@ -24,6 +24,15 @@ namespace mra {
 __device__ double2 g_tw64[kTwN];
 __device__ float2 g_tw32[kTwN];
 
+// Operator symbols at theta = 2 pi k / N for every N = 2^J <= 2048, entry
+// N + k (k < N), rows [p - 2][kind]:
+//   kind 0: sigma_1 = 2 sum_n a_n sin(n theta)    (h / i times the eigenvalue of D1)
+//   kind 1: sigma_2 = c0 + 2 sum_n c_n cos(n theta)  (h^2 times the eigenvalue of D2)
+// with the D1 filter a_n and the Lagrange D2 weights c_n of the stencils.
+constexpr int kSymN = 2 * kTwN;
+__device__ double g_sym64[2][2][kSymN];
+__device__ float g_sym32[2][2][kSymN];
+
 __global__ void k_init_tw() {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < kTwN; k += gridDim.x * blockDim.x) {
     double sn, cs;
@@ -31,10 +40,25 @@ __global__ void k_init_tw() {
     g_tw64[k] = make_double2(cs, sn);
     g_tw32[k] = make_float2((float)cs, (float)sn);
   }
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kSymN; e += gridDim.x * blockDim.x) {
+    if (e < 2) continue;
+    const int N = 1 << ilog2((unsigned)e), k = e - N;
+    double c[5], sn[5];
+    for (int n = 1; n <= 4; ++n) sincospi(2.0 * (double)((n * k) & (N - 1)) / N, &sn[n], &c[n]);
+    const double s2a = -2.5 + 2.0 * ((4.0 / 3.0) * c[1] + (-1.0 / 12.0) * c[2]);
+    const double s1a = 2.0 * ((2.0 / 3.0) * sn[1] + (-1.0 / 12.0) * sn[2]);
+    const double s2b = -49.0 / 18.0 + 2.0 * (1.5 * c[1] + (-0.15) * c[2] + (1.0 / 90.0) * c[3]);
+    const double s1b = 2.0 * ((272.0 / 365.0) * sn[1] + (-53.0 / 365.0) * sn[2] + (16.0 / 1095.0) * sn[3] +
+                              (1.0 / 2920.0) * sn[4]);
+    g_sym64[0][0][e] = s1a; g_sym64[0][1][e] = s2a;
+    g_sym64[1][0][e] = s1b; g_sym64[1][1][e] = s2b;
+    g_sym32[0][0][e] = (float)s1a; g_sym32[0][1][e] = (float)s2a;
+    g_sym32[1][0][e] = (float)s1b; g_sym32[1][1][e] = (float)s2b;
+  }
 }
 
 hipError_t fft_init_tables(hipStream_t st) {
-  hipLaunchKernelGGL(k_init_tw, dim3(8), dim3(256), 0, st);
+  hipLaunchKernelGGL(k_init_tw, dim3(16), dim3(256), 0, st);
   return hipGetLastError();
 }
 
@@ -42,11 +66,18 @@ template <typename T> struct C2;
 template <> struct C2<double> {
   using t = double2;
   __device__ static t tw(int k) { return g_tw64[k]; }
+  __device__ static double sym(int p, int kind, int e) { return g_sym64[p - 2][kind][e]; }
 };
 template <> struct C2<float> {
   using t = float2;
   __device__ static t tw(int k) { return g_tw32[k]; }
+  __device__ static float sym(int p, int kind, int e) { return g_sym32[p - 2][kind][e]; }
 };
+
+// LDS slot of FFT element i: one pad slot per 32 elements spreads the
+// strided writes of the early Stockham passes over the banks.
+__device__ inline int lx(int i) { return i + (i >> 5); }
+__host__ __device__ inline int lds_slots(int n) { return n + (n >> 5); }
 
 template <typename V> __device__ inline V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ inline V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
@@ -61,11 +92,32 @@ template <typename V> __device__ inline V cconj(V a) { return V{a.x, -a.y}; }
 // L = 2^lg held in LDS at stride L, by a block of 256 threads.  Passes of
 // radix 8 (the last one of radix 2, 4 or 8 to complete L): every thread keeps
 // 8 complex values in registers per pass, so a pass is one LDS read phase,
-// one barrier, the small DFTs and twiddles in registers, one LDS write phase.
+// a barrier, the small DFTs and twiddles in registers, one LDS write phase.
 // The block handles nfft * L <= 2048 points.  S = -1 forward, +1 inverse
 // (unnormalised).
+//
+// Work items are dealt so that wavefront w handles exactly the elements
+// [512 w, 512 (w + 1)) in every pass.  For L <= 512 each vector then lives in
+// one wavefront, whose lanes exchange data through LDS with only a wavefront
+// barrier: the four wavefronts of a block run their passes independently.
+// Larger L takes block barriers.  The elementwise phases around the FFTs use
+// the same ownership, so they need no block barrier either when L <= 512.
 constexpr int kFftThreads = 256;
 constexpr int kFftPoints = 2048;
+constexpr int kWaveSpan = 512;             // elements owned by one wavefront
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline void fft_sync(bool wave_local) {
+  if (wave_local) wave_sync();
+  else __syncthreads();
+}
+// first element owned by this thread's wavefront, and its lane
+__device__ inline int own0() { return (threadIdx.x >> 6) * kWaveSpan; }
+__device__ inline int lane() { return threadIdx.x & 63; }
 
 template <int S, typename V> __device__ inline V mul_i(V a) {   // (S i) * a
   return S < 0 ? V{a.y, -a.x} : V{-a.y, a.x};
@@ -106,55 +158,62 @@ __device__ inline void small_dft(typename C2<T>::t* v) {
 }
 
 template <int R, int S, typename T>
-__device__ inline void stockham_pass(typename C2<T>::t* buf, int L, int nfft, int Ns) {
+__device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int lgL, int nfft, int lgNs, bool wl) {
   using V = typename C2<T>::t;
   constexpr int IPT = 8 / R;               // work items per thread
-  const int per = L / R;
-  const int total = nfft * per;
-  const int twstep = kTwN / (Ns * R);
+  constexpr int lgR = R == 8 ? 3 : (R == 4 ? 2 : 1);
+  constexpr int lgIPT = 3 - lgR;
+  const int lgper = lgL - lgR;             // L / R items per vector, all powers of two
+  const int total = nfft << lgper;
+  const int Ns = 1 << lgNs;
+  const int twshift = ilog2(kTwN) - lgNs - lgR;
+  // item of (thread, it): wavefront w takes items [64 IPT w, 64 IPT (w + 1))
+  const int qbase = ((threadIdx.x >> 6) << (6 + lgIPT)) + (threadIdx.x & 63);
   V v[IPT][R];
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
-    const int q = threadIdx.x + it * kFftThreads;
+    const int q = qbase + (it << 6);
     if (q < total) {
-      const int f = q / per, j = q - f * per;
+      const int j = q & ((1 << lgper) - 1);
       const int k = j & (Ns - 1);
-      const V* src = buf + f * L + j;
-      v[it][0] = src[0];
+      const int base = ((q >> lgper) << lgL) + j;
+      v[it][0] = buf[lx(base)];
       // twiddles w^r, w = exp(-2 pi i k / (Ns R)): one table load, then powers
-      const V w1 = C2<T>::tw(k * twstep);
+      const V w1 = C2<T>::tw(k << twshift);
       V wr = w1;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const V x = src[r * per];
+        const V x = buf[lx(base + (r << lgper))];
         v[it][r] = S < 0 ? cmul(x, wr) : cmulc(x, wr);
         wr = cmul(wr, w1);
       }
     }
   }
-  __syncthreads();
+  fft_sync(wl);
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
-    const int q = threadIdx.x + it * kFftThreads;
+    const int q = qbase + (it << 6);
     if (q < total) {
-      const int f = q / per, j = q - f * per;
+      const int j = q & ((1 << lgper) - 1);
       const int k = j & (Ns - 1);
       small_dft<R, S, T>(v[it]);
-      V* dst = buf + f * L + (j - k) * R + k;
+      const int base = ((q >> lgper) << lgL) + ((j - k) << lgR) + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[it][r];
+      for (int r = 0; r < R; ++r) buf[lx(base + (r << lgNs))] = v[it][r];
     }
   }
-  __syncthreads();
+  fft_sync(wl);
 }
 
+// nfft vectors of length 2^lgL at stride 2^lgL; wavefront-local when L <= 512
 template <int S, typename T>
-__device__ void fft_block(typename C2<T>::t* buf, int L, int nfft) {
-  for (int Ns = 1; Ns < L;) {
-    const int rem = L / Ns;
-    if (rem >= 8) { stockham_pass<8, S, T>(buf, L, nfft, Ns); Ns *= 8; }
-    else if (rem == 4) { stockham_pass<4, S, T>(buf, L, nfft, Ns); Ns *= 4; }
-    else { stockham_pass<2, S, T>(buf, L, nfft, Ns); Ns *= 2; }
+__device__ __forceinline__ void fft_block(typename C2<T>::t* buf, int lgL, int nfft) {
+  const bool wl = lgL <= 9;
+  for (int lgNs = 0; lgNs < lgL;) {
+    const int rem = lgL - lgNs;
+    if (rem >= 3) { stockham_pass<8, S, T>(buf, lgL, nfft, lgNs, wl); lgNs += 3; }
+    else if (rem == 2) { stockham_pass<4, S, T>(buf, lgL, nfft, lgNs, wl); lgNs += 2; }
+    else { stockham_pass<2, S, T>(buf, lgL, nfft, lgNs, wl); lgNs += 1; }
   }
 }
 
@@ -182,44 +241,23 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src, 
   const int N = s.N, M = N >> 1;
   const int y0 = MRA_BX(b) * R;
   const V* in = reinterpret_cast<const V*>(poisson_src<T>(s, src));
-  for (int q = threadIdx.x; q < R * M; q += blockDim.x) buf[q] = in[(size_t)y0 * M + q];
+  const int lgR = ilog2((unsigned)R), lgM = s.J - 1;
+  const int n = R * M, e1 = min(own0() + kWaveSpan, n);
+  for (int q = own0() + lane(); q < e1; q += 64) buf[lx(q)] = in[(size_t)y0 * M + q];
+  fft_sync(lgM <= 9);
+  fft_block<-1, T>(buf, lgM, R);
   __syncthreads();
-  fft_block<-1, T>(buf, M, R);
   V* spec = reinterpret_cast<V*>(s.spec);
   const int twN = kTwN / N;
   for (int q = threadIdx.x; q < (M + 1) * R; q += blockDim.x) {
-    const int k = q / R, r = q - k * R;
-    const V* row = buf + r * M;
-    const V zk = row[k & (M - 1)];
-    const V zc = cconj(row[(M - k) & (M - 1)]);
+    const int k = q >> lgR, r = q & (R - 1);
+    const V zk = buf[lx((r << lgM) + (k & (M - 1)))];
+    const V zc = cconj(buf[lx((r << lgM) + ((M - k) & (M - 1)))]);
     const V e = cmul(csub(zk, zc), C2<T>::tw(k * twN));
     V x;
     x.x = T(0.5) * (zk.x + zc.x + e.y);
     x.y = T(0.5) * (zk.y + zc.y - e.x);
     spec[(size_t)k * N + y0 + r] = x;
-  }
-}
-
-// Symbols at theta = 2 pi k / N, FP64: sigma_2 = c0 + 2 sum_n c_n cos(n theta)
-// (h^2 times the eigenvalue of D2) and sigma_1 = 2 sum_n a_n sin(n theta)
-// (h / i times the eigenvalue of D1).  Table entry m: exp(-2 pi i m / 2048).
-template <int P>
-__device__ inline void symbols(int k, int N, double* s1, double* s2) {
-  const int tws = kTwN / N;
-  double c[4], sn[5];
-#pragma unroll
-  for (int n = 1; n <= 2 * P - 2; ++n) {
-    const double2 t = g_tw64[((n * k) & (N - 1)) * tws];
-    if (n <= P) c[n] = t.x;
-    sn[n] = -t.y;
-  }
-  if constexpr (P == 2) {
-    *s2 = -2.5 + 2.0 * ((4.0 / 3.0) * c[1] + (-1.0 / 12.0) * c[2]);
-    *s1 = 2.0 * ((2.0 / 3.0) * sn[1] + (-1.0 / 12.0) * sn[2]);
-  } else {
-    *s2 = -49.0 / 18.0 + 2.0 * (1.5 * c[1] + (-0.15) * c[2] + (1.0 / 90.0) * c[3]);
-    *s1 = 2.0 * ((272.0 / 365.0) * sn[1] + (-53.0 / 365.0) * sn[2] + (16.0 / 1095.0) * sn[3] +
-                 (1.0 / 2920.0) * sn[4]);
   }
 }
 
@@ -229,46 +267,44 @@ template <int P, typename T>
 __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b, int C) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem[];
-  V* A = reinterpret_cast<V*>(smem);
-  V* Bv = A + C * (1 << MRA_SOLVE(b).J);
   const SolveDev& s = MRA_SOLVE(b);
   const int J = s.J, N = s.N, M = N >> 1;
+  V* A = reinterpret_cast<V*>(smem);
+  V* Bv = A + lds_slots(C * N);
   const int k0 = MRA_BX(b) * C;
   const int nr = (M + 1 - k0) < C ? (M + 1 - k0) : C;
   V* specU = reinterpret_cast<V*>(s.spec);
   V* specV = reinterpret_cast<V*>(s.spec2);
-  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) A[q] = specU[(size_t)k0 * N + q];
-  __syncthreads();
-  fft_block<-1, T>(A, N, nr);
-  const double h2n = s.h * s.h / ((double)N * (double)N);
-  const double ih = 1.0 / s.h;
-  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) {
+  const bool wl = J <= 9;
+  const int e1 = min(own0() + kWaveSpan, nr * N);
+  for (int q = own0() + lane(); q < e1; q += 64) A[lx(q)] = specU[(size_t)k0 * N + q];
+  fft_sync(wl);
+  fft_block<-1, T>(A, J, nr);
+  const T h2n = T(-s.h * s.h / ((double)N * (double)N));
+  const T ih = T(1.0 / s.h);
+  for (int q = own0() + lane(); q < e1; q += 64) {
     const int r = q >> J, ky = q & (N - 1);
     const int kx = k0 + r;
-    double s1x, s2x, s1y, s2y;
-    symbols<P>(kx, N, &s1x, &s2x);
-    symbols<P>(ky, N, &s1y, &s2y);
-    const T g = (kx == 0 && ky == 0) ? T(0) : (T)(-h2n / (s2x + s2y));
-    const V z = A[q];
-    const T sy = (T)(s1y * ih);
-    A[q] = V{z.x * g, z.y * g};
-    Bv[q] = V{-sy * (z.y * g), sy * (z.x * g)};          // i s1(ky) psi_hat
+    const T den = C2<T>::sym(P, 1, N + kx) + C2<T>::sym(P, 1, N + ky);
+    const T g = (kx == 0 && ky == 0) ? T(0) : h2n / den;
+    const T sy = C2<T>::sym(P, 0, N + ky) * ih;
+    const V z = A[lx(q)];
+    const V ps = V{z.x * g, z.y * g};
+    A[lx(q)] = ps;
+    Bv[lx(q)] = V{-sy * ps.y, sy * ps.x};                  // i s1(ky) psi_hat
   }
-  __syncthreads();
-  fft_block<1, T>(Bv, N, nr);
-  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) specU[(size_t)k0 * N + q] = Bv[q];
-  __syncthreads();
-  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) {
-    const int r = q >> J;
-    double s1x, s2x;
-    symbols<P>(k0 + r, N, &s1x, &s2x);
-    const T sx = (T)(s1x * ih);
-    const V z = A[q];
-    Bv[q] = V{sx * z.y, -sx * z.x};                       // -i s1(kx) psi_hat
+  fft_sync(wl);
+  fft_block<1, T>(Bv, J, nr);
+  for (int q = own0() + lane(); q < e1; q += 64) specU[(size_t)k0 * N + q] = Bv[lx(q)];
+  fft_sync(wl);
+  for (int q = own0() + lane(); q < e1; q += 64) {
+    const T sx = C2<T>::sym(P, 0, N + k0 + (q >> J)) * ih;
+    const V z = A[lx(q)];
+    Bv[lx(q)] = V{sx * z.y, -sx * z.x};                    // -i s1(kx) psi_hat
   }
-  __syncthreads();
-  fft_block<1, T>(Bv, N, nr);
-  for (int q = threadIdx.x; q < nr * N; q += blockDim.x) specV[(size_t)k0 * N + q] = Bv[q];
+  fft_sync(wl);
+  fft_block<1, T>(Bv, J, nr);
+  for (int q = own0() + lane(); q < e1; q += 64) specV[(size_t)k0 * N + q] = Bv[lx(q)];
 }
 
 // pass C: spec[kx][y] -> real rows, R rows per block (R * N/2 <= 2048), for
@@ -282,22 +318,24 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src, 
   const int N = s.N, M = N >> 1;
   const int y0 = MRA_BX(b) * R;
   const int twN = kTwN / N;
+  const int lgR = ilog2((unsigned)R), lgM = s.J - 1;
   for (int comp = 0; comp < 2; ++comp) {
     const V* spec = reinterpret_cast<const V*>(comp == 0 ? s.spec : s.spec2);
     for (int q = threadIdx.x; q < M * R; q += blockDim.x) {
-      const int k = q / R, r = q - k * R;
+      const int k = q >> lgR, r = q & (R - 1);
       const V xk = spec[(size_t)k * N + y0 + r];
       const V xc = cconj(spec[(size_t)(M - k) * N + y0 + r]);
       const V e = cmulc(csub(xk, xc), C2<T>::tw(k * twN));
       V z;
       z.x = xk.x + xc.x - e.y;
       z.y = xk.y + xc.y + e.x;
-      buf[r * M + k] = z;
+      buf[lx((r << lgM) + k)] = z;
     }
     __syncthreads();
-    fft_block<1, T>(buf, M, R);
+    fft_block<1, T>(buf, lgM, R);
     V* out = reinterpret_cast<V*>(poisson_dst<T>(s, src, comp));
-    for (int q = threadIdx.x; q < R * M; q += blockDim.x) out[(size_t)y0 * M + q] = buf[q];
+    const int e1 = min(own0() + kWaveSpan, R * M);
+    for (int q = own0() + lane(); q < e1; q += 64) out[(size_t)y0 * M + q] = buf[lx(q)];
     __syncthreads();
   }
 }
@@ -318,16 +356,16 @@ static hipError_t poisson_t(const Batch& b, const LaunchCfg& c, int src, int pas
   const int R = rows_per_block(N);
   const int C = cols_per_block(N);
   if (pass < 0 || pass == 0)
-    hipLaunchKernelGGL(k_fft_rows_fwd<T>, dim3((N / R) * b.n), dim3(kFftThreads), (size_t)R * M * sizeof(V), st, b,
+    hipLaunchKernelGGL(k_fft_rows_fwd<T>, dim3((N / R) * b.n), dim3(kFftThreads), lds_slots(R * M) * sizeof(V), st, b,
                        src, R);
   if (pass < 0 || pass == 1) {
     dim3 g(((M + 1 + C - 1) / C) * b.n);
-    const size_t lds = 2 * (size_t)C * N * sizeof(V);
+    const size_t lds = 2 * (size_t)lds_slots(C * N) * sizeof(V);
     if (c.p == 2) hipLaunchKernelGGL((k_fft_cols<2, T>), g, dim3(kFftThreads), lds, st, b, C);
     else hipLaunchKernelGGL((k_fft_cols<3, T>), g, dim3(kFftThreads), lds, st, b, C);
   }
   if (pass < 0 || pass == 2)
-    hipLaunchKernelGGL(k_fft_rows_inv<T>, dim3((N / R) * b.n), dim3(kFftThreads), (size_t)R * M * sizeof(V), st, b,
+    hipLaunchKernelGGL(k_fft_rows_inv<T>, dim3((N / R) * b.n), dim3(kFftThreads), lds_slots(R * M) * sizeof(V), st, b,
                        src, R);
   return hipGetLastError();
 }

@@ -17,49 +17,11 @@
 
 namespace mra {
 
-// Chunk parts of V_i . w for i <= j and, if with_norm, of w . w (slot j+1):
-// each wavefront reduces its own elements and writes buf[(ch*4+wave)][.].
-// Four basis vectors per pass keep many independent loads in flight.
-__device__ inline void chunk_dots(const SolveDev& s, int j, int lo, int hi, bool with_norm, double* buf,
-                                  int ch) {
-  const size_t Nf = (size_t)s.N * s.N;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double* out = buf + (size_t)(ch * kWavesPerBlock + wid) * (kMaxM + 2);
-  const double* w = s.w;
-  const int top = with_norm ? j + 1 : j;
-  for (int i0 = 0; i0 <= top; i0 += 4) {
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
-    const double* a[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + u;
-      a[u] = i <= j ? s.V + i * Nf : w;
-    }
-    for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) {
-      const double wk = w[k];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (i0 + u <= top) t[u] += a[u][k] * wk;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (i0 + u > top) break;
-      const double r = wave_sum(t[u]);
-      if (lane == 0) out[i0 + u] = r;
-    }
-  }
-}
-
-// w -= V_j h over the chunk
-__device__ inline void chunk_axpy(const SolveDev& s, int j, int lo, int hi, const double* h) {
-  const size_t Nf = (size_t)s.N * s.N;
-  for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-    double t = s.w[k];
-    for (int i = 0; i <= j; ++i) t -= h[i] * s.V[i * Nf + k];
-    s.w[k] = t;
-  }
-  __syncthreads();
-}
+// Gram-Schmidt kernels.  A thread takes the elements lo + tid, lo + tid + 256,
+// ... of its chunk; for each it loads w and all basis entries V_i[k], i <= j,
+// at once (MJ >= j + 1 register slots, MJ fixed at compile time from m), so a
+// chunk costs one dependent global round per element instead of one per group
+// of basis vectors.
 
 // ||F||^2 partials (buffer B).
 __global__ void __launch_bounds__(256) k_norm0(Batch b) {
@@ -68,23 +30,48 @@ __global__ void __launch_bounds__(256) k_norm0(Batch b) {
   const int nb = nchunks(na);
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
-    chunk_dots(s, -1, c.lo, c.hi, true, part_buf(s, 1), ch);
+    double acc[1] = {0.0};
+    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) acc[0] += s.w[k] * s.w[k];
+    block_sums_store<1>(acc, 1, part_buf(s, 1) + (size_t)ch * (kMaxM + 2));
+    __syncthreads();
   }
 }
 
-// Stage 1: h1 = V_j^T w, ||w||^2 (= ||A v_j||^2) partials (buffer A).
+// Stage 1: h1 = V_j^T w and ||w||^2 (= ||A v_j||^2) partials (buffer A).
+template <int MJ>
 __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int j) {
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
+  const size_t Nf = (size_t)s.N * s.N;
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
-    chunk_dots(s, j, c.lo, c.hi, true, part_buf(s, 0), ch);
+    double acc[MJ + 1];
+#pragma unroll
+    for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
+    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
+      const double wk = s.w[k];
+      double v[MJ];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) v[i] = s.V[i * Nf + k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) acc[i] += v[i] * wk;
+      acc[MJ] += wk * wk;
+    }
+    // slot layout: h1[0 .. j], then ||w||^2 at j + 1 (static register indices)
+#pragma unroll
+    for (int i = 0; i < MJ; ++i)
+      if (i == j + 1) acc[i] = acc[MJ];
+    block_sums_store<MJ + 1>(acc, j + 2, part_buf(s, 0) + (size_t)ch * (kMaxM + 2));
+    __syncthreads();
   }
 }
 
 // Stage 2: h1 from A; w -= V_j h1; h2 = V_j^T w partials (buffer B).
+template <int MJ>
 __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
@@ -97,15 +84,34 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
     for (int i = threadIdx.x; i <= j; i += blockDim.x) s.hpart[i] = h[i];
     if (threadIdx.x == 0) s.scal[S_NRMAV] = sqrt(h[j + 1]);
   }
+  const size_t Nf = (size_t)s.N * s.N;
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
-    chunk_axpy(s, j, c.lo, c.hi, h);
-    chunk_dots(s, j, c.lo, c.hi, false, part_buf(s, 1), ch);
+    double acc[MJ];
+#pragma unroll
+    for (int i = 0; i < MJ; ++i) acc[i] = 0.0;
+    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
+      double t = s.w[k];
+      double v[MJ];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) v[i] = s.V[i * Nf + k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) t -= h[i] * v[i];
+      s.w[k] = t;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) acc[i] += v[i] * t;
+    }
+    block_sums_store<MJ>(acc, j + 1, part_buf(s, 1) + (size_t)ch * (kMaxM + 2));
+    __syncthreads();
   }
 }
 
 // Stage 3: h2 from B; w -= V_j h2; H[:j+1, j] = h1 + h2; ||w||^2 partials
 // (buffer A), consumed by the next scaling (next_scale) or by phi_1.
+template <int MJ>
 __global__ void __launch_bounds__(256) k_gs_axpy_norm(Batch b, int j) {
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
@@ -116,13 +122,24 @@ __global__ void __launch_bounds__(256) k_gs_axpy_norm(Batch b, int j) {
   reduce_partials(part_buf(s, 1), nb, j + 1, h);
   if (MRA_BX(b) == 0)
     for (int i = threadIdx.x; i <= j; i += blockDim.x) s.H[i * s.m + j] = s.hpart[i] + h[i];
+  const size_t Nf = (size_t)s.N * s.N;
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
-    chunk_axpy(s, j, c.lo, c.hi, h);
-    double t = 0.0;
-    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) t += s.w[k] * s.w[k];
-    t = wave_sum(t);
-    if ((threadIdx.x & 63) == 0) part_buf(s, 0)[(size_t)(ch * kWavesPerBlock + (threadIdx.x >> 6)) * (kMaxM + 2)] = t;
+    double acc[1] = {0.0};
+    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
+      double t = s.w[k];
+      double v[MJ];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) v[i] = s.V[i * Nf + k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) t -= h[i] * v[i];
+      s.w[k] = t;
+      acc[0] += t * t;
+    }
+    block_sums_store<1>(acc, 1, part_buf(s, 0) + (size_t)ch * (kMaxM + 2));
+    __syncthreads();
   }
 }
 
@@ -139,11 +156,22 @@ hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int MJ>
+static void arnoldi_mj(const Batch& b, dim3 g, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_gs_dot<MJ>, g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL(k_gs_axpy_dot<MJ>, g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL(k_gs_axpy_norm<MJ>, g, dim3(256), 0, st, b, j);
+}
+
+// basis-vector register slots: the smallest bucket holding m vectors
 hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st) {
   dim3 g((red_grid(c.J)) * b.n);
-  hipLaunchKernelGGL(k_gs_dot, g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL(k_gs_axpy_dot, g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL(k_gs_axpy_norm, g, dim3(256), 0, st, b, j);
+  if (j >= c.m || c.m > kMaxM) return hipErrorInvalidValue;
+  if (c.m <= 8) arnoldi_mj<8>(b, g, j, st);
+  else if (c.m <= 16) arnoldi_mj<16>(b, g, j, st);
+  else if (c.m <= 24) arnoldi_mj<24>(b, g, j, st);
+  else if (c.m <= 32) arnoldi_mj<32>(b, g, j, st);
+  else arnoldi_mj<48>(b, g, j, st);
   return hipGetLastError();
 }
 

@@ -51,14 +51,33 @@ template <int P, typename T> __device__ inline T lap5(const T* a, int W, int r, 
   return s;
 }
 
+// A W x W periodic region staged through registers: fetch() issues every
+// global load of this thread at once, put() writes them to LDS, so the loads
+// of several regions (and other register loads) are in flight together
+// instead of one latency per loop trip.
 template <int W, typename T>
-__device__ inline void load_region(T* dst, const T* __restrict__ src, int x0, int y0, int N) {
-  const int nm = N - 1;
-  for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
-    const int r = q / W, c = q - r * W;
-    dst[q] = src[((y0 + r) & nm) * N + ((x0 + c) & nm)];
+struct Region {
+  static constexpr int NI = (W * W + 255) / 256;
+  T v[NI];
+  __device__ inline void fetch(const T* __restrict__ src, int x0, int y0, int N) {
+    const int nm = N - 1;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      if (q < W * W) {
+        const int r = q / W, c = q - r * W;
+        v[i] = src[((y0 + r) & nm) * N + ((x0 + c) & nm)];
+      }
+    }
   }
-}
+  __device__ inline void put(T* dst) const {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      if (q < W * W) dst[q] = v[i];
+    }
+  }
+};
 
 // XCD-aware tile order.  Block L of a batch of n solves runs on XCD L % 8
 // and serves solve L % n as its block L / n, so one solve's blocks are spread
@@ -104,9 +123,16 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   T* nu = vv + Wu * Wu;
   T* ww = nu + Wn * Wn;
   T* cn = ww + Ww * Ww;
-  load_region<Wu>(uu, reinterpret_cast<const T*>(s.u), x0 - G::HU, y0 - G::HU, N);
-  load_region<Wu>(vv, reinterpret_cast<const T*>(s.v), x0 - G::HU, y0 - G::HU, N);
-  load_region<Ww>(ww, reinterpret_cast<const T*>(s.wt), x0 - G::R1, y0 - G::R1, N);
+  {
+    Region<Wu, T> ru, rv;
+    Region<Ww, T> rw;
+    ru.fetch(reinterpret_cast<const T*>(s.u), x0 - G::HU, y0 - G::HU, N);
+    rv.fetch(reinterpret_cast<const T*>(s.v), x0 - G::HU, y0 - G::HU, N);
+    rw.fetch(reinterpret_cast<const T*>(s.wt), x0 - G::R1, y0 - G::R1, N);
+    ru.put(uu);
+    rv.put(vv);
+    rw.put(ww);
+  }
   __syncthreads();
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
   // nu_e on the Wn region
@@ -176,10 +202,10 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   using G = Geo<P>;
   extern __shared__ unsigned char smem[];
   const SolveDev& s = MRA_SOLVE(b);
-  if (s.ctrl[C_DONE]) return;
   const int N = s.N, ntx = s.ntx, nm = N - 1;
   const int tile = tile_of_block(MRA_BX(b), ntx * ntx, b.n);
-  if (s.tile_count[tile] == 0) return;
+  const int done = s.ctrl[C_DONE], cnt = s.tile_count[tile];
+  if (done || cnt == 0) return;
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   constexpr int Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
   constexpr int NQ = (Ww * Ww + 255) / 256;       // flux points per thread
@@ -214,8 +240,14 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
     const int q = threadIdx.x + 256 * i;
     kr[i] = q < TS * TS ? s.rank[(y0 + q / TS) * N + x0 + (q % TS)] : -1;
   }
-  load_region<Ww>(vt, reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, N);
-  load_region<Wn>(nu, reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, N);
+  {
+    Region<Ww, T> rvt;
+    Region<Wn, T> rnu;
+    rvt.fetch(reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, N);
+    rnu.fetch(reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, N);
+    rvt.put(vt);
+    rnu.put(nu);
+  }
   __syncthreads();
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
   // fluxes of the linearised advection on the Ww region, nu v~ on the Wn region

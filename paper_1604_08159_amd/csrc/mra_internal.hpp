@@ -55,7 +55,7 @@ struct SolveDev {
   double* H;                // [(m+1)][m]
   double* hpart;            // [3][kMaxM+1] Gram-Schmidt coefficients of the current column
   double* y;                // [kMaxM + 1]
-  double* partials;         // [2][kRedBlocks * 4][kMaxM + 2]
+  double* partials;         // [2][kRedBlocks][kMaxM + 2]
   double* scal;             // [S_NSCAL]
   int* ctrl;                // [C_NCTRL]
   // dense fields (element type by prec)
@@ -201,7 +201,7 @@ __host__ __device__ inline int tile_edge(int J, int p, int prec) {
 
 // ------------------------------------------------- Krylov reductions
 constexpr double kBreakdown = 1e-13;
-constexpr int kChunkMin = 512;
+constexpr int kChunkMin = 256;
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -227,27 +227,58 @@ __device__ inline Chunk chunk_of(int na, int ch) {
 
 // Partial-sum buffers: stage 1 and 3 write A, the residual norm and stage 2
 // write B, so that a kernel never overwrites partials another block of the
-// same kernel is still reading.  One slot per (chunk, wavefront).
+// same kernel is still reading.  One slot of kMaxM + 2 sums per chunk.
 constexpr int kWavesPerBlock = 4;
-constexpr int kPartSlots = kRedBlocks * kWavesPerBlock;
+constexpr int kPartSlots = kRedBlocks;
 __device__ inline double* part_buf(const SolveDev& s, int which) {
   return s.partials + (size_t)which * kPartSlots * (kMaxM + 2);
 }
 
-// totals[i] = sum over the nb * 4 slots of buf[slot][i], i < cnt, in a fixed
-// order (lanes stride the slots, then a fixed butterfly): every block that
-// calls this gets bit-identical totals.
+// totals[i] = sum over the nb slots of buf[slot][i], i < cnt <= kMaxM + 2, in
+// a fixed order (wavefront w adds slots w, w + 4, ... in turn, lane i holds
+// sum i, then the four wavefronts in order): every block that calls this gets
+// bit-identical totals.  totals is in LDS.
 __device__ inline void reduce_partials(const double* buf, int nb, int cnt, double* totals) {
+  __shared__ double part[kWavesPerBlock][kMaxM + 2];
   const int stride = kMaxM + 2;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int nslots = nb * kWavesPerBlock;
-  for (int i = wid; i < cnt; i += nw) {
-    double t = 0.0;
-    for (int q = lane; q < nslots; q += 64) t += buf[q * stride + i];
-    t = wave_sum(t);
-    if (lane == 0) totals[i] = t;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double t = 0.0;
+  if (lane < cnt) {
+#pragma unroll 8
+    for (int q = wid; q < nb; q += kWavesPerBlock) t += buf[q * stride + lane];
+    part[wid][lane] = t;
   }
   __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    double a = part[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kWavesPerBlock; ++w) a += part[w][threadIdx.x];
+    totals[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
+// Sums of acc[0 .. cnt) over the block (fixed order: within each wavefront a
+// butterfly, then the wavefronts in order) written to out[0 .. cnt).
+template <int NA>
+__device__ inline void block_sums_store(const double (&acc)[NA], int cnt, double* out) {
+  __shared__ double part[kWavesPerBlock][NA];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    if (i < cnt) {
+      double v = acc[i];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) part[wid][i] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    double a = part[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kWavesPerBlock; ++w) a += part[w][threadIdx.x];
+    out[threadIdx.x] = a;
+  }
 }
 
 // The scaling of the next basis vector, from the partials of the previous
