@@ -157,7 +157,7 @@ __device__ inline void small_dft(typename C2<T>::t* v) {
   }
 }
 
-template <int R, int S, typename T>
+template <int R, int S, typename T, bool First>
 __device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int lgL, int nfft, int lgNs, bool wl) {
   using V = typename C2<T>::t;
   constexpr int IPT = 8 / R;               // work items per thread
@@ -178,14 +178,19 @@ __device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int lgL, i
       const int k = j & (Ns - 1);
       const int base = ((q >> lgper) << lgL) + j;
       v[it][0] = buf[lx(base)];
-      // twiddles w^r, w = exp(-2 pi i k / (Ns R)): one table load, then powers
-      const V w1 = C2<T>::tw(k << twshift);
-      V wr = w1;
+      if constexpr (First) {                 // Ns = 1: every twiddle is 1
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const V x = buf[lx(base + (r << lgper))];
-        v[it][r] = S < 0 ? cmul(x, wr) : cmulc(x, wr);
-        wr = cmul(wr, w1);
+        for (int r = 1; r < R; ++r) v[it][r] = buf[lx(base + (r << lgper))];
+      } else {
+        // twiddles w^r, w = exp(-2 pi i k / (Ns R)): one table load, then powers
+        const V w1 = C2<T>::tw(k << twshift);
+        V wr = w1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const V x = buf[lx(base + (r << lgper))];
+          v[it][r] = S < 0 ? cmul(x, wr) : cmulc(x, wr);
+          wr = cmul(wr, w1);
+        }
       }
     }
   }
@@ -209,11 +214,16 @@ __device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int lgL, i
 template <int S, typename T>
 __device__ __forceinline__ void fft_block(typename C2<T>::t* buf, int lgL, int nfft) {
   const bool wl = lgL <= 9;
-  for (int lgNs = 0; lgNs < lgL;) {
+  // first pass: no twiddles
+  int lgNs;
+  if (lgL >= 3) { stockham_pass<8, S, T, true>(buf, lgL, nfft, 0, wl); lgNs = 3; }
+  else if (lgL == 2) { stockham_pass<4, S, T, true>(buf, lgL, nfft, 0, wl); lgNs = 2; }
+  else { stockham_pass<2, S, T, true>(buf, lgL, nfft, 0, wl); lgNs = 1; }
+  while (lgNs < lgL) {
     const int rem = lgL - lgNs;
-    if (rem >= 3) { stockham_pass<8, S, T>(buf, lgL, nfft, lgNs, wl); lgNs += 3; }
-    else if (rem == 2) { stockham_pass<4, S, T>(buf, lgL, nfft, lgNs, wl); lgNs += 2; }
-    else { stockham_pass<2, S, T>(buf, lgL, nfft, lgNs, wl); lgNs += 1; }
+    if (rem >= 3) { stockham_pass<8, S, T, false>(buf, lgL, nfft, lgNs, wl); lgNs += 3; }
+    else if (rem == 2) { stockham_pass<4, S, T, false>(buf, lgL, nfft, lgNs, wl); lgNs += 2; }
+    else { stockham_pass<2, S, T, false>(buf, lgL, nfft, lgNs, wl); lgNs += 1; }
   }
 }
 

@@ -165,6 +165,7 @@ __device__ inline T predict_lattice(const T* prev, int pn, int dx, int dy, int s
 // entry of V_j.
 constexpr int kFineTile = 32;
 constexpr int kLatMax = kFineTile * kFineTile;   // lattice nodes of one level of a tile
+constexpr int kSlotsPerLevel = kLatMax / 256;    // nodes of one level per thread
 
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int src, int j) {
@@ -178,22 +179,32 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
   const int x0 = (t % ntx) * B, y0 = (t / ntx) * B;
   T* f = dense_target<T>(s, target);
   const int* __restrict__ rank = s.rank;
-  const double inv = src == 1 ? next_scale(s, j, t) : 0.0;
   double* Vj = s.V + (size_t)j * N * N;
   auto owned = [&](int x, int y) { return x >= x0 && x < x0 + B && y >= y0 && y < y0 + B; };
   int pox, poy, pn, tmp;
   fine_box(J, P, B, x0, j0, &pox, &pn);
   fine_box(J, P, B, y0, j0, &poy, &tmp);
-  {
-    const int sh = J - j0;
-    for (int q = threadIdx.x; q < pn * pn; q += blockDim.x) {
-      const int iy = q / pn, ix = q - iy * pn;
-      const int x = pox + (ix << sh), y = poy + (iy << sh);
-      const int k = rank[(y & nm) * N + (x & nm)];
-      const double a = active_value(s, src, k, inv);
-      if (src == 1 && inv != 0.0 && owned(x, y)) Vj[k] = a;
-      buf[0][q] = (T)a;
+  // the coarsest lattice (all active, at most 256 nodes): rank and raw value
+  // of this thread's node are fetched while the scale is being reduced
+  const bool has0 = (int)threadIdx.x < pn * pn;
+  int x0n = 0, y0n = 0, k0n = 0;
+  double raw = 0.0;
+  if (has0) {
+    const int sh = J - j0, q = threadIdx.x;
+    const int iy = q / pn, ix = q - iy * pn;
+    x0n = pox + (ix << sh);
+    y0n = poy + (iy << sh);
+    k0n = rank[(y0n & nm) * N + (x0n & nm)];
+    raw = src == 0 ? s.omega[k0n] : (src == 2 ? s.vin[k0n] : s.w[k0n]);
+  }
+  const double inv = src == 1 ? next_scale(s, j, t) : 0.0;
+  if (has0) {
+    double a = raw;
+    if (src == 1) {
+      a = inv == 0.0 ? 0.0 : raw * inv;
+      if (inv != 0.0 && owned(x0n, y0n)) Vj[k0n] = a;
     }
+    buf[0][threadIdx.x] = (T)a;
   }
   __syncthreads();
   int cur = 0;
@@ -204,23 +215,42 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     fine_box(J, P, B, y0, l, &oy, &tmp);
     const T* prev = buf[cur];
     T* nxt = buf[cur ^ 1];
-    for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
-      const int iy = q / n, ix = q - iy * n;
-      const int x = ox + (ix << sh), y = oy + (iy << sh);
-      T v;
-      if (((x | y) & sv) == 0) {
-        v = prev[((y - poy) >> (sh + 1)) * pn + ((x - pox) >> (sh + 1))];
-      } else {
-        const int k = rank[(y & nm) * N + (x & nm)];
-        if (k >= 0) {
-          const double a = active_value(s, src, k, inv);
-          if (src == 1 && inv != 0.0 && owned(x, y)) Vj[k] = a;
-          v = (T)a;
-        } else {
-          v = predict_lattice<P, T>(prev, pn, x - pox, y - poy, sh, (x & sv) != 0, (y & sv) != 0);
-        }
+    const int nn = n * n;
+    const float rn = 1.0f / (float)n;   // exact row of q < n^2 <= 1024 for n <= 32
+    // a thread's (at most kSlotsPerLevel) nodes of this level: ranks first,
+    // then the values of the active ones, then the predictions
+    int xs[kSlotsPerLevel], ys[kSlotsPerLevel], ks[kSlotsPerLevel];
+#pragma unroll
+    for (int i = 0; i < kSlotsPerLevel; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      ks[i] = -1;
+      if (q < nn) {
+        const int iy = (int)(((float)q + 0.5f) * rn), ix = q - iy * n;
+        xs[i] = ox + (ix << sh);
+        ys[i] = oy + (iy << sh);
+        if ((xs[i] | ys[i]) & sv) ks[i] = rank[(ys[i] & nm) * N + (xs[i] & nm)];
       }
-      nxt[q] = v;
+    }
+    double av[kSlotsPerLevel];
+#pragma unroll
+    for (int i = 0; i < kSlotsPerLevel; ++i) {
+      av[i] = 0.0;
+      if (ks[i] >= 0) {
+        av[i] = active_value(s, src, ks[i], inv);
+        if (src == 1 && inv != 0.0 && owned(xs[i], ys[i])) Vj[ks[i]] = av[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kSlotsPerLevel; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      if (q < nn) {
+        const int x = xs[i], y = ys[i];
+        T v;
+        if (((x | y) & sv) == 0) v = prev[((y - poy) >> (sh + 1)) * pn + ((x - pox) >> (sh + 1))];
+        else if (ks[i] >= 0) v = (T)av[i];
+        else v = predict_lattice<P, T>(prev, pn, x - pox, y - poy, sh, (x & sv) != 0, (y & sv) != 0);
+        nxt[q] = v;
+      }
     }
     __syncthreads();
     cur ^= 1;
@@ -270,7 +300,7 @@ static bool lattice_fits(int J, int P) {
     for (int l = j0; l <= J; ++l) {
       const int n = lattice_count(J, P, B, x0, l);
       if (n != lattice_count(J, P, B, 0, l)) return false;
-      if (n * n > kLatMax) return false;
+      if (n * n > kLatMax || (l == j0 && n * n > 256)) return false;
     }
   }
   return true;
