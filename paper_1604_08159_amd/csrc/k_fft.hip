@@ -157,74 +157,76 @@ __device__ inline void small_dft(typename C2<T>::t* v) {
   }
 }
 
-template <int R, int S, typename T, bool First>
-__device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int lgL, int nfft, int lgNs, bool wl) {
+// One radix-2^LGR pass over NF vectors of length 2^LGL (Ns = 2^LGNS), all
+// sizes compile-time, so index arithmetic is shifts and immediate offsets.
+template <int S, typename T, int LGL, int NF, int LGNS, int LGR>
+__device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int nfft) {
   using V = typename C2<T>::t;
-  constexpr int IPT = 8 / R;               // work items per thread
-  constexpr int lgR = R == 8 ? 3 : (R == 4 ? 2 : 1);
-  constexpr int lgIPT = 3 - lgR;
-  const int lgper = lgL - lgR;             // L / R items per vector, all powers of two
-  const int total = nfft << lgper;
-  const int Ns = 1 << lgNs;
-  const int twshift = ilog2(kTwN) - lgNs - lgR;
+  constexpr int R = 1 << LGR, IPT = 8 / R, LGIPT = 3 - LGR;
+  constexpr int LGPER = LGL - LGR, PER = 1 << LGPER;      // items per vector
+  constexpr int NS = 1 << LGNS;
+  constexpr int TWSHIFT = 11 - LGNS - LGR;                // kTwN = 2^11
+  constexpr bool WL = LGL <= 9;
+  constexpr bool FULL = NF * PER == kFftThreads * IPT;    // every (thread, it) has an item
+  static_assert(NF * (1 << LGL) <= kFftPoints, "FFT block size");
+  const int total = nfft << LGPER;
   // item of (thread, it): wavefront w takes items [64 IPT w, 64 IPT (w + 1))
-  const int qbase = ((threadIdx.x >> 6) << (6 + lgIPT)) + (threadIdx.x & 63);
+  const int qbase = ((threadIdx.x >> 6) << (6 + LGIPT)) + (threadIdx.x & 63);
   V v[IPT][R];
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
     const int q = qbase + (it << 6);
-    if (q < total) {
-      const int j = q & ((1 << lgper) - 1);
-      const int k = j & (Ns - 1);
-      const int base = ((q >> lgper) << lgL) + j;
-      v[it][0] = buf[lx(base)];
-      if constexpr (First) {                 // Ns = 1: every twiddle is 1
+    if (FULL || q < total) {
+      const int j = q & (PER - 1);
+      const int base = ((q >> LGPER) << LGL) + j;
+      if constexpr (LGNS == 0) {             // first pass: every twiddle is 1
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[it][r] = buf[lx(base + (r << lgper))];
+        for (int r = 0; r < R; ++r) v[it][r] = buf[lx(base + r * PER)];
       } else {
         // twiddles w^r, w = exp(-2 pi i k / (Ns R)): one table load, then powers
-        const V w1 = C2<T>::tw(k << twshift);
+        const V w1 = C2<T>::tw((j & (NS - 1)) << TWSHIFT);
+        v[it][0] = buf[lx(base)];
         V wr = w1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const V x = buf[lx(base + (r << lgper))];
+          const V x = buf[lx(base + r * PER)];
           v[it][r] = S < 0 ? cmul(x, wr) : cmulc(x, wr);
           wr = cmul(wr, w1);
         }
       }
     }
   }
-  fft_sync(wl);
+  fft_sync(WL);
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
     const int q = qbase + (it << 6);
-    if (q < total) {
-      const int j = q & ((1 << lgper) - 1);
-      const int k = j & (Ns - 1);
+    if (FULL || q < total) {
+      const int j = q & (PER - 1);
+      const int k = j & (NS - 1);
       small_dft<R, S, T>(v[it]);
-      const int base = ((q >> lgper) << lgL) + ((j - k) << lgR) + k;
+      const int base = ((q >> LGPER) << LGL) + ((j - k) << LGR) + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lx(base + (r << lgNs))] = v[it][r];
+      for (int r = 0; r < R; ++r) buf[lx(base + r * NS)] = v[it][r];
     }
   }
-  fft_sync(wl);
+  fft_sync(WL);
 }
 
-// nfft vectors of length 2^lgL at stride 2^lgL; wavefront-local when L <= 512
-template <int S, typename T>
-__device__ __forceinline__ void fft_block(typename C2<T>::t* buf, int lgL, int nfft) {
-  const bool wl = lgL <= 9;
-  // first pass: no twiddles
-  int lgNs;
-  if (lgL >= 3) { stockham_pass<8, S, T, true>(buf, lgL, nfft, 0, wl); lgNs = 3; }
-  else if (lgL == 2) { stockham_pass<4, S, T, true>(buf, lgL, nfft, 0, wl); lgNs = 2; }
-  else { stockham_pass<2, S, T, true>(buf, lgL, nfft, 0, wl); lgNs = 1; }
-  while (lgNs < lgL) {
-    const int rem = lgL - lgNs;
-    if (rem >= 3) { stockham_pass<8, S, T, false>(buf, lgL, nfft, lgNs, wl); lgNs += 3; }
-    else if (rem == 2) { stockham_pass<4, S, T, false>(buf, lgL, nfft, lgNs, wl); lgNs += 2; }
-    else { stockham_pass<2, S, T, false>(buf, lgL, nfft, lgNs, wl); lgNs += 1; }
+template <int S, typename T, int LGL, int NF, int LGNS>
+__device__ __forceinline__ void fft_passes(typename C2<T>::t* buf, int nfft) {
+  if constexpr (LGNS < LGL) {
+    constexpr int REM = LGL - LGNS;
+    constexpr int LGR = REM >= 3 ? 3 : REM;
+    stockham_pass<S, T, LGL, NF, LGNS, LGR>(buf, nfft);
+    fft_passes<S, T, LGL, NF, LGNS + LGR>(buf, nfft);
   }
+}
+
+// nfft <= NF vectors of length 2^LGL at stride 2^LGL; wavefront-local when
+// L <= 512
+template <int S, typename T, int LGL, int NF>
+__device__ __forceinline__ void fft_block(typename C2<T>::t* buf, int nfft) {
+  fft_passes<S, T, LGL, NF, 0>(buf, nfft);
 }
 
 template <typename T>
@@ -241,28 +243,37 @@ __device__ inline T* poisson_dst(const SolveDev& s, int src, int comp) {
   return reinterpret_cast<T*>(s.vel64 + (size_t)comp * s.N * s.N);
 }
 
+// Launch geometry, compile-time per grid level J (N = 2^J, M = N/2):
+// rows per row-pass block and spectrum rows per column-pass block.
+template <int J> struct FftGeo {
+  static constexpr int N = 1 << J, M = N >> 1, LGM = J - 1;
+  static constexpr int R = (kFftPoints >> LGM) < N ? (kFftPoints >> LGM) : N;
+  static constexpr int C = (kFftPoints >> J) < M + 1 ? (kFftPoints >> J) : M + 1;
+};
+
 // pass A: rows -> spec[kx][y], R rows per block (R * N/2 <= 2048)
-template <typename T>
-__global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src, int R) {
+template <typename T, int J>
+__global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src) {
   using V = typename C2<T>::t;
+  using G = FftGeo<J>;
+  constexpr int N = G::N, M = G::M, R = G::R;
   extern __shared__ unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
   const SolveDev& s = MRA_SOLVE(b);
-  const int N = s.N, M = N >> 1;
   const int y0 = MRA_BX(b) * R;
   const V* in = reinterpret_cast<const V*>(poisson_src<T>(s, src));
-  const int lgR = ilog2((unsigned)R), lgM = s.J - 1;
-  const int n = R * M, e1 = min(own0() + kWaveSpan, n);
+  constexpr int n = R * M;
+  const int e1 = min(own0() + kWaveSpan, n);
   for (int q = own0() + lane(); q < e1; q += 64) buf[lx(q)] = in[(size_t)y0 * M + q];
-  fft_sync(lgM <= 9);
-  fft_block<-1, T>(buf, lgM, R);
+  fft_sync(G::LGM <= 9);
+  fft_block<-1, T, G::LGM, R>(buf, R);
   __syncthreads();
   V* spec = reinterpret_cast<V*>(s.spec);
-  const int twN = kTwN / N;
-  for (int q = threadIdx.x; q < (M + 1) * R; q += blockDim.x) {
-    const int k = q >> lgR, r = q & (R - 1);
-    const V zk = buf[lx((r << lgM) + (k & (M - 1)))];
-    const V zc = cconj(buf[lx((r << lgM) + ((M - k) & (M - 1)))]);
+  constexpr int twN = kTwN / N;
+  for (int q = threadIdx.x; q < (M + 1) * R; q += kFftThreads) {
+    const int k = q / R, r = q % R;
+    const V zk = buf[lx(r * M + (k & (M - 1)))];
+    const V zc = cconj(buf[lx(r * M + ((M - k) & (M - 1)))]);
     const V e = cmul(csub(zk, zc), C2<T>::tw(k * twN));
     V x;
     x.x = T(0.5) * (zk.x + zc.x + e.y);
@@ -273,23 +284,24 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src, 
 
 // pass B: C spectrum rows (fixed kx) per block (C * N <= 2048).  LDS: A holds
 // psi_hat, B the u (then the v) spectrum; 2 * 2048 complex values at most.
-template <int P, typename T>
-__global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b, int C) {
+template <int P, typename T, int J>
+__global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b) {
   using V = typename C2<T>::t;
+  using G = FftGeo<J>;
+  constexpr int N = G::N, M = G::M, C = G::C;
   extern __shared__ unsigned char smem[];
   const SolveDev& s = MRA_SOLVE(b);
-  const int J = s.J, N = s.N, M = N >> 1;
   V* A = reinterpret_cast<V*>(smem);
   V* Bv = A + lds_slots(C * N);
   const int k0 = MRA_BX(b) * C;
   const int nr = (M + 1 - k0) < C ? (M + 1 - k0) : C;
   V* specU = reinterpret_cast<V*>(s.spec);
   V* specV = reinterpret_cast<V*>(s.spec2);
-  const bool wl = J <= 9;
+  constexpr bool wl = J <= 9;
   const int e1 = min(own0() + kWaveSpan, nr * N);
   for (int q = own0() + lane(); q < e1; q += 64) A[lx(q)] = specU[(size_t)k0 * N + q];
   fft_sync(wl);
-  fft_block<-1, T>(A, J, nr);
+  fft_block<-1, T, J, C>(A, nr);
   const T h2n = T(-s.h * s.h / ((double)N * (double)N));
   const T ih = T(1.0 / s.h);
   for (int q = own0() + lane(); q < e1; q += 64) {
@@ -304,7 +316,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b, int C) {
     Bv[lx(q)] = V{-sy * ps.y, sy * ps.x};                  // i s1(ky) psi_hat
   }
   fft_sync(wl);
-  fft_block<1, T>(Bv, J, nr);
+  fft_block<1, T, J, C>(Bv, nr);
   for (int q = own0() + lane(); q < e1; q += 64) specU[(size_t)k0 * N + q] = Bv[lx(q)];
   fft_sync(wl);
   for (int q = own0() + lane(); q < e1; q += 64) {
@@ -313,36 +325,36 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b, int C) {
     Bv[lx(q)] = V{sx * z.y, -sx * z.x};                    // -i s1(kx) psi_hat
   }
   fft_sync(wl);
-  fft_block<1, T>(Bv, J, nr);
+  fft_block<1, T, J, C>(Bv, nr);
   for (int q = own0() + lane(); q < e1; q += 64) specV[(size_t)k0 * N + q] = Bv[lx(q)];
 }
 
 // pass C: spec[kx][y] -> real rows, R rows per block (R * N/2 <= 2048), for
 // the u spectrum and then the v spectrum.
-template <typename T>
-__global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src, int R) {
+template <typename T, int J>
+__global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) {
   using V = typename C2<T>::t;
+  using G = FftGeo<J>;
+  constexpr int N = G::N, M = G::M, R = G::R;
   extern __shared__ unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
   const SolveDev& s = MRA_SOLVE(b);
-  const int N = s.N, M = N >> 1;
   const int y0 = MRA_BX(b) * R;
-  const int twN = kTwN / N;
-  const int lgR = ilog2((unsigned)R), lgM = s.J - 1;
+  constexpr int twN = kTwN / N;
   for (int comp = 0; comp < 2; ++comp) {
     const V* spec = reinterpret_cast<const V*>(comp == 0 ? s.spec : s.spec2);
-    for (int q = threadIdx.x; q < M * R; q += blockDim.x) {
-      const int k = q >> lgR, r = q & (R - 1);
+    for (int q = threadIdx.x; q < M * R; q += kFftThreads) {
+      const int k = q / R, r = q % R;
       const V xk = spec[(size_t)k * N + y0 + r];
       const V xc = cconj(spec[(size_t)(M - k) * N + y0 + r]);
       const V e = cmulc(csub(xk, xc), C2<T>::tw(k * twN));
       V z;
       z.x = xk.x + xc.x - e.y;
       z.y = xk.y + xc.y + e.x;
-      buf[lx((r << lgM) + k)] = z;
+      buf[lx(r * M + k)] = z;
     }
     __syncthreads();
-    fft_block<1, T>(buf, lgM, R);
+    fft_block<1, T, G::LGM, R>(buf, R);
     V* out = reinterpret_cast<V*>(poisson_dst<T>(s, src, comp));
     const int e1 = min(own0() + kWaveSpan, R * M);
     for (int q = own0() + lane(); q < e1; q += 64) out[(size_t)y0 * M + q] = buf[lx(q)];
@@ -350,33 +362,38 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src, 
   }
 }
 
-static int rows_per_block(int N) {
-  int r = kFftPoints / (N / 2);
-  return r < N ? r : N;
-}
-static int cols_per_block(int N) {
-  int c = kFftPoints / N;
-  return c < N / 2 + 1 ? c : N / 2 + 1;
+template <typename T, int J>
+static void poisson_j(const Batch& b, int p, int src, int pass, hipStream_t st) {
+  using V = typename C2<T>::t;
+  using G = FftGeo<J>;
+  if (pass < 0 || pass == 0)
+    hipLaunchKernelGGL((k_fft_rows_fwd<T, J>), dim3((G::N / G::R) * b.n), dim3(kFftThreads),
+                       lds_slots(G::R * G::M) * sizeof(V), st, b, src);
+  if (pass < 0 || pass == 1) {
+    dim3 g(((G::M + 1 + G::C - 1) / G::C) * b.n);
+    const size_t lds = 2 * (size_t)lds_slots(G::C * G::N) * sizeof(V);
+    if (p == 2) hipLaunchKernelGGL((k_fft_cols<2, T, J>), g, dim3(kFftThreads), lds, st, b);
+    else hipLaunchKernelGGL((k_fft_cols<3, T, J>), g, dim3(kFftThreads), lds, st, b);
+  }
+  if (pass < 0 || pass == 2)
+    hipLaunchKernelGGL((k_fft_rows_inv<T, J>), dim3((G::N / G::R) * b.n), dim3(kFftThreads),
+                       lds_slots(G::R * G::M) * sizeof(V), st, b, src);
 }
 
 template <typename T>
 static hipError_t poisson_t(const Batch& b, const LaunchCfg& c, int src, int pass, hipStream_t st) {
-  using V = typename C2<T>::t;
-  const int N = 1 << c.J, M = N / 2;
-  const int R = rows_per_block(N);
-  const int C = cols_per_block(N);
-  if (pass < 0 || pass == 0)
-    hipLaunchKernelGGL(k_fft_rows_fwd<T>, dim3((N / R) * b.n), dim3(kFftThreads), lds_slots(R * M) * sizeof(V), st, b,
-                       src, R);
-  if (pass < 0 || pass == 1) {
-    dim3 g(((M + 1 + C - 1) / C) * b.n);
-    const size_t lds = 2 * (size_t)lds_slots(C * N) * sizeof(V);
-    if (c.p == 2) hipLaunchKernelGGL((k_fft_cols<2, T>), g, dim3(kFftThreads), lds, st, b, C);
-    else hipLaunchKernelGGL((k_fft_cols<3, T>), g, dim3(kFftThreads), lds, st, b, C);
+  switch (c.J) {
+    case 3: poisson_j<T, 3>(b, c.p, src, pass, st); break;
+    case 4: poisson_j<T, 4>(b, c.p, src, pass, st); break;
+    case 5: poisson_j<T, 5>(b, c.p, src, pass, st); break;
+    case 6: poisson_j<T, 6>(b, c.p, src, pass, st); break;
+    case 7: poisson_j<T, 7>(b, c.p, src, pass, st); break;
+    case 8: poisson_j<T, 8>(b, c.p, src, pass, st); break;
+    case 9: poisson_j<T, 9>(b, c.p, src, pass, st); break;
+    case 10: poisson_j<T, 10>(b, c.p, src, pass, st); break;
+    case 11: poisson_j<T, 11>(b, c.p, src, pass, st); break;
+    default: return hipErrorInvalidValue;
   }
-  if (pass < 0 || pass == 2)
-    hipLaunchKernelGGL(k_fft_rows_inv<T>, dim3((N / R) * b.n), dim3(kFftThreads), lds_slots(R * M) * sizeof(V), st, b,
-                       src, R);
   return hipGetLastError();
 }
 
