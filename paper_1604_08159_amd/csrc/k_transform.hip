@@ -162,39 +162,143 @@ __device__ inline T predict_lattice(const T* prev, int pn, int dx, int dy, int s
 // Active nodes take their value through the rank map; for src 1 every block
 // derives the scale of the new Arnoldi vector from the previous kernel's
 // partial sums (block 0 records it) and the tile that owns a node writes its
-// entry of V_j.
+// entry of V_j.  The kernel is specialised per grid level J: every lattice
+// size, halo and shift is a compile-time constant.
 constexpr int kFineTile = 32;
 constexpr int kLatMax = kFineTile * kFineTile;   // lattice nodes of one level of a tile
-constexpr int kSlotsPerLevel = kLatMax / 256;    // nodes of one level per thread
 
-template <int P, typename T>
+// halo E_l of the level-l lattice (fine units) and its node count per side
+// (independent of the tile offset; checked on the host for every offset)
+__host__ __device__ constexpr int lat_halo(int J, int P, int l) {
+  int E = 0;
+  for (int q = J; q > l; --q) E += (2 * P - 1) << (J - q);
+  return E;
+}
+__host__ __device__ constexpr int lat_floor(int v, int sh) {   // largest multiple of 2^sh <= v
+  return v >= 0 ? (v >> sh) << sh : -((((-v) + (1 << sh) - 1) >> sh) << sh);
+}
+__host__ __device__ constexpr int lat_count(int J, int P, int B, int x0, int l) {
+  const int sh = J - l, E = lat_halo(J, P, l);
+  const int lo = x0 - E, hi = x0 + B - 1 + E;
+  return ((hi - lat_floor(lo, sh)) >> sh) + 1;
+}
+template <int J, int P, int L>
+__device__ inline int lat_origin(int x0) {
+  constexpr int SH = J - L, E = lat_halo(J, P, L);
+  return ((x0 - E) >> SH) << SH;         // floor to the lattice (arithmetic shift)
+}
+
+template <int P, typename T, int PN, int SH>
+__device__ inline T predict_lattice_ct(const T* prev, int dx, int dy, bool oxd, bool oyd) {
+  constexpr int SV = 1 << SH;
+  T c[2 * P];
+  if (oxd && !oyd) {
+    const int r = dy >> (SH + 1), a = ((dx - SV) >> (SH + 1)) - (P - 1);
+#pragma unroll
+    for (int o = 0; o < 2 * P; ++o) c[o] = prev[r * PN + a + o];
+    return dd_pred<P, T>(c);
+  } else if (oyd && !oxd) {
+    const int a = dx >> (SH + 1), bb = ((dy - SV) >> (SH + 1)) - (P - 1);
+#pragma unroll
+    for (int o = 0; o < 2 * P; ++o) c[o] = prev[(bb + o) * PN + a];
+    return dd_pred<P, T>(c);
+  } else {
+    const int a = ((dx - SV) >> (SH + 1)) - (P - 1), bb = ((dy - SV) >> (SH + 1)) - (P - 1);
+    T py[2 * P];
+#pragma unroll
+    for (int o2 = 0; o2 < 2 * P; ++o2) {
+#pragma unroll
+      for (int o = 0; o < 2 * P; ++o) c[o] = prev[(bb + o) * PN + a + o2];
+      py[o2] = dd_pred<P, T>(c);
+    }
+    return dd_pred<P, T>(py);
+  }
+}
+
+// Level L of the sweep (lattice of level L - 1 in buf[cur]), then the next.
+template <int P, typename T, int J, int L>
+__device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLatMax], int cur, int x0, int y0,
+                                                 int src, double inv, double* Vj, T* f) {
+#pragma clang fp contract(off)
+  constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile;
+  constexpr int SH = J - L, SV = 1 << SH;
+  constexpr int n = lat_count(J, P, B, 0, L), pn = lat_count(J, P, B, 0, L - 1);
+  constexpr int NN = n * n, SLOTS = (NN + 255) / 256;
+  static_assert(NN <= kLatMax && SLOTS <= 4, "lattice of one level exceeds the tile buffer");
+  const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
+  const int pox = lat_origin<J, P, L - 1>(x0), poy = lat_origin<J, P, L - 1>(y0);
+  const int* __restrict__ rank = s.rank;
+  const T* prev = buf[cur];
+  T* nxt = buf[cur ^ 1];
+  // a thread's nodes of this level: ranks first, then the values of the
+  // active ones, then the predictions
+  int xs[SLOTS], ys[SLOTS], ks[SLOTS];
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    ks[i] = -1;
+    if (q < NN) {
+      const int iy = q / n, ix = q - iy * n;
+      xs[i] = ox + (ix << SH);
+      ys[i] = oy + (iy << SH);
+      if ((xs[i] | ys[i]) & SV) ks[i] = rank[(ys[i] & NM) * N + (xs[i] & NM)];
+    }
+  }
+  double av[SLOTS];
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) {
+    av[i] = 0.0;
+    if (ks[i] >= 0) {
+      av[i] = active_value(s, src, ks[i], inv);
+      if (src == 1 && inv != 0.0 && xs[i] >= x0 && xs[i] < x0 + B && ys[i] >= y0 && ys[i] < y0 + B)
+        Vj[ks[i]] = av[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    if (q < NN) {
+      const int x = xs[i], y = ys[i];
+      T v;
+      if (((x | y) & SV) == 0) v = prev[((y - poy) >> (SH + 1)) * pn + ((x - pox) >> (SH + 1))];
+      else if (ks[i] >= 0) v = (T)av[i];
+      else v = predict_lattice_ct<P, T, pn, SH>(prev, x - pox, y - poy, (x & SV) != 0, (y & SV) != 0);
+      if constexpr (L == J) f[(y0 + q / B) * N + x0 + (q % B)] = v;   // finest lattice = the tile
+      else nxt[q] = v;
+    }
+  }
+  if constexpr (L < J) {
+    __syncthreads();
+    prolong_level_ct<P, T, J, L + 1>(s, buf, cur ^ 1, x0, y0, src, inv, Vj, f);
+  }
+}
+
+template <int P, typename T, int J>
 __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int src, int j) {
 #pragma clang fp contract(off)
-  __shared__ T buf[2][kFineTile * kFineTile];
+  constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile, NTX = N / B;
+  constexpr int J0 = P == 2 ? 2 : 3;
+  constexpr int pn = lat_count(J, P, B, 0, J0), SH0 = J - J0;
+  static_assert(pn * pn <= 256, "coarsest lattice exceeds one node per thread");
+  static_assert(lat_count(J, P, B, 0, J) == B, "finest lattice is the tile");
+  __shared__ T buf[2][kLatMax];
   const SolveDev& s = MRA_SOLVE(b);
-  const int J = s.J, N = s.N, nm = N - 1, j0 = s.j0;
-  const int B = N < kFineTile ? N : kFineTile;
-  const int ntx = N / B;
   const int t = MRA_BX(b);
-  const int x0 = (t % ntx) * B, y0 = (t / ntx) * B;
+  const int x0 = (t % NTX) * B, y0 = (t / NTX) * B;
   T* f = dense_target<T>(s, target);
-  const int* __restrict__ rank = s.rank;
   double* Vj = s.V + (size_t)j * N * N;
-  auto owned = [&](int x, int y) { return x >= x0 && x < x0 + B && y >= y0 && y < y0 + B; };
-  int pox, poy, pn, tmp;
-  fine_box(J, P, B, x0, j0, &pox, &pn);
-  fine_box(J, P, B, y0, j0, &poy, &tmp);
+  const int pox = lat_origin<J, P, J0>(x0), poy = lat_origin<J, P, J0>(y0);
   // the coarsest lattice (all active, at most 256 nodes): rank and raw value
   // of this thread's node are fetched while the scale is being reduced
   const bool has0 = (int)threadIdx.x < pn * pn;
   int x0n = 0, y0n = 0, k0n = 0;
   double raw = 0.0;
   if (has0) {
-    const int sh = J - j0, q = threadIdx.x;
+    const int q = threadIdx.x;
     const int iy = q / pn, ix = q - iy * pn;
-    x0n = pox + (ix << sh);
-    y0n = poy + (iy << sh);
-    k0n = rank[(y0n & nm) * N + (x0n & nm)];
+    x0n = pox + (ix << SH0);
+    y0n = poy + (iy << SH0);
+    k0n = s.rank[(y0n & NM) * N + (x0n & NM)];
     raw = src == 0 ? s.omega[k0n] : (src == 2 ? s.vin[k0n] : s.w[k0n]);
   }
   const double inv = src == 1 ? next_scale(s, j, t) : 0.0;
@@ -202,63 +306,12 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     double a = raw;
     if (src == 1) {
       a = inv == 0.0 ? 0.0 : raw * inv;
-      if (inv != 0.0 && owned(x0n, y0n)) Vj[k0n] = a;
+      if (inv != 0.0 && x0n >= x0 && x0n < x0 + B && y0n >= y0 && y0n < y0 + B) Vj[k0n] = a;
     }
     buf[0][threadIdx.x] = (T)a;
   }
   __syncthreads();
-  int cur = 0;
-  for (int l = j0 + 1; l <= J; ++l) {
-    const int sh = J - l, sv = 1 << sh;
-    int ox, oy, n;
-    fine_box(J, P, B, x0, l, &ox, &n);
-    fine_box(J, P, B, y0, l, &oy, &tmp);
-    const T* prev = buf[cur];
-    T* nxt = buf[cur ^ 1];
-    const int nn = n * n;
-    const float rn = 1.0f / (float)n;   // exact row of q < n^2 <= 1024 for n <= 32
-    // a thread's (at most kSlotsPerLevel) nodes of this level: ranks first,
-    // then the values of the active ones, then the predictions
-    int xs[kSlotsPerLevel], ys[kSlotsPerLevel], ks[kSlotsPerLevel];
-#pragma unroll
-    for (int i = 0; i < kSlotsPerLevel; ++i) {
-      const int q = threadIdx.x + 256 * i;
-      ks[i] = -1;
-      if (q < nn) {
-        const int iy = (int)(((float)q + 0.5f) * rn), ix = q - iy * n;
-        xs[i] = ox + (ix << sh);
-        ys[i] = oy + (iy << sh);
-        if ((xs[i] | ys[i]) & sv) ks[i] = rank[(ys[i] & nm) * N + (xs[i] & nm)];
-      }
-    }
-    double av[kSlotsPerLevel];
-#pragma unroll
-    for (int i = 0; i < kSlotsPerLevel; ++i) {
-      av[i] = 0.0;
-      if (ks[i] >= 0) {
-        av[i] = active_value(s, src, ks[i], inv);
-        if (src == 1 && inv != 0.0 && owned(xs[i], ys[i])) Vj[ks[i]] = av[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kSlotsPerLevel; ++i) {
-      const int q = threadIdx.x + 256 * i;
-      if (q < nn) {
-        const int x = xs[i], y = ys[i];
-        T v;
-        if (((x | y) & sv) == 0) v = prev[((y - poy) >> (sh + 1)) * pn + ((x - pox) >> (sh + 1))];
-        else if (ks[i] >= 0) v = (T)av[i];
-        else v = predict_lattice<P, T>(prev, pn, x - pox, y - poy, sh, (x & sv) != 0, (y & sv) != 0);
-        nxt[q] = v;
-      }
-    }
-    __syncthreads();
-    cur ^= 1;
-    pox = ox;
-    poy = oy;
-    pn = n;
-  }
-  for (int q = threadIdx.x; q < B * B; q += blockDim.x) f[(y0 + q / B) * N + x0 + (q % B)] = buf[cur][q];
+  prolong_level_ct<P, T, J, J0 + 1>(s, buf, 0, x0, y0, src, inv, Vj, f);
 }
 
 template <int P, typename T>
@@ -282,39 +335,44 @@ __global__ void k_inverse_coarse(Batch b, int target) {
 }
 
 // Host check of k_prolong_tiles' assumptions for a grid, over every tile
-// offset: each level's lattice count is the same for every offset (so the
-// x and y lattices of a tile have equal size) and all lattices fit in LDS.
-static int lattice_count(int J, int P, int B, int x0, int l) {
-  int E = 0;
-  for (int q = J; q > l; --q) E += (2 * P - 1) << (J - q);
-  const int sh = J - l;
-  const int lo = x0 - E, hi = x0 + B - 1 + E;
-  const int oo = (lo >> sh) << sh;
-  return ((hi - oo) >> sh) + 1;
-}
-
+// offset: each level's lattice count is the one the kernel was compiled for
+// (the count at offset 0, so the x and y lattices of a tile have equal size).
 static bool lattice_fits(int J, int P) {
   const int N = 1 << J, j0 = P == 2 ? 2 : 3;
   const int B = N < kFineTile ? N : kFineTile;
-  for (int x0 = 0; x0 < N; x0 += B) {
-    for (int l = j0; l <= J; ++l) {
-      const int n = lattice_count(J, P, B, x0, l);
-      if (n != lattice_count(J, P, B, 0, l)) return false;
-      if (n * n > kLatMax || (l == j0 && n * n > 256)) return false;
-    }
-  }
+  for (int x0 = 0; x0 < N; x0 += B)
+    for (int l = j0; l <= J; ++l)
+      if (lat_count(J, P, B, x0, l) != lat_count(J, P, B, 0, l)) return false;
   return true;
+}
+
+template <int P, typename T, int J>
+static void prolong_j(const Batch& b, int target, int src, int j, hipStream_t st) {
+  constexpr int N = 1 << J, B = N < kFineTile ? N : kFineTile;
+  hipLaunchKernelGGL((k_prolong_tiles<P, T, J>), dim3((N / B) * (N / B) * b.n), dim3(256), 0, st, b, target, src, j);
+}
+
+template <int P, typename T>
+static hipError_t prolong_p(const Batch& b, int J, int target, int src, int j, hipStream_t st) {
+  switch (J) {
+    case 3: if constexpr (P == 2) { prolong_j<P, T, 3>(b, target, src, j, st); break; } return hipErrorInvalidValue;
+    case 4: prolong_j<P, T, 4>(b, target, src, j, st); break;
+    case 5: prolong_j<P, T, 5>(b, target, src, j, st); break;
+    case 6: prolong_j<P, T, 6>(b, target, src, j, st); break;
+    case 7: prolong_j<P, T, 7>(b, target, src, j, st); break;
+    case 8: prolong_j<P, T, 8>(b, target, src, j, st); break;
+    case 9: prolong_j<P, T, 9>(b, target, src, j, st); break;
+    case 10: prolong_j<P, T, 10>(b, target, src, j, st); break;
+    case 11: prolong_j<P, T, 11>(b, target, src, j, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t prolong_t(const Batch& b, const LaunchCfg& c, int target, int src, int j, hipStream_t st) {
-  const int N = 1 << c.J;
-  const int B = N < kFineTile ? N : kFineTile;
-  const int nt = (N / B) * (N / B);
   if (!lattice_fits(c.J, c.p)) return hipErrorInvalidValue;
-  if (c.p == 2) hipLaunchKernelGGL((k_prolong_tiles<2, T>), dim3(nt * b.n), dim3(256), 0, st, b, target, src, j);
-  else hipLaunchKernelGGL((k_prolong_tiles<3, T>), dim3(nt * b.n), dim3(256), 0, st, b, target, src, j);
-  return hipGetLastError();
+  return c.p == 2 ? prolong_p<2, T>(b, c.J, target, src, j, st) : prolong_p<3, T>(b, c.J, target, src, j, st);
 }
 
 // inverse transform: coarse copy, coarse kernel, one launch per finer level
