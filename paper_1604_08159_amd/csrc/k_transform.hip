@@ -221,7 +221,7 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
                                                  int src, double inv, double* Vj, T* f) {
 #pragma clang fp contract(off)
   constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile;
-  constexpr int SH = J - L, SV = 1 << SH;
+  constexpr int SH = J - L, SV = 1 << SH;  // node spacing of level L (fine units)
   constexpr int n = lat_count(J, P, B, 0, L), pn = lat_count(J, P, B, 0, L - 1);
   constexpr int NN = n * n, SLOTS = (NN + 255) / 256;
   static_assert(NN <= kLatMax && SLOTS <= 4, "lattice of one level exceeds the tile buffer");
