@@ -143,12 +143,13 @@ __global__ void __launch_bounds__(256) k_gs_axpy_norm(Batch b, int j) {
   }
 }
 
-// Grid of the reductions: enough blocks for the largest possible active set
-// of the grid, at most 256 per solve (blocks loop over chunks).
+// Grid of the reductions: at most kRedGrid blocks per solve (blocks loop
+// over chunks), fewer on grids too small to fill them.
+constexpr int kRedGrid = 64;
 static int red_grid(int J) {
   const int nf = 1 << (2 * J);
   int g = (nf + kChunkMin - 1) / kChunkMin;
-  return g < 256 ? g : 256;
+  return g < kRedGrid ? g : kRedGrid;
 }
 
 hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st) {
