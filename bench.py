@@ -99,6 +99,30 @@ def fp64_per_solve(m, W, dev, steps: int) -> dict:
             "solves_per_s_at_2000_steps": 1.0 / (wall / steps * 2000)}
 
 
+def accuracy_vs_fp64(m, W, dev, solve, seed: int, steps: int) -> dict:
+    """Mixed-precision solve against the same solve run with FP64 bulk fields
+    for the same number of steps: relative L2 of the vorticity field and the
+    relative differences of energy and enstrophy."""
+    import torch
+    stream = torch.cuda.Stream(device=dev)
+    pb = W.fujiwhara_pair(seed)
+    with torch.cuda.stream(stream):
+        w0 = torch.from_numpy(W.initial_field(pb)).to(dev)
+        ref = m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_FP64, pb.m, pb.dt, w0,
+                      stream=stream)
+    ref.step(steps, stream=stream)
+    a, da = ref.read(stream=stream)
+    b, db = solve.read(stream=stream)
+    stream.synchronize()
+    ref.close()
+    rel = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a))
+    return {"seed": seed, "steps": steps, "rel_l2_vorticity": rel,
+            "rel_energy": abs(da["energy"] - db["energy"]) / da["energy"],
+            "rel_enstrophy": abs(da["enstrophy"] - db["enstrophy"]) / da["enstrophy"],
+            "n_active_fp64": int(da["n_active"]), "n_active_mixed": int(db["n_active"]),
+            "tolerance": 1e-5, "within": rel <= 1e-5}
+
+
 def cpu_baseline(steps: int) -> dict:
     """The FP64 oracle on one solve of the batch, single-threaded, timed here."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
@@ -302,8 +326,10 @@ def main() -> int:
     torch.cuda.synchronize()
     del cal_a, cal_b
     compare = None
+    accuracy = None
     if not args.no_fp64_compare and prec == m.MRA_MIXED:
         compare = fp64_per_solve(m, W, dev, max(10, args.steps // 10))
+        accuracy = accuracy_vs_fp64(m, W, dev, solves[0], seeds[0], args.warmup + args.steps)
 
     out = {
         "metric": METRIC,
@@ -333,6 +359,8 @@ def main() -> int:
                        "note": "batch solves/s if each solve ran the configuration's 2000 steps"}
     if compare is not None:
         out["fp64_per_solve_gpu"] = compare
+    if accuracy is not None:
+        out["fp32_vs_fp64"] = accuracy
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     for s in solves:
