@@ -319,12 +319,23 @@ def main() -> int:
     nbytes = kernel_bytes(args.kernel, N, int(sum(nas) / len(nas)), frac_t, n, esz)
     achieved = nbytes / (k_ms * 1e-3) / 1e9
 
-    # plain copy of known size: the byte-counter scale of profiled runs
+    # plain copy of known size: the byte-counter scale of profiled runs, and
+    # (timed) the practical streaming ceiling of this device
     cal_a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
     cal_b = torch.empty_like(cal_a)
     cal_b.copy_(cal_a)
     torch.cuda.synchronize()
-    del cal_a, cal_b
+    big_a = torch.empty(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB, far beyond the caches
+    big_b = torch.empty_like(big_a)
+    big_b.copy_(big_a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        big_b.copy_(big_a)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2 * big_a.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del cal_a, cal_b, big_a, big_b
     compare = None
     accuracy = None
     if not args.no_fp64_compare and prec == m.MRA_MIXED:
@@ -352,7 +363,9 @@ def main() -> int:
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.kernel),
                      "avg_launch_ms": k_ms, "algorithmic_bytes_per_launch": nbytes,
-                     "active_tile_fraction": frac_t},
+                     "active_tile_fraction": frac_t,
+                     "copy_ceiling_gbs": copy_gbs, "frac_of_copy_ceiling": achieved / copy_gbs},
+        "finest_pt_evals_per_s": value * N * N / (sum(nas) / len(nas)),
     }
     step_s = wall / args.steps
     out["ensemble"] = {"solves_per_s_at_2000_steps": n / (step_s * 2000),

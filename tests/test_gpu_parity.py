@@ -266,3 +266,32 @@ def test_batch_equals_alone(M):
     M.solve_batch(solves, [2] * len(solves))
     for s, a in zip(solves, alone):
         assert np.array_equal(s.read()[0].cpu().numpy(), a)
+
+
+def test_stream_batch_equals_alone(M):
+    """17 equal-configuration solves advanced together on a stream (captured
+    step graphs); solve 0 stops a step early, so the batch changes
+    composition.  Every solve is bit-identical to the same solve stepped alone
+    with krylov_step on the same stream."""
+    pbs = [W.fujiwhara_pair(2000 + i, J=6) for i in range(17)]
+    steps = [2] + [3] * 16
+    st = torch.cuda.Stream(device=DEV)
+
+    def make(pb):
+        with torch.cuda.stream(st):
+            w0 = _t(W.initial_field(pb))
+            return M.Solve(M.grid_desc(pb.J, pb.p, pb.eps), M.flow_desc(pb.nu0, pb.cs), M.MRA_MIXED, 12, pb.dt,
+                           w0, stream=st)
+
+    alone = []
+    for pb, k in zip(pbs, steps):
+        s = make(pb)
+        s.step(k, stream=st)
+        alone.append(s.read(stream=st)[0].cpu().numpy())
+        s.close()
+    solves = [make(pb) for pb in pbs]
+    M.solve_batch(solves, steps, stream=st)
+    for s, a in zip(solves, alone):
+        assert np.array_equal(s.read(stream=st)[0].cpu().numpy(), a)
+    for s in solves:
+        s.close()
