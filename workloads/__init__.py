@@ -99,6 +99,16 @@ def initial_field(pb: Problem) -> np.ndarray:
     return vorticity_field(pb.N, pb.vortices, pb.length, pb.noise_amp, pb.noise_seed)
 
 
+def vapor_field(N: int, sharpness: float = 8.0, length: float = TWO_PI) -> np.ndarray:
+    """Initial vapor mixing ratio of the passive-scalar experiment (Section
+    3.6): moist (1) in one half of the domain, dry (0) in the other.  The step is the periodic, smooth
+    1/2 (1 + tanh(-A sin(2 pi y / length))) with A = sharpness, so that both
+    interfaces (y = 0 and y = length/2) are resolved by the grid."""
+    y = (np.arange(N) * (length / N))[:, None]
+    r = 0.5 * (1.0 + np.tanh(-sharpness * np.sin(TWO_PI * y / length)))
+    return np.repeat(r, N, axis=1)
+
+
 def random_field(N: int, seed: int, smooth: int = 0) -> np.ndarray:
     """Seeded N(0,1) field, optionally box-smoothed `smooth` times (periodic)."""
     rng = np.random.default_rng(seed)
