@@ -234,9 +234,54 @@ def run_serving(args) -> int:
     return 0
 
 
+def run_vapor(args) -> int:
+    """Passive vapor (Section 3.6) carried by the Fujiwhara flow: each of the
+    batch's 512^2 vortex solves has a vapor solve on its own adaptive grid,
+    both advanced in one solve_batch per step."""
+    import torch
+    import workloads as W
+    import paper_1604_08159_amd as m
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    seeds = [SEEDS[i % len(SEEDS)] + 100 * (i // len(SEEDS)) for i in range(args.batch)]
+    pairs = []
+    with torch.cuda.stream(stream):
+        for sd in seeds:
+            pb = W.fujiwhara_pair(sd)
+            v = m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_MIXED, pb.m, pb.dt,
+                        torch.from_numpy(W.initial_field(pb)).to(dev), stream=stream)
+            r0 = torch.from_numpy(W.vapor_field(pb.N, 8.0)).to(dev)
+            sc = m.ScalarSolve(v, m.grid_desc(pb.J, pb.p, 1e-4), pb.m, pb.dt, r0, eddy=True, stream=stream)
+            pairs.append((v, sc))
+    handles = [x for pr in pairs for x in pr]
+    _, d0 = pairs[0][1].read(stream=stream)
+    r0_0, _ = pairs[0][1].read(stream=stream)
+    m.solve_batch(handles, [args.warmup] * len(handles), stream=stream)
+    stream.synchronize()
+    ev0 = [h.scalars()["evals"] for h in handles]
+    t0 = time.perf_counter()
+    m.solve_batch(handles, [args.steps] * len(handles), stream=stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    ev1 = [h.scalars()["evals"] for h in handles]
+    dv = sum(ev1[i] - ev0[i] for i in range(0, len(handles), 2))
+    ds = sum(ev1[i] - ev0[i] for i in range(1, len(handles), 2))
+    r1, d1 = pairs[0][1].read(stream=stream)
+    nas = [int(sc.read(dense=False, stream=stream)[1]["n_active"]) for _, sc in pairs]
+    print(json.dumps({"workload": f"vapor carried by the Fujiwhara pair, 512^2, batch of {len(pairs)} vortex + "
+                                  f"{len(pairs)} vapor solves, mixed precision, {args.steps} steps",
+                      "metric": "active-pt RHS evals/s", "value": (dv + ds) / wall,
+                      "vortex_evals_per_s": dv / wall, "vapor_evals_per_s": ds / wall,
+                      "ms_per_step": wall / args.steps * 1e3, "mean_vapor_active_points": sum(nas) / len(nas),
+                      "vapor_mass_rel_change": abs(d1["gamma"] - d0["gamma"]) / abs(d0["gamma"]),
+                      "vapor_min_max_initial": [float(r0_0.min()), float(r0_0.max())],
+                      "vapor_min_max_final": [float(r1.min()), float(r1.max())]}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["fujiwhara", "ensemble", "serving"], default="fujiwhara")
+    ap.add_argument("--workload", choices=["fujiwhara", "ensemble", "serving", "vapor"], default="fujiwhara")
     ap.add_argument("--solves", type=int, default=256)
     ap.add_argument("--ens-steps", type=int, default=200)
     ap.add_argument("--round-steps", type=int, default=20)
@@ -263,6 +308,8 @@ def main() -> int:
         return run_ensemble(args)
     if args.workload == "serving":
         return run_serving(args)
+    if args.workload == "vapor":
+        return run_vapor(args)
 
     import torch
     import paper_1604_08159_amd as m

@@ -191,6 +191,31 @@ int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t p
                        int32_t m, double dt, const double* omega0_dense,
                        void* arena, size_t arena_bytes, void* stream, mra_solve* out);
 int32_t krylov_step(mra_solve s, int32_t nsteps, void* stream);
+
+/* ------------------------------------------------------------------------
+ * mra_scalar_init -- a passive scalar (the water vapor mixing ratio of
+ * Section 3.6: eq. (3) with only a diffusion term) carried by the flow of the
+ * vorticity solve `partner`:
+ *
+ *   dr/dt = -[D1_x(u r~) + D1_y(v r~)]
+ *           + 1/2 [L(kappa r~) + kappa L r~ - r~ L kappa],   r~ = Pi(r),
+ *
+ * on its own adaptive grid (g: same J and p as the partner, its own eps) with
+ * the same exponential step (the operator is linear in r) and FP64 regrid.
+ * kappa = the partner's nu_e (eddy != 0) or the constant kappa0 >= 0.
+ * Coupling is first-order splitting: the scalar's step k uses u, v (and
+ * nu_e) of the partner's step k, i.e. of the vorticity at the start of that
+ * step.  So a scalar step must follow its partner's step and precede the
+ * next: krylov_step on a scalar takes nsteps = 1 right after one partner step
+ * (else MRA_E_ARG); solve_batch orders every step itself when the partner is
+ * in the same call.  Precision follows the partner; the arena is
+ * mra_solve_footprint(g, precision, m) bytes.  The partner must outlive the
+ * scalar (destroy scalars first).  r0_dense: device double [N][N].
+ * mra_solve_read on a scalar returns its field and its mass as diag[4].
+ * ------------------------------------------------------------------------ */
+int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, double dt, double kappa0,
+                        int32_t eddy, const double* r0_dense, void* arena, size_t arena_bytes,
+                        void* stream, mra_solve* out);
 int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* stream);
 int32_t mra_solve_read(mra_solve s, double* omega_dense_out, double* diag_out, void* stream);
 int32_t mra_solve_ptrs_get(mra_solve s, mra_solve_ptrs* out);

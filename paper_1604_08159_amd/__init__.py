@@ -199,6 +199,29 @@ class Solve:
             pass
 
 
+class ScalarSolve(Solve):
+    """A passive scalar carried by the flow of a vorticity solve (mra_scalar_init):
+    its own adaptive grid and Krylov state, the partner's velocity.  Keep the
+    partner alive while this solve exists."""
+
+    def __init__(self, partner: Solve, g: GridDesc, m: int, dt: float, r0: torch.Tensor, kappa0: float = 0.0,
+                 eddy: bool = True, stream=None, arena: Optional[torch.Tensor] = None):
+        N = 1 << g.J
+        if r0.dtype != torch.float64 or tuple(r0.shape) != (N, N):
+            raise ValueError("r0 must be a float64 [N, N] device tensor")
+        self.g, self.f, self.prec, self.m, self.dt = g, partner.f, partner.prec, m, dt
+        self.N = N
+        self.partner = partner
+        self.nbytes = solve_footprint(g, partner.prec, m)
+        self.arena = arena if arena is not None else _alloc(self.nbytes, r0.device)
+        h = C.c_void_p()
+        st = lib().mra_scalar_init(partner.handle, C.byref(g), m, dt, kappa0, 1 if eddy else 0,
+                                   _ptr(r0.contiguous()), _ptr(self.arena), self.arena.numel(), _stream(stream),
+                                   C.byref(h))
+        _check("mra_scalar_init", st)
+        self.handle = h
+
+
 KERNELS = {"jvp": 0, "fft_rows": 1, "fft_cols": 2, "fft_rows_inv": 3, "prolong_finest": 4,
            "forward": 5, "rhs": 6}
 

@@ -49,6 +49,9 @@ EXPORTS = {
                                    C.c_double, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                    C.POINTER(C.c_void_p)]),
     "krylov_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "mra_scalar_init": (C.c_int32, [C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_double, C.c_double,
+                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
     "solve_batch": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
     "mra_solve_read": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     "mra_solve_ptrs_get": (C.c_int32, [C.c_void_p, C.POINTER(SolvePtrs)]),

@@ -284,6 +284,128 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   }
 }
 
+// Passive scalar (Section 3.6): L v~ = -[D1_x(u v~) + D1_y(v v~)]
+// + 1/2 [L(kappa v~) + kappa L v~ - v~ L kappa] at the active nodes of one
+// tile, with u, v (and the diffusivity kappa, stored in s.nu) the fields the
+// scalar was coupled to.  The operator is linear in the scalar, so the same
+// kernel gives its residual (v~ = Pi(r), check_done = 0) and its products
+// with the Arnoldi vectors.
+template <int P, typename T, int TS>
+__global__ void __launch_bounds__(256) k_scalar(Batch b, int check_done) {
+  using G = Geo<P>;
+  extern __shared__ unsigned char smem[];
+  const SolveDev& s = MRA_SOLVE(b);
+  const int N = s.N, ntx = s.ntx, nm = N - 1;
+  const int tile = tile_of_block(MRA_BX(b), ntx * ntx, b.n);
+  const int done = check_done ? s.ctrl[C_DONE] : 0, cnt = s.tile_count[tile];
+  if (done || cnt == 0) return;
+  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
+  constexpr int Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
+  constexpr int NQ = (Ww * Ww + 255) / 256;       // flux points per thread
+  constexpr int NO = (TS * TS + 255) / 256;       // output nodes per thread
+  T* vt = reinterpret_cast<T*>(smem);
+  T* fa = vt + Ww * Ww;
+  T* fb = fa + Ww * Ww;
+  T* nu = fb + Ww * Ww;
+  T* cn = nu + Wn * Wn;
+  const T* gu = reinterpret_cast<const T*>(s.u);
+  const T* gv = reinterpret_cast<const T*>(s.v);
+  T ur[NQ], vr[NQ];
+  int kr[NO];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    if (q < Ww * Ww) {
+      const int r = q / Ww, c = q - r * Ww;
+      const int f = ((y0 - G::R1 + r) & nm) * N + ((x0 - G::R1 + c) & nm);
+      ur[i] = gu[f];
+      vr[i] = gv[f];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NO; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    kr[i] = q < TS * TS ? s.rank[(y0 + q / TS) * N + x0 + (q % TS)] : -1;
+  }
+  {
+    Region<Ww, T> rvt;
+    Region<Wn, T> rnu;
+    rvt.fetch(reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, N);
+    rnu.fetch(reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, N);
+    rvt.put(vt);
+    rnu.put(nu);
+  }
+  __syncthreads();
+  const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    if (q < Ww * Ww) {
+      const T vtv = vt[q];
+      fa[q] = ur[i] * vtv;
+      fb[q] = vr[i] * vtv;
+    }
+  }
+  constexpr int on = G::R1 - P;
+  for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
+    const int r = q / Wn, c = q - r * Wn;
+    cn[q] = nu[q] * vt[(r + on) * Ww + c + on];
+  }
+  __syncthreads();
+  double* out = s.out_jvp;
+#pragma unroll
+  for (int i = 0; i < NO; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    const int k = kr[i];
+    if (k < 0) continue;
+    const int r = q / TS, c = q - r * TS;
+    const int ra = r + G::R1, ca = c + G::R1, rn = r + P, cn_ = c + P;
+    const T adv = -ih * (dx1<P, T>(fa, Ww, ra, ca) + dy1<P, T>(fb, Ww, ra, ca));
+    const T vv = vt[ra * Ww + ca];
+    const T nv = nu[rn * Wn + cn_];
+    const T diff = T(0.5) * ih2 * (lap5<P, T>(cn, Wn, rn, cn_) + nv * lap5<P, T>(vt, Ww, ra, ca) -
+                                   vv * lap5<P, T>(nu, Wn, rn, cn_));
+    out[k] = (double)(adv + diff);
+  }
+}
+
+template <int P, typename T, int TS>
+static hipError_t scalar_ts(const Batch& b, int N, int check_done, hipStream_t st) {
+  const int nt = (N / TS) * (N / TS);
+  const size_t lds = jvp_lds_elems<P, T>(TS) * sizeof(T);
+  hipLaunchKernelGGL((k_scalar<P, T, TS>), dim3(nt * b.n), dim3(256), lds, st, b, check_done);
+  return hipGetLastError();
+}
+
+template <int P, typename T>
+static hipError_t scalar_t(const Batch& b, const LaunchCfg& c, int check_done, hipStream_t st) {
+  const int N = 1 << c.J;
+  const int TS = tile_edge(c.J, c.p, c.prec);
+  if (TS == 32) return scalar_ts<P, T, 32>(b, N, check_done, st);
+  if (TS == 16) return scalar_ts<P, T, 16>(b, N, check_done, st);
+  return scalar_ts<P, T, 8>(b, N, check_done, st);
+}
+
+hipError_t launch_scalar(const Batch& b, const LaunchCfg& c, int check_done, hipStream_t st) {
+  if (c.prec == 0) return c.p == 2 ? scalar_t<2, double>(b, c, check_done, st) : scalar_t<3, double>(b, c, check_done, st);
+  return c.p == 2 ? scalar_t<2, float>(b, c, check_done, st) : scalar_t<3, float>(b, c, check_done, st);
+}
+
+// fill n elements of a bulk field with a constant
+template <typename T>
+__global__ void k_fill(T* f, size_t n, double value) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    f[i] = (T)value;
+}
+
+hipError_t launch_fill(void* f, size_t n, int prec, double value, hipStream_t st) {
+  const size_t gb = (n + 255) / 256;
+  const int g = (int)(gb < 4096 ? gb : 4096);
+  if (prec == 0) hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, st, static_cast<double*>(f), n, value);
+  else hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, st, static_cast<float*>(f), n, value);
+  return hipGetLastError();
+}
+
 template <int P, typename T, int TS>
 static hipError_t rhs_ts(const Batch& b, int N, bool jvp, hipStream_t st) {
   const int nt = (N / TS) * (N / TS);

@@ -24,6 +24,8 @@ struct mra_solve_s {
   hipGraph_t graph_def = nullptr;
   hipStream_t graph_stream = nullptr;
   std::vector<double> diag_rows;
+  long steps = 0;                 // steps enqueued so far
+  mra_solve_s* partner = nullptr; // passive scalar: the vorticity solve it rides on
 };
 
 namespace {
@@ -191,8 +193,32 @@ Batch one(const SolveDev* d) {
   return b;
 }
 
+// One exponential step of passive scalars: the operator is linear in the
+// scalar, so its residual and its Arnoldi products are the same stencil on
+// Pi(r) and Pi(v_j); no Poisson solve (the velocity is the partner's).
+hipError_t enqueue_scalar_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  const int dbl = c.prec == 0;
+  hipError_t e;
+  if ((e = launch_prolong(b, c, 1, dbl, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_scalar(b, c, 0, st)) != hipSuccess) return e;
+  if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
+  for (int j = 0; j < c.m; ++j) {
+    if ((e = launch_prolong(b, c, 1, dbl, 1, j, st)) != hipSuccess) return e;
+    if ((e = launch_scalar(b, c, 1, st)) != hipSuccess) return e;
+    if ((e = launch_arnoldi(b, c, j, st)) != hipSuccess) return e;
+  }
+  if ((e = launch_phi1(b, c, st)) != hipSuccess) return e;
+  if ((e = launch_update(b, c, st)) != hipSuccess) return e;
+  if ((e = launch_prolong(b, c, 2, 1, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_reset_max(b, st)) != hipSuccess) return e;
+  if ((e = launch_forward(b, c, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_threshold(b, c, 1, st)) != hipSuccess) return e;
+  return launch_gather(b, c, st);
+}
+
 // One exponential Rosenbrock-Euler step with regrid for every solve of b.
 hipError_t enqueue_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  if (c.kind == 1) return enqueue_scalar_step(b, c, st);
   const int dbl = c.prec == 0;
   hipError_t e;
   // residual F at omega
@@ -457,11 +483,70 @@ int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t p
   return MRA_OK;
 }
 
+int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, double dt, double kappa0,
+                        int32_t eddy, const double* r0_dense, void* arena, size_t arena_bytes, void* stream,
+                        mra_solve* out) {
+  if (!partner || partner->cfg.kind != 0) return MRA_E_ARG;
+  int32_t r = check_grid(g);
+  if (r != MRA_OK) return r;
+  if (g->J != partner->cfg.J || g->p != partner->cfg.p) return MRA_E_ARG;
+  if (!r0_dense || !arena || !out) return MRA_E_ARG;
+  if (m < 1 || m > kMaxM) return MRA_E_SIZE;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(kappa0 >= 0.0) || !std::isfinite(kappa0)) return MRA_E_ARG;
+  if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return MRA_E_ARG;
+  const int32_t prec = partner->host.prec == 0 ? MRA_FP64 : MRA_MIXED;
+  size_t need = 0;
+  mra_solve_footprint(g, prec, m, &need);
+  if (arena_bytes < need) return MRA_E_NOMEM;
+  if ((r = ensure_init()) != MRA_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  mra_solve_s* h = new (std::nothrow) mra_solve_s();
+  if (!h) return MRA_E_NOMEM;
+  SolveDev& s = h->host;
+  fill_geometry(s, g, prec);
+  s.m = m;
+  s.dt = dt;
+  Layout L(arena);
+  solve_layout(L, s);
+  // the flow the scalar rides on: the partner's velocity and, for eddy
+  // diffusion, its nu_e; otherwise a constant field of the scalar's own
+  s.u = partner->host.u;
+  s.v = partner->host.v;
+  const size_t Nf = (size_t)s.N * s.N;
+  if (eddy) s.nu = partner->host.nu;
+  h->dev = reinterpret_cast<SolveDev*>(arena);
+  h->cfg = LaunchCfg{s.J, s.p, s.prec, m, 1};
+  h->partner = partner;
+  h->steps = partner->steps;   // the next scalar step follows the partner's next step
+  (void)hipGetDevice(&h->device);
+  h->diag_rows.resize((size_t)s.N * 5);
+  Batch b = one(h->dev);
+  hipError_t e;
+  if ((e = launch_write_desc(h->dev, s, st)) != hipSuccess || (e = launch_reset_ctrl(b, st)) != hipSuccess ||
+      (!eddy && (e = launch_fill(s.nu, Nf, s.prec, kappa0, st)) != hipSuccess) ||
+      (e = hipMemcpyAsync(s.dense64, r0_dense, Nf * sizeof(double), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+      (e = launch_reset_max(b, st)) != hipSuccess || (e = launch_forward(b, h->cfg, 0, 0, st)) != hipSuccess ||
+      (e = launch_threshold(b, h->cfg, 1, st)) != hipSuccess || (e = launch_gather(b, h->cfg, st)) != hipSuccess) {
+    delete h;
+    return MRA_E_DEVICE;
+  }
+  *out = h;
+  return MRA_OK;
+}
+
+// A passive scalar's step k uses the velocity of its partner's step k, which
+// lives in the partner's fields from that step's start until the next step.
+static bool scalar_step_ready(const mra_solve_s* h) {
+  return h->cfg.kind == 0 || (h->partner && h->partner->steps == h->steps + 1);
+}
+
 int32_t krylov_step(mra_solve h, int32_t nsteps, void* stream) {
   if (!h || nsteps < 0) return MRA_E_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   Batch b = one(h->dev);
   if (nsteps == 0) return MRA_OK;
+  if (h->cfg.kind == 1 && (nsteps != 1 || !scalar_step_ready(h))) return MRA_E_ARG;
+  h->steps += nsteps;
   if (!st || !graphs_enabled()) {
     for (int i = 0; i < nsteps; ++i) MRA_TRY(enqueue_step(b, h->cfg, st));
     return MRA_OK;
@@ -486,14 +571,19 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
   const bool use_graph = st && graphs_enabled();
   for (int t = 0; t < maxs; ++t) {
     // group the solves still running by launch configuration
-    std::map<std::tuple<int, int, int, int>, std::vector<mra_solve>> groups;
+    // (vorticity solves first: a scalar's step reads its partner's step)
+    std::map<std::tuple<int, int, int, int, int>, std::vector<mra_solve>> groups;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > t) {
         const LaunchCfg& c = solves[i]->cfg;
-        groups[std::make_tuple(c.J, c.p, c.prec, c.m)].push_back(solves[i]);
+        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m)].push_back(solves[i]);
       }
     for (auto& kv : groups) {
       auto& v = kv.second;
+      for (mra_solve h : v) {
+        if (!scalar_step_ready(h)) return MRA_E_ARG;
+        h->steps += 1;
+      }
       for (size_t o = 0; o < v.size(); o += kMaxBatch) {
         Batch b;
         std::memset(&b, 0, sizeof(b));

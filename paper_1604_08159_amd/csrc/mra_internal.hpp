@@ -328,6 +328,7 @@ __device__ inline double next_scale(const SolveDev& s, int j, int bx) {
 // Each returns hipSuccess or the launch error.  `nb` solves in `b`.
 struct LaunchCfg {
   int J, p, prec, m;
+  int kind = 0;   // 0 vorticity, 1 passive scalar coupled to a vorticity solve
 };
 
 hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);
@@ -354,6 +355,9 @@ hipError_t launch_poisson_pass(const Batch& b, const LaunchCfg& c, int src, int 
 // stencils
 hipError_t launch_rhs(const Batch& b, const LaunchCfg& c, hipStream_t st);
 hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st);
+// passive-scalar operator at the active nodes (check_done: skip once the basis is complete)
+hipError_t launch_scalar(const Batch& b, const LaunchCfg& c, int check_done, hipStream_t st);
+hipError_t launch_fill(void* f, size_t n, int prec, double value, hipStream_t st);
 hipError_t launch_diag(const Batch& b, const LaunchCfg& c, hipStream_t st);
 
 // Krylov
