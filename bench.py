@@ -24,6 +24,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -279,9 +281,97 @@ def run_vapor(args) -> int:
     return 0
 
 
+def run_three(args) -> int:
+    """The three-vortex Re = 37440 configuration at 2048^2 (6-point DD, m = 30,
+    noise everywhere at first, so nearly every node is active): a batch of
+    args.batch3 solves with noise seeds 37440 + i, mixed precision."""
+    import dataclasses
+    import torch
+    import workloads as W
+    import paper_1604_08159_amd as m
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    pbs = [dataclasses.replace(W.three_vortex(), noise_seed=37440 + i) for i in range(args.batch3)]
+    solves = []
+    with torch.cuda.stream(stream):
+        for pb in pbs:
+            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_MIXED, pb.m,
+                                  pb.dt, torch.from_numpy(W.initial_field(pb)).to(dev), stream=stream))
+    m.solve_batch(solves, [2] * len(solves), stream=stream)
+    stream.synchronize()
+    ev0 = sum(s.scalars()["evals"] for s in solves)
+    t0 = time.perf_counter()
+    m.solve_batch(solves, [args.steps3] * len(solves), stream=stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    ev1 = sum(s.scalars()["evals"] for s in solves)
+    nas = [int(s.read(dense=False, stream=stream)[1]["n_active"]) for s in solves]
+    N = pbs[0].N
+    k_ms = m.time_kernel(solves, "jvp", 10, stream=stream)
+    nbytes = kernel_bytes("jvp", N, int(sum(nas) / len(nas)), 1.0, len(solves), 4)
+    print(json.dumps({"workload": f"three vortices Re=37440 + noise, finest 2048^2 (J=11), 6-point DD, eps=1e-4, "
+                                  f"m=30, dt=0.002; batch of {len(solves)}, mixed precision, {args.steps3} steps",
+                      "metric": "active-pt RHS evals/s", "value": (ev1 - ev0) / wall,
+                      "ms_per_step": wall / args.steps3 * 1e3, "mean_active_points": sum(nas) / len(nas),
+                      "active_fraction": sum(nas) / len(nas) / (N * N),
+                      "jvp_ms": k_ms, "jvp_algorithmic_gbs": nbytes / (k_ms * 1e-3) / 1e9}))
+    return 0
+
+
+def run_longrun(args) -> int:
+    """The Fujiwhara configuration over its full length (2000 steps) for one
+    seed, in mixed precision and in FP64: vortex separation b(t*)/b(0) from
+    the centre tracker every 20 steps, and the mixed run against the FP64 run
+    at the end (vorticity, energy, enstrophy)."""
+    import torch
+    import workloads as W
+    import paper_1604_08159_amd as m
+    dev = torch.device("cuda:0")
+    pb = W.fujiwhara_pair(SEEDS[0])
+    gamma = pb.vortices[0].gamma
+    c0 = [(v.cx, v.cy) for v in pb.vortices]
+    b0 = float(np.hypot(c0[1][0] - c0[0][0], c0[1][1] - c0[0][1]))
+    tc = 2.0 * np.pi * b0 * b0 / gamma
+    out = {"workload": f"Fujiwhara pair Re=5000, 512^2, seed {SEEDS[0]}, {args.long_steps} steps",
+           "b0": b0, "t_c": tc}
+    res = {}
+    for name, prec in (("mixed", m.MRA_MIXED), ("fp64", m.MRA_FP64)):
+        stream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(stream):
+            s = m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m, pb.dt,
+                        torch.from_numpy(W.initial_field(pb)).to(dev), stream=stream)
+        cs = list(c0)
+        curve = []
+        t0 = time.perf_counter()
+        for k in range(0, args.long_steps, 20):
+            n = min(20, args.long_steps - k)
+            s.step(n, stream=stream)
+            cs = s.track(cs, stream=stream)
+            b = float(np.hypot(*[((cs[1][i] - cs[0][i] + np.pi) % (2 * np.pi)) - np.pi for i in range(2)]))
+            curve.append([round((k + n) * pb.dt / tc, 4), round(b / b0, 5)])
+        wall = time.perf_counter() - t0
+        dense, diag = s.read(stream=stream)
+        res[name] = (dense, diag)
+        out[name] = {"seconds": wall, "b_over_b0_vs_tstar": curve[::5] + ([curve[-1]] if len(curve) % 5 != 1 else []),
+                     "n_active_final": int(diag["n_active"]), "status": int(diag["status"])}
+        s.close()
+        log(f"{name}: {wall:.1f} s")
+    a, da = res["fp64"]
+    b_, db = res["mixed"]
+    out["mixed_vs_fp64"] = {"rel_l2_vorticity": float(torch.linalg.vector_norm(a - b_) / torch.linalg.vector_norm(a)),
+                            "rel_energy": abs(da["energy"] - db["energy"]) / da["energy"],
+                            "rel_enstrophy": abs(da["enstrophy"] - db["enstrophy"]) / da["enstrophy"]}
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["fujiwhara", "ensemble", "serving", "vapor"], default="fujiwhara")
+    ap.add_argument("--workload", choices=["fujiwhara", "ensemble", "serving", "vapor", "three2048", "longrun"],
+                    default="fujiwhara")
+    ap.add_argument("--batch3", type=int, default=2)
+    ap.add_argument("--steps3", type=int, default=10)
+    ap.add_argument("--long-steps", type=int, default=2000)
     ap.add_argument("--solves", type=int, default=256)
     ap.add_argument("--ens-steps", type=int, default=200)
     ap.add_argument("--round-steps", type=int, default=20)
@@ -310,6 +400,10 @@ def main() -> int:
         return run_serving(args)
     if args.workload == "vapor":
         return run_vapor(args)
+    if args.workload == "three2048":
+        return run_three(args)
+    if args.workload == "longrun":
+        return run_longrun(args)
 
     import torch
     import paper_1604_08159_amd as m

@@ -193,6 +193,19 @@ int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t p
 int32_t krylov_step(mra_solve s, int32_t nsteps, void* stream);
 
 /* ------------------------------------------------------------------------
+ * mra_solve_track -- vortex centres for the separation b(t) of Section 3.2.
+ * centres: HOST double [k][2] (x, y), 1 <= k <= 4, the previous centres on
+ * input and the updated ones on output.  Each finest node of Pi(omega_M) is
+ * given to the nearest previous centre (periodic distance, ties to the lower
+ * index); a centre moves by the mean periodic displacement of its nodes
+ * weighted by max(omega, 0), and stays if that weight is zero.  One call is one
+ * update: track a run by calling it after every step (or every few steps,
+ * while the centres move much less than their spacing).  Synchronises
+ * `stream`.
+ * ------------------------------------------------------------------------ */
+int32_t mra_solve_track(mra_solve s, int32_t k, double* centres, void* stream);
+
+/* ------------------------------------------------------------------------
  * mra_scalar_init -- a passive scalar (the water vapor mixing ratio of
  * Section 3.6: eq. (3) with only a diffusion term) carried by the flow of the
  * vorticity solve `partner`:

@@ -156,6 +156,13 @@ class Solve:
             _check("mra_solve_read", st)
         return out, dict(zip(DIAG_KEYS, list(diag)))
 
+    def track(self, centres, stream=None):
+        """One update of the vortex centres [(x, y), ...] (mra_solve_track)."""
+        k = len(centres)
+        buf = (C.c_double * (2 * k))(*[float(v) for c in centres for v in c])
+        _check("mra_solve_track", lib().mra_solve_track(self.handle, k, buf, _stream(stream)))
+        return [(buf[2 * i], buf[2 * i + 1]) for i in range(k)]
+
     def ptrs(self) -> SolvePtrs:
         p = SolvePtrs()
         _check("mra_solve_ptrs_get", lib().mra_solve_ptrs_get(self.handle, C.byref(p)))

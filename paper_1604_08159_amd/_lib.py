@@ -54,6 +54,7 @@ EXPORTS = {
                                     C.POINTER(C.c_void_p)]),
     "solve_batch": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
     "mra_solve_read": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "mra_solve_track": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p]),
     "mra_solve_ptrs_get": (C.c_int32, [C.c_void_p, C.POINTER(SolvePtrs)]),
     "mra_solve_destroy": (C.c_int32, [C.c_void_p]),
     "mra_time_kernel": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_void_p,

@@ -486,4 +486,68 @@ hipError_t launch_diag(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------- centre tracking
+// One block per row y of the FP64 field dense64: each node is given to the
+// nearest of the K previous centres (periodic distance, ties to the lower
+// index) and adds max(w, 0), and that weight times its periodic displacement
+// from the centre, to the centre's row sums.  Row sums go to rows[y][K][3];
+// the host adds the rows in order (Section 3.2: separation of the centres).
+struct Centres {
+  double x[kMaxTrack], y[kMaxTrack];
+  int k;
+};
+
+__device__ inline double periodic_delta(double a, double c, double L) {
+  const double t = a - c + 0.5 * L;
+  return t - L * floor(t / L) - 0.5 * L;
+}
+
+__global__ void __launch_bounds__(256) k_track(Batch b, Centres cs, double* rows) {
+  const SolveDev& s = MRA_SOLVE(b);
+  const int N = s.N, y = MRA_BX(b);
+  const double L = s.length, h = s.h;
+  const double* w = s.dense64;
+  double acc[kMaxTrack][3];
+#pragma unroll
+  for (int k = 0; k < kMaxTrack; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
+  const double yy = y * h;
+  for (int x = threadIdx.x; x < N; x += blockDim.x) {
+    const double xx = x * h;
+    int best = 0;
+    double bd = 0.0, bx = 0.0, by = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxTrack; ++k) {
+      if (k >= cs.k) break;
+      const double dx = periodic_delta(xx, cs.x[k], L), dy = periodic_delta(yy, cs.y[k], L);
+      const double d2 = dx * dx + dy * dy;
+      if (k == 0 || d2 < bd) { best = k; bd = d2; bx = dx; by = dy; }
+    }
+    const double wv = fmax(w[y * N + x], 0.0);
+#pragma unroll
+    for (int k = 0; k < kMaxTrack; ++k)
+      if (k == best) { acc[k][0] += wv; acc[k][1] += wv * bx; acc[k][2] += wv * by; }
+  }
+  __shared__ double red[kMaxTrack * 3][256];
+#pragma unroll
+  for (int k = 0; k < kMaxTrack; ++k)
+    for (int c = 0; c < 3; ++c) red[k * 3 + c][threadIdx.x] = acc[k][c];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int q = 0; q < kMaxTrack * 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < cs.k * 3) rows[(size_t)y * cs.k * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_track(const Batch& b, const LaunchCfg& c, const double* cx, const double* cy, int k,
+                        double* rows, hipStream_t st) {
+  if (k < 1 || k > kMaxTrack) return hipErrorInvalidValue;
+  Centres cs{};
+  for (int i = 0; i < k; ++i) { cs.x[i] = cx[i]; cs.y[i] = cy[i]; }
+  cs.k = k;
+  hipLaunchKernelGGL(k_track, dim3((1 << c.J) * b.n), dim3(256), 0, st, b, cs, rows);
+  return hipGetLastError();
+}
+
 }  // namespace mra

@@ -462,56 +462,61 @@ hipError_t launch_forward(const Batch& b, const LaunchCfg& c, int src, int dst, 
 }
 
 // ---------------------------------------------------------------- threshold
-// Active test of packed position i: coarsest mesh, significant detail, or in
-// the adjacent zone of a significant node Q of level l, i.e. this node lies on
+// Active set: the coarsest mesh, every significant node (|d| >= tau), and the
+// adjacent zone of every significant node Q of level l > j0: the nodes of
 // G^{min(l+1,J)} within periodic Chebyshev distance 2^(J-l) of Q.  Written as
-// a gather: for every level l >= max(level-1, j0+1) the level-l nodes within
-// that distance are examined.
+// a scatter (each significant node marks its 5 x 5, on the finest level 3 x 3,
+// zone), so the cost follows the number of significant nodes; concurrent
+// marks all write 1.  Three passes: significance, zones, per-block counts.
 template <typename TP>
-__device__ inline bool is_active(const TP* __restrict__ d, int i, int J, int j0, double tau, int az) {
-  if (i < (1 << (2 * j0))) return true;
-  if (fabs((double)d[i]) >= tau) return true;
-  if (!az) return false;
-  int lp;
-  const int f = packed_to_fine(i, J, j0, &lp);
-  const int N = 1 << J, nm = N - 1;
-  const int px = f & nm, py = f >> J;
-  const int lmin = lp - 1 > j0 + 1 ? lp - 1 : j0 + 1;
-  for (int l = lmin; l <= J; ++l) {
-    const int s = 1 << (J - l), hs = s >> 1;
-    int cx[3], cy[3], nx, ny;
-    if ((px & (s - 1)) == 0) { cx[0] = px - s; cx[1] = px; cx[2] = px + s; nx = 3; }
-    else { cx[0] = px - hs; cx[1] = px + hs; nx = 2; }
-    if ((py & (s - 1)) == 0) { cy[0] = py - s; cy[1] = py; cy[2] = py + s; ny = 3; }
-    else { cy[0] = py - hs; cy[1] = py + hs; ny = 2; }
-    for (int a = 0; a < ny; ++a) {
-      const int qy = cy[a] & nm;
-      for (int c = 0; c < nx; ++c) {
-        const int qx = cx[c] & nm;
-        if (level_of(qx, qy, J, j0) != l) continue;
-        if (fabs((double)d[fine_to_packed(qx, qy, l, J, j0)]) >= tau) return true;
-      }
-    }
-  }
-  return false;
+__device__ inline const TP* packed_details(const SolveDev& s, int packed_is_double) {
+  return packed_is_double ? reinterpret_cast<const TP*>(s.packed64) : reinterpret_cast<const TP*>(s.spec);
 }
 
 template <typename TP>
-__global__ void __launch_bounds__(kScanBlock) k_mask_count(Batch b, int packed_is_double) {
+__global__ void __launch_bounds__(256) k_mask_sig(Batch b, int packed_is_double) {
   const SolveDev& s = MRA_SOLVE(b);
-  const TP* d = packed_is_double ? reinterpret_cast<const TP*>(s.packed64) : reinterpret_cast<const TP*>(s.spec);
-  const int Nf = s.N * s.N;
+  const TP* d = packed_details<TP>(s, packed_is_double);
+  const int Nf = s.N * s.N, n0 = 1 << (2 * s.j0);
   const double tau = s.eps * __longlong_as_double((long long)*s.umax);
+  for (int i = MRA_BX(b) * blockDim.x + threadIdx.x; i < Nf; i += MRA_GX(b) * blockDim.x)
+    s.mask[i] = (i < n0 || fabs((double)d[i]) >= tau) ? 1 : 0;
+}
+
+template <typename TP>
+__global__ void __launch_bounds__(256) k_mask_zone(Batch b, int packed_is_double) {
+  const SolveDev& s = MRA_SOLVE(b);
+  if (!s.adjacent_zone) return;
+  const TP* d = packed_details<TP>(s, packed_is_double);
+  const int J = s.J, j0 = s.j0, N = s.N, nm = N - 1, Nf = N * N, n0 = 1 << (2 * j0);
+  const double tau = s.eps * __longlong_as_double((long long)*s.umax);
+  for (int i = n0 + MRA_BX(b) * blockDim.x + threadIdx.x; i < Nf; i += MRA_GX(b) * blockDim.x) {
+    if (!(fabs((double)d[i]) >= tau)) continue;
+    int l;
+    const int f = packed_to_fine(i, J, j0, &l);
+    const int px = f & nm, py = f >> J;
+    const int sp = l < J ? 1 << (J - l - 1) : 1;   // spacing of G^{min(l+1,J)}
+    const int R = l < J ? 2 : 1;                    // 2^(J-l) / spacing
+    for (int bq = -R; bq <= R; ++bq) {
+      const int qy = (py + bq * sp) & nm;
+      for (int aq = -R; aq <= R; ++aq) {
+        const int qx = (px + aq * sp) & nm;
+        s.mask[fine_to_packed(qx, qy, level_of(qx, qy, J, j0), J, j0)] = 1;
+      }
+    }
+  }
+}
+
+// active count of each compaction block (kScanBlock threads x kScanItems)
+__global__ void __launch_bounds__(kScanBlock) k_mask_count(Batch b) {
+  const SolveDev& s = MRA_SOLVE(b);
+  const int Nf = s.N * s.N;
   const int base = MRA_BX(b) * (kScanBlock * kScanItems) + threadIdx.x * kScanItems;
   int cnt = 0;
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
     const int i = base + q;
-    if (i < Nf) {
-      const bool a = is_active<TP>(d, i, s.J, s.j0, tau, s.adjacent_zone);
-      s.mask[i] = a ? 1 : 0;
-      cnt += a;
-    }
+    if (i < Nf) cnt += s.mask[i];
   }
   __shared__ int red[kScanBlock / 64];
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
@@ -605,14 +610,21 @@ __global__ void __launch_bounds__(kScanBlock) k_compact(Batch b) {
   }
 }
 
+static int grid_blocks(int J);
+
 hipError_t launch_threshold(const Batch& b, const LaunchCfg& c, int packed_is_double, hipStream_t st) {
   const int nf = 1 << (2 * c.J);
   const int nblk = (nf + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
   dim3 g((nblk) * b.n);
-  if (packed_is_double || c.prec == 0)
-    hipLaunchKernelGGL(k_mask_count<double>, g, dim3(kScanBlock), 0, st, b, packed_is_double);
-  else
-    hipLaunchKernelGGL(k_mask_count<float>, g, dim3(kScanBlock), 0, st, b, packed_is_double);
+  dim3 gm(grid_blocks(c.J) * b.n);
+  if (packed_is_double || c.prec == 0) {
+    hipLaunchKernelGGL(k_mask_sig<double>, gm, dim3(256), 0, st, b, packed_is_double);
+    hipLaunchKernelGGL(k_mask_zone<double>, gm, dim3(256), 0, st, b, packed_is_double);
+  } else {
+    hipLaunchKernelGGL(k_mask_sig<float>, gm, dim3(256), 0, st, b, packed_is_double);
+    hipLaunchKernelGGL(k_mask_zone<float>, gm, dim3(256), 0, st, b, packed_is_double);
+  }
+  hipLaunchKernelGGL(k_mask_count, g, dim3(kScanBlock), 0, st, b);
   hipLaunchKernelGGL(k_scan, dim3((1) * b.n), dim3(1024), 0, st, b);
   hipLaunchKernelGGL(k_compact, g, dim3(kScanBlock), 0, st, b);
   return hipGetLastError();

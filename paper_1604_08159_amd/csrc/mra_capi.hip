@@ -659,6 +659,36 @@ int32_t mra_solve_read(mra_solve h, double* omega_dense_out, double* diag_out, v
   return ctrl[C_STATUS] == 0 ? MRA_OK : MRA_E_NONFINITE;
 }
 
+int32_t mra_solve_track(mra_solve h, int32_t k, double* centres, void* stream) {
+  if (!h || !centres || k < 1 || k > kMaxTrack) return MRA_E_ARG;
+  const SolveDev& s = h->host;
+  for (int i = 0; i < 2 * k; ++i)
+    if (!std::isfinite(centres[i])) return MRA_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Batch b = one(h->dev);
+  const LaunchCfg& c = h->cfg;
+  double cx[kMaxTrack], cy[kMaxTrack];
+  for (int i = 0; i < k; ++i) { cx[i] = centres[2 * i]; cy[i] = centres[2 * i + 1]; }
+  std::vector<double> rows((size_t)s.N * k * 3);
+  MRA_TRY(launch_prolong(b, c, 2, 1, 0, 0, st));
+  MRA_TRY(launch_track(b, c, cx, cy, k, s.vel64, st));
+  MRA_TRY(hipMemcpyAsync(rows.data(), s.vel64, rows.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  MRA_TRY(hipStreamSynchronize(st));
+  const double L = s.length;
+  for (int i = 0; i < k; ++i) {
+    double sw = 0.0, sx = 0.0, sy = 0.0;
+    for (int y = 0; y < s.N; ++y) {
+      const double* r = &rows[((size_t)y * k + i) * 3];
+      sw += r[0]; sx += r[1]; sy += r[2];
+    }
+    if (!(sw > 0.0)) continue;                 // no positive vorticity: the centre stays
+    const double nx = cx[i] + sx / sw, ny = cy[i] + sy / sw;
+    centres[2 * i] = nx - L * std::floor(nx / L);
+    centres[2 * i + 1] = ny - L * std::floor(ny / L);
+  }
+  return MRA_OK;
+}
+
 int32_t mra_solve_ptrs_get(mra_solve h, mra_solve_ptrs* out) {
   if (!h || !out) return MRA_E_ARG;
   const SolveDev& s = h->host;

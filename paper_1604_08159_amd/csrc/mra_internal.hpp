@@ -259,18 +259,22 @@ __device__ inline void reduce_partials(const double* buf, int nb, int cnt, doubl
 }
 
 // Sums of acc[0 .. cnt) over the block (fixed order: within each wavefront a
-// butterfly, then the wavefronts in order) written to out[0 .. cnt).
+// butterfly, then the wavefronts in order) written to out[0 .. cnt).  The
+// butterfly runs stage by stage over all NA sums, so the shuffles of
+// different sums are independent and overlap; acc is consumed.
 template <int NA>
-__device__ inline void block_sums_store(const double (&acc)[NA], int cnt, double* out) {
+__device__ inline void block_sums_store(double (&acc)[NA], int cnt, double* out) {
   __shared__ double part[kWavesPerBlock][NA];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < NA; ++i) {
-    if (i < cnt) {
-      double v = acc[i];
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      if (lane == 0) part[wid][i] = v;
-    }
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acc[i] += __shfl_xor(acc[i], o);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+      if (i < cnt) part[wid][i] = acc[i];
   }
   __syncthreads();
   if ((int)threadIdx.x < cnt) {
@@ -358,6 +362,10 @@ hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st);
 // passive-scalar operator at the active nodes (check_done: skip once the basis is complete)
 hipError_t launch_scalar(const Batch& b, const LaunchCfg& c, int check_done, hipStream_t st);
 hipError_t launch_fill(void* f, size_t n, int prec, double value, hipStream_t st);
+// vortex-centre row sums of dense64 (K <= kMaxTrack centres) into rows[N][K][3]
+constexpr int kMaxTrack = 4;
+hipError_t launch_track(const Batch& b, const LaunchCfg& c, const double* cx, const double* cy, int k,
+                        double* rows, hipStream_t st);
 hipError_t launch_diag(const Batch& b, const LaunchCfg& c, hipStream_t st);
 
 // Krylov
