@@ -259,22 +259,18 @@ __device__ inline void reduce_partials(const double* buf, int nb, int cnt, doubl
 }
 
 // Sums of acc[0 .. cnt) over the block (fixed order: within each wavefront a
-// butterfly, then the wavefronts in order) written to out[0 .. cnt).  The
-// butterfly runs stage by stage over all NA sums, so the shuffles of
-// different sums are independent and overlap; acc is consumed.
+// butterfly, then the wavefronts in order) written to out[0 .. cnt).
 template <int NA>
 __device__ inline void block_sums_store(double (&acc)[NA], int cnt, double* out) {
   __shared__ double part[kWavesPerBlock][NA];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) acc[i] += __shfl_xor(acc[i], o);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i)
-      if (i < cnt) part[wid][i] = acc[i];
+  for (int i = 0; i < NA; ++i) {
+    if (i < cnt) {
+      double v = acc[i];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) part[wid][i] = v;
+    }
   }
   __syncthreads();
   if ((int)threadIdx.x < cnt) {
