@@ -64,6 +64,8 @@ enum {
 enum { MRA_FP64 = 0, MRA_FP32 = 1, MRA_MIXED = 2 };   /* MIXED: FP32 bulk fields,
                                                          FP64 Krylov / regrid      */
 enum { MRA_FORWARD = 1, MRA_INVERSE = -1, MRA_PROLONG = 2 };
+enum { MRA_EXPONENTIAL = 0, MRA_THETA_NEWTON = 1 };   /* time integrator of a solve */
+#define MRA_MAX_NEWTON 8
 
 /* Grid: J in [j0+1, 11]; p in {2, 3} (4- and 6-point DD); j0 must equal
  * ceil(log2(2p)) (2 for p = 2, 3 for p = 3); length > 0 is the side of the
@@ -179,7 +181,8 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
  *   step.  The first call captures one step into a HIP graph on `stream`;
  *   later calls replay it.
  * solve_batch: advances solves[i] by nsteps[i] steps; solves of equal
- *   (J, p, precision, m) share every kernel launch.  Results are bit for bit
+ *   (J, p, precision, m, integrator, Newton iterations) share every kernel
+ *   launch.  Results are bit for bit
  *   those of krylov_step on each solve alone.
  * mra_solve_read: synchronises `stream`; omega_dense_out (device double
  *   [N][N], may be NULL) receives Pi(omega_M); diag_out (HOST double[8],
@@ -233,6 +236,34 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
 int32_t mra_solve_read(mra_solve s, double* omega_dense_out, double* diag_out, void* stream);
 int32_t mra_solve_ptrs_get(mra_solve s, mra_solve_ptrs* out);
 int32_t mra_solve_destroy(mra_solve s);
+
+/* ------------------------------------------------------------------------
+ * mra_solve_set_integrator -- the time scheme of later steps of a vorticity
+ * solve.  Section 2.1 places the method among Newton-Krylov solvers of the
+ * collocation system; besides the default exponential step
+ * (MRA_EXPONENTIAL) a solve can take the implicit theta-scheme
+ *
+ *   G(w) = w - w_n - dt [theta F(w) + (1 - theta) F(w_n)] = 0
+ *
+ * on the active set of the step's start (MRA_THETA_NEWTON; theta in [0, 1]:
+ * 1/2 Crank-Nicolson, 1 backward Euler, 0 explicit Euler), solved by
+ * newton_iters (1..MRA_MAX_NEWTON) Newton iterations from w_0 = w_n:
+ * (I - theta dt J(w_k)) d = -G(w_k), w_{k+1} = w_k + d, with J the Jacobian at
+ * eddy viscosity frozen at w_k (the exponential step's operator) and each
+ * linear system solved by one GMRES(m) cycle from a zero guess: the Arnoldi
+ * process of J from -G (CGS2, the same breakdown rule), then the least-squares
+ * problem on I~ - theta dt H (Givens rotations).  Each step ends with the
+ * FP64 regrid.  No extra arena memory.  theta and newton_iters are ignored for
+ * MRA_EXPONENTIAL.  Takes effect for steps enqueued after the call (theta is
+ * written on `stream`); drops the captured graphs that launch the solve.
+ * Errors: MRA_E_ARG (null handle, unknown integrator, theta or newton_iters out
+ * of range); MRA_E_UNSUPPORTED on a passive scalar, or for MRA_THETA_NEWTON
+ * while a passive scalar rides on the solve (its coupling reads the flow at
+ * the start of the partner's step, which Newton iterations overwrite);
+ * mra_scalar_init likewise refuses a partner with MRA_THETA_NEWTON.
+ * ------------------------------------------------------------------------ */
+int32_t mra_solve_set_integrator(mra_solve s, int32_t integrator, double theta, int32_t newton_iters,
+                                 void* stream);
 
 /* Profiling hook: times `reps` back-to-back launches of one kernel of the
  * step, launched exactly as the step launches it for the batch `solves`

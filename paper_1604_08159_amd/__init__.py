@@ -24,7 +24,8 @@ import torch
 
 from . import _lib
 from ._lib import (FlowDesc, GridDesc, MraError, SolvePtrs, MRA_FORWARD, MRA_INVERSE, MRA_PROLONG,
-                   MRA_FP64, MRA_FP32, MRA_MIXED, MRA_OK, MRA_E_NONFINITE)
+                   MRA_FP64, MRA_FP32, MRA_MIXED, MRA_OK, MRA_E_NONFINITE, MRA_EXPONENTIAL,
+                   MRA_THETA_NEWTON, MRA_MAX_NEWTON)
 
 _LIB: Optional[C.CDLL] = None
 
@@ -147,6 +148,13 @@ class Solve:
 
     def step(self, nsteps: int = 1, stream=None) -> None:
         _check("krylov_step", lib().krylov_step(self.handle, nsteps, _stream(stream)))
+
+    def set_integrator(self, integrator: int, theta: float = 0.5, newton_iters: int = 2, stream=None) -> None:
+        """Time scheme of later steps: MRA_EXPONENTIAL, or MRA_THETA_NEWTON
+        (theta-scheme by newton_iters Newton-GMRES iterations)."""
+        _check("mra_solve_set_integrator",
+               lib().mra_solve_set_integrator(self.handle, integrator, float(theta), int(newton_iters),
+                                              _stream(stream)))
 
     def read(self, dense: bool = True, stream=None) -> Tuple[Optional[torch.Tensor], Dict[str, float]]:
         out = torch.empty((self.N, self.N), dtype=torch.float64, device=self.arena.device) if dense else None

@@ -265,21 +265,26 @@ hipError_t launch_phi1(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   return hipGetLastError();
 }
 
-// omega_M += dt beta V_k y; the time advances.
-__global__ void __launch_bounds__(256) k_update(Batch b) {
+// State update from the Krylov solution y:
+//   mode 0 (exponential step):   omega_M += dt beta V_k y, the time advances;
+//   mode 1 (Newton iteration):   omega_M += V_k y (y carries beta);
+//   mode 2 (last Newton iteration): as mode 1, then the time advances.
+__global__ void __launch_bounds__(256) k_update(Batch b, int mode) {
   const SolveDev& s = MRA_SOLVE(b);
   const int k = s.ctrl[C_MEFF];
   const int na = (int)*s.n_active;
   if (MRA_BX(b) == 0 && threadIdx.x == 0) {
-    s.scal[S_T] += s.dt;
-    s.scal[S_STEPS] += 1.0;
-    // active-point residual evaluations of this step: F and k products J v
+    if (mode != 1) {
+      s.scal[S_T] += s.dt;
+      s.scal[S_STEPS] += 1.0;
+    }
+    // active-point residual evaluations: one F and k products J v
     s.scal[S_EVALS] += (double)(1 + k) * (double)na;
   }
   if (k <= 0) return;
   const size_t Nf = (size_t)s.N * s.N;
   __shared__ double yy[kMaxM + 1];
-  const double f = s.dt * s.scal[S_BETA];
+  const double f = mode == 0 ? s.dt * s.scal[S_BETA] : 1.0;
   for (int i = threadIdx.x; i < k; i += blockDim.x) yy[i] = f * s.y[i];
   __syncthreads();
   bool bad = false;
@@ -293,11 +298,145 @@ __global__ void __launch_bounds__(256) k_update(Batch b) {
   if (bad) s.ctrl[C_STATUS] = 5;
 }
 
-hipError_t launch_update(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  const int nf = 1 << (2 * c.J);
+static int update_grid(int J) {
+  const int nf = 1 << (2 * J);
   int nb = (nf + 255) / 256;
-  if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(k_update, dim3((nb) * b.n), dim3(256), 0, st, b);
+  return nb > 1024 ? 1024 : nb;
+}
+
+hipError_t launch_update(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_newton_update(const Batch& b, const LaunchCfg& c, int last, hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, last ? 2 : 1);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- theta-scheme Newton
+// The implicit alternative to the exponential step: the theta-scheme
+//   G(omega) = omega - omega_n - dt [theta F(omega) + (1 - theta) F(omega_n)] = 0
+// on the active set of the step's start, solved by a fixed number of Newton
+// iterations (I - theta dt J(omega_k)) d = -G(omega_k), each linear system by
+// one GMRES(m) cycle from a zero guess (Section 2.1 places the method among
+// Newton-Krylov solvers).  J is the Jacobian at frozen eddy viscosity, the
+// operator of the exponential step.
+
+// w <- -G(omega_k) = (omega_n - omega_k) + dt (theta F(omega_k) + (1 - theta) F(omega_n)),
+// with F(omega_k) in w on entry.  The first iteration (omega_0 = omega_n)
+// keeps omega_n and F(omega_n) in the FP64 regrid buffers, which the step
+// does not otherwise use before its regrid.
+__global__ void __launch_bounds__(256) k_newton_rhs(Batch b, int first) {
+  const SolveDev& s = MRA_SOLVE(b);
+  const int na = (int)*s.n_active;
+  const double th = s.scal[S_THETA], dt = s.dt;
+  double* wn = s.packed64;
+  double* fn = s.dense64;
+  for (int q = MRA_BX(b) * blockDim.x + threadIdx.x; q < na; q += MRA_GX(b) * blockDim.x) {
+    const double f = s.w[q], om = s.omega[q];
+    double on, f0;
+    if (first) {
+      wn[q] = om;
+      fn[q] = f;
+      on = om;
+      f0 = f;
+    } else {
+      on = wn[q];
+      f0 = fn[q];
+    }
+    s.w[q] = (on - om) + dt * (th * f + (1.0 - th) * f0);
+  }
+}
+
+hipError_t launch_newton_rhs(const Batch& b, const LaunchCfg& c, int first, hipStream_t st) {
+  hipLaunchKernelGGL(k_newton_rhs, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, first);
+  return hipGetLastError();
+}
+
+// GMRES least squares.  The Arnoldi basis of J started from r = -G spans the
+// Krylov space of A = I - theta dt J, and A V_k = V_{k+1} (I~ - theta dt H_k)
+// with I~ the k x k identity over a zero row; the correction is d = V_k y with
+// y minimising ||beta e_1 - (I~ - theta dt H_k) y||.  Givens rotations reduce
+// the (k+1) x k Hessenberg matrix to triangular form; one thread does the
+// O(k^2) work (k <= 47).
+__global__ void __launch_bounds__(256) k_gmres(Batch b) {
+  const SolveDev& s = MRA_SOLVE(b);
+  // A complete basis (no breakdown, k = m) leaves h_{m+1,m} = ||w|| in the
+  // partials of stage 3; after a breakdown at column k the scaling kernel has
+  // stored h_{k+1,k} in H.
+  const bool done = s.ctrl[C_DONE] != 0;
+  __shared__ double hlast;
+  if (!done) {
+    __shared__ double tot[2];
+    reduce_partials(part_buf(s, 0), nchunks((int)*s.n_active), 1, tot);
+    if (threadIdx.x == 0) {
+      hlast = sqrt(tot[0]);
+      if (!isfinite(tot[0])) {
+        s.ctrl[C_STATUS] = 5;
+        s.ctrl[C_MEFF] = 0;
+      }
+    }
+    __syncthreads();
+  }
+  const int k = s.ctrl[C_MEFF];
+  if (k <= 0) return;
+  const int m = s.m;
+  const double a = s.scal[S_THETA] * s.dt;
+  __shared__ double R[(kMaxM + 1) * kMaxM];
+  __shared__ double g[kMaxM + 1];
+  for (int q = threadIdx.x; q < (k + 1) * k; q += blockDim.x) {
+    const int i = q / k, j = q - i * k;
+    double v = 0.0;
+    if (i == k) {
+      if (j == k - 1) v = -a * (done ? s.H[i * m + j] : hlast);
+    } else if (i <= j + 1) {
+      v = (i == j ? 1.0 : 0.0) - a * s.H[i * m + j];
+    }
+    R[q] = v;
+  }
+  for (int i = threadIdx.x; i <= k; i += blockDim.x) g[i] = i == 0 ? s.scal[S_BETA] : 0.0;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int j = 0; j < k; ++j) {
+    const double x = R[j * k + j], y = R[(j + 1) * k + j];
+    const double r = hypot(x, y);
+    const double c = r > 0.0 ? x / r : 1.0, sn = r > 0.0 ? y / r : 0.0;
+    for (int l = j; l < k; ++l) {
+      const double p = R[j * k + l], q = R[(j + 1) * k + l];
+      R[j * k + l] = c * p + sn * q;
+      R[(j + 1) * k + l] = c * q - sn * p;
+    }
+    const double p = g[j], q = g[j + 1];
+    g[j] = c * p + sn * q;
+    g[j + 1] = c * q - sn * p;
+  }
+  bool bad = false;
+  for (int j = k - 1; j >= 0; --j) {
+    double t = g[j];
+    for (int l = j + 1; l < k; ++l) t -= R[j * k + l] * g[l];
+    const double d = R[j * k + j];
+    g[j] = d != 0.0 ? t / d : 0.0;      // a singular projected system takes no step there
+    bad |= !isfinite(g[j]);
+  }
+  for (int j = 0; j < k; ++j) s.y[j] = g[j];
+  if (bad) {
+    s.ctrl[C_STATUS] = 5;
+    s.ctrl[C_MEFF] = 0;
+  }
+}
+
+hipError_t launch_gmres(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres, dim3((1) * b.n), dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+__global__ void k_set_theta(Batch b, double theta) {
+  if (threadIdx.x == 0) MRA_SOLVE(b).scal[S_THETA] = theta;
+}
+
+hipError_t launch_set_theta(const Batch& b, double theta, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_theta, dim3((1) * b.n), dim3(64), 0, st, b, theta);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct mra_solve_s {
   std::vector<double> diag_rows;
   long steps = 0;                 // steps enqueued so far
   mra_solve_s* partner = nullptr; // passive scalar: the vorticity solve it rides on
+  int riders = 0;                 // passive scalars riding on this solve
 };
 
 namespace {
@@ -216,9 +217,39 @@ hipError_t enqueue_scalar_step(const Batch& b, const LaunchCfg& c, hipStream_t s
   return launch_gather(b, c, st);
 }
 
+// One theta-scheme step by Newton-GMRES: Newton iteration k evaluates
+// F(omega_k) (and the frozen fields of J at omega_k), forms -G(omega_k), runs
+// the Arnoldi process of J from it, solves the GMRES least squares on the
+// shifted Hessenberg matrix and adds V y; then the FP64 regrid.
+hipError_t enqueue_theta_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  const int dbl = c.prec == 0;
+  hipError_t e;
+  for (int it = 0; it < c.newton; ++it) {
+    if ((e = launch_prolong(b, c, 0, dbl, 0, 0, st)) != hipSuccess) return e;
+    if ((e = launch_poisson(b, c, 0, st)) != hipSuccess) return e;
+    if ((e = launch_rhs(b, c, st)) != hipSuccess) return e;
+    if ((e = launch_newton_rhs(b, c, it == 0, st)) != hipSuccess) return e;
+    if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
+    for (int j = 0; j < c.m; ++j) {
+      if ((e = launch_prolong(b, c, 1, dbl, 1, j, st)) != hipSuccess) return e;
+      if ((e = launch_poisson(b, c, 1, st)) != hipSuccess) return e;
+      if ((e = launch_jvp(b, c, st)) != hipSuccess) return e;
+      if ((e = launch_arnoldi(b, c, j, st)) != hipSuccess) return e;
+    }
+    if ((e = launch_gmres(b, c, st)) != hipSuccess) return e;
+    if ((e = launch_newton_update(b, c, it == c.newton - 1, st)) != hipSuccess) return e;
+  }
+  if ((e = launch_prolong(b, c, 2, 1, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_reset_max(b, st)) != hipSuccess) return e;
+  if ((e = launch_forward(b, c, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_threshold(b, c, 1, st)) != hipSuccess) return e;
+  return launch_gather(b, c, st);
+}
+
 // One exponential Rosenbrock-Euler step with regrid for every solve of b.
 hipError_t enqueue_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   if (c.kind == 1) return enqueue_scalar_step(b, c, st);
+  if (c.integ == 1) return enqueue_theta_step(b, c, st);
   const int dbl = c.prec == 0;
   hipError_t e;
   // residual F at omega
@@ -487,6 +518,9 @@ int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, do
                         int32_t eddy, const double* r0_dense, void* arena, size_t arena_bytes, void* stream,
                         mra_solve* out) {
   if (!partner || partner->cfg.kind != 0) return MRA_E_ARG;
+  // a scalar step reads the partner's flow at the start of its step, which a
+  // Newton step overwrites with the flow at its last iterate
+  if (partner->cfg.integ != 0) return MRA_E_UNSUPPORTED;
   int32_t r = check_grid(g);
   if (r != MRA_OK) return r;
   if (g->J != partner->cfg.J || g->p != partner->cfg.p) return MRA_E_ARG;
@@ -517,6 +551,7 @@ int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, do
   h->dev = reinterpret_cast<SolveDev*>(arena);
   h->cfg = LaunchCfg{s.J, s.p, s.prec, m, 1};
   h->partner = partner;
+  partner->riders += 1;
   h->steps = partner->steps;   // the next scalar step follows the partner's next step
   (void)hipGetDevice(&h->device);
   h->diag_rows.resize((size_t)s.N * 5);
@@ -572,11 +607,11 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
   for (int t = 0; t < maxs; ++t) {
     // group the solves still running by launch configuration
     // (vorticity solves first: a scalar's step reads its partner's step)
-    std::map<std::tuple<int, int, int, int, int>, std::vector<mra_solve>> groups;
+    std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > t) {
         const LaunchCfg& c = solves[i]->cfg;
-        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m)].push_back(solves[i]);
+        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton)].push_back(solves[i]);
       }
     for (auto& kv : groups) {
       auto& v = kv.second;
@@ -704,11 +739,11 @@ int32_t mra_solve_ptrs_get(mra_solve h, mra_solve_ptrs* out) {
   return MRA_OK;
 }
 
-int32_t mra_solve_destroy(mra_solve h) {
-  if (!h) return MRA_E_ARG;
+// Drops every captured graph that launches h (its own and the cached batch
+// graphs), after the work they may still have in flight.
+static void drop_graphs_of(mra_solve h) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    // drop the cached batch graphs that launch this solve
     bool synced = false;
     for (auto it = g_batch_graphs.begin(); it != g_batch_graphs.end();) {
       const auto& key = it->first.first;
@@ -722,8 +757,37 @@ int32_t mra_solve_destroy(mra_solve h) {
   if (h->graph) {
     (void)hipStreamSynchronize(h->graph_stream);
     (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
   }
-  if (h->graph_def) (void)hipGraphDestroy(h->graph_def);
+  if (h->graph_def) {
+    (void)hipGraphDestroy(h->graph_def);
+    h->graph_def = nullptr;
+  }
+  h->graph_stream = nullptr;
+}
+
+int32_t mra_solve_set_integrator(mra_solve h, int32_t integrator, double theta, int32_t newton_iters,
+                                 void* stream) {
+  if (!h) return MRA_E_ARG;
+  if (integrator != MRA_EXPONENTIAL && integrator != MRA_THETA_NEWTON) return MRA_E_ARG;
+  if (integrator == MRA_THETA_NEWTON) {
+    if (!(theta >= 0.0 && theta <= 1.0)) return MRA_E_ARG;
+    if (newton_iters < 1 || newton_iters > MRA_MAX_NEWTON) return MRA_E_ARG;
+  }
+  if (h->cfg.kind != 0) return MRA_E_UNSUPPORTED;
+  if (integrator == MRA_THETA_NEWTON && h->riders > 0) return MRA_E_UNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  drop_graphs_of(h);
+  if (integrator == MRA_THETA_NEWTON) MRA_TRY(launch_set_theta(one(h->dev), theta, st));
+  h->cfg.integ = integrator;
+  h->cfg.newton = integrator == MRA_THETA_NEWTON ? newton_iters : 0;
+  return MRA_OK;
+}
+
+int32_t mra_solve_destroy(mra_solve h) {
+  if (!h) return MRA_E_ARG;
+  drop_graphs_of(h);
+  if (h->partner) h->partner->riders -= 1;
   delete h;
   return MRA_OK;
 }

@@ -27,7 +27,7 @@ constexpr int kTwN = 2048;          // twiddle table size (largest FFT length)
 enum Ctrl : int { C_MEFF = 0, C_DONE = 1, C_STATUS = 2, C_CNT0 = 4, C_CNT1 = 5, C_CNT2 = 6,
                   C_CNT3 = 7, C_NCTRL = 16 };
 enum Scal : int { S_BETA = 0, S_INV = 1, S_NRMAV = 2, S_UMAX = 3, S_T = 4, S_EVALS = 5, S_STEPS = 6,
-                  S_NSCAL = 16 };
+                  S_THETA = 7, S_NSCAL = 16 };
 
 struct SolveDev {
   // geometry / numbers
@@ -69,8 +69,8 @@ struct SolveDev {
   void* spec;               // complex half spectrum [(N/2+1)][N]: omega, then u
   void* spec2;              // the v spectrum, same shape
   double* vel64;            // FP64 velocity [2][Nf] of dense64 (diagnostics)
-  double* dense64;          // FP64 regrid field [Nf]
-  double* packed64;         // FP64 packed pyramid [Nf]
+  double* dense64;          // FP64 regrid field [Nf]; F(omega_n) during Newton iterations
+  double* packed64;         // FP64 packed pyramid [Nf]; omega_n during Newton iterations
   double* out_rhs;          // residual at the active nodes [Nf]
   double* out_jvp;          // J v at the active nodes [Nf]
   const double* vin;        // active vector scattered by src 2 of the scatter
@@ -329,6 +329,8 @@ __device__ inline double next_scale(const SolveDev& s, int j, int bx) {
 struct LaunchCfg {
   int J, p, prec, m;
   int kind = 0;   // 0 vorticity, 1 passive scalar coupled to a vorticity solve
+  int integ = 0;  // 0 exponential Rosenbrock-Euler, 1 theta-scheme by Newton-GMRES
+  int newton = 0; // Newton iterations per step (integ 1)
 };
 
 hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);
@@ -369,6 +371,13 @@ hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st);
 hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st);
 hipError_t launch_phi1(const Batch& b, const LaunchCfg& c, hipStream_t st);
 hipError_t launch_update(const Batch& b, const LaunchCfg& c, hipStream_t st);
+// theta-scheme Newton iteration: w <- -G(omega_k) (first: keep omega_n, F_n);
+// GMRES least squares on the shifted Hessenberg matrix; omega += V y
+// (last: the step's time advance)
+hipError_t launch_newton_rhs(const Batch& b, const LaunchCfg& c, int first, hipStream_t st);
+hipError_t launch_gmres(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_newton_update(const Batch& b, const LaunchCfg& c, int last, hipStream_t st);
+hipError_t launch_set_theta(const Batch& b, double theta, hipStream_t st);
 hipError_t launch_reset_ctrl(const Batch& b, hipStream_t st);
 hipError_t launch_clear_done(const Batch& b, hipStream_t st);
 
