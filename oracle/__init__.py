@@ -11,6 +11,9 @@ Modules
   ops     collocation derivatives, Poisson solve, Smagorinsky viscosity,
           advection-diffusion residual and its Jacobian-vector product
   krylov  Arnoldi + phi_1 exponential step with regrid, diagnostics
+  implicit  theta-scheme step by Newton iterations with GMRES
+  scalar  passive scalar (vapor) transported by the vortex flow
+  track   vortex centres and the convective time
   brute   pure-Python loop twins for tiny grids (used to pin the above)
 
 Everything here follows the method of Walsh & Alam, "Fujiwhara interaction of
