@@ -425,14 +425,71 @@ def run_implicit(args) -> int:
     return 0
 
 
+def run_families(args) -> int:
+    """The unequal-strength (Section 3.3: U2/U1 = 1 .. 0.5 at equal size) and
+    unequal-size (Section 3.4: equal peak vorticity, R2/R1 = 0.9, 0.7, 0.5)
+    pairs at 512^2 in one batch: energy and enstrophy relative to their
+    initial values and the tracked separation at the paper's output times
+    9.375 h, 18.75 h and 37.5 h.  Time is converted with R/U1: 100 km at
+    46.8 m/s against the model's r0 / (Gamma1 / (2 pi r0))."""
+    import torch
+    import workloads as W
+    import paper_1604_08159_amd as m
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    pbs = [W.unequal_strength_pair(r) for r in W.E6_U2_OVER_U1] + [W.unequal_size_pair(r) for r in W.E7_R2_OVER_R1]
+    r0 = pbs[0].vortices[0].r0
+    t_model_per_hour = (r0 / (1.0 / (2 * np.pi * r0))) / (100e3 / 46.8 / 3600.0)
+    marks = [int(round(hrs * t_model_per_hour / pbs[0].dt)) for hrs in (9.375, 18.75, 37.5)]
+    if args.fam_steps <= 0:
+        args.fam_steps = marks[-1]
+    marks = [min(k, args.fam_steps) for k in marks]
+    solves = []
+    with torch.cuda.stream(stream):
+        for pb in pbs:
+            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_MIXED, pb.m,
+                                  pb.dt, torch.from_numpy(W.initial_field(pb)).to(dev), stream=stream))
+    d0 = [s.read(dense=False, stream=stream)[1] for s in solves]
+    cs = [[(v.cx, v.cy) for v in pb.vortices] for pb in pbs]
+    hist = [[] for _ in pbs]
+    done, wall, ev = 0, 0.0, 0.0
+    ev0 = sum(s.scalars()["evals"] for s in solves)
+    for target in sorted(set(list(range(50, args.fam_steps + 1, 50)) + marks)):
+        t0 = time.perf_counter()
+        m.solve_batch(solves, [target - done] * len(solves), stream=stream)
+        stream.synchronize()
+        wall += time.perf_counter() - t0
+        done = target
+        for i, s in enumerate(solves):
+            cs[i] = s.track(cs[i], stream=stream)
+            if target in marks:
+                _, d = s.read(dense=False, stream=stream)
+                b = float(np.hypot(*[((cs[i][1][k] - cs[i][0][k] + np.pi) % (2 * np.pi)) - np.pi for k in range(2)]))
+                b0 = abs(pbs[i].vortices[1].cx - pbs[i].vortices[0].cx)
+                hist[i].append({"hours": round(target * pbs[i].dt / t_model_per_hour, 3),
+                                "E_over_E0": d["energy"] / d0[i]["energy"],
+                                "Z_over_Z0": d["enstrophy"] / d0[i]["enstrophy"],
+                                "b_over_b0": b / b0, "n_active": int(d["n_active"]), "status": int(d["status"])})
+        log(f"families: {done} steps")
+    ev = sum(s.scalars()["evals"] for s in solves) - ev0
+    print(json.dumps({"workload": f"unequal-strength (U2/U1 = 1, 0.80, 0.70, 0.60, 0.50) and unequal-size "
+                                  f"(R2/R1 = 0.9, 0.7, 0.5) pairs, Re=37440, 512^2, batch of {len(pbs)}, mixed "
+                                  f"precision, {args.fam_steps} steps",
+                      "metric": "active-pt RHS evals/s", "value": ev / wall, "wall_s": wall,
+                      "model_time_per_hour": t_model_per_hour,
+                      "runs": {pb.name: h for pb, h in zip(pbs, hist)}}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["fujiwhara", "ensemble", "serving", "vapor", "three2048", "longrun",
-                                           "implicit"],
+                                           "implicit", "families"],
                     default="fujiwhara")
     ap.add_argument("--batch3", type=int, default=2)
     ap.add_argument("--steps3", type=int, default=10)
     ap.add_argument("--long-steps", type=int, default=2000)
+    ap.add_argument("--fam-steps", type=int, default=0, help="0: up to 37.5 h")
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--newton", type=int, default=2)
     ap.add_argument("--solves", type=int, default=256)
@@ -465,6 +522,8 @@ def main() -> int:
         return run_vapor(args)
     if args.workload == "three2048":
         return run_three(args)
+    if args.workload == "families":
+        return run_families(args)
     if args.workload == "implicit":
         return run_implicit(args)
     if args.workload == "longrun":

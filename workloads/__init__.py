@@ -142,6 +142,38 @@ def fujiwhara_pair(seed: int, J: int = 9) -> Problem:
                    dt=0.01, steps=2000, vortices=vs)
 
 
+# Section 3.3's unequal-strength runs: U1 = 46.8 m/s against U2, equal core
+# size, b = 450 km at R = 100 km (b/R = 4.5), Re = 37440 from U1.
+E6_U2_OVER_U1 = (1.0, 37.5 / 46.8, 32.8 / 46.8, 28.1 / 46.8, 23.4 / 46.8)
+# Section 3.4's cyclone and convection-induced vortex: equal peak vorticity,
+# R2/R1 in {0.9, 0.7, 0.5}.
+E7_R2_OVER_R1 = (0.9, 0.7, 0.5)
+
+
+def unequal_strength_pair(u2_over_u1: float, J: int = 9, r0: float = 0.3) -> Problem:
+    """Two Gaussians of equal radius r0 whose core-edge speeds Gamma/(2 pi r0)
+    are in the ratio u2_over_u1 (so Gamma2 = u2_over_u1 * Gamma1, Gamma1 = 1),
+    separation b = 4.5 r0 along x; 4-point DD, threshold 1e-4, Re = 37440,
+    m = 20, dt = 0.01."""
+    c, b = math.pi, 4.5 * r0
+    vs = (Vortex(1.0, r0, c - b / 2, c), Vortex(float(u2_over_u1), r0, c + b / 2, c))
+    return Problem(f"unequal_u{u2_over_u1:.3f}", J=J, p=2, eps=1e-4, re=37440.0, cs=0.17, m=20, dt=0.01,
+                   steps=2000, vortices=vs)
+
+
+def unequal_size_pair(r2_over_r1: float, J: int = 9, r1: float = 0.3) -> Problem:
+    """A Gaussian of radius r1 (Gamma1 = 1) and one of radius r2 = r2_over_r1 * r1
+    with the same peak vorticity Gamma/(pi r^2), so Gamma2 = r2_over_r1^2;
+    separation b = 4.5 r1 between the centres (the paper gives none for these
+    runs: the unequal-strength spacing is reused); other numbers as
+    unequal_strength_pair."""
+    c, b = math.pi, 4.5 * r1
+    r2 = r2_over_r1 * r1
+    vs = (Vortex(1.0, r1, c - b / 2, c), Vortex(float(r2_over_r1) ** 2, r2, c + b / 2, c))
+    return Problem(f"unequal_r{r2_over_r1:.2f}", J=J, p=2, eps=1e-4, re=37440.0, cs=0.17, m=20, dt=0.01,
+                   steps=2000, vortices=vs)
+
+
 def three_vortex(J: int = 11) -> Problem:
     """Three Gaussians shaped like the unequal-strength Re = 37440 runs
     (Gamma ratios 1.6 and 2.7, radius ratios 1.25 and 1.7, b/R = 4.5) plus
