@@ -14,7 +14,7 @@ alternative to the exponential step of `krylov.py` (readings, S20):
       (I - theta dt J(w_k)) d = -G(w_k),   w_{k+1} = w_k + d,
   with J = R J Pi at eddy viscosity frozen at w_k (the same Jacobian as the
   exponential step; exact when the Smagorinsky term is off, an inexact Newton
-  otherwise);
+  otherwise), or the exact Jacobian (exact=True: Newton proper);
 * each linear system by one cycle of GMRES(m) from a zero guess: Arnoldi
   (modified Gram-Schmidt) on A = I - theta dt J from r = -G, the happy
   breakdown rule of `krylov.py` (h_{j+1,j} <= 1e-13 ||A v_j||), and the
@@ -41,8 +41,8 @@ def gmres(Av, b: np.ndarray, m: int):
 
 
 def theta_step(st: krylov.State, g: krylov.Grid, fl: ops.Flow, m: int, dt: float, theta: float,
-               newton_iters: int, do_regrid: bool = True) -> krylov.State:
-    op = krylov.Operator(g, fl, st.index_fine)
+               newton_iters: int, do_regrid: bool = True, exact: bool = False) -> krylov.State:
+    op = krylov.Operator(g, fl, st.index_fine, exact)
     wn = st.omega_M.copy()
     Fn = op.F(wn)                          # also sets the frozen fields at w_0
     w, F = wn.copy(), Fn

@@ -6,7 +6,8 @@ used here is the exponential Rosenbrock-Euler step
 
     omega_M <- omega_M + dt * phi_1(dt A) F_M,     phi_1(z) = (e^z - 1)/z,
 
-with A = R J Pi the Jacobian (eddy viscosity frozen) restricted to the active
+with A = R J Pi the Jacobian (eddy viscosity frozen; or, with exact=True, the
+exact Jacobian that also linearises the viscosity) restricted to the active
 nodes, approximated in the Arnoldi basis of K_m(A, F_M):
 phi_1(dt A) F_M ~= beta V_m phi_1(dt H_m) e_1.  phi_1(dt H_m) e_1 is the last
 column of expm([[dt H_m, e_1], [0, 0]]) (scipy's expm is the library step).
@@ -67,10 +68,11 @@ def regrid(dense: np.ndarray, g: Grid):
 
 
 class Operator:
-    """F and A = R J Pi at a fixed active set."""
+    """F and A = R J Pi at a fixed active set; J at frozen eddy viscosity, or
+    the exact Jacobian (exact=True)."""
 
-    def __init__(self, g: Grid, fl: ops.Flow, index_fine: np.ndarray):
-        self.g, self.fl, self.fi = g, fl, index_fine
+    def __init__(self, g: Grid, fl: ops.Flow, index_fine: np.ndarray, exact: bool = False):
+        self.g, self.fl, self.fi, self.exact = g, fl, index_fine, exact
 
     def dense(self, vals):
         return mra.prolong(vals, self.fi, self.g.J, self.g.p)
@@ -82,7 +84,8 @@ class Operator:
 
     def Av(self, v):
         vt = self.dense(v)
-        return ops.jvp(vt, self.base, self.g.h, self.g.p, self.fl).ravel()[self.fi]
+        f = ops.jvp_exact if self.exact else ops.jvp
+        return f(vt, self.base, self.g.h, self.g.p, self.fl).ravel()[self.fi]
 
 
 def arnoldi_mgs(Av, v0: np.ndarray, m: int):
@@ -126,8 +129,9 @@ def init_state(omega0: np.ndarray, g: Grid) -> State:
     return State(vals, mask, ip, fi)
 
 
-def step(st: State, g: Grid, fl: ops.Flow, m: int, dt: float, do_regrid: bool = True) -> State:
-    op = Operator(g, fl, st.index_fine)
+def step(st: State, g: Grid, fl: ops.Flow, m: int, dt: float, do_regrid: bool = True,
+         exact: bool = False) -> State:
+    op = Operator(g, fl, st.index_fine, exact)
     F = op.F(st.omega_M)
     V, H, m_eff, beta = arnoldi_mgs(op.Av, F, m)
     om = st.omega_M.copy()
@@ -157,8 +161,8 @@ def diagnostics(omega: np.ndarray, g: Grid) -> Dict[str, float]:
 
 
 def run(omega0: np.ndarray, g: Grid, fl: ops.Flow, m: int, dt: float, nsteps: int,
-        st: Optional[State] = None) -> State:
+        st: Optional[State] = None, exact: bool = False) -> State:
     st = st if st is not None else init_state(omega0, g)
     for _ in range(nsteps):
-        st = step(st, g, fl, m, dt)
+        st = step(st, g, fl, m, dt, exact=exact)
     return st

@@ -140,3 +140,35 @@ def jvp(vt: np.ndarray, base: Dict[str, np.ndarray], h: float, p: int, fl: Flow)
         w = base["omega"]
         out = out - (d1(uv * w + base["u"] * vt, 1, h, p) + d1(vv * w + base["v"] * vt, 0, h, p))
     return out
+
+
+def nu_prime(base: Dict[str, np.ndarray], uv: np.ndarray, vv: np.ndarray, h: float, p: int,
+             fl: Flow) -> np.ndarray:
+    """Derivative of the eddy viscosity of eq. (5) in the direction whose
+    velocity is (u_v, v_v): nu' = (Cs h)^2 d|S| with, for |S| = sqrt(2 Q),
+    Q = S11^2 + S22^2 + 2 S12^2, d|S| = dQ / |S| = 2 (S11 S11' + S22 S22'
+    + 2 S12 S12') / |S|.  |S| is not differentiable where it vanishes; there
+    the numerator vanishes too and nu' is taken as 0 (reading S22).  Zero
+    unless the viscosity follows the local strain (smag_mode 2)."""
+    if fl.smag_mode != 2:
+        return np.zeros_like(uv)
+    u, v = base["u"], base["v"]
+    s11, s22 = d1(u, 1, h, p), d1(v, 0, h, p)
+    s12 = 0.5 * (d1(u, 0, h, p) + d1(v, 1, h, p))
+    t11, t22 = d1(uv, 1, h, p), d1(vv, 0, h, p)
+    t12 = 0.5 * (d1(uv, 0, h, p) + d1(vv, 1, h, p))
+    S = np.sqrt(2.0 * (s11 * s11 + s22 * s22 + 2.0 * s12 * s12))
+    num = 2.0 * (s11 * t11 + s22 * t22 + 2.0 * s12 * t12)
+    dS = np.divide(num, S, out=np.zeros_like(num), where=S > 0.0)
+    return (fl.cs * h) ** 2 * dS
+
+
+def jvp_exact(vt: np.ndarray, base: Dict[str, np.ndarray], h: float, p: int, fl: Flow) -> np.ndarray:
+    """The exact Jacobian-vector product of F: the frozen-viscosity product
+    plus the viscosity's own variation, 1/2 [L(nu' w) + nu' L w - w L nu']."""
+    out = jvp(vt, base, h, p, fl)
+    if fl.smag_mode != 2:
+        return out
+    uv, vv = velocities(poisson(vt, h, p), h, p)
+    return out + diffusion(nu_prime(base, uv, vv, h, p, fl), base["omega"], h, p)
+
