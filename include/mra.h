@@ -65,6 +65,7 @@ enum { MRA_FP64 = 0, MRA_FP32 = 1, MRA_MIXED = 2 };   /* MIXED: FP32 bulk fields
                                                          FP64 Krylov / regrid      */
 enum { MRA_FORWARD = 1, MRA_INVERSE = -1, MRA_PROLONG = 2 };
 enum { MRA_EXPONENTIAL = 0, MRA_THETA_NEWTON = 1 };   /* time integrator of a solve */
+enum { MRA_JAC_FROZEN = 0, MRA_JAC_EXACT = 1 };        /* Jacobian of its Krylov products */
 #define MRA_MAX_NEWTON 8
 
 /* Grid: J in [j0+1, 11]; p in {2, 3} (4- and 6-point DD); j0 must equal
@@ -181,8 +182,8 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
  *   step.  The first call captures one step into a HIP graph on `stream`;
  *   later calls replay it.
  * solve_batch: advances solves[i] by nsteps[i] steps; solves of equal
- *   (J, p, precision, m, integrator, Newton iterations) share every kernel
- *   launch.  Results are bit for bit
+ *   (J, p, precision, m, integrator, Newton iterations, Jacobian) share every
+ *   kernel launch.  Results are bit for bit
  *   those of krylov_step on each solve alone.
  * mra_solve_read: synchronises `stream`; omega_dense_out (device double
  *   [N][N], may be NULL) receives Pi(omega_M); diag_out (HOST double[8],
@@ -264,6 +265,28 @@ int32_t mra_solve_destroy(mra_solve s);
  * ------------------------------------------------------------------------ */
 int32_t mra_solve_set_integrator(mra_solve s, int32_t integrator, double theta, int32_t newton_iters,
                                  void* stream);
+
+/* ------------------------------------------------------------------------
+ * mra_solve_set_jacobian -- the Jacobian J in the Krylov products of later
+ * steps of a vorticity solve (either integrator).  MRA_JAC_FROZEN (default):
+ * eddy viscosity frozen at the linearisation point.  MRA_JAC_EXACT: the
+ * viscosity of eq. (5) is linearised too, adding
+ *
+ *   1/2 [L(nu' w~) + nu' L w~ - w~ L nu'],
+ *   nu' = (Cs h)^2 2 (S11 S11' + S22 S22' + 2 S12 S12') / |S|,
+ *
+ * with S the strain of the base velocity and S' that of (u_v, v_v); nu' = 0
+ * where |S| = 0 (the numerator vanishes there too; |nu'| <= (Cs h)^2 |S'|).
+ * Only the local-strain model (smag_mode 2) depends on omega; for the other
+ * modes both choices give the same products.  With it the exponential step is
+ * second order in dt and the theta-scheme's Newton iteration is Newton's
+ * method proper.  Each product also evaluates nu' on the tiles around the
+ * active ones (one more stencil pass, no extra arena memory).  Drops the
+ * captured graphs that launch the solve.  Errors: MRA_E_ARG (null handle,
+ * unknown value); MRA_E_UNSUPPORTED on a passive scalar (its operator is
+ * linear).
+ * ------------------------------------------------------------------------ */
+int32_t mra_solve_set_jacobian(mra_solve s, int32_t jacobian);
 
 /* Profiling hook: times `reps` back-to-back launches of one kernel of the
  * step, launched exactly as the step launches it for the batch `solves`

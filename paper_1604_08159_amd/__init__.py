@@ -25,7 +25,7 @@ import torch
 from . import _lib
 from ._lib import (FlowDesc, GridDesc, MraError, SolvePtrs, MRA_FORWARD, MRA_INVERSE, MRA_PROLONG,
                    MRA_FP64, MRA_FP32, MRA_MIXED, MRA_OK, MRA_E_NONFINITE, MRA_EXPONENTIAL,
-                   MRA_THETA_NEWTON, MRA_MAX_NEWTON)
+                   MRA_THETA_NEWTON, MRA_MAX_NEWTON, MRA_JAC_FROZEN, MRA_JAC_EXACT)
 
 _LIB: Optional[C.CDLL] = None
 
@@ -155,6 +155,10 @@ class Solve:
         _check("mra_solve_set_integrator",
                lib().mra_solve_set_integrator(self.handle, integrator, float(theta), int(newton_iters),
                                               _stream(stream)))
+
+    def set_jacobian(self, jacobian: int) -> None:
+        """Jacobian of later steps' Krylov products: MRA_JAC_FROZEN or MRA_JAC_EXACT."""
+        _check("mra_solve_set_jacobian", lib().mra_solve_set_jacobian(self.handle, int(jacobian)))
 
     def read(self, dense: bool = True, stream=None) -> Tuple[Optional[torch.Tensor], Dict[str, float]]:
         out = torch.empty((self.N, self.N), dtype=torch.float64, device=self.arena.device) if dense else None

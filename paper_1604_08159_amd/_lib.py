@@ -15,6 +15,7 @@ MRA_OK, MRA_E_ARG, MRA_E_SIZE, MRA_E_NOMEM, MRA_E_DEVICE, MRA_E_NONFINITE, MRA_E
 MRA_FP64, MRA_FP32, MRA_MIXED = 0, 1, 2
 MRA_FORWARD, MRA_INVERSE, MRA_PROLONG = 1, -1, 2
 MRA_EXPONENTIAL, MRA_THETA_NEWTON = 0, 1
+MRA_JAC_FROZEN, MRA_JAC_EXACT = 0, 1
 MRA_MAX_NEWTON = 8
 
 
@@ -60,6 +61,7 @@ EXPORTS = {
     "mra_solve_ptrs_get": (C.c_int32, [C.c_void_p, C.POINTER(SolvePtrs)]),
     "mra_solve_destroy": (C.c_int32, [C.c_void_p]),
     "mra_solve_set_integrator": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p]),
+    "mra_solve_set_jacobian": (C.c_int32, [C.c_void_p, C.c_int32]),
     "mra_time_kernel": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_float)]),
 }

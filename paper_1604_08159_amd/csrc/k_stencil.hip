@@ -103,10 +103,10 @@ __host__ __device__ inline size_t rhs_lds_elems(int TS) {
   return 2 * Wu * Wu + 2 * Wn * Wn + Ww * Ww;
 }
 template <int P, typename T>
-__host__ __device__ inline size_t jvp_lds_elems(int TS) {
+__host__ __device__ inline size_t jvp_lds_elems(int TS, bool exact = false) {
   using G = Geo<P>;
   const size_t Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
-  return 3 * Ww * Ww + 2 * Wn * Wn;
+  return exact ? 4 * Ww * Ww + 4 * Wn * Wn : 3 * Ww * Ww + 2 * Wn * Wn;
 }
 
 template <int P, typename T, int TS>
@@ -194,10 +194,66 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   }
 }
 
+// Derivative of the eddy viscosity in the direction of the current Arnoldi
+// vector, for the exact Jacobian: with S the strain of (u, v) and S' that of
+// (u_v, v_v), nu' = (Cs h)^2 2 (S11 S11' + S22 S22' + 2 S12 S12') / |S|
+// (0 where |S| = 0, where the numerator vanishes too; |nu'| <= (Cs h)^2 |S'|).
+// Written to the solve's FP64 diagnostics buffer (unused during a step) as T,
+// on every tile whose 3 x 3 tile neighbourhood holds an active node: the
+// product on an active tile reads nu' within its halo.
+template <int P, typename T, int TS>
+__global__ void __launch_bounds__(256) k_nuprime(Batch b) {
+  using G = Geo<P>;
+  constexpr int W = TS + 2 * G::R1;
+  __shared__ T su[W * W], sv[W * W], suv[W * W], svv[W * W];
+  const SolveDev& s = MRA_SOLVE(b);
+  const int N = s.N, ntx = s.ntx;
+  const int tile = tile_of_block(MRA_BX(b), ntx * ntx, b.n);
+  if (s.ctrl[C_DONE] || s.smag_mode != 2) return;
+  const int tx = tile % ntx, ty = tile / ntx;
+  int near = 0;
+  for (int d = 0; d < 9; ++d) {
+    const int nx = (tx + d % 3 - 1 + ntx) % ntx, ny = (ty + d / 3 - 1 + ntx) % ntx;
+    near |= s.tile_count[ny * ntx + nx];
+  }
+  if (!near) return;
+  const int x0 = tx * TS, y0 = ty * TS;
+  {
+    Region<W, T> ru, rv, ruv, rvv;
+    ru.fetch(reinterpret_cast<const T*>(s.u), x0 - G::R1, y0 - G::R1, N);
+    rv.fetch(reinterpret_cast<const T*>(s.v), x0 - G::R1, y0 - G::R1, N);
+    ruv.fetch(reinterpret_cast<const T*>(s.uv), x0 - G::R1, y0 - G::R1, N);
+    rvv.fetch(reinterpret_cast<const T*>(s.vv), x0 - G::R1, y0 - G::R1, N);
+    ru.put(su);
+    rv.put(sv);
+    ruv.put(suv);
+    rvv.put(svv);
+  }
+  __syncthreads();
+  const T ih = T(1.0 / s.h);
+  const T cs2 = T((s.cs * s.h) * (s.cs * s.h));
+  T* out = reinterpret_cast<T*>(s.vel64);
+  for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+    const int r = q / TS, c = q - r * TS;
+    const int ra = r + G::R1, ca = c + G::R1;
+    const T s11 = ih * dx1<P, T>(su, W, ra, ca);
+    const T s22 = ih * dy1<P, T>(sv, W, ra, ca);
+    const T s12 = T(0.5) * ih * (dy1<P, T>(su, W, ra, ca) + dx1<P, T>(sv, W, ra, ca));
+    const T t11 = ih * dx1<P, T>(suv, W, ra, ca);
+    const T t22 = ih * dy1<P, T>(svv, W, ra, ca);
+    const T t12 = T(0.5) * ih * (dy1<P, T>(suv, W, ra, ca) + dx1<P, T>(svv, W, ra, ca));
+    const T sn = sqrt(T(2) * (s11 * s11 + s22 * s22 + T(2) * s12 * s12));
+    const T num = T(2) * (s11 * t11 + s22 * t22 + T(2) * s12 * t12);
+    out[(y0 + r) * N + x0 + c] = sn > T(0) ? cs2 * (num / sn) : T(0);
+  }
+}
+
 // Jacobian-vector product on one tile.  Every global load is issued in one
 // phase: v~ and nu_e regions into LDS; u, v, u_v, v_v, w~ at this thread's
-// flux points and the ranks of its output nodes into registers.
-template <int P, typename T, int TS>
+// flux points and the ranks of its output nodes into registers.  EX (the
+// exact Jacobian, local strain) adds the viscosity's variation
+// 1/2 [L(nu' w~) + nu' L w~ - w~ L nu'] with nu' from k_nuprime.
+template <int P, typename T, int TS, bool EX>
 __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   using G = Geo<P>;
   extern __shared__ unsigned char smem[];
@@ -215,6 +271,11 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   T* fb = fa + Ww * Ww;
   T* nu = fb + Ww * Ww;
   T* cn = nu + Wn * Wn;
+  // exact Jacobian: w~ (Ww region), nu' and nu' w~ (Wn regions)
+  T* wl = cn + Wn * Wn;
+  T* np = wl + Ww * Ww;
+  T* cp = np + Wn * Wn;
+  const bool ex = EX && s.smag_mode == 2;
   const T* gu = reinterpret_cast<const T*>(s.u);
   const T* gv = reinterpret_cast<const T*>(s.v);
   const T* guv = reinterpret_cast<const T*>(s.uv);
@@ -245,6 +306,13 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
     Region<Wn, T> rnu;
     rvt.fetch(reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, N);
     rnu.fetch(reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, N);
+    if constexpr (EX) {
+      if (ex) {
+        Region<Wn, T> rnp;
+        rnp.fetch(reinterpret_cast<const T*>(s.vel64), x0 - P, y0 - P, N);
+        rnp.put(np);
+      }
+    }
     rvt.put(vt);
     rnu.put(nu);
   }
@@ -258,6 +326,7 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
       const T vtv = vt[q];
       fa[q] = uvr[i] * wr[i] + ur[i] * vtv;
       fb[q] = vvr[i] * wr[i] + vr[i] * vtv;
+      if constexpr (EX) wl[q] = wr[i];
     }
   }
   constexpr int on = G::R1 - P;
@@ -266,6 +335,15 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
     cn[q] = nu[q] * vt[(r + on) * Ww + c + on];
   }
   __syncthreads();
+  if constexpr (EX) {
+    if (ex) {
+      for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
+        const int r = q / Wn, c = q - r * Wn;
+        cp[q] = np[q] * wl[(r + on) * Ww + c + on];
+      }
+      __syncthreads();
+    }
+  }
   const T mu = T(s.mu);
   double* out = s.out_jvp;
 #pragma unroll
@@ -280,7 +358,16 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
     const T nv = nu[rn * Wn + cn_];
     const T diff = T(0.5) * ih2 * (lap5<P, T>(cn, Wn, rn, cn_) + nv * lap5<P, T>(vt, Ww, ra, ca) -
                                    vv * lap5<P, T>(nu, Wn, rn, cn_));
-    out[k] = (double)(adv + diff - mu * vv);
+    T tot = adv + diff - mu * vv;
+    if constexpr (EX) {
+      if (ex) {
+        const T wv = wl[ra * Ww + ca];
+        const T pv = np[rn * Wn + cn_];
+        tot += T(0.5) * ih2 * (lap5<P, T>(cp, Wn, rn, cn_) + pv * lap5<P, T>(wl, Ww, ra, ca) -
+                               wv * lap5<P, T>(np, Wn, rn, cn_));
+      }
+    }
+    out[k] = (double)tot;
   }
 }
 
@@ -407,14 +494,18 @@ hipError_t launch_fill(void* f, size_t n, int prec, double value, hipStream_t st
 }
 
 template <int P, typename T, int TS>
-static hipError_t rhs_ts(const Batch& b, int N, bool jvp, hipStream_t st) {
+static hipError_t rhs_ts(const Batch& b, int N, bool jvp, bool exact, hipStream_t st) {
   const int nt = (N / TS) * (N / TS);
   if (!jvp) {
     const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
     hipLaunchKernelGGL((k_rhs<P, T, TS>), dim3((nt) * b.n), dim3(256), lds, st, b);
-  } else {
+  } else if (!exact) {
     const size_t lds = jvp_lds_elems<P, T>(TS) * sizeof(T);
-    hipLaunchKernelGGL((k_jvp<P, T, TS>), dim3((nt) * b.n), dim3(256), lds, st, b);
+    hipLaunchKernelGGL((k_jvp<P, T, TS, false>), dim3((nt) * b.n), dim3(256), lds, st, b);
+  } else {
+    hipLaunchKernelGGL((k_nuprime<P, T, TS>), dim3((nt) * b.n), dim3(256), 0, st, b);
+    const size_t lds = jvp_lds_elems<P, T>(TS, true) * sizeof(T);
+    hipLaunchKernelGGL((k_jvp<P, T, TS, true>), dim3((nt) * b.n), dim3(256), lds, st, b);
   }
   return hipGetLastError();
 }
@@ -423,9 +514,10 @@ template <int P, typename T>
 static hipError_t rhs_t(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {
   const int N = 1 << c.J;
   const int TS = tile_edge(c.J, c.p, c.prec);
-  if (TS == 32) return rhs_ts<P, T, 32>(b, N, jvp, st);
-  if (TS == 16) return rhs_ts<P, T, 16>(b, N, jvp, st);
-  return rhs_ts<P, T, 8>(b, N, jvp, st);
+  const bool exact = jvp && c.jac == 1;
+  if (TS == 32) return rhs_ts<P, T, 32>(b, N, jvp, exact, st);
+  if (TS == 16) return rhs_ts<P, T, 16>(b, N, jvp, exact, st);
+  return rhs_ts<P, T, 8>(b, N, jvp, exact, st);
 }
 
 static hipError_t rhs_dispatch(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {

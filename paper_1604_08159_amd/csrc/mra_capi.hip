@@ -607,11 +607,11 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
   for (int t = 0; t < maxs; ++t) {
     // group the solves still running by launch configuration
     // (vorticity solves first: a scalar's step reads its partner's step)
-    std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
+    std::map<std::tuple<int, int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > t) {
         const LaunchCfg& c = solves[i]->cfg;
-        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton)].push_back(solves[i]);
+        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton, c.jac)].push_back(solves[i]);
       }
     for (auto& kv : groups) {
       auto& v = kv.second;
@@ -781,6 +781,15 @@ int32_t mra_solve_set_integrator(mra_solve h, int32_t integrator, double theta, 
   if (integrator == MRA_THETA_NEWTON) MRA_TRY(launch_set_theta(one(h->dev), theta, st));
   h->cfg.integ = integrator;
   h->cfg.newton = integrator == MRA_THETA_NEWTON ? newton_iters : 0;
+  return MRA_OK;
+}
+
+int32_t mra_solve_set_jacobian(mra_solve h, int32_t jacobian) {
+  if (!h) return MRA_E_ARG;
+  if (jacobian != MRA_JAC_FROZEN && jacobian != MRA_JAC_EXACT) return MRA_E_ARG;
+  if (h->cfg.kind != 0) return MRA_E_UNSUPPORTED;
+  drop_graphs_of(h);
+  h->cfg.jac = jacobian;
   return MRA_OK;
 }
 

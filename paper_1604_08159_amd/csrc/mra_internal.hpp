@@ -331,6 +331,7 @@ struct LaunchCfg {
   int kind = 0;   // 0 vorticity, 1 passive scalar coupled to a vorticity solve
   int integ = 0;  // 0 exponential Rosenbrock-Euler, 1 theta-scheme by Newton-GMRES
   int newton = 0; // Newton iterations per step (integ 1)
+  int jac = 0;    // Jacobian of the Krylov products: 0 eddy viscosity frozen, 1 exact
 };
 
 hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);

@@ -80,3 +80,4 @@ def test_size_queries_and_argument_checks(lib):
     assert lib.mra_scalar_init(None, C.byref(_grid(6, 2)), 10, 0.01, 0.0, 1, None, None, 0, None,
                                C.byref(C.c_void_p())) == 1
     assert lib.mra_solve_set_integrator(None, 1, 0.5, 2, None) == 1
+    assert lib.mra_solve_set_jacobian(None, 1) == 1
