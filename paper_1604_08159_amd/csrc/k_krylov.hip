@@ -70,7 +70,8 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int j) {
   }
 }
 
-// Stage 2: h1 from A; w -= V_j h1; h2 = V_j^T w partials (buffer B).
+// Stage 2: h1 from A; w -= V_j h1; h2 = V_j^T w and ||w||^2 partials
+// (buffer B).
 template <int MJ>
 __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
   const SolveDev& s = MRA_SOLVE(b);
@@ -87,9 +88,9 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
   const size_t Nf = (size_t)s.N * s.N;
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
-    double acc[MJ];
+    double acc[MJ + 1];
 #pragma unroll
-    for (int i = 0; i < MJ; ++i) acc[i] = 0.0;
+    for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
       double t = s.w[k];
       double v[MJ];
@@ -103,29 +104,57 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) acc[i] += v[i] * t;
+      acc[MJ] += t * t;
     }
-    block_sums_store<MJ>(acc, j + 1, part_buf(s, 1) + (size_t)ch * (kMaxM + 2));
+    // slot layout: h2[0 .. j], then ||w||^2 at j + 1 (static register indices)
+#pragma unroll
+    for (int i = 0; i < MJ; ++i)
+      if (i == j + 1) acc[i] = acc[MJ];
+    block_sums_store<MJ + 1>(acc, j + 2, part_buf(s, 1) + (size_t)ch * (kMaxM + 2));
     __syncthreads();
   }
 }
 
-// Stage 3: h2 from B; w -= V_j h2; H[:j+1, j] = h1 + h2; ||w||^2 partials
-// (buffer A), consumed by the next scaling (next_scale) or by phi_1.
+// Stage 3: h2 and ||w||^2 from B; H[:j+1, j] = h1 + h2; the next basis vector
+// V_{j+1} = (w - V_j h2) / h_{j+1,j}.  The norm of w - V_j h2 is taken from
+// Pythagoras, ||w||^2 - ||h2||^2 (V_j orthonormal, h2 = V_j^T w), before the
+// update, so the stage writes V_{j+1} normalised in the same pass.  In CGS2
+// h2 is a rounding-level correction, so no cancellation arises; a breakdown
+// (h_{j+1,j} <= 1e-13 ||A v_j||) or a non-finite value ends the basis.
 template <int MJ>
-__global__ void __launch_bounds__(256) k_gs_axpy_norm(Batch b, int j) {
+__global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int j) {
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
   if ((int)MRA_BX(b) >= nb) return;
   __shared__ double h[kMaxM + 2];
-  reduce_partials(part_buf(s, 1), nb, j + 1, h);
+  __shared__ double inv_sh;
+  reduce_partials(part_buf(s, 1), nb, j + 2, h);
+  if (threadIdx.x == 0) {
+    double h2sq = 0.0;
+    for (int i = 0; i <= j; ++i) h2sq += h[i] * h[i];
+    const double nrm = sqrt(fmax(h[j + 1] - h2sq, 0.0));
+    const double nav = s.scal[S_NRMAV];
+    const bool bad = !isfinite(nrm) || !isfinite(nav);
+    const bool brk = bad || nrm <= kBreakdown * nav;
+    inv_sh = brk ? 0.0 : 1.0 / nrm;
+    if (MRA_BX(b) == 0) {
+      s.H[(j + 1) * s.m + j] = nrm;
+      if (bad) { s.ctrl[C_STATUS] = 5; s.ctrl[C_MEFF] = 0; }
+      else if (brk) s.ctrl[C_MEFF] = j + 1;
+      if (brk) s.ctrl[C_DONE] = 1;
+    }
+  }
+  __syncthreads();
   if (MRA_BX(b) == 0)
     for (int i = threadIdx.x; i <= j; i += blockDim.x) s.H[i * s.m + j] = s.hpart[i] + h[i];
+  if (j + 1 >= s.m) return;          // the last column: no further basis vector
+  const double inv = inv_sh;
   const size_t Nf = (size_t)s.N * s.N;
+  double* Vn = s.V + (size_t)(j + 1) * Nf;
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
-    double acc[1] = {0.0};
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
       double t = s.w[k];
       double v[MJ];
@@ -135,11 +164,8 @@ __global__ void __launch_bounds__(256) k_gs_axpy_norm(Batch b, int j) {
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) t -= h[i] * v[i];
-      s.w[k] = t;
-      acc[0] += t * t;
+      Vn[k] = inv == 0.0 ? 0.0 : t * inv;
     }
-    block_sums_store<1>(acc, 1, part_buf(s, 0) + (size_t)ch * (kMaxM + 2));
-    __syncthreads();
   }
 }
 
@@ -161,7 +187,7 @@ template <int MJ>
 static void arnoldi_mj(const Batch& b, dim3 g, int j, hipStream_t st) {
   hipLaunchKernelGGL(k_gs_dot<MJ>, g, dim3(256), 0, st, b, j);
   hipLaunchKernelGGL(k_gs_axpy_dot<MJ>, g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL(k_gs_axpy_norm<MJ>, g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL(k_gs_axpy_next<MJ>, g, dim3(256), 0, st, b, j);
 }
 
 // basis-vector register slots: the smallest bucket holding m vectors
@@ -194,17 +220,7 @@ __device__ void mat_mul(const double* A, const double* B, double* C, int K) {
 
 __global__ void __launch_bounds__(256) k_phi1(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
-  // the last column's norm (partials of stage 3): only its finiteness matters
-  if (!s.ctrl[C_DONE]) {
-    __shared__ double tot[2];
-    reduce_partials(part_buf(s, 0), nchunks((int)*s.n_active), 1, tot);
-    if (threadIdx.x == 0 && !isfinite(tot[0])) {
-      s.ctrl[C_STATUS] = 5;
-      s.ctrl[C_MEFF] = 0;
-    }
-    __syncthreads();
-  }
-  const int k = s.ctrl[C_MEFF];
+  const int k = s.ctrl[C_MEFF];      // 0 after a non-finite value or for F = 0
   if (k <= 0) return;
   const int K = k + 1, m = s.m;
   __shared__ double A[(kMaxM + 1) * (kMaxM + 1)];
@@ -362,24 +378,7 @@ hipError_t launch_newton_rhs(const Batch& b, const LaunchCfg& c, int first, hipS
 // O(k^2) work (k <= 47).
 __global__ void __launch_bounds__(256) k_gmres(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
-  // A complete basis (no breakdown, k = m) leaves h_{m+1,m} = ||w|| in the
-  // partials of stage 3; after a breakdown at column k the scaling kernel has
-  // stored h_{k+1,k} in H.
-  const bool done = s.ctrl[C_DONE] != 0;
-  __shared__ double hlast;
-  if (!done) {
-    __shared__ double tot[2];
-    reduce_partials(part_buf(s, 0), nchunks((int)*s.n_active), 1, tot);
-    if (threadIdx.x == 0) {
-      hlast = sqrt(tot[0]);
-      if (!isfinite(tot[0])) {
-        s.ctrl[C_STATUS] = 5;
-        s.ctrl[C_MEFF] = 0;
-      }
-    }
-    __syncthreads();
-  }
-  const int k = s.ctrl[C_MEFF];
+  const int k = s.ctrl[C_MEFF];      // 0 after a non-finite value or for -G = 0
   if (k <= 0) return;
   const int m = s.m;
   const double a = s.scal[S_THETA] * s.dt;
@@ -389,7 +388,7 @@ __global__ void __launch_bounds__(256) k_gmres(Batch b) {
     const int i = q / k, j = q - i * k;
     double v = 0.0;
     if (i == k) {
-      if (j == k - 1) v = -a * (done ? s.H[i * m + j] : hlast);
+      if (j == k - 1) v = -a * s.H[i * m + j];      // h_{k+1,k}, stored by the last stage
     } else if (i <= j + 1) {
       v = (i == j ? 1.0 : 0.0) - a * s.H[i * m + j];
     }

@@ -31,11 +31,13 @@ __device__ inline T* dense_target(const SolveDev& s, int target) {
 
 // ------------------------------------------------------- active values
 // The value of active node k in the prolongation of: src 0 the state omega,
-// src 1 the next Arnoldi vector w * inv (inv = 0: the basis is complete),
-// src 2 a caller vector.
-__device__ inline double active_value(const SolveDev& s, int src, int k, double inv) {
+// src 1 the first Arnoldi vector F * inv (inv = 0: no basis), src 2 a caller
+// vector, src 3 the Arnoldi vector V_j, written normalised by the last
+// Gram-Schmidt stage.
+__device__ inline double active_value(const SolveDev& s, int src, int k, double inv, const double* Vj) {
   if (src == 0) return s.omega[k];
   if (src == 2) return s.vin[k];
+  if (src == 3) return Vj[k];
   return inv == 0.0 ? 0.0 : s.w[k] * inv;
 }
 
@@ -73,7 +75,7 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
   const int n0sq = 1 << (2 * j0);
   double inv = 0.0;
   if (mode == 0 && src == 1) {
-    inv = next_scale(s, j, 0);
+    inv = first_scale(s, 0);
     if (threadIdx.x == 0) s.scal[S_INV] = inv;
   }
   double* Vj = s.V + (size_t)j * s.N * s.N;
@@ -85,7 +87,7 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
     if (a) {
       if (mode == 0) {
         const int k = s.rank[fi];
-        const double v = active_value(s, src, k, inv);
+        const double v = active_value(s, src, k, inv, Vj);
         if (src == 1 && inv != 0.0) Vj[k] = v;
         val[sub] = (T)v;
       } else {
@@ -159,10 +161,11 @@ __device__ inline T predict_lattice(const T* prev, int pn, int dx, int dy, int s
 // than the next (the reach of the next level's prediction), and writes the
 // tile.  The level-j0 lattice is all active.  Halo nodes are recomputed by
 // every tile that needs them, with identical arithmetic, so all tiles agree.
-// Active nodes take their value through the rank map; for src 1 every block
-// derives the scale of the new Arnoldi vector from the previous kernel's
-// partial sums (block 0 records it) and the tile that owns a node writes its
-// entry of V_j.  The kernel is specialised per grid level J: every lattice
+// Active nodes take their value through the rank map; for src 1 (the first
+// Arnoldi vector) every block derives beta from the partial sums of k_norm0
+// (block 0 records it) and the tile that owns a node writes its entry of V_0;
+// later Arnoldi vectors (src 3) are read from V_j as the Gram-Schmidt stage
+// wrote them.  The kernel is specialised per grid level J: every lattice
 // size, halo and shift is a compile-time constant.
 constexpr int kFineTile = 32;
 constexpr int kLatMax = kFineTile * kFineTile;   // lattice nodes of one level of a tile
@@ -188,88 +191,96 @@ __device__ inline int lat_origin(int x0) {
   return ((x0 - E) >> SH) << SH;         // floor to the lattice (arithmetic shift)
 }
 
-template <int P, typename T, int PN, int SH>
-__device__ inline T predict_lattice_ct(const T* prev, int dx, int dy, bool oxd, bool oyd) {
-  constexpr int SV = 1 << SH;
-  T c[2 * P];
-  if (oxd && !oyd) {
-    const int r = dy >> (SH + 1), a = ((dx - SV) >> (SH + 1)) - (P - 1);
-#pragma unroll
-    for (int o = 0; o < 2 * P; ++o) c[o] = prev[r * PN + a + o];
-    return dd_pred<P, T>(c);
-  } else if (oyd && !oxd) {
-    const int a = dx >> (SH + 1), bb = ((dy - SV) >> (SH + 1)) - (P - 1);
-#pragma unroll
-    for (int o = 0; o < 2 * P; ++o) c[o] = prev[(bb + o) * PN + a];
-    return dd_pred<P, T>(c);
-  } else {
-    const int a = ((dx - SV) >> (SH + 1)) - (P - 1), bb = ((dy - SV) >> (SH + 1)) - (P - 1);
-    T py[2 * P];
-#pragma unroll
-    for (int o2 = 0; o2 < 2 * P; ++o2) {
-#pragma unroll
-      for (int o = 0; o < 2 * P; ++o) c[o] = prev[(bb + o) * PN + a + o2];
-      py[o2] = dd_pred<P, T>(c);
-    }
-    return dd_pred<P, T>(py);
-  }
-}
-
 // Level L of the sweep (lattice of level L - 1 in buf[cur]), then the next.
+// The tensor-product prediction is separable: pass 1 fills `half`, the level-L
+// rows of the level-(L - 1) columns (a sample on even rows, the y-prediction
+// on odd rows); pass 2 takes every node of level L from its row of `half` (a
+// copy on even columns, the x-prediction on odd columns).  Odd-odd nodes thus
+// get the x-prediction of the y-predictions, the canonical order, and every
+// y-prediction is computed once per column instead of once per neighbour.
+// Active nodes then take their value.
 template <int P, typename T, int J, int L>
-__device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLatMax], int cur, int x0, int y0,
-                                                 int src, double inv, double* Vj, T* f) {
+__device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLatMax], T* half, int cur, int x0,
+                                                 int y0, int src, double inv, double* Vj, T* f) {
 #pragma clang fp contract(off)
   constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile;
   constexpr int SH = J - L, SV = 1 << SH;  // node spacing of level L (fine units)
   constexpr int n = lat_count(J, P, B, 0, L), pn = lat_count(J, P, B, 0, L - 1);
   constexpr int NN = n * n, SLOTS = (NN + 255) / 256;
+  constexpr int NH = n * pn;
   static_assert(NN <= kLatMax && SLOTS <= 4, "lattice of one level exceeds the tile buffer");
+  static_assert(NH <= kLatMax, "half-predicted lattice exceeds its buffer");
   const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
   const int pox = lat_origin<J, P, L - 1>(x0), poy = lat_origin<J, P, L - 1>(y0);
   const int* __restrict__ rank = s.rank;
   const T* prev = buf[cur];
   T* nxt = buf[cur ^ 1];
   // a thread's nodes of this level: ranks first, then the values of the
-  // active ones, then the predictions
-  int xs[SLOTS], ys[SLOTS], ks[SLOTS];
+  // active ones (their latency hides behind pass 1)
+  int ks[SLOTS];
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i) {
     const int q = threadIdx.x + 256 * i;
     ks[i] = -1;
     if (q < NN) {
       const int iy = q / n, ix = q - iy * n;
-      xs[i] = ox + (ix << SH);
-      ys[i] = oy + (iy << SH);
-      if ((xs[i] | ys[i]) & SV) ks[i] = rank[(ys[i] & NM) * N + (xs[i] & NM)];
+      const int x = ox + (ix << SH), y = oy + (iy << SH);
+      if ((x | y) & SV) ks[i] = rank[(y & NM) * N + (x & NM)];
     }
   }
   double av[SLOTS];
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i) {
     av[i] = 0.0;
-    if (ks[i] >= 0) {
-      av[i] = active_value(s, src, ks[i], inv);
-      if (src == 1 && inv != 0.0 && xs[i] >= x0 && xs[i] < x0 + B && ys[i] >= y0 && ys[i] < y0 + B)
-        Vj[ks[i]] = av[i];
-    }
+    if (ks[i] >= 0) av[i] = active_value(s, src, ks[i], inv, Vj);
   }
+  // pass 1: level-L rows of the level-(L - 1) columns
+  for (int q = threadIdx.x; q < NH; q += 256) {
+    const int iy = q / pn, c = q - iy * pn;
+    const int dy = oy + (iy << SH) - poy;
+    T v;
+    if ((dy & SV) == 0) {
+      v = prev[(dy >> (SH + 1)) * pn + c];
+    } else {
+      const int bb = ((dy - SV) >> (SH + 1)) - (P - 1);
+      T cc[2 * P];
+#pragma unroll
+      for (int o = 0; o < 2 * P; ++o) cc[o] = prev[(bb + o) * pn + c];
+      v = dd_pred<P, T>(cc);
+    }
+    half[q] = v;
+  }
+  __syncthreads();
+  // pass 2: every node of level L from its row of `half`
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i) {
     const int q = threadIdx.x + 256 * i;
     if (q < NN) {
-      const int x = xs[i], y = ys[i];
+      const int iy = q / n, ix = q - iy * n;
+      const int x = ox + (ix << SH), y = oy + (iy << SH);
+      const T* row = half + iy * pn;
+      const int dx = x - pox;
       T v;
-      if (((x | y) & SV) == 0) v = prev[((y - poy) >> (SH + 1)) * pn + ((x - pox) >> (SH + 1))];
-      else if (ks[i] >= 0) v = (T)av[i];
-      else v = predict_lattice_ct<P, T, pn, SH>(prev, x - pox, y - poy, (x & SV) != 0, (y & SV) != 0);
+      if ((dx & SV) == 0) {
+        v = row[dx >> (SH + 1)];
+      } else {
+        const int a = ((dx - SV) >> (SH + 1)) - (P - 1);
+        T cc[2 * P];
+#pragma unroll
+        for (int o = 0; o < 2 * P; ++o) cc[o] = row[a + o];
+        v = dd_pred<P, T>(cc);
+      }
+      if (ks[i] >= 0) {
+        v = (T)av[i];
+        if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) Vj[ks[i]] = av[i];
+      }
       if constexpr (L == J) f[(y0 + q / B) * N + x0 + (q % B)] = v;   // finest lattice = the tile
       else nxt[q] = v;
     }
   }
   if constexpr (L < J) {
     __syncthreads();
-    prolong_level_ct<P, T, J, L + 1>(s, buf, cur ^ 1, x0, y0, src, inv, Vj, f);
+    prolong_level_ct<P, T, J, L + 1>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vj, f);
   }
 }
 
@@ -282,6 +293,7 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
   static_assert(pn * pn <= 256, "coarsest lattice exceeds one node per thread");
   static_assert(lat_count(J, P, B, 0, J) == B, "finest lattice is the tile");
   __shared__ T buf[2][kLatMax];
+  __shared__ T half[kLatMax];
   const SolveDev& s = MRA_SOLVE(b);
   const int t = MRA_BX(b);
   const int x0 = (t % NTX) * B, y0 = (t / NTX) * B;
@@ -299,9 +311,9 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     x0n = pox + (ix << SH0);
     y0n = poy + (iy << SH0);
     k0n = s.rank[(y0n & NM) * N + (x0n & NM)];
-    raw = src == 0 ? s.omega[k0n] : (src == 2 ? s.vin[k0n] : s.w[k0n]);
+    raw = src == 0 ? s.omega[k0n] : (src == 2 ? s.vin[k0n] : (src == 3 ? Vj[k0n] : s.w[k0n]));
   }
-  const double inv = src == 1 ? next_scale(s, j, t) : 0.0;
+  const double inv = src == 1 ? first_scale(s, t) : 0.0;
   if (has0) {
     double a = raw;
     if (src == 1) {
@@ -311,7 +323,7 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     buf[0][threadIdx.x] = (T)a;
   }
   __syncthreads();
-  prolong_level_ct<P, T, J, J0 + 1>(s, buf, 0, x0, y0, src, inv, Vj, f);
+  prolong_level_ct<P, T, J, J0 + 1>(s, buf, half, 0, x0, y0, src, inv, Vj, f);
 }
 
 template <int P, typename T>

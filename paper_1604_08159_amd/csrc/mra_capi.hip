@@ -204,7 +204,7 @@ hipError_t enqueue_scalar_step(const Batch& b, const LaunchCfg& c, hipStream_t s
   if ((e = launch_scalar(b, c, 0, st)) != hipSuccess) return e;
   if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
   for (int j = 0; j < c.m; ++j) {
-    if ((e = launch_prolong(b, c, 1, dbl, 1, j, st)) != hipSuccess) return e;
+    if ((e = launch_prolong(b, c, 1, dbl, j == 0 ? 1 : 3, j, st)) != hipSuccess) return e;
     if ((e = launch_scalar(b, c, 1, st)) != hipSuccess) return e;
     if ((e = launch_arnoldi(b, c, j, st)) != hipSuccess) return e;
   }
@@ -231,7 +231,7 @@ hipError_t enqueue_theta_step(const Batch& b, const LaunchCfg& c, hipStream_t st
     if ((e = launch_newton_rhs(b, c, it == 0, st)) != hipSuccess) return e;
     if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
     for (int j = 0; j < c.m; ++j) {
-      if ((e = launch_prolong(b, c, 1, dbl, 1, j, st)) != hipSuccess) return e;
+      if ((e = launch_prolong(b, c, 1, dbl, j == 0 ? 1 : 3, j, st)) != hipSuccess) return e;
       if ((e = launch_poisson(b, c, 1, st)) != hipSuccess) return e;
       if ((e = launch_jvp(b, c, st)) != hipSuccess) return e;
       if ((e = launch_arnoldi(b, c, j, st)) != hipSuccess) return e;
@@ -259,7 +259,7 @@ hipError_t enqueue_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
   // Arnoldi
   for (int j = 0; j < c.m; ++j) {
-    if ((e = launch_prolong(b, c, 1, dbl, 1, j, st)) != hipSuccess) return e;
+    if ((e = launch_prolong(b, c, 1, dbl, j == 0 ? 1 : 3, j, st)) != hipSuccess) return e;
     if ((e = launch_poisson(b, c, 1, st)) != hipSuccess) return e;
     if ((e = launch_jvp(b, c, st)) != hipSuccess) return e;
     if ((e = launch_arnoldi(b, c, j, st)) != hipSuccess) return e;

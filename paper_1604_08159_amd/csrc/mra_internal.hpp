@@ -281,44 +281,28 @@ __device__ inline void block_sums_store(double (&acc)[NA], int cnt, double* out)
   }
 }
 
-// The scaling of the next basis vector, from the partials of the previous
-// kernel.  j = 0: beta = ||F|| (buffer B); j > 0: h_{j,j-1} = ||w|| (buffer A)
-// with the happy-breakdown test.  Every block computes the same values;
-// block 0 records them.  Returns 1 / norm, or 0 when the basis is complete.
-__device__ inline double next_scale(const SolveDev& s, int j, int bx) {
+// The scaling of the first basis vector: beta = ||F|| from the partials of
+// k_norm0 (buffer B).  Every block computes the same value; block 0 records
+// beta and starts the basis (C_MEFF = m, or 0 and C_DONE when F = 0 or is not
+// finite).  Returns 1 / beta, or 0.  Later basis vectors are scaled by the
+// last Gram-Schmidt stage, which writes them normalised.
+__device__ inline double first_scale(const SolveDev& s, int bx) {
   __shared__ double tot[2];
   __shared__ double inv_sh;
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
-  if (j > 0 && s.ctrl[C_DONE]) return 0.0;
-  reduce_partials(part_buf(s, j == 0 ? 1 : 0), nb, 1, tot);
+  reduce_partials(part_buf(s, 1), nb, 1, tot);
   if (threadIdx.x == 0) {
     const double nrm = sqrt(tot[0]);
-    const bool rec = bx == 0;
-    double inv = 0.0;
-    if (j == 0) {
-      const bool ok = isfinite(nrm);
-      const bool zero = !(nrm > 0.0) || !ok;
-      inv = zero ? 0.0 : 1.0 / nrm;
-      if (rec) {
-        s.scal[S_BETA] = nrm;
-        if (!ok) s.ctrl[C_STATUS] = 5;
-        s.ctrl[C_DONE] = zero ? 1 : 0;
-        s.ctrl[C_MEFF] = zero ? 0 : s.m;
-      }
-    } else {
-      const double nav = s.scal[S_NRMAV];
-      const bool bad = !isfinite(nrm) || !isfinite(nav);
-      const bool brk = bad || nrm <= kBreakdown * nav;
-      inv = brk ? 0.0 : 1.0 / nrm;
-      if (rec) {
-        s.H[j * s.m + (j - 1)] = nrm;
-        if (bad) { s.ctrl[C_STATUS] = 5; s.ctrl[C_MEFF] = 0; }
-        else if (brk) s.ctrl[C_MEFF] = j;
-        if (brk) s.ctrl[C_DONE] = 1;
-      }
+    const bool ok = isfinite(nrm);
+    const bool zero = !(nrm > 0.0) || !ok;
+    if (bx == 0) {
+      s.scal[S_BETA] = nrm;
+      if (!ok) s.ctrl[C_STATUS] = 5;
+      s.ctrl[C_DONE] = zero ? 1 : 0;
+      s.ctrl[C_MEFF] = zero ? 0 : s.m;
     }
-    inv_sh = inv;
+    inv_sh = zero ? 0.0 : 1.0 / nrm;
   }
   __syncthreads();
   return inv_sh;
