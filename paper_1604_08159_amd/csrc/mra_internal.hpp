@@ -201,7 +201,7 @@ __host__ __device__ inline int tile_edge(int J, int p, int prec) {
 
 // ------------------------------------------------- Krylov reductions
 constexpr double kBreakdown = 1e-13;
-constexpr int kChunkMin = 256;
+constexpr int kChunkMin = 512;
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
