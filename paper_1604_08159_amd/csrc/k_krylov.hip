@@ -13,6 +13,8 @@
 // basis vector reduces a chunk in a fixed order into a per-chunk partial, and
 // every block of the NEXT kernel adds the partials in the same fixed order
 // (the kernel boundary orders the writes before the reads).
+#include <utility>
+
 #include "mra_internal.hpp"
 
 namespace mra {
@@ -38,8 +40,9 @@ __global__ void __launch_bounds__(256) k_norm0(Batch b) {
 }
 
 // Stage 1: h1 = V_j^T w and ||w||^2 (= ||A v_j||^2) partials (buffer A).
-template <int MJ>
-__global__ void __launch_bounds__(256) k_gs_dot(Batch b, int j) {
+template <int MJ, int JC>
+__global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
+  const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
   const int na = (int)*s.n_active;
@@ -72,8 +75,9 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int j) {
 
 // Stage 2: h1 from A; w -= V_j h1; h2 = V_j^T w and ||w||^2 partials
 // (buffer B).
-template <int MJ>
-__global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
+template <int MJ, int JC>
+__global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
+  const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
   const int na = (int)*s.n_active;
@@ -121,8 +125,9 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int j) {
 // update, so the stage writes V_{j+1} normalised in the same pass.  In CGS2
 // h2 is a rounding-level correction, so no cancellation arises; a breakdown
 // (h_{j+1,j} <= 1e-13 ||A v_j||) or a non-finite value ends the basis.
-template <int MJ>
-__global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int j) {
+template <int MJ, int JC>
+__global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
+  const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
   const int na = (int)*s.n_active;
@@ -183,22 +188,28 @@ hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int MJ>
+template <int MJ, int JC>
 static void arnoldi_mj(const Batch& b, dim3 g, int j, hipStream_t st) {
-  hipLaunchKernelGGL(k_gs_dot<MJ>, g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL(k_gs_axpy_dot<MJ>, g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL(k_gs_axpy_next<MJ>, g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL((k_gs_dot<MJ, JC>), g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL((k_gs_axpy_dot<MJ, JC>), g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL((k_gs_axpy_next<MJ, JC>), g, dim3(256), 0, st, b, j);
 }
 
-// basis-vector register slots: the smallest bucket holding m vectors
+// Columns j < kFixedCols run kernels instantiated for that column (exactly
+// j + 1 basis vectors, no per-vector predicates); later columns use the
+// smallest register bucket holding m vectors with a run-time column.
+constexpr int kFixedCols = 24;
+template <int... Js>
+static void arnoldi_fixed(const Batch& b, dim3 g, int j, hipStream_t st, std::integer_sequence<int, Js...>) {
+  (void)((j == Js ? (arnoldi_mj<Js + 1, Js>(b, g, j, st), true) : false) || ...);
+}
+
 hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st) {
   dim3 g((red_grid(c.J)) * b.n);
   if (j >= c.m || c.m > kMaxM) return hipErrorInvalidValue;
-  if (c.m <= 8) arnoldi_mj<8>(b, g, j, st);
-  else if (c.m <= 16) arnoldi_mj<16>(b, g, j, st);
-  else if (c.m <= 24) arnoldi_mj<24>(b, g, j, st);
-  else if (c.m <= 32) arnoldi_mj<32>(b, g, j, st);
-  else arnoldi_mj<48>(b, g, j, st);
+  if (j < kFixedCols) arnoldi_fixed(b, g, j, st, std::make_integer_sequence<int, kFixedCols>{});
+  else if (c.m <= 32) arnoldi_mj<32, -1>(b, g, j, st);
+  else arnoldi_mj<48, -1>(b, g, j, st);
   return hipGetLastError();
 }
 
