@@ -79,6 +79,22 @@ template <> struct C2<float> {
 __device__ inline int lx(int i) { return i + (i >> 5); }
 __host__ __device__ inline int lds_slots(int n) { return n + (n >> 5); }
 
+// Global loads and stores of complex values through plain 2-vectors (the
+// HIP vector types do not bind to address-space-qualified references).
+template <typename V> struct Raw2;
+template <> struct Raw2<float2> { typedef float t __attribute__((ext_vector_type(2))); };
+template <> struct Raw2<double2> { typedef double t __attribute__((ext_vector_type(2))); };
+template <typename V> __device__ inline V gload(const V* p, size_t i) {
+  const auto r = glb(reinterpret_cast<const typename Raw2<V>::t*>(p))[i];
+  return V{r.x, r.y};
+}
+template <typename V> __device__ inline void gstore(V* p, size_t i, V v) {
+  typename Raw2<V>::t r;
+  r.x = v.x;
+  r.y = v.y;
+  glb(reinterpret_cast<typename Raw2<V>::t*>(p))[i] = r;
+}
+
 template <typename V> __device__ inline V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ inline V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
 template <typename V> __device__ inline V cmul(V a, V b) { return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
@@ -264,7 +280,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src) 
   const V* in = reinterpret_cast<const V*>(poisson_src<T>(s, src));
   constexpr int n = R * M;
   const int e1 = min(own0() + kWaveSpan, n);
-  for (int q = own0() + lane(); q < e1; q += 64) buf[lx(q)] = in[(size_t)y0 * M + q];
+  for (int q = own0() + lane(); q < e1; q += 64) buf[lx(q)] = gload(in, (size_t)y0 * M + q);
   fft_sync(G::LGM <= 9);
   fft_block<-1, T, G::LGM, R>(buf, R);
   __syncthreads();
@@ -278,7 +294,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src) 
     V x;
     x.x = T(0.5) * (zk.x + zc.x + e.y);
     x.y = T(0.5) * (zk.y + zc.y - e.x);
-    spec[(size_t)k * N + y0 + r] = x;
+    gstore(spec, (size_t)k * N + y0 + r, x);
   }
 }
 
@@ -345,8 +361,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) 
     const V* spec = reinterpret_cast<const V*>(comp == 0 ? s.spec : s.spec2);
     for (int q = threadIdx.x; q < M * R; q += kFftThreads) {
       const int k = q / R, r = q % R;
-      const V xk = spec[(size_t)k * N + y0 + r];
-      const V xc = cconj(spec[(size_t)(M - k) * N + y0 + r]);
+      const V xk = gload(spec, (size_t)k * N + y0 + r);
+      const V xc = cconj(gload(spec, (size_t)(M - k) * N + y0 + r));
       const V e = cmulc(csub(xk, xc), C2<T>::tw(k * twN));
       V z;
       z.x = xk.x + xc.x - e.y;
@@ -357,7 +373,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) 
     fft_block<1, T, G::LGM, R>(buf, R);
     V* out = reinterpret_cast<V*>(poisson_dst<T>(s, src, comp));
     const int e1 = min(own0() + kWaveSpan, R * M);
-    for (int q = own0() + lane(); q < e1; q += 64) out[(size_t)y0 * M + q] = buf[lx(q)];
+    for (int q = own0() + lane(); q < e1; q += 64) gstore(out, (size_t)y0 * M + q, buf[lx(q)]);
     __syncthreads();
   }
 }

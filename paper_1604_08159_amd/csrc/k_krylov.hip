@@ -33,7 +33,8 @@ __global__ void __launch_bounds__(256) k_norm0(Batch b) {
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     double acc[1] = {0.0};
-    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) acc[0] += s.w[k] * s.w[k];
+    const auto* W = glb(s.w);
+    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) acc[0] += W[k] * W[k];
     block_sums_store<1>(acc, 1, part_buf(s, 1) + (size_t)ch * (kMaxM + 2));
     __syncthreads();
   }
@@ -48,17 +49,19 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
   const size_t Nf = (size_t)s.N * s.N;
+  auto* W = glb(s.w);
+  const auto* V = glb(s.V);
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     double acc[MJ + 1];
 #pragma unroll
     for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
-      const double wk = s.w[k];
+      const double wk = W[k];
       double v[MJ];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) v[i] = s.V[i * Nf + k];
+        if (i <= j) v[i] = V[i * Nf + k];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) acc[i] += v[i] * wk;
@@ -90,21 +93,23 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
     if (threadIdx.x == 0) s.scal[S_NRMAV] = sqrt(h[j + 1]);
   }
   const size_t Nf = (size_t)s.N * s.N;
+  auto* W = glb(s.w);
+  const auto* V = glb(s.V);
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     double acc[MJ + 1];
 #pragma unroll
     for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
-      double t = s.w[k];
+      double t = W[k];
       double v[MJ];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) v[i] = s.V[i * Nf + k];
+        if (i <= j) v[i] = V[i * Nf + k];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) t -= h[i] * v[i];
-      s.w[k] = t;
+      W[k] = t;
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) acc[i] += v[i] * t;
@@ -157,15 +162,17 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
   if (j + 1 >= s.m) return;          // the last column: no further basis vector
   const double inv = inv_sh;
   const size_t Nf = (size_t)s.N * s.N;
-  double* Vn = s.V + (size_t)(j + 1) * Nf;
+  const auto* W = glb(s.w);
+  const auto* V = glb(s.V);
+  auto* Vn = glb(s.V + (size_t)(j + 1) * Nf);
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
-      double t = s.w[k];
+      double t = W[k];
       double v[MJ];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) v[i] = s.V[i * Nf + k];
+        if (i <= j) v[i] = V[i * Nf + k];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) t -= h[i] * v[i];
@@ -315,12 +322,14 @@ __global__ void __launch_bounds__(256) k_update(Batch b, int mode) {
   for (int i = threadIdx.x; i < k; i += blockDim.x) yy[i] = f * s.y[i];
   __syncthreads();
   bool bad = false;
+  const auto* V = glb(s.V);
+  auto* om = glb(s.omega);
   for (int q = MRA_BX(b) * blockDim.x + threadIdx.x; q < na; q += MRA_GX(b) * blockDim.x) {
     double t = 0.0;
-    for (int i = 0; i < k; ++i) t += yy[i] * s.V[i * Nf + q];
-    const double nv = s.omega[q] + t;
+    for (int i = 0; i < k; ++i) t += yy[i] * V[i * Nf + q];
+    const double nv = om[q] + t;
     bad |= !isfinite(nv);
-    s.omega[q] = nv;
+    om[q] = nv;
   }
   if (bad) s.ctrl[C_STATUS] = 5;
 }
@@ -358,10 +367,12 @@ __global__ void __launch_bounds__(256) k_newton_rhs(Batch b, int first) {
   const SolveDev& s = MRA_SOLVE(b);
   const int na = (int)*s.n_active;
   const double th = s.scal[S_THETA], dt = s.dt;
-  double* wn = s.packed64;
-  double* fn = s.dense64;
+  auto* wn = glb(s.packed64);
+  auto* fn = glb(s.dense64);
+  auto* W = glb(s.w);
+  const auto* Om = glb(s.omega);
   for (int q = MRA_BX(b) * blockDim.x + threadIdx.x; q < na; q += MRA_GX(b) * blockDim.x) {
-    const double f = s.w[q], om = s.omega[q];
+    const double f = W[q], om = Om[q];
     double on, f0;
     if (first) {
       wn[q] = om;
@@ -372,7 +383,7 @@ __global__ void __launch_bounds__(256) k_newton_rhs(Batch b, int first) {
       on = wn[q];
       f0 = fn[q];
     }
-    s.w[q] = (on - om) + dt * (th * f + (1.0 - th) * f0);
+    W[q] = (on - om) + dt * (th * f + (1.0 - th) * f0);
   }
 }
 

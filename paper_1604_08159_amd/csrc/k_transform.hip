@@ -35,10 +35,10 @@ __device__ inline T* dense_target(const SolveDev& s, int target) {
 // vector, src 3 the Arnoldi vector V_j, written normalised by the last
 // Gram-Schmidt stage.
 __device__ inline double active_value(const SolveDev& s, int src, int k, double inv, const double* Vj) {
-  if (src == 0) return s.omega[k];
-  if (src == 2) return s.vin[k];
-  if (src == 3) return Vj[k];
-  return inv == 0.0 ? 0.0 : s.w[k] * inv;
+  if (src == 0) return glb(s.omega)[k];
+  if (src == 2) return glb(s.vin)[k];
+  if (src == 3) return glb(Vj)[k];
+  return inv == 0.0 ? 0.0 : glb(s.w)[k] * inv;
 }
 
 // ---------------------------------------------------------------- prolong
@@ -212,7 +212,7 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
   static_assert(NH <= kLatMax, "half-predicted lattice exceeds its buffer");
   const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
   const int pox = lat_origin<J, P, L - 1>(x0), poy = lat_origin<J, P, L - 1>(y0);
-  const int* __restrict__ rank = s.rank;
+  const auto* __restrict__ rank = glb(s.rank);
   const T* prev = buf[cur];
   T* nxt = buf[cur ^ 1];
   // a thread's nodes of this level: ranks first, then the values of the
@@ -272,9 +272,9 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
       }
       if (ks[i] >= 0) {
         v = (T)av[i];
-        if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) Vj[ks[i]] = av[i];
+        if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) glb(Vj)[ks[i]] = av[i];
       }
-      if constexpr (L == J) f[(y0 + q / B) * N + x0 + (q % B)] = v;   // finest lattice = the tile
+      if constexpr (L == J) glb(f)[(y0 + q / B) * N + x0 + (q % B)] = v;   // finest lattice = the tile
       else nxt[q] = v;
     }
   }
@@ -310,15 +310,15 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     const int iy = q / pn, ix = q - iy * pn;
     x0n = pox + (ix << SH0);
     y0n = poy + (iy << SH0);
-    k0n = s.rank[(y0n & NM) * N + (x0n & NM)];
-    raw = src == 0 ? s.omega[k0n] : (src == 2 ? s.vin[k0n] : (src == 3 ? Vj[k0n] : s.w[k0n]));
+    k0n = glb(s.rank)[(y0n & NM) * N + (x0n & NM)];
+    raw = src == 0 ? glb(s.omega)[k0n] : (src == 2 ? glb(s.vin)[k0n] : (src == 3 ? glb(Vj)[k0n] : glb(s.w)[k0n]));
   }
   const double inv = src == 1 ? first_scale(s, t) : 0.0;
   if (has0) {
     double a = raw;
     if (src == 1) {
       a = inv == 0.0 ? 0.0 : raw * inv;
-      if (inv != 0.0 && x0n >= x0 && x0n < x0 + B && y0n >= y0 && y0n < y0 + B) Vj[k0n] = a;
+      if (inv != 0.0 && x0n >= x0 && x0n < x0 + B && y0n >= y0 && y0n < y0 + B) glb(Vj)[k0n] = a;
     }
     buf[0][threadIdx.x] = (T)a;
   }
@@ -436,8 +436,8 @@ template <int P, typename T>
 __global__ void __launch_bounds__(256) k_forward(Batch b, int src, int dst) {
 #pragma clang fp contract(off)
   const SolveDev& s = MRA_SOLVE(b);
-  const T* f = src == 0 ? reinterpret_cast<const T*>(s.dense64) : reinterpret_cast<const T*>(s.wt);
-  T* out = dst == 0 ? reinterpret_cast<T*>(s.packed64) : reinterpret_cast<T*>(s.spec);
+  const auto* f = glb(src == 0 ? reinterpret_cast<const T*>(s.dense64) : reinterpret_cast<const T*>(s.wt));
+  auto* out = glb(dst == 0 ? reinterpret_cast<T*>(s.packed64) : reinterpret_cast<T*>(s.spec));
   const int J = s.J, j0 = s.j0, N = s.N;
   const int Nf = N * N;
   const int i = MRA_BX(b) * blockDim.x + threadIdx.x;
@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(256) k_forward(Batch b, int src, int dst) {
     const int fi = packed_to_fine(i, J, j0, &l);
     const T val = f[fi];
     am = fabs((double)val);
-    out[i] = l == j0 ? val : val - predict_node<P, T>(f, fi & (N - 1), fi >> J, l, J);
+    out[i] = l == j0 ? val : val - predict_node<P, T, decltype(f)>(f, fi & (N - 1), fi >> J, l, J);
   }
   __shared__ double red[4];
   am = warp_max(am);

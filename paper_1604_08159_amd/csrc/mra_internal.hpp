@@ -157,8 +157,8 @@ __device__ inline T dd_pred(const T* c) {
 
 // Prediction of a non-coarse node (x, y) of level l from the level-(l-1)
 // values of the dense field f (coarse stride S = 2^(J-l+1)).
-template <int P, typename T>
-__device__ inline T predict_node(const T* __restrict__ f, int x, int y, int l, int J) {
+template <int P, typename T, typename Ptr = const T*>
+__device__ inline T predict_node(Ptr __restrict__ f, int x, int y, int l, int J) {
   const int N = 1 << J;
   const int s = 1 << (J - l);
   const int S = 2 * s;
@@ -197,6 +197,15 @@ __host__ __device__ inline int tile_edge(int J, int p, int prec) {
   const int t = (prec == 0 && p == 3) ? 16 : kTile;
   const int N = 1 << J;
   return N < t ? N : t;
+}
+
+// Solve buffers are device (global) memory, but their pointers reach the
+// kernels through the solve descriptor, where the compiler cannot tell and
+// emits flat accesses, which on gfx9 also hold the LDS wait counter.  Hot
+// loops take them through glb().
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
 }
 
 // ------------------------------------------------- Krylov reductions
@@ -242,10 +251,11 @@ __device__ inline void reduce_partials(const double* buf, int nb, int cnt, doubl
   __shared__ double part[kWavesPerBlock][kMaxM + 2];
   const int stride = kMaxM + 2;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const auto* g = glb(buf);
   double t = 0.0;
   if (lane < cnt) {
 #pragma unroll 8
-    for (int q = wid; q < nb; q += kWavesPerBlock) t += buf[q * stride + lane];
+    for (int q = wid; q < nb; q += kWavesPerBlock) t += g[q * stride + lane];
     part[wid][lane] = t;
   }
   __syncthreads();
@@ -277,7 +287,7 @@ __device__ inline void block_sums_store(double (&acc)[NA], int cnt, double* out)
     double a = part[0][threadIdx.x];
 #pragma unroll
     for (int w = 1; w < kWavesPerBlock; ++w) a += part[w][threadIdx.x];
-    out[threadIdx.x] = a;
+    glb(out)[threadIdx.x] = a;
   }
 }
 
