@@ -113,49 +113,6 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
   }
 }
 
-// Lattice of level l held by a fine tile: the G^l nodes within E_l of the
-// tile [x0, x0 + B), E_J = 0, E_{l-1} = E_l + (2p-1) 2^(J-l) (the reach of
-// the level-l prediction); origin o (a multiple of 2^(J-l)) and count n.
-__device__ inline void fine_box(int J, int P, int B, int x0, int l, int* o, int* n) {
-  int E = 0;
-  for (int q = J; q > l; --q) E += (2 * P - 1) << (J - q);
-  const int sh = J - l;
-  const int lo = x0 - E, hi = x0 + B - 1 + E;
-  const int oo = (lo >> sh) << sh;       // floor to the lattice (arithmetic shift)
-  *o = oo;
-  *n = ((hi - oo) >> sh) + 1;
-}
-
-// DD prediction of a level-l node from the level-(l-1) lattice prev (pitch
-// pn) whose origin is (dx, dy) fine units away; sh = J - l.  Same operand
-// order as predict_node.
-template <int P, typename T>
-__device__ inline T predict_lattice(const T* prev, int pn, int dx, int dy, int sh, bool oxd, bool oyd) {
-  const int sv = 1 << sh;
-  T c[2 * P];
-  if (oxd && !oyd) {
-    const int r = dy >> (sh + 1), a = ((dx - sv) >> (sh + 1)) - (P - 1);
-#pragma unroll
-    for (int o = 0; o < 2 * P; ++o) c[o] = prev[r * pn + a + o];
-    return dd_pred<P, T>(c);
-  } else if (oyd && !oxd) {
-    const int a = dx >> (sh + 1), bb = ((dy - sv) >> (sh + 1)) - (P - 1);
-#pragma unroll
-    for (int o = 0; o < 2 * P; ++o) c[o] = prev[(bb + o) * pn + a];
-    return dd_pred<P, T>(c);
-  } else {
-    const int a = ((dx - sv) >> (sh + 1)) - (P - 1), bb = ((dy - sv) >> (sh + 1)) - (P - 1);
-    T py[2 * P];
-#pragma unroll
-    for (int o2 = 0; o2 < 2 * P; ++o2) {
-#pragma unroll
-      for (int o = 0; o < 2 * P; ++o) c[o] = prev[(bb + o) * pn + a + o2];
-      py[o2] = dd_pred<P, T>(c);
-    }
-    return dd_pred<P, T>(py);
-  }
-}
-
 // Pi in one launch: one block per B x B tile of the finest grid (B =
 // min(N, 32)) sweeps the lattices of levels j0 .. J in LDS, each a halo wider
 // than the next (the reach of the next level's prediction), and writes the
