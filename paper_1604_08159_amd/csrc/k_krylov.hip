@@ -1,7 +1,8 @@
-// Krylov part of the exponential Rosenbrock-Euler step, FP64:
-// Arnoldi with classical Gram-Schmidt and one reorthogonalisation (CGS2),
-// phi_1(dt H) e_1 from the exponential of the augmented Hessenberg matrix,
-// and the state update omega_M += dt beta V y.
+// Krylov part of the time steps, FP64: Arnoldi with classical Gram-Schmidt
+// and one reorthogonalisation (CGS2); for the exponential Rosenbrock-Euler
+// step phi_1(dt H) e_1 from the exponential of the augmented Hessenberg
+// matrix and the update omega_M += dt beta V y; for the theta-scheme the
+// Newton residual, the GMRES least squares and the Newton update.
 //
 // The paper advances the collocation system by projecting it onto a Krylov
 // subspace (abstract; Section 2.1); the exponential Euler step with the
@@ -9,10 +10,11 @@
 //
 // Reductions over the active nodes are deterministic and need no cross-block
 // signalling: the active list is cut into the same fixed chunks in every
-// kernel of a step (the chunk count depends only on N_a), one wavefront per
-// basis vector reduces a chunk in a fixed order into a per-chunk partial, and
-// every block of the NEXT kernel adds the partials in the same fixed order
-// (the kernel boundary orders the writes before the reads).
+// kernel of a step (the chunk count depends only on N_a), each block reduces
+// its chunk in a fixed order into a per-chunk partial (wavefront butterflies,
+// then the wavefronts in order), and every block of the NEXT kernel adds the
+// partials in the same fixed order (the kernel boundary orders the writes
+// before the reads).
 #include <utility>
 
 #include "mra_internal.hpp"
