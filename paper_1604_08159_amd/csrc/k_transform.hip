@@ -403,7 +403,8 @@ __global__ void __launch_bounds__(256) k_forward(Batch b, int src, int dst) {
     int l;
     const int fi = packed_to_fine(i, J, j0, &l);
     const T val = f[fi];
-    am = fabs((double)val);
+    // a NaN would vanish in the fmax reduction: count it as +inf
+    am = isfinite((double)val) ? fabs((double)val) : __builtin_huge_val();
     out[i] = l == j0 ? val : val - predict_node<P, T, decltype(f)>(f, fi & (N - 1), fi >> J, l, J);
   }
   __shared__ double red[4];
@@ -447,7 +448,11 @@ __global__ void __launch_bounds__(256) k_mask_sig(Batch b, int packed_is_double)
   const SolveDev& s = MRA_SOLVE(b);
   const TP* d = packed_details<TP>(s, packed_is_double);
   const int Nf = s.N * s.N, n0 = 1 << (2 * s.j0);
-  const double tau = s.eps * __longlong_as_double((long long)*s.umax);
+  const double umax = __longlong_as_double((long long)*s.umax);
+  // max|u| over the field is NaN or inf exactly when a value is: report it
+  // (every comparison with tau would fail and silently drop the details)
+  if (MRA_BX(b) == 0 && threadIdx.x == 0 && !isfinite(umax)) s.ctrl[C_STATUS] = 5;
+  const double tau = s.eps * umax;
   for (int i = MRA_BX(b) * blockDim.x + threadIdx.x; i < Nf; i += MRA_GX(b) * blockDim.x)
     s.mask[i] = (i < n0 || fabs((double)d[i]) >= tau) ? 1 : 0;
 }
