@@ -236,6 +236,45 @@ def run_serving(args) -> int:
     return 0
 
 
+def run_serving_spec(args) -> int:
+    """The serving configuration's request mix (1-3 vortices, finest 64^2..2048^2
+    log-uniform over levels, 200-2000 steps, Re 1e3..4e4) on a bounded sample:
+    capacity from a closed-loop run (every request queued at once), then
+    Poisson arrivals at 70% of that capacity for the latency percentiles.  The
+    configuration's 50 req/s is far above one GPU's capacity for this mix, so
+    its queue would grow without bound."""
+    import torch
+    import workloads as W
+    from paper_1604_08159_amd import MRA_MIXED, serve
+    n = args.spec_requests
+
+    def server():
+        return serve.Server(hbm_budget=args.hbm_gb << 30, prec=MRA_MIXED, round_steps=args.round_steps,
+                            progress=progress_printer())
+
+    timed = W.serving_requests(n, seed=50, rate=50.0, J_range=(6, 11), steps_range=(200, 2000))
+    log(f"serving_spec: capacity run, {n} requests queued at once")
+    t0 = time.perf_counter()
+    recs = server().run(serve.requests_from_problems(timed, W.initial_field), realtime=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cap = {k: v for k, v in serve.summarize(recs, wall).items() if "latency" not in k}   # no arrival clock here
+    rate = 0.7 * cap["solves_per_s"]
+    timed70 = W.serving_requests(n, seed=51, rate=rate, J_range=(6, 11), steps_range=(200, 2000))
+    log(f"serving_spec: {n} Poisson arrivals at {rate:.2f}/s (70% of capacity)")
+    t0 = time.perf_counter()
+    recs70 = server().run(serve.requests_from_problems(timed70, W.initial_field), realtime=True)
+    torch.cuda.synchronize()
+    wall70 = time.perf_counter() - t0
+    at70 = serve.summarize(recs70, wall70)
+    print(json.dumps({"workload": f"serving configuration mix: 1-3 vortices, finest 64^2..2048^2, 200-2000 steps, "
+                                  f"{n} requests per run, mixed precision",
+                      "metric": "solves/s and p50/p99 latency",
+                      "capacity_closed_loop": cap, "offered_req_per_s_at_70pct": rate, "at_70pct_of_capacity": at70,
+                      "configured_rate_req_per_s": 50.0}))
+    return 0
+
+
 def run_vapor(args) -> int:
     """Passive vapor (Section 3.6) carried by the Fujiwhara flow: each of the
     batch's 512^2 vortex solves has a vapor solve on its own adaptive grid,
@@ -492,12 +531,13 @@ def run_families(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["fujiwhara", "ensemble", "serving", "vapor", "three2048", "longrun",
-                                           "implicit", "families"],
+                                           "implicit", "families", "serving_spec"],
                     default="fujiwhara")
     ap.add_argument("--batch3", type=int, default=2)
     ap.add_argument("--steps3", type=int, default=10)
     ap.add_argument("--long-steps", type=int, default=2000)
     ap.add_argument("--fam-steps", type=int, default=0, help="0: up to 37.5 h")
+    ap.add_argument("--spec-requests", type=int, default=40)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--newton", type=int, default=2)
     ap.add_argument("--jacobian", choices=["frozen", "exact"], default="frozen")
@@ -531,6 +571,8 @@ def main() -> int:
         return run_vapor(args)
     if args.workload == "three2048":
         return run_three(args)
+    if args.workload == "serving_spec":
+        return run_serving_spec(args)
     if args.workload == "families":
         return run_families(args)
     if args.workload == "implicit":
