@@ -148,6 +148,44 @@ def cpu_baseline(steps: int) -> dict:
                       f"{r['sec']:.1f} s"}
 
 
+def ensemble_cpu_baseline(probs, steps: int = 2) -> dict:
+    """The FP64 oracle for the ensemble: for every grid size, one solve of the
+    ensemble is timed over `steps` steps, single-threaded, in its own process
+    (the sizes run side by side); the per-step times, applied to every solve's
+    step count and spread over the host's cores one solve per process, give
+    the oracle's ensemble rate."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               NUMEXPR_NUM_THREADS="1")
+    code = (
+        "import json,sys,time; sys.path.insert(0, %r)\n"
+        "import workloads as W\n"
+        "from oracle import krylov as ok, ops as oo\n"
+        "pb = W.ensemble(%d, steps=%d)[%d]\n"
+        "g = ok.Grid(J=pb.J, p=pb.p, eps=pb.eps); fl = oo.Flow(nu0=pb.nu0, cs=pb.cs)\n"
+        "st = ok.init_state(W.initial_field(pb), g)\n"
+        "t0 = time.perf_counter()\n"
+        "for _ in range(%d):\n"
+        "    st = ok.step(st, g, fl, pb.m, pb.dt)\n"
+        "print(json.dumps({'sec_per_step': (time.perf_counter() - t0) / %d}))\n")
+    first = {}
+    for i, pb in enumerate(probs):
+        first.setdefault(pb.J, i)
+    procs = {J: subprocess.Popen([sys.executable, "-c", code % (ROOT, len(probs), probs[0].steps, i, steps, steps)],
+                                 env=env, stdout=subprocess.PIPE, text=True) for J, i in first.items()}
+    per_step = {}
+    for J, pr in procs.items():
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"oracle ensemble timing failed for J={J}")
+        per_step[J] = json.loads(out.strip().splitlines()[-1])["sec_per_step"]
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    total = sum(per_step[pb.J] * pb.steps for pb in probs) / cores
+    return {"value": len(probs) / total, "unit": "ensemble solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} oracle steps of one solve per grid size ({', '.join(str(1 << J) + '^2' for J in sorted(per_step))}), "
+                      f"single-threaded; per-step seconds {', '.join(f'{per_step[J]:.2f}' for J in sorted(per_step))}, "
+                      f"applied to every solve's step count over {cores} cores, one solve per process (extrapolated)"}
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -200,6 +238,7 @@ def run_ensemble(args) -> int:
         s.close()
         log(f"fp64 per-solve J={J}: {per_step[J] * 1e3:.2f} ms/step")
     fp64_total = sum(per_step[pb.J] * pb.steps for pb in probs)
+    cpu = None if args.no_cpu else ensemble_cpu_baseline(probs)
     print(json.dumps({"workload": f"ensemble of {len(probs)} two-vortex solves, finest 128^2..1024^2, "
                                   f"{args.ens_steps} steps each, mixed precision, one GPU",
                       "metric": "ensemble solves/s", "value": summ["solves_per_s"], "wall_s": wall,
@@ -207,7 +246,8 @@ def run_ensemble(args) -> int:
                       "fp64_per_solve_gpu": {"solves_per_s_extrapolated": len(probs) / fp64_total,
                                              "sec_per_step_by_J": per_step,
                                              "note": "one warmed solve per size timed over 8 steps, "
-                                                     "applied to every solve's step count"}}))
+                                                     "applied to every solve's step count"},
+                      "cpu_baseline": cpu}))
     return 0
 
 
