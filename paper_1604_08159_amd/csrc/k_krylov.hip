@@ -183,17 +183,23 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
   }
 }
 
-// Grid of the reductions: at most kRedGrid blocks per solve (blocks loop
-// over chunks), fewer on grids too small to fill them.
+// Grid of the reductions, blocks per solve (blocks loop over chunks): at
+// least kRedGrid, more for small batches so that the launch still has about
+// kRedTarget blocks (four per CU; a batch of two 2048^2 solves would
+// otherwise run 128 blocks), never more than the chunks a grid can have.
 constexpr int kRedGrid = 64;
-static int red_grid(int J) {
+constexpr int kRedTarget = 1024;
+static int red_grid(int J, int nbatch) {
   const int nf = 1 << (2 * J);
-  int g = (nf + kChunkMin - 1) / kChunkMin;
-  return g < kRedGrid ? g : kRedGrid;
+  int cap = (nf + kChunkMin - 1) / kChunkMin;
+  if (cap > kRedBlocks) cap = kRedBlocks;
+  int g = (kRedTarget + nbatch - 1) / nbatch;
+  if (g < kRedGrid) g = kRedGrid;
+  return g < cap ? g : cap;
 }
 
 hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_norm0, dim3((red_grid(c.J)) * b.n), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_norm0, dim3(red_grid(c.J, b.n) * b.n), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
@@ -214,7 +220,7 @@ static void arnoldi_fixed(const Batch& b, dim3 g, int j, hipStream_t st, std::in
 }
 
 hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st) {
-  dim3 g((red_grid(c.J)) * b.n);
+  dim3 g(red_grid(c.J, b.n) * b.n);
   if (j >= c.m || c.m > kMaxM) return hipErrorInvalidValue;
   if (j < kFixedCols) arnoldi_fixed(b, g, j, st, std::make_integer_sequence<int, kFixedCols>{});
   else if (c.m <= 32) arnoldi_mj<32, -1>(b, g, j, st);
