@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
 // kRedTarget blocks (four per CU; a batch of two 2048^2 solves would
 // otherwise run 128 blocks), never more than the chunks a grid can have.
 constexpr int kRedGrid = 64;
-constexpr int kRedTarget = 1024;
+constexpr int kRedTarget = 2048;
 static int red_grid(int J, int nbatch) {
   const int nf = 1 << (2 * J);
   int cap = (nf + kChunkMin - 1) / kChunkMin;

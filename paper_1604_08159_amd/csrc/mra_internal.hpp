@@ -17,7 +17,7 @@ constexpr int kMaxJ = 11;
 constexpr int kMaxM = 47;           // Krylov dimension cap (augmented size <= 48)
 constexpr int kMaxBatch = 64;       // solves per launch
 constexpr int kTile = 32;           // stencil tile edge (clamped to N)
-constexpr int kRedBlocks = 256;     // max chunks per solve of the Krylov reductions
+constexpr int kRedBlocks = 512;     // max chunks per solve of the Krylov reductions
 constexpr int kScanItems = 4;       // packed entries per thread in compaction
 constexpr int kScanBlock = 256;     // threads per compaction block
 constexpr int kCoarseLevels = 6;    // levels <= this are prolonged by one block
