@@ -227,7 +227,8 @@ int32_t mra_solve_track(mra_solve s, int32_t k, double* centres, void* stream);
  * (else MRA_E_ARG); solve_batch orders every step itself when the partner is
  * in the same call.  Precision follows the partner; the arena is
  * mra_solve_footprint(g, precision, m) bytes.  The partner must outlive the
- * scalar (destroy scalars first).  r0_dense: device double [N][N].
+ * scalar: mra_solve_destroy refuses (MRA_E_ARG) a solve that still carries
+ * scalars, so destroy scalars first.  r0_dense: device double [N][N].
  * mra_solve_read on a scalar returns its field and its mass as diag[4].
  * ------------------------------------------------------------------------ */
 int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, double dt, double kappa0,

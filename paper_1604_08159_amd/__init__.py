@@ -208,7 +208,7 @@ class Solve:
 
     def close(self) -> None:
         if getattr(self, "handle", None):
-            lib().mra_solve_destroy(self.handle)
+            _check("mra_solve_destroy", lib().mra_solve_destroy(self.handle))   # refused while scalars ride on it
             self.handle = None
 
     def __del__(self):

@@ -562,6 +562,7 @@ int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, do
       (e = hipMemcpyAsync(s.dense64, r0_dense, Nf * sizeof(double), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
       (e = launch_reset_max(b, st)) != hipSuccess || (e = launch_forward(b, h->cfg, 0, 0, st)) != hipSuccess ||
       (e = launch_threshold(b, h->cfg, 1, st)) != hipSuccess || (e = launch_gather(b, h->cfg, st)) != hipSuccess) {
+    partner->riders -= 1;
     delete h;
     return MRA_E_DEVICE;
   }
@@ -795,6 +796,7 @@ int32_t mra_solve_set_jacobian(mra_solve h, int32_t jacobian) {
 
 int32_t mra_solve_destroy(mra_solve h) {
   if (!h) return MRA_E_ARG;
+  if (h->riders > 0) return MRA_E_ARG;          // passive scalars still read its fields
   drop_graphs_of(h);
   if (h->partner) h->partner->riders -= 1;
   delete h;

@@ -70,3 +70,19 @@ def test_failing_solve_does_not_disturb_its_batch(M):
     assert np.array_equal(d2.cpu().numpy(), alone[1])
     for s in solves:
         s.close()
+
+
+def test_partner_cannot_be_destroyed_before_its_scalar(M):
+    pb = W.plain_pair()
+    s = _make(M, pb, M.MRA_MIXED)
+    sc = M.ScalarSolve(s, M.grid_desc(pb.J, pb.p, 1e-3), 10, pb.dt,
+                       torch.from_numpy(W.vapor_field(pb.N)).to(DEV))
+    with pytest.raises(M.MraError) as e:
+        s.close()
+    assert e.value.status == 1 and s.handle is not None
+    s.step(1)
+    sc.step(1)                                  # both still usable
+    sc.close()
+    s.close()
+    assert s.handle is None
+
