@@ -1,0 +1,121 @@
+"""Host logic of the continuous-batching server without a GPU: the solve, the
+batched step and the streams are replaced by fakes that count steps, so the
+admission by footprint, FIFO order, rejection of oversized requests, the
+exact step count of every solve, the round size and the latency summary are
+checked on the CPU (virtual clock)."""
+import contextlib
+
+import numpy as np
+import pytest
+
+from paper_1604_08159_amd import serve
+
+
+class FakeSolve:
+    live = 0
+    peak = 0
+    bytes_live = 0
+    peak_bytes = 0
+
+    def __init__(self, g, f, prec, m, dt, w0, stream=None):
+        self.J, self.m = g.J, m
+        self.nbytes = FOOTPRINT[g.J]
+        self.steps = 0
+        FakeSolve.live += 1
+        FakeSolve.peak = max(FakeSolve.peak, FakeSolve.live)
+        FakeSolve.bytes_live += self.nbytes
+        FakeSolve.peak_bytes = max(FakeSolve.peak_bytes, FakeSolve.bytes_live)
+
+    def read(self, dense=True, stream=None):
+        return None, {"n_active": 10.0, "status": 0.0}
+
+    def scalars(self):
+        return {"evals": 21.0 * 10 * self.steps}
+
+    def close(self):
+        FakeSolve.live -= 1
+        FakeSolve.bytes_live -= self.nbytes
+
+
+FOOTPRINT = {6: 100, 7: 400, 8: 1600}
+BATCHES = []
+
+
+def fake_solve_batch(solves, nsteps, stream=None):
+    assert len({s.J for s in solves}) == 1            # one launch configuration per batch
+    BATCHES.append((solves[0].J, len(solves), nsteps[0]))
+    for s, k in zip(solves, nsteps):
+        s.steps += k
+
+
+class FakeStream:
+    def synchronize(self):
+        pass
+
+
+@pytest.fixture
+def fakes(monkeypatch):
+    FakeSolve.live = FakeSolve.peak = FakeSolve.bytes_live = FakeSolve.peak_bytes = 0
+    BATCHES.clear()
+    monkeypatch.setattr(serve, "Solve", FakeSolve)
+    monkeypatch.setattr(serve, "solve_batch", fake_solve_batch)
+    monkeypatch.setattr(serve, "solve_footprint", lambda g, prec, m: FOOTPRINT[g.J])
+    monkeypatch.setattr(serve.torch.cuda, "Stream", lambda device=None: FakeStream())
+    monkeypatch.setattr(serve.torch.cuda, "stream", lambda st: contextlib.nullcontext())
+    monkeypatch.setattr(serve.torch, "from_numpy", lambda a: a)          # host arrays stay put
+    yield
+
+
+class _Host(np.ndarray):
+    def to(self, *a, **k):
+        return self
+
+
+def _req(rid, arrival, J, steps):
+    w = np.zeros((1 << J, 1 << J)).view(_Host)
+    return serve.Request(rid, arrival, J, 2, 1e-4, 1e-4, 0.17, 20, 0.01, steps, w)
+
+
+def test_admission_rounds_and_step_counts(fakes):
+    reqs = [_req(0, 0.0, 6, 45), _req(1, 0.1, 8, 30), _req(2, 0.2, 7, 10), _req(3, 0.3, 6, 20),
+            _req(4, 0.4, 8, 5)]
+    srv = serve.Server(hbm_budget=2000, round_steps=20, device="cpu")
+    recs = {r.rid: r for r in srv.run(reqs, realtime=False)}
+    assert sorted(recs) == [0, 1, 2, 3, 4]
+    assert all(r.status == 0 for r in recs.values())
+    # every solve ran exactly its steps, in rounds of at most 20
+    for J, n, k in BATCHES:
+        assert 1 <= k <= 20
+    assert all(recs[r.rid].evals == 21.0 * 10 * r.steps for r in reqs)
+    # the budget (2000) is never exceeded: the two 1600-byte solves never coexist,
+    # so request 4 (J = 8) waits for request 1, and every arena is released
+    assert FakeSolve.peak_bytes <= 2000 and FakeSolve.live == 0
+    assert recs[4].admitted >= recs[1].finished
+    for rec in recs.values():
+        assert rec.admitted >= rec.arrival and rec.finished >= rec.admitted
+
+
+def test_oversized_request_is_rejected_alone(fakes):
+    reqs = [_req(0, 0.0, 8, 10), _req(1, 0.0, 6, 10)]
+    srv = serve.Server(hbm_budget=1000, round_steps=20, device="cpu")
+    recs = {r.rid: r for r in srv.run(reqs, realtime=False)}
+    assert recs[0].status == -1 and recs[1].status == 0
+    s = serve.summarize(list(recs.values()), 1.0)
+    assert s["rejected"] == 1 and s["failed"] == 0 and s["requests"] == 2
+
+
+def test_budget_limits_residency(fakes):
+    reqs = [_req(i, 0.0, 7, 40) for i in range(6)]          # 400 bytes each
+    srv = serve.Server(hbm_budget=1000, round_steps=20, device="cpu")
+    srv.run(reqs, realtime=False)
+    assert FakeSolve.peak == 2                              # 2 x 400 <= 1000 < 3 x 400
+
+
+def test_summary_percentiles():
+    recs = []
+    for i, lat in enumerate([1.0, 2.0, 3.0, 4.0, 10.0]):
+        r = serve.Record(i, 6, 10, 0.0, admitted=0.0, finished=lat, evals=5.0)
+        recs.append(r)
+    s = serve.summarize(recs, 2.0)
+    assert s["p50_latency_s"] == 3.0 and s["p99_latency_s"] == 10.0 and s["max_latency_s"] == 10.0
+    assert s["solves_per_s"] == 2.5 and s["active_pt_evals_per_s"] == 12.5
