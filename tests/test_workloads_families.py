@@ -47,3 +47,29 @@ def test_unequal_size_pair(ratio):
     assert abs(p2 / p1 - 1.0) < 1e-14
     assert abs(w2.max() / w1.max() - 1.0) < 0.05
     assert abs(pb.vortices[1].r0 / pb.vortices[0].r0 - ratio) < 1e-15
+
+
+def test_ensemble_generator_follows_its_distribution():
+    probs = W.ensemble(256)
+    assert len(probs) == 256 and {pb.J for pb in probs} == {7, 8, 9, 10}
+    for pb in probs:
+        b = pb.vortices[1].cx - pb.vortices[0].cx
+        assert 0.8 <= b <= 2.0 and 2000.0 <= pb.re <= 37440.0 and 1e-5 <= pb.eps <= 1e-3
+        assert pb.p == 2 and pb.m == 20 and pb.steps == 200
+    assert [pb.name for pb in W.ensemble(256)] == [pb.name for pb in probs]            # seeded
+
+
+def test_serving_requests_follow_their_distribution():
+    timed = W.serving_requests(300, rate=50.0)
+    t = np.array([a for a, _ in timed])
+    assert np.all(np.diff(t) > 0)
+    assert abs(len(t) / t[-1] - 50.0) < 10.0                 # Poisson arrivals at about 50/s
+    for _, pb in timed:
+        assert 6 <= pb.J <= 11 and 200 <= pb.steps <= 2000 and 1e3 <= pb.re <= 4e4
+        assert 1 <= len(pb.vortices) <= 3 and pb.vortices[0].gamma == 1.0
+        assert pb.dt == min(0.01, 2 * math.pi / pb.N)
+        rmax = max(v.r0 for v in pb.vortices)
+        for i, a in enumerate(pb.vortices):
+            assert math.hypot(a.cx - math.pi, a.cy - math.pi) <= 1.5 + 1e-12
+            for q in pb.vortices[i + 1:]:
+                assert math.hypot(a.cx - q.cx, a.cy - q.cy) >= 2.5 * rmax
