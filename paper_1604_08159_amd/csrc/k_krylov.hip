@@ -78,8 +78,8 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   }
 }
 
-// Stage 2: h1 from A; w -= V_j h1; h2 = V_j^T w and ||w||^2 partials
-// (buffer B).
+// Stage 2: h1 from A; w1 = w - V_j h1 (not stored); h2 = V_j^T w1 and
+// ||w1||^2 partials (buffer B).
 template <int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
@@ -111,7 +111,6 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) t -= h[i] * v[i];
-      W[k] = t;
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) acc[i] += v[i] * t;
@@ -126,9 +125,9 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
   }
 }
 
-// Stage 3: h2 and ||w||^2 from B; H[:j+1, j] = h1 + h2; the next basis vector
-// V_{j+1} = (w - V_j h2) / h_{j+1,j}.  The norm of w - V_j h2 is taken from
-// Pythagoras, ||w||^2 - ||h2||^2 (V_j orthonormal, h2 = V_j^T w), before the
+// Stage 3: h2 and ||w1||^2 from B; H[:j+1, j] = h1 + h2; the next basis
+// vector V_{j+1} = (w1 - V_j h2) / h_{j+1,j}.  The norm of w1 - V_j h2 is taken
+// from Pythagoras, ||w1||^2 - ||h2||^2 (V_j orthonormal, h2 = V_j^T w1), before the
 // update, so the stage writes V_{j+1} normalised in the same pass.  In CGS2
 // h2 is a rounding-level correction, so no cancellation arises; a breakdown
 // (h_{j+1,j} <= 1e-13 ||A v_j||) or a non-finite value ends the basis.
@@ -167,6 +166,11 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
   const auto* W = glb(s.w);
   const auto* V = glb(s.V);
   auto* Vn = glb(s.V + (size_t)(j + 1) * Nf);
+  // the once-orthogonalised w1 is rebuilt from w with h1 (the same operations
+  // in the same order as stage 2), so stage 2 need not store it
+  __shared__ double h1[kMaxM + 2];
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) h1[i] = s.hpart[i];
+  __syncthreads();
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
@@ -175,6 +179,9 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) v[i] = V[i * Nf + k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) t -= h1[i] * v[i];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) t -= h[i] * v[i];
