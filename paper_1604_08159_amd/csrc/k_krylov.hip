@@ -90,10 +90,23 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
   if ((int)MRA_BX(b) >= nb) return;
   __shared__ double h[kMaxM + 2];
   reduce_partials(part_buf(s, 0), nb, j + 2, h);
+  // selective reorthogonalisation ("twice is enough"): when the first pass
+  // keeps at least half of ||w||^2, w1 is orthogonal to V_j to rounding and
+  // the second pass is skipped; ||w1||^2 = ||w||^2 - ||h1||^2 has no
+  // cancellation in that case.  Every block takes the same decision.
+  double h1sq = 0.0;
+  for (int i = 0; i <= j; ++i) h1sq += h[i] * h[i];
+  const double w1sq = h[j + 1] - h1sq;
+  const bool once = w1sq >= 0.5 * h[j + 1];
   if (MRA_BX(b) == 0) {
     for (int i = threadIdx.x; i <= j; i += blockDim.x) s.hpart[i] = h[i];
-    if (threadIdx.x == 0) s.scal[S_NRMAV] = sqrt(h[j + 1]);
+    if (threadIdx.x == 0) {
+      s.scal[S_NRMAV] = sqrt(h[j + 1]);
+      s.scal[S_W1SQ] = w1sq;
+      s.ctrl[C_REORTH] = once ? 0 : 1;
+    }
   }
+  if (once) return;
   const size_t Nf = (size_t)s.N * s.N;
   auto* W = glb(s.w);
   const auto* V = glb(s.V);
@@ -129,7 +142,9 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
 // vector V_{j+1} = (w1 - V_j h2) / h_{j+1,j}.  The norm of w1 - V_j h2 is taken
 // from Pythagoras, ||w1||^2 - ||h2||^2 (V_j orthonormal, h2 = V_j^T w1), before the
 // update, so the stage writes V_{j+1} normalised in the same pass.  In CGS2
-// h2 is a rounding-level correction, so no cancellation arises; a breakdown
+// h2 is a rounding-level correction, so no cancellation arises.  When stage 2
+// found the second pass unnecessary (C_REORTH = 0), h2 = 0 and only h1 is
+// applied.  A breakdown
 // (h_{j+1,j} <= 1e-13 ||A v_j||) or a non-finite value ends the basis.
 template <int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
@@ -141,7 +156,14 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
   if ((int)MRA_BX(b) >= nb) return;
   __shared__ double h[kMaxM + 2];
   __shared__ double inv_sh;
-  reduce_partials(part_buf(s, 1), nb, j + 2, h);
+  const bool reorth = s.ctrl[C_REORTH] != 0;
+  if (reorth) {
+    reduce_partials(part_buf(s, 1), nb, j + 2, h);
+  } else {                           // one pass sufficed: h2 = 0, ||w1||^2 from stage 2
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) h[i] = 0.0;
+    if (threadIdx.x == 0) h[j + 1] = s.scal[S_W1SQ];
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     double h2sq = 0.0;
     for (int i = 0; i <= j; ++i) h2sq += h[i] * h[i];
@@ -182,9 +204,11 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) t -= h1[i] * v[i];
+      if (reorth) {
 #pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i <= j) t -= h[i] * v[i];
+        for (int i = 0; i < MJ; ++i)
+          if (i <= j) t -= h[i] * v[i];
+      }
       Vn[k] = inv == 0.0 ? 0.0 : t * inv;
     }
   }
