@@ -2,7 +2,7 @@
 
 Workload: the Fujiwhara pair at Re = 5000 on a 512 x 512 finest grid
 (J = 9), 4-point DD, threshold 1e-4, Krylov dimension 20, dt = 0.01; a batch
-of 8 solves whose radii and separations are drawn from seeds 1000..1007.
+of 24 solves whose radii and separations are drawn from seeds 1000..1023.
 One step = one exponential Rosenbrock-Euler step of every solve of the batch
 (residual, 20 Jacobian-vector products, Arnoldi, phi_1, update and FP64
 regrid), launched together through solve_batch and replayed as a HIP graph.
@@ -43,17 +43,19 @@ def kernel_bytes(name: str, N: int, na: int, tiles_active_frac: float, nbatch: i
     """Algorithmic HBM bytes of one launch of a step kernel for the batch."""
     nf = N * N
     if name == "jvp":
-        # u_v, v_v, v~, w~, u, v, nu_e on active tiles + rank map; J v out (FP64)
-        per = (7 * esz + 4) * nf * tiles_active_frac + 8 * na
+        # psi~, v~, w~, u, v, nu_e on active tiles + rank map; J v out (FP64)
+        per = (6 * esz + 4) * nf * tiles_active_frac + 8 * na
     elif name == "rhs":
         # u, v, w~ in; nu_e out; rank map; F out (FP64)
         per = (4 * esz + 4) * nf + 8 * na
     elif name == "fft_rows":
         per = esz * nf + 2 * esz * (N // 2 + 1) * N
     elif name == "fft_rows_inv":
-        per = 2 * (esz * nf + 2 * esz * (N // 2 + 1) * N)
+        # the products' pass: psi~ alone
+        per = esz * nf + 2 * esz * (N // 2 + 1) * N
     elif name == "fft_cols":
-        per = 3 * (2 * esz * (N // 2 + 1) * N)
+        # spectrum in, psi~ spectrum out
+        per = 2 * (2 * esz * (N // 2 + 1) * N)
     elif name == "prolong_finest":
         lev = 3 * nf // 4
         per = lev * (1 + esz)          # mask byte + written value (inputs are re-read coarse values)

@@ -251,7 +251,8 @@ __device__ inline const T* poisson_src(const SolveDev& s, int src) {
   if (src == 1) return reinterpret_cast<const T*>(s.vt);
   return reinterpret_cast<const T*>(s.dense64);
 }
-// velocity outputs: src 0 -> (u, v), src 1 -> (u_v, v_v), src 2 -> FP64 pair
+// velocity outputs: src 0 -> (u, v), src 1 -> (u_v, v_v), or psi~ alone in u_v
+// when only the stream function is formed, src 2 -> FP64 pair
 template <typename T>
 __device__ inline T* poisson_dst(const SolveDev& s, int src, int comp) {
   if (src == 0) return reinterpret_cast<T*>(comp == 0 ? s.u : s.v);
@@ -300,7 +301,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src) 
 
 // pass B: C spectrum rows (fixed kx) per block (C * N <= 2048).  LDS: A holds
 // psi_hat, B the u (then the v) spectrum; 2 * 2048 complex values at most.
-template <int P, typename T, int J>
+// PSI: only the stream function is wanted (the products of the frozen
+// Jacobian take u = D1_y psi and v = -D1_x psi with the collocation stencil,
+// which is the same circulant operator as the symbol): psi_hat goes back
+// along y in place and B is not used.
+template <int P, typename T, int J, bool PSI>
 __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b) {
   using V = typename C2<T>::t;
   using G = FftGeo<J>;
@@ -308,7 +313,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b) {
   extern __shared__ unsigned char smem[];
   const SolveDev& s = MRA_SOLVE(b);
   V* A = reinterpret_cast<V*>(smem);
-  V* Bv = A + lds_slots(C * N);
+  V* Bv = A + (PSI ? 0 : lds_slots(C * N));
   const int k0 = MRA_BX(b) * C;
   const int nr = (M + 1 - k0) < C ? (M + 1 - k0) : C;
   V* specU = reinterpret_cast<V*>(s.spec);
@@ -329,9 +334,14 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b) {
     const V z = A[lx(q)];
     const V ps = V{z.x * g, z.y * g};
     A[lx(q)] = ps;
-    Bv[lx(q)] = V{-sy * ps.y, sy * ps.x};                  // i s1(ky) psi_hat
+    if constexpr (!PSI) Bv[lx(q)] = V{-sy * ps.y, sy * ps.x};   // i s1(ky) psi_hat
   }
   fft_sync(wl);
+  if constexpr (PSI) {
+    fft_block<1, T, J, C>(A, nr);
+    for (int q = own0() + lane(); q < e1; q += 64) specU[(size_t)k0 * N + q] = A[lx(q)];
+    return;
+  }
   fft_block<1, T, J, C>(Bv, nr);
   for (int q = own0() + lane(); q < e1; q += 64) specU[(size_t)k0 * N + q] = Bv[lx(q)];
   fft_sync(wl);
@@ -346,8 +356,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b) {
 }
 
 // pass C: spec[kx][y] -> real rows, R rows per block (R * N/2 <= 2048), for
-// the u spectrum and then the v spectrum.
-template <typename T, int J>
+// the u spectrum and then the v spectrum (NC = 2), or for psi alone (NC = 1).
+template <typename T, int J, int NC>
 __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) {
   using V = typename C2<T>::t;
   using G = FftGeo<J>;
@@ -357,7 +367,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) 
   const SolveDev& s = MRA_SOLVE(b);
   const int y0 = MRA_BX(b) * R;
   constexpr int twN = kTwN / N;
-  for (int comp = 0; comp < 2; ++comp) {
+  for (int comp = 0; comp < NC; ++comp) {
     const V* spec = reinterpret_cast<const V*>(comp == 0 ? s.spec : s.spec2);
     for (int q = threadIdx.x; q < M * R; q += kFftThreads) {
       const int k = q / R, r = q % R;
@@ -378,8 +388,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) 
   }
 }
 
-template <typename T, int J>
-static void poisson_j(const Batch& b, int p, int src, int pass, hipStream_t st) {
+template <typename T, int J, bool PSI>
+static void poisson_jp(const Batch& b, int p, int src, int pass, hipStream_t st) {
   using V = typename C2<T>::t;
   using G = FftGeo<J>;
   if (pass < 0 || pass == 0)
@@ -387,27 +397,36 @@ static void poisson_j(const Batch& b, int p, int src, int pass, hipStream_t st) 
                        lds_slots(G::R * G::M) * sizeof(V), st, b, src);
   if (pass < 0 || pass == 1) {
     dim3 g(((G::M + 1 + G::C - 1) / G::C) * b.n);
-    const size_t lds = 2 * (size_t)lds_slots(G::C * G::N) * sizeof(V);
-    if (p == 2) hipLaunchKernelGGL((k_fft_cols<2, T, J>), g, dim3(kFftThreads), lds, st, b);
-    else hipLaunchKernelGGL((k_fft_cols<3, T, J>), g, dim3(kFftThreads), lds, st, b);
+    const size_t lds = (PSI ? 1 : 2) * (size_t)lds_slots(G::C * G::N) * sizeof(V);
+    if (p == 2) hipLaunchKernelGGL((k_fft_cols<2, T, J, PSI>), g, dim3(kFftThreads), lds, st, b);
+    else hipLaunchKernelGGL((k_fft_cols<3, T, J, PSI>), g, dim3(kFftThreads), lds, st, b);
   }
   if (pass < 0 || pass == 2)
-    hipLaunchKernelGGL((k_fft_rows_inv<T, J>), dim3((G::N / G::R) * b.n), dim3(kFftThreads),
+    hipLaunchKernelGGL((k_fft_rows_inv<T, J, PSI ? 1 : 2>), dim3((G::N / G::R) * b.n), dim3(kFftThreads),
                        lds_slots(G::R * G::M) * sizeof(V), st, b, src);
 }
 
+template <typename T, int J>
+static void poisson_j(const Batch& b, int p, int src, bool psi, int pass, hipStream_t st) {
+  if (psi) poisson_jp<T, J, true>(b, p, src, pass, st);
+  else poisson_jp<T, J, false>(b, p, src, pass, st);
+}
+
+// The products of the frozen Jacobian (src 1, Jacobian 0) need the stream
+// function only; every other source needs both velocity components.
 template <typename T>
 static hipError_t poisson_t(const Batch& b, const LaunchCfg& c, int src, int pass, hipStream_t st) {
+  const bool psi = src == 1 && c.jac == 0;
   switch (c.J) {
-    case 3: poisson_j<T, 3>(b, c.p, src, pass, st); break;
-    case 4: poisson_j<T, 4>(b, c.p, src, pass, st); break;
-    case 5: poisson_j<T, 5>(b, c.p, src, pass, st); break;
-    case 6: poisson_j<T, 6>(b, c.p, src, pass, st); break;
-    case 7: poisson_j<T, 7>(b, c.p, src, pass, st); break;
-    case 8: poisson_j<T, 8>(b, c.p, src, pass, st); break;
-    case 9: poisson_j<T, 9>(b, c.p, src, pass, st); break;
-    case 10: poisson_j<T, 10>(b, c.p, src, pass, st); break;
-    case 11: poisson_j<T, 11>(b, c.p, src, pass, st); break;
+    case 3: poisson_j<T, 3>(b, c.p, src, psi, pass, st); break;
+    case 4: poisson_j<T, 4>(b, c.p, src, psi, pass, st); break;
+    case 5: poisson_j<T, 5>(b, c.p, src, psi, pass, st); break;
+    case 6: poisson_j<T, 6>(b, c.p, src, psi, pass, st); break;
+    case 7: poisson_j<T, 7>(b, c.p, src, psi, pass, st); break;
+    case 8: poisson_j<T, 8>(b, c.p, src, psi, pass, st); break;
+    case 9: poisson_j<T, 9>(b, c.p, src, psi, pass, st); break;
+    case 10: poisson_j<T, 10>(b, c.p, src, psi, pass, st); break;
+    case 11: poisson_j<T, 11>(b, c.p, src, psi, pass, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -9,7 +9,8 @@
 // Section 2.3, eq. (5): Smagorinsky eddy viscosity nu_e = nu0 + (Cs h)^2 |S|,
 // |S| = sqrt(2 S_ij S_ij) from the resolved strain of the velocity
 // u = D1_y psi, v = -D1_x psi (computed by the Fourier pass of the Poisson
-// solve and read here).
+// solve and read here for the residual; the products of the frozen Jacobian
+// read psi~ and apply D1 themselves).
 // Residual (flux form, symmetric conservative diffusion):
 //   F = -[D1_x(u w) + D1_y(v w)] + 1/2 [L(nu w) + nu L w - w L nu] - mu w,
 // evaluated only at the active nodes of a tile (written to their position in
@@ -106,7 +107,7 @@ template <int P, typename T>
 __host__ __device__ inline size_t jvp_lds_elems(int TS, bool exact = false) {
   using G = Geo<P>;
   const size_t Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
-  return exact ? 4 * Ww * Ww + 4 * Wn * Wn : 3 * Ww * Ww + 2 * Wn * Wn;
+  return exact ? 4 * Ww * Ww + 4 * Wn * Wn : 4 * Ww * Ww + 2 * Wn * Wn;
 }
 
 template <int P, typename T, int TS>
@@ -249,9 +250,13 @@ __global__ void __launch_bounds__(256) k_nuprime(Batch b) {
 }
 
 // Jacobian-vector product on one tile.  Every global load is issued in one
-// phase: v~ and nu_e regions into LDS; u, v, u_v, v_v, w~ at this thread's
-// flux points and the ranks of its output nodes into registers.  EX (the
-// exact Jacobian, local strain) adds the viscosity's variation
+// phase: v~ and nu_e regions into LDS; u, v, w~ at this thread's flux points
+// and the ranks of its output nodes into registers.  The frozen Jacobian takes
+// the stream function psi~ of v~ (into LDS) and forms u_v = D1_y psi~ and
+// v_v = -D1_x psi~ with the collocation stencil: one field read instead of
+// two, and the Poisson pass skips one inverse transform.  EX (the exact
+// Jacobian, local strain) reads u_v and v_v, which k_nuprime differentiates
+// as well, and adds the viscosity's variation
 // 1/2 [L(nu' w~) + nu' L w~ - w~ L nu'] with nu' from k_nuprime.
 template <int P, typename T, int TS, bool EX>
 __global__ void __launch_bounds__(256) k_jvp(Batch b) {
@@ -271,6 +276,8 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   T* fb = fa + Ww * Ww;
   T* nu = fb + Ww * Ww;
   T* cn = nu + Wn * Wn;
+  // frozen Jacobian: psi~ (Ww region), whose D1 gives u~ and v~ in place
+  T* ps = cn + Wn * Wn;
   // exact Jacobian: w~ (Ww region), nu' and nu' w~ (Wn regions)
   T* wl = cn + Wn * Wn;
   T* np = wl + Ww * Ww;
@@ -281,7 +288,7 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   const T* guv = reinterpret_cast<const T*>(s.uv);
   const T* gvv = reinterpret_cast<const T*>(s.vv);
   const T* gw = reinterpret_cast<const T*>(s.wt);
-  T ur[NQ], vr[NQ], wr[NQ], uvr[NQ], vvr[NQ];
+  T ur[NQ], vr[NQ], wr[NQ], uvr[EX ? NQ : 1], vvr[EX ? NQ : 1];
   int kr[NO];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
@@ -292,8 +299,10 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
       ur[i] = gu[f];
       vr[i] = gv[f];
       wr[i] = gw[f];
-      uvr[i] = guv[f];
-      vvr[i] = gvv[f];
+      if constexpr (EX) {
+        uvr[i] = guv[f];
+        vvr[i] = gvv[f];
+      }
     }
   }
 #pragma unroll
@@ -312,21 +321,37 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
         rnp.fetch(reinterpret_cast<const T*>(s.vel64), x0 - P, y0 - P, N);
         rnp.put(np);
       }
+      rvt.put(vt);
+      rnu.put(nu);
+    } else {
+      Region<Ww, T> rps;
+      rps.fetch(guv, x0 - G::R1, y0 - G::R1, N);
+      rvt.put(vt);
+      rnu.put(nu);
+      rps.put(ps);
     }
-    rvt.put(vt);
-    rnu.put(nu);
   }
   __syncthreads();
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
-  // fluxes of the linearised advection on the Ww region, nu v~ on the Wn region
+  // fluxes of the linearised advection on the Ww region, nu v~ on the Wn region.
+  // With psi~: D1_x of the x-flux is taken on the tile's rows only and D1_y of
+  // the y-flux on its columns only, so u~ = D1_y psi~ is needed on rows
+  // [R1, R1 + TS) and v~ = -D1_x psi~ on columns [R1, R1 + TS) of the region,
+  // and their stencils stay inside it.
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int q = threadIdx.x + 256 * i;
     if (q < Ww * Ww) {
       const T vtv = vt[q];
-      fa[q] = uvr[i] * wr[i] + ur[i] * vtv;
-      fb[q] = vvr[i] * wr[i] + vr[i] * vtv;
-      if constexpr (EX) wl[q] = wr[i];
+      if constexpr (EX) {
+        fa[q] = uvr[i] * wr[i] + ur[i] * vtv;
+        fb[q] = vvr[i] * wr[i] + vr[i] * vtv;
+        wl[q] = wr[i];
+      } else {
+        const int r = q / Ww, c = q - r * Ww;
+        if (r >= G::R1 && r < G::R1 + TS) fa[q] = (ih * dy1<P, T>(ps, Ww, r, c)) * wr[i] + ur[i] * vtv;
+        if (c >= G::R1 && c < G::R1 + TS) fb[q] = -(ih * dx1<P, T>(ps, Ww, r, c)) * wr[i] + vr[i] * vtv;
+      }
     }
   }
   constexpr int on = G::R1 - P;
