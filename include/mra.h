@@ -95,7 +95,9 @@ typedef struct {
   int32_t* index_packed;     /* [N*N], first N_a valid                           */
   int32_t* index_fine;       /* [N*N], first N_a valid                           */
   int64_t* n_active;         /* device scalar                                    */
-  double* krylov_V;          /* [(m+1)][N*N] FP64 Arnoldi basis                  */
+  void* krylov_V;            /* [(m+1)][N*N] Arnoldi basis: double in FP64 solves,
+                                float in mixed precision (the products take the
+                                basis rounded to FP32; sums over it are FP64)   */
   double* hessenberg;        /* [(m+1)][m] FP64                                  */
   double* scalars;           /* [16] FP64: [0] beta, [2] ||A v_last||, [4] t,
                                 [5] active-point residual evaluations so far
@@ -170,14 +172,15 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
 /* ------------------------------------------------------------------------
  * Solves.  A solve keeps its whole state in a caller-owned device arena of
  * mra_solve_footprint bytes: active values (FP64), active set, Krylov basis
- * V [(m+1) x N*N] FP64, Hessenberg matrix, dense work fields and FFT
- * spectra.  1 <= m <= 47.
+ * V [(m+1) x N*N] (FP64, or FP32 in mixed precision), Hessenberg matrix,
+ * dense work fields and FFT spectra.  1 <= m <= 47.
  *
  * mra_solve_init: omega0_dense (device, double [N][N]) is transformed and
  *   thresholded to the first active set; the host handle is written to *out.
  * krylov_step: nsteps exponential Rosenbrock-Euler steps
- *   omega_M <- omega_M + dt beta V_m phi_1(dt H_m) e_1, with Arnoldi (CGS2,
- *   happy breakdown h_{j+1,j} <= 1e-13 ||A v_j||, beta = 0 -> no update) and
+ *   omega_M <- omega_M + dt beta V_m phi_1(dt H_m) e_1, with Arnoldi
+ *   (classical Gram-Schmidt with a second pass where the first loses more
+ *   than half of ||A v_j||^2, happy breakdown h_{j+1,j} <= 1e-13 ||A v_j||, beta = 0 -> no update) and
  *   an FP64 regrid (Pi, forward transform, threshold, gather) after each
  *   step.  The first call captures one step into a HIP graph on `stream`;
  *   later calls replay it.

@@ -1,5 +1,6 @@
-// Krylov part of the time steps, FP64: Arnoldi with classical Gram-Schmidt
-// and one reorthogonalisation (CGS2); for the exponential Rosenbrock-Euler
+// Krylov part of the time steps, in FP64 arithmetic (the basis is stored in
+// FP32 in mixed precision): Arnoldi with classical Gram-Schmidt and a
+// selective reorthogonalisation (CGS2); for the exponential Rosenbrock-Euler
 // step phi_1(dt H) e_1 from the exponential of the augmented Hessenberg
 // matrix and the update omega_M += dt beta V y; for the theta-scheme the
 // Newton residual, the GMRES least squares and the Newton update.
@@ -43,7 +44,7 @@ __global__ void __launch_bounds__(256) k_norm0(Batch b) {
 }
 
 // Stage 1: h1 = V_j^T w and ||w||^2 (= ||A v_j||^2) partials (buffer A).
-template <int MJ, int JC>
+template <typename TV, int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
@@ -52,7 +53,7 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   const int nb = nchunks(na);
   const size_t Nf = (size_t)s.N * s.N;
   auto* W = glb(s.w);
-  const auto* V = glb(s.V);
+  const auto* V = glb(vbasis<TV>(s));
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     double acc[MJ + 1];
@@ -60,13 +61,13 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
     for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
       const double wk = W[k];
-      double v[MJ];
+      TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) v[i] = V[i * Nf + k];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) acc[i] += v[i] * wk;
+        if (i <= j) acc[i] += (double)v[i] * wk;
       acc[MJ] += wk * wk;
     }
     // slot layout: h1[0 .. j], then ||w||^2 at j + 1 (static register indices)
@@ -80,7 +81,7 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
 
 // Stage 2: h1 from A; w1 = w - V_j h1 (not stored); h2 = V_j^T w1 and
 // ||w1||^2 partials (buffer B).
-template <int MJ, int JC>
+template <typename TV, int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
   if (once) return;
   const size_t Nf = (size_t)s.N * s.N;
   auto* W = glb(s.w);
-  const auto* V = glb(s.V);
+  const auto* V = glb(vbasis<TV>(s));
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     double acc[MJ + 1];
@@ -117,16 +118,16 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
     for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
       double t = W[k];
-      double v[MJ];
+      TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) v[i] = V[i * Nf + k];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) t -= h[i] * v[i];
+        if (i <= j) t -= h[i] * (double)v[i];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) acc[i] += v[i] * t;
+        if (i <= j) acc[i] += (double)v[i] * t;
       acc[MJ] += t * t;
     }
     // slot layout: h2[0 .. j], then ||w||^2 at j + 1 (static register indices)
@@ -146,7 +147,7 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
 // found the second pass unnecessary (C_REORTH = 0), h2 = 0 and only h1 is
 // applied.  A breakdown
 // (h_{j+1,j} <= 1e-13 ||A v_j||) or a non-finite value ends the basis.
-template <int MJ, int JC>
+template <typename TV, int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
@@ -186,8 +187,8 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
   const double inv = inv_sh;
   const size_t Nf = (size_t)s.N * s.N;
   const auto* W = glb(s.w);
-  const auto* V = glb(s.V);
-  auto* Vn = glb(s.V + (size_t)(j + 1) * Nf);
+  const auto* V = glb(vbasis<TV>(s));
+  auto* Vn = glb(vbasis<TV>(s) + (size_t)(j + 1) * Nf);
   // the once-orthogonalised w1 is rebuilt from w with h1 (the same operations
   // in the same order as stage 2), so stage 2 need not store it
   __shared__ double h1[kMaxM + 2];
@@ -197,19 +198,19 @@ __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
     const Chunk c = chunk_of(na, ch);
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
       double t = W[k];
-      double v[MJ];
+      TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) v[i] = V[i * Nf + k];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) t -= h1[i] * v[i];
+        if (i <= j) t -= h1[i] * (double)v[i];
       if (reorth) {
 #pragma unroll
         for (int i = 0; i < MJ; ++i)
-          if (i <= j) t -= h[i] * v[i];
+          if (i <= j) t -= h[i] * (double)v[i];
       }
-      Vn[k] = inv == 0.0 ? 0.0 : t * inv;
+      Vn[k] = (TV)(inv == 0.0 ? 0.0 : t * inv);
     }
   }
 }
@@ -234,28 +235,34 @@ hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int MJ, int JC>
+template <typename TV, int MJ, int JC>
 static void arnoldi_mj(const Batch& b, dim3 g, int j, hipStream_t st) {
-  hipLaunchKernelGGL((k_gs_dot<MJ, JC>), g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL((k_gs_axpy_dot<MJ, JC>), g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL((k_gs_axpy_next<MJ, JC>), g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL((k_gs_dot<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL((k_gs_axpy_dot<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL((k_gs_axpy_next<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
 }
 
 // Columns j < kFixedCols run kernels instantiated for that column (exactly
 // j + 1 basis vectors, no per-vector predicates); later columns use the
 // smallest register bucket holding m vectors with a run-time column.
 constexpr int kFixedCols = 24;
-template <int... Js>
+template <typename TV, int... Js>
 static void arnoldi_fixed(const Batch& b, dim3 g, int j, hipStream_t st, std::integer_sequence<int, Js...>) {
-  (void)((j == Js ? (arnoldi_mj<Js + 1, Js>(b, g, j, st), true) : false) || ...);
+  (void)((j == Js ? (arnoldi_mj<TV, Js + 1, Js>(b, g, j, st), true) : false) || ...);
+}
+
+template <typename TV>
+static void arnoldi_t(const Batch& b, const LaunchCfg& c, dim3 g, int j, hipStream_t st) {
+  if (j < kFixedCols) arnoldi_fixed<TV>(b, g, j, st, std::make_integer_sequence<int, kFixedCols>{});
+  else if (c.m <= 32) arnoldi_mj<TV, 32, -1>(b, g, j, st);
+  else arnoldi_mj<TV, 48, -1>(b, g, j, st);
 }
 
 hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st) {
   dim3 g(red_grid(c.J, b.n) * b.n);
   if (j >= c.m || c.m > kMaxM) return hipErrorInvalidValue;
-  if (j < kFixedCols) arnoldi_fixed(b, g, j, st, std::make_integer_sequence<int, kFixedCols>{});
-  else if (c.m <= 32) arnoldi_mj<32, -1>(b, g, j, st);
-  else arnoldi_mj<48, -1>(b, g, j, st);
+  if (c.prec == 0) arnoldi_t<double>(b, c, g, j, st);
+  else arnoldi_t<float>(b, c, g, j, st);
   return hipGetLastError();
 }
 
@@ -342,6 +349,7 @@ hipError_t launch_phi1(const Batch& b, const LaunchCfg& c, hipStream_t st) {
 //   mode 0 (exponential step):   omega_M += dt beta V_k y, the time advances;
 //   mode 1 (Newton iteration):   omega_M += V_k y (y carries beta);
 //   mode 2 (last Newton iteration): as mode 1, then the time advances.
+template <typename TV>
 __global__ void __launch_bounds__(256) k_update(Batch b, int mode) {
   const SolveDev& s = MRA_SOLVE(b);
   const int k = s.ctrl[C_MEFF];
@@ -361,11 +369,11 @@ __global__ void __launch_bounds__(256) k_update(Batch b, int mode) {
   for (int i = threadIdx.x; i < k; i += blockDim.x) yy[i] = f * s.y[i];
   __syncthreads();
   bool bad = false;
-  const auto* V = glb(s.V);
+  const auto* V = glb(vbasis<TV>(s));
   auto* om = glb(s.omega);
   for (int q = MRA_BX(b) * blockDim.x + threadIdx.x; q < na; q += MRA_GX(b) * blockDim.x) {
     double t = 0.0;
-    for (int i = 0; i < k; ++i) t += yy[i] * V[i * Nf + q];
+    for (int i = 0; i < k; ++i) t += yy[i] * (double)V[i * Nf + q];
     const double nv = om[q] + t;
     bad |= !isfinite(nv);
     om[q] = nv;
@@ -380,12 +388,15 @@ static int update_grid(int J) {
 }
 
 hipError_t launch_update(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_update, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, 0);
+  if (c.prec == 0) hipLaunchKernelGGL(k_update<double>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, 0);
+  else hipLaunchKernelGGL(k_update<float>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_newton_update(const Batch& b, const LaunchCfg& c, int last, hipStream_t st) {
-  hipLaunchKernelGGL(k_update, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, last ? 2 : 1);
+  const int mode = last ? 2 : 1;
+  if (c.prec == 0) hipLaunchKernelGGL(k_update<double>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, mode);
+  else hipLaunchKernelGGL(k_update<float>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, mode);
   return hipGetLastError();
 }
 

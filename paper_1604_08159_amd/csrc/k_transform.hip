@@ -34,10 +34,10 @@ __device__ inline T* dense_target(const SolveDev& s, int target) {
 // src 1 the first Arnoldi vector F * inv (inv = 0: no basis), src 2 a caller
 // vector, src 3 the Arnoldi vector V_j, written normalised by the last
 // Gram-Schmidt stage.
-__device__ inline double active_value(const SolveDev& s, int src, int k, double inv, const double* Vj) {
+__device__ inline double active_value(const SolveDev& s, int src, int k, double inv, size_t vj) {
   if (src == 0) return glb(s.omega)[k];
   if (src == 2) return glb(s.vin)[k];
-  if (src == 3) return glb(Vj)[k];
+  if (src == 3) return vb_load(s, vj + k);
   return inv == 0.0 ? 0.0 : glb(s.w)[k] * inv;
 }
 
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
     inv = first_scale(s, 0);
     if (threadIdx.x == 0) s.scal[S_INV] = inv;
   }
-  double* Vj = s.V + (size_t)j * s.N * s.N;
+  const size_t Vj = (size_t)j * s.N * s.N;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     const int fi = packed_to_fine(i, J, j0, nullptr);
     const int sub = ((fi >> J) / S) * n + (fi & (s.N - 1)) / S;
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
       if (mode == 0) {
         const int k = s.rank[fi];
         const double v = active_value(s, src, k, inv, Vj);
-        if (src == 1 && inv != 0.0) Vj[k] = v;
+        if (src == 1 && inv != 0.0) vb_store(s, Vj + k, v);
         val[sub] = (T)v;
       } else {
         val[sub] = f[fi];
@@ -158,7 +158,7 @@ __device__ inline int lat_origin(int x0) {
 // Active nodes then take their value.
 template <int P, typename T, int J, int L>
 __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLatMax], T* half, int cur, int x0,
-                                                 int y0, int src, double inv, double* Vj, T* f) {
+                                                 int y0, int src, double inv, size_t Vj, T* f) {
 #pragma clang fp contract(off)
   constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile;
   constexpr int SH = J - L, SV = 1 << SH;  // node spacing of level L (fine units)
@@ -185,11 +185,23 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
       if ((x | y) & SV) ks[i] = rank[(y & NM) * N + (x & NM)];
     }
   }
+  // the basis (src 3) is stored in the tile precision T and loaded raw, so
+  // no conversion waits for a load before the next one is issued
   double av[SLOTS];
+  T ab[SLOTS];
+  if (src == 3) {
+    const auto* Vb = glb(vbasis<T>(s) + Vj);
 #pragma unroll
-  for (int i = 0; i < SLOTS; ++i) {
-    av[i] = 0.0;
-    if (ks[i] >= 0) av[i] = active_value(s, src, ks[i], inv, Vj);
+    for (int i = 0; i < SLOTS; ++i) {
+      ab[i] = T(0);
+      if (ks[i] >= 0) ab[i] = Vb[ks[i]];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) {
+      av[i] = 0.0;
+      if (ks[i] >= 0) av[i] = active_value(s, src, ks[i], inv, Vj);
+    }
   }
   // pass 1: level-L rows of the level-(L - 1) columns
   for (int q = threadIdx.x; q < NH; q += 256) {
@@ -228,8 +240,8 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
         v = dd_pred<P, T>(cc);
       }
       if (ks[i] >= 0) {
-        v = (T)av[i];
-        if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) glb(Vj)[ks[i]] = av[i];
+        v = src == 3 ? ab[i] : (T)av[i];
+        if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) vb_store(s, Vj + ks[i], av[i]);
       }
       if constexpr (L == J) glb(f)[(y0 + q / B) * N + x0 + (q % B)] = v;   // finest lattice = the tile
       else nxt[q] = v;
@@ -255,7 +267,7 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
   const int t = MRA_BX(b);
   const int x0 = (t % NTX) * B, y0 = (t / NTX) * B;
   T* f = dense_target<T>(s, target);
-  double* Vj = s.V + (size_t)j * N * N;
+  const size_t Vj = (size_t)j * N * N;   // offset of V_j in the basis
   const int pox = lat_origin<J, P, J0>(x0), poy = lat_origin<J, P, J0>(y0);
   // the coarsest lattice (all active, at most 256 nodes): rank and raw value
   // of this thread's node are fetched while the scale is being reduced
@@ -268,14 +280,15 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     x0n = pox + (ix << SH0);
     y0n = poy + (iy << SH0);
     k0n = glb(s.rank)[(y0n & NM) * N + (x0n & NM)];
-    raw = src == 0 ? glb(s.omega)[k0n] : (src == 2 ? glb(s.vin)[k0n] : (src == 3 ? glb(Vj)[k0n] : glb(s.w)[k0n]));
+    raw = src == 0 ? glb(s.omega)[k0n]
+                   : (src == 2 ? glb(s.vin)[k0n] : (src == 3 ? (double)glb(vbasis<T>(s))[Vj + k0n] : glb(s.w)[k0n]));
   }
   const double inv = src == 1 ? first_scale(s, t) : 0.0;
   if (has0) {
     double a = raw;
     if (src == 1) {
       a = inv == 0.0 ? 0.0 : raw * inv;
-      if (inv != 0.0 && x0n >= x0 && x0n < x0 + B && y0n >= y0 && y0n < y0 + B) glb(Vj)[k0n] = a;
+      if (inv != 0.0 && x0n >= x0 && x0n < x0 + B && y0n >= y0 && y0n < y0 + B) vb_store(s, Vj + k0n, a);
     }
     buf[0][threadIdx.x] = (T)a;
   }
@@ -362,6 +375,8 @@ static hipError_t inverse_t(const Batch& b, const LaunchCfg& c, hipStream_t st) 
 
 hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as_double, int src, int j,
                           hipStream_t st) {
+  // the basis is read in the tile precision, which must be the one it is stored in
+  if (src == 3 && (as_double != 0) != (c.prec == 0)) return hipErrorInvalidValue;
   if (as_double) return prolong_t<double>(b, c, target, src, j, st);
   return prolong_t<float>(b, c, target, src, j, st);
 }

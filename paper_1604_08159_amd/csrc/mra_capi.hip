@@ -163,7 +163,10 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.tile_count = L.take<int32_t>((size_t)s.ntx * s.ntx);
   s.block_off = L.take<int32_t>(nscan_of(s.J));
   s.omega = L.take<double>(Nf);
-  s.V = L.take<double>((size_t)(s.m + 1) * Nf);
+  s.V = nullptr;
+  s.V32 = nullptr;
+  if (s.prec == 0) s.V = L.take<double>((size_t)(s.m + 1) * Nf);
+  else s.V32 = L.take<float>((size_t)(s.m + 1) * Nf);
   s.w = L.take<double>(Nf);
   s.H = L.take<double>((size_t)(s.m + 1) * s.m);
   s.hpart = L.take<double>(2 * (kMaxM + 1));
@@ -733,7 +736,7 @@ int32_t mra_solve_ptrs_get(mra_solve h, mra_solve_ptrs* out) {
   out->index_packed = s.index_packed;
   out->index_fine = s.index_fine;
   out->n_active = s.n_active;
-  out->krylov_V = s.V;
+  out->krylov_V = s.prec == 0 ? (void*)s.V : (void*)s.V32;
   out->hessenberg = s.H;
   out->scalars = s.scal;
   out->control = s.ctrl;

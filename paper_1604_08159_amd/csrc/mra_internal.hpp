@@ -48,9 +48,10 @@ struct SolveDev {
   int64_t* n_active;        // device scalar
   int32_t* block_off;       // [nscan] compaction block counts -> offsets
   unsigned long long* umax; // bits of max|u| (non-negative doubles order as integers)
-  // Krylov (FP64)
+  // Krylov (FP64 arithmetic)
   double* omega;            // [Nf] active values
-  double* V;                // [(m+1)][Nf]
+  double* V;                // [(m+1)][Nf] basis, FP64 precision (null in mixed precision)
+  float* V32;               // [(m+1)][Nf] basis, mixed precision (null in FP64)
   double* w;                // [Nf]
   double* H;                // [(m+1)][m]
   double* hpart;            // [3][kMaxM+1] Gram-Schmidt coefficients of the current column
@@ -206,6 +207,20 @@ __host__ __device__ inline int tile_edge(int J, int p, int prec) {
 template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
   return (__attribute__((address_space(1))) T*)p;
+}
+
+// The Krylov basis is stored in the precision of the bulk fields: FP64 in
+// FP64 solves, FP32 in mixed precision (the products already take the basis
+// vectors rounded to FP32, and every sum over the basis stays FP64).
+template <typename TV> __device__ inline TV* vbasis(const SolveDev& s);
+template <> __device__ inline double* vbasis<double>(const SolveDev& s) { return s.V; }
+template <> __device__ inline float* vbasis<float>(const SolveDev& s) { return s.V32; }
+__device__ inline double vb_load(const SolveDev& s, size_t idx) {
+  return s.V32 ? (double)glb(s.V32)[idx] : glb(s.V)[idx];
+}
+__device__ inline void vb_store(const SolveDev& s, size_t idx, double v) {
+  if (s.V32) glb(s.V32)[idx] = (float)v;
+  else glb(s.V)[idx] = v;
 }
 
 // ------------------------------------------------- Krylov reductions

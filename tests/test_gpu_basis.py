@@ -4,7 +4,8 @@ column, whichever Gram-Schmidt path the column took: the second pass runs
 only where the first lost more than half of ||w||^2 (Kahan's twice-is-enough
 test), and the skipped columns must still be orthogonal to rounding level.
 The subdiagonal of the Hessenberg matrix holds the norms taken before
-normalisation, so it is positive."""
+normalisation, so it is positive.  Mixed precision stores the basis in FP32,
+so its orthonormality is checked at that precision's bar."""
 import dataclasses
 
 import numpy as np
@@ -56,11 +57,14 @@ def test_basis_orthonormal(M, case, prec):
     k = int(ctrl[0])
     assert ctrl[2] == 0 and k == m_                        # no breakdown at these sizes
     nf = s.N * s.N
-    V = s._arena_view(p.krylov_V, (m_ + 1) * nf, torch.float64).view(m_ + 1, nf)[:k, :na].cpu().numpy()
+    vdt = torch.float64 if prec == "fp64" else torch.float32     # mixed precision stores the basis in FP32
+    V = s._arena_view(p.krylov_V, (m_ + 1) * nf, vdt).view(m_ + 1, nf)[:k, :na].cpu().numpy().astype(np.float64)
     G = V @ V.T
     err = np.abs(G - np.eye(k)).max()
     print(f"  N_a {na}, max |V^T V - I| = {err:.2e}")
-    assert err <= 1e-12
+    # FP64: rounding of the Gram-Schmidt sums; FP32 storage: each entry rounded
+    # to 2^-24 relative, so an inner product of unit vectors moves by ~2^-23
+    assert err <= (1e-12 if prec == "fp64" else 1e-6)
     H = s._arena_view(p.hessenberg, (m_ + 1) * m_, torch.float64).view(m_ + 1, m_).cpu().numpy()
     sub = np.array([H[j + 1, j] for j in range(k)])
     assert np.all(np.isfinite(H[:k + 1, :k])) and np.all(sub > 0)
