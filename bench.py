@@ -373,10 +373,11 @@ def run_three(args) -> int:
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     pbs = [dataclasses.replace(W.three_vortex(), noise_seed=37440 + i) for i in range(args.batch3)]
+    prec = m.MRA_FP32 if args.prec3 == "fp32" else m.MRA_MIXED
     solves = []
     with torch.cuda.stream(stream):
         for pb in pbs:
-            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_MIXED, pb.m,
+            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m,
                                   pb.dt, torch.from_numpy(W.initial_field(pb)).to(dev), stream=stream))
     m.solve_batch(solves, [2] * len(solves), stream=stream)
     stream.synchronize()
@@ -391,7 +392,8 @@ def run_three(args) -> int:
     k_ms = m.time_kernel(solves, "jvp", 10, stream=stream)
     nbytes = kernel_bytes("jvp", N, int(sum(nas) / len(nas)), 1.0, len(solves), 4)
     print(json.dumps({"workload": f"three vortices Re=37440 + noise, finest 2048^2 (J=11), 6-point DD, eps=1e-4, "
-                                  f"m=30, dt=0.002; batch of {len(solves)}, mixed precision, {args.steps3} steps",
+                                  f"m=30, dt=0.002; batch of {len(solves)}, mixed precision"
+                                  f"{' (Krylov basis in FP32)' if args.prec3 == 'fp32' else ''}, {args.steps3} steps",
                       "metric": "active-pt RHS evals/s", "value": (ev1 - ev0) / wall,
                       "ms_per_step": wall / args.steps3 * 1e3, "mean_active_points": sum(nas) / len(nas),
                       "active_fraction": sum(nas) / len(nas) / (N * N),
@@ -536,7 +538,7 @@ def run_families(args) -> int:
     solves = []
     with torch.cuda.stream(stream):
         for pb in pbs:
-            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_MIXED, pb.m,
+            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m,
                                   pb.dt, torch.from_numpy(W.initial_field(pb)).to(dev), stream=stream))
     d0 = [s.read(dense=False, stream=stream)[1] for s in solves]
     cs = [[(v.cx, v.cy) for v in pb.vortices] for pb in pbs]
@@ -577,6 +579,8 @@ def main() -> int:
                     default="fujiwhara")
     ap.add_argument("--batch3", type=int, default=2)
     ap.add_argument("--steps3", type=int, default=10)
+    ap.add_argument("--prec3", choices=["mixed", "fp32"], default="mixed",
+                    help="three2048: fp32 stores the Krylov basis in FP32")
     ap.add_argument("--long-steps", type=int, default=2000)
     ap.add_argument("--fam-steps", type=int, default=0, help="0: up to 37.5 h")
     ap.add_argument("--spec-requests", type=int, default=40)
@@ -595,7 +599,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--prec", choices=["mixed", "fp64", "fp32"], default="mixed",
+                    help="fp32: mixed with the Krylov basis stored in FP32")
     ap.add_argument("--batch", type=int, default=len(SEEDS))
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
@@ -627,7 +632,7 @@ def main() -> int:
     import workloads as W
 
     dev = torch.device("cuda:0")
-    prec = m.MRA_MIXED if args.prec == "mixed" else m.MRA_FP64
+    prec = {"mixed": m.MRA_MIXED, "fp64": m.MRA_FP64, "fp32": m.MRA_FP32}[args.prec]
     stream = torch.cuda.Stream(device=dev)
     seeds = [SEEDS[i % len(SEEDS)] + 100 * (i // len(SEEDS)) for i in range(args.batch)]
     pbs = [W.fujiwhara_pair(s) for s in seeds]
@@ -659,7 +664,7 @@ def main() -> int:
             print(json.dumps({"error": f"solve reported status {diag['status']}"}))
             return 1
     N = 1 << pbs[0].J
-    esz = 4 if prec == m.MRA_MIXED else 8
+    esz = 8 if prec == m.MRA_FP64 else 4
 
     # dominant kernel: HIP events around back-to-back launches of the same
     # launch configuration, on the stream the step runs on
@@ -696,7 +701,7 @@ def main() -> int:
     del cal_a, cal_b, big_a, big_b
     compare = None
     accuracy = None
-    if not args.no_fp64_compare and prec == m.MRA_MIXED:
+    if not args.no_fp64_compare and prec != m.MRA_FP64:
         compare = fp64_per_solve(m, W, dev, max(10, args.steps // 10))
         accuracy = accuracy_vs_fp64(m, W, dev, solves[0], seeds[0], args.warmup + args.steps)
 
@@ -711,7 +716,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if prec == m.MRA_MIXED else "f64",
+        "dtype": "f64" if prec == m.MRA_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"Fujiwhara pair Re=5000, finest 512^2 (J=9), 4-point DD, eps=1e-4, m=20, "
                                f"dt=0.01; batch of {n} seeded solves",

@@ -62,7 +62,10 @@ enum {
 };
 
 enum { MRA_FP64 = 0, MRA_FP32 = 1, MRA_MIXED = 2 };   /* MIXED: FP32 bulk fields,
-                                                         FP64 Krylov / regrid      */
+                                                         FP64 Krylov / regrid.
+                                                         FP32 (solves): as MIXED, but
+                                                         the Krylov basis is stored
+                                                         in FP32 (its sums stay FP64) */
 enum { MRA_FORWARD = 1, MRA_INVERSE = -1, MRA_PROLONG = 2 };
 enum { MRA_EXPONENTIAL = 0, MRA_THETA_NEWTON = 1 };   /* time integrator of a solve */
 enum { MRA_JAC_FROZEN = 0, MRA_JAC_EXACT = 1 };        /* Jacobian of its Krylov products */
@@ -95,9 +98,8 @@ typedef struct {
   int32_t* index_packed;     /* [N*N], first N_a valid                           */
   int32_t* index_fine;       /* [N*N], first N_a valid                           */
   int64_t* n_active;         /* device scalar                                    */
-  void* krylov_V;            /* [(m+1)][N*N] Arnoldi basis: double in FP64 solves,
-                                float in mixed precision (the products take the
-                                basis rounded to FP32; sums over it are FP64)   */
+  void* krylov_V;            /* [(m+1)][N*N] Arnoldi basis: double, or float for
+                                precision MRA_FP32 (sums over it are FP64)      */
   double* hessenberg;        /* [(m+1)][m] FP64                                  */
   double* scalars;           /* [16] FP64: [0] beta, [2] ||A v_last||, [4] t,
                                 [5] active-point residual evaluations so far
@@ -172,7 +174,7 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
 /* ------------------------------------------------------------------------
  * Solves.  A solve keeps its whole state in a caller-owned device arena of
  * mra_solve_footprint bytes: active values (FP64), active set, Krylov basis
- * V [(m+1) x N*N] (FP64, or FP32 in mixed precision), Hessenberg matrix,
+ * V [(m+1) x N*N] (FP64, or FP32 for MRA_FP32), Hessenberg matrix,
  * dense work fields and FFT spectra.  1 <= m <= 47.
  *
  * mra_solve_init: omega0_dense (device, double [N][N]) is transformed and

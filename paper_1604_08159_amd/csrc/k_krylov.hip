@@ -1,6 +1,7 @@
 // Krylov part of the time steps, in FP64 arithmetic (the basis is stored in
-// FP32 in mixed precision): Arnoldi with classical Gram-Schmidt and a
-// selective reorthogonalisation (CGS2); for the exponential Rosenbrock-Euler
+// FP64, or in FP32 for precision MRA_FP32): Arnoldi with classical
+// Gram-Schmidt and a selective reorthogonalisation (CGS2); for the
+// exponential Rosenbrock-Euler
 // step phi_1(dt H) e_1 from the exponential of the augmented Hessenberg
 // matrix and the update omega_M += dt beta V y; for the theta-scheme the
 // Newton residual, the GMRES least squares and the Newton update.
@@ -261,8 +262,8 @@ static void arnoldi_t(const Batch& b, const LaunchCfg& c, dim3 g, int j, hipStre
 hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st) {
   dim3 g(red_grid(c.J, b.n) * b.n);
   if (j >= c.m || c.m > kMaxM) return hipErrorInvalidValue;
-  if (c.prec == 0) arnoldi_t<double>(b, c, g, j, st);
-  else arnoldi_t<float>(b, c, g, j, st);
+  if (c.vb) arnoldi_t<float>(b, c, g, j, st);
+  else arnoldi_t<double>(b, c, g, j, st);
   return hipGetLastError();
 }
 
@@ -388,14 +389,14 @@ static int update_grid(int J) {
 }
 
 hipError_t launch_update(const Batch& b, const LaunchCfg& c, hipStream_t st) {
-  if (c.prec == 0) hipLaunchKernelGGL(k_update<double>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, 0);
+  if (!c.vb) hipLaunchKernelGGL(k_update<double>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, 0);
   else hipLaunchKernelGGL(k_update<float>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_newton_update(const Batch& b, const LaunchCfg& c, int last, hipStream_t st) {
   const int mode = last ? 2 : 1;
-  if (c.prec == 0) hipLaunchKernelGGL(k_update<double>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, mode);
+  if (!c.vb) hipLaunchKernelGGL(k_update<double>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, mode);
   else hipLaunchKernelGGL(k_update<float>, dim3(update_grid(c.J) * b.n), dim3(256), 0, st, b, mode);
   return hipGetLastError();
 }

@@ -11,6 +11,8 @@
 // samples), so one launch covers every packed position.  The prolongation is
 // sequential in the level: the levels up to kCoarseLevels are done by one
 // workgroup per solve, finer levels by one launch each.
+#include <type_traits>
+
 #include "mra_internal.hpp"
 
 namespace mra {
@@ -33,12 +35,22 @@ __device__ inline T* dense_target(const SolveDev& s, int target) {
 // The value of active node k in the prolongation of: src 0 the state omega,
 // src 1 the first Arnoldi vector F * inv (inv = 0: no basis), src 2 a caller
 // vector, src 3 the Arnoldi vector V_j, written normalised by the last
-// Gram-Schmidt stage.
-__device__ inline double active_value(const SolveDev& s, int src, int k, double inv, size_t vj) {
+// Gram-Schmidt stage.  Vd is V_j of an FP64 basis; callers read a basis stored
+// in FP32 (Vf) themselves.  Both pointers are taken once per kernel, so no
+// descriptor load is repeated after a store.
+__device__ inline double active_value(const SolveDev& s, int src, int k, double inv, const double* Vd) {
   if (src == 0) return glb(s.omega)[k];
   if (src == 2) return glb(s.vin)[k];
-  if (src == 3) return vb_load(s, vj + k);
+  if (src == 3) return glb(Vd)[k];
   return inv == 0.0 ? 0.0 : glb(s.w)[k] * inv;
+}
+// entry k of V_j, whichever precision the basis is stored in
+__device__ inline double basis_value(const double* Vd, const float* Vf, int k) {
+  return Vf ? (double)glb(Vf)[k] : glb(Vd)[k];
+}
+__device__ inline void basis_store(double* Vd, float* Vf, int k, double v) {
+  if (Vf) glb(Vf)[k] = (float)v;
+  else glb(Vd)[k] = v;
 }
 
 // ---------------------------------------------------------------- prolong
@@ -78,7 +90,8 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
     inv = first_scale(s, 0);
     if (threadIdx.x == 0) s.scal[S_INV] = inv;
   }
-  const size_t Vj = (size_t)j * s.N * s.N;
+  double* Vd = s.V ? s.V + (size_t)j * s.N * s.N : nullptr;
+  float* Vf = s.V32 ? s.V32 + (size_t)j * s.N * s.N : nullptr;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     const int fi = packed_to_fine(i, J, j0, nullptr);
     const int sub = ((fi >> J) / S) * n + (fi & (s.N - 1)) / S;
@@ -87,8 +100,8 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
     if (a) {
       if (mode == 0) {
         const int k = s.rank[fi];
-        const double v = active_value(s, src, k, inv, Vj);
-        if (src == 1 && inv != 0.0) vb_store(s, Vj + k, v);
+        const double v = src == 3 ? basis_value(Vd, Vf, k) : active_value(s, src, k, inv, Vd);
+        if (src == 1 && inv != 0.0) basis_store(Vd, Vf, k, v);
         val[sub] = (T)v;
       } else {
         val[sub] = f[fi];
@@ -156,9 +169,9 @@ __device__ inline int lat_origin(int x0) {
 // get the x-prediction of the y-predictions, the canonical order, and every
 // y-prediction is computed once per column instead of once per neighbour.
 // Active nodes then take their value.
-template <int P, typename T, int J, int L>
+template <int P, typename T, int J, int L, bool FB>
 __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLatMax], T* half, int cur, int x0,
-                                                 int y0, int src, double inv, size_t Vj, T* f) {
+                                                 int y0, int src, double inv, double* Vd, float* Vf, T* f) {
 #pragma clang fp contract(off)
   constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile;
   constexpr int SH = J - L, SV = 1 << SH;  // node spacing of level L (fine units)
@@ -185,22 +198,23 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
       if ((x | y) & SV) ks[i] = rank[(y & NM) * N + (x & NM)];
     }
   }
-  // the basis (src 3) is stored in the tile precision T and loaded raw, so
-  // no conversion waits for a load before the next one is issued
+  // FB: the basis is stored in FP32 (precision MRA_FP32).  For src 3 its
+  // entries are loaded raw, so that no conversion waits for a load before the
+  // next one is issued
   double av[SLOTS];
-  T ab[SLOTS];
-  if (src == 3) {
-    const auto* Vb = glb(vbasis<T>(s) + Vj);
+  float af[SLOTS];
+  if (FB && src == 3) {
+    const auto* Vb = glb(Vf);
 #pragma unroll
     for (int i = 0; i < SLOTS; ++i) {
-      ab[i] = T(0);
-      if (ks[i] >= 0) ab[i] = Vb[ks[i]];
+      af[i] = 0.0f;
+      if (ks[i] >= 0) af[i] = Vb[ks[i]];
     }
   } else {
 #pragma unroll
     for (int i = 0; i < SLOTS; ++i) {
       av[i] = 0.0;
-      if (ks[i] >= 0) av[i] = active_value(s, src, ks[i], inv, Vj);
+      if (ks[i] >= 0) av[i] = active_value(s, src, ks[i], inv, Vd);
     }
   }
   // pass 1: level-L rows of the level-(L - 1) columns
@@ -240,8 +254,11 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
         v = dd_pred<P, T>(cc);
       }
       if (ks[i] >= 0) {
-        v = src == 3 ? ab[i] : (T)av[i];
-        if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) vb_store(s, Vj + ks[i], av[i]);
+        v = (FB && src == 3) ? (T)af[i] : (T)av[i];
+        if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) {
+          if constexpr (FB) glb(Vf)[ks[i]] = (float)av[i];
+          else glb(Vd)[ks[i]] = av[i];
+        }
       }
       if constexpr (L == J) glb(f)[(y0 + q / B) * N + x0 + (q % B)] = v;   // finest lattice = the tile
       else nxt[q] = v;
@@ -249,11 +266,11 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
   }
   if constexpr (L < J) {
     __syncthreads();
-    prolong_level_ct<P, T, J, L + 1>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vj, f);
+    prolong_level_ct<P, T, J, L + 1, FB>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vd, Vf, f);
   }
 }
 
-template <int P, typename T, int J>
+template <int P, typename T, int J, bool FB>
 __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int src, int j) {
 #pragma clang fp contract(off)
   constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile, NTX = N / B;
@@ -267,7 +284,8 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
   const int t = MRA_BX(b);
   const int x0 = (t % NTX) * B, y0 = (t / NTX) * B;
   T* f = dense_target<T>(s, target);
-  const size_t Vj = (size_t)j * N * N;   // offset of V_j in the basis
+  double* Vd = s.V ? s.V + (size_t)j * N * N : nullptr;      // V_j, FP64 basis
+  float* Vf = s.V32 ? s.V32 + (size_t)j * N * N : nullptr;   // V_j, FP32 basis
   const int pox = lat_origin<J, P, J0>(x0), poy = lat_origin<J, P, J0>(y0);
   // the coarsest lattice (all active, at most 256 nodes): rank and raw value
   // of this thread's node are fetched while the scale is being reduced
@@ -281,19 +299,23 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     y0n = poy + (iy << SH0);
     k0n = glb(s.rank)[(y0n & NM) * N + (x0n & NM)];
     raw = src == 0 ? glb(s.omega)[k0n]
-                   : (src == 2 ? glb(s.vin)[k0n] : (src == 3 ? (double)glb(vbasis<T>(s))[Vj + k0n] : glb(s.w)[k0n]));
+                   : (src == 2 ? glb(s.vin)[k0n]
+                               : (src == 3 ? (FB ? (double)glb(Vf)[k0n] : glb(Vd)[k0n]) : glb(s.w)[k0n]));
   }
   const double inv = src == 1 ? first_scale(s, t) : 0.0;
   if (has0) {
     double a = raw;
     if (src == 1) {
       a = inv == 0.0 ? 0.0 : raw * inv;
-      if (inv != 0.0 && x0n >= x0 && x0n < x0 + B && y0n >= y0 && y0n < y0 + B) vb_store(s, Vj + k0n, a);
+      if (inv != 0.0 && x0n >= x0 && x0n < x0 + B && y0n >= y0 && y0n < y0 + B) {
+        if constexpr (FB) glb(Vf)[k0n] = (float)a;
+        else glb(Vd)[k0n] = a;
+      }
     }
     buf[0][threadIdx.x] = (T)a;
   }
   __syncthreads();
-  prolong_level_ct<P, T, J, J0 + 1>(s, buf, half, 0, x0, y0, src, inv, Vj, f);
+  prolong_level_ct<P, T, J, J0 + 1, FB>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f);
 }
 
 template <int P, typename T>
@@ -328,33 +350,44 @@ static bool lattice_fits(int J, int P) {
   return true;
 }
 
-template <int P, typename T, int J>
+template <int P, typename T, int J, bool FB>
 static void prolong_j(const Batch& b, int target, int src, int j, hipStream_t st) {
   constexpr int N = 1 << J, B = N < kFineTile ? N : kFineTile;
-  hipLaunchKernelGGL((k_prolong_tiles<P, T, J>), dim3((N / B) * (N / B) * b.n), dim3(256), 0, st, b, target, src, j);
+  hipLaunchKernelGGL((k_prolong_tiles<P, T, J, FB>), dim3((N / B) * (N / B) * b.n), dim3(256), 0, st, b, target,
+                     src, j);
 }
 
-template <int P, typename T>
+template <int P, typename T, bool FB>
 static hipError_t prolong_p(const Batch& b, int J, int target, int src, int j, hipStream_t st) {
   switch (J) {
-    case 3: if constexpr (P == 2) { prolong_j<P, T, 3>(b, target, src, j, st); break; } return hipErrorInvalidValue;
-    case 4: prolong_j<P, T, 4>(b, target, src, j, st); break;
-    case 5: prolong_j<P, T, 5>(b, target, src, j, st); break;
-    case 6: prolong_j<P, T, 6>(b, target, src, j, st); break;
-    case 7: prolong_j<P, T, 7>(b, target, src, j, st); break;
-    case 8: prolong_j<P, T, 8>(b, target, src, j, st); break;
-    case 9: prolong_j<P, T, 9>(b, target, src, j, st); break;
-    case 10: prolong_j<P, T, 10>(b, target, src, j, st); break;
-    case 11: prolong_j<P, T, 11>(b, target, src, j, st); break;
+    case 3: if constexpr (P == 2) { prolong_j<P, T, 3, FB>(b, target, src, j, st); break; } return hipErrorInvalidValue;
+    case 4: prolong_j<P, T, 4, FB>(b, target, src, j, st); break;
+    case 5: prolong_j<P, T, 5, FB>(b, target, src, j, st); break;
+    case 6: prolong_j<P, T, 6, FB>(b, target, src, j, st); break;
+    case 7: prolong_j<P, T, 7, FB>(b, target, src, j, st); break;
+    case 8: prolong_j<P, T, 8, FB>(b, target, src, j, st); break;
+    case 9: prolong_j<P, T, 9, FB>(b, target, src, j, st); break;
+    case 10: prolong_j<P, T, 10, FB>(b, target, src, j, st); break;
+    case 11: prolong_j<P, T, 11, FB>(b, target, src, j, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// The Arnoldi vectors (src 1 writes V_0, src 3 reads V_j) of a basis stored
+// in FP32 take the FB kernels, which exist for FP32 tiles (the precision of
+// such solves).
 template <typename T>
 static hipError_t prolong_t(const Batch& b, const LaunchCfg& c, int target, int src, int j, hipStream_t st) {
   if (!lattice_fits(c.J, c.p)) return hipErrorInvalidValue;
-  return c.p == 2 ? prolong_p<2, T>(b, c.J, target, src, j, st) : prolong_p<3, T>(b, c.J, target, src, j, st);
+  if ((src == 1 || src == 3) && c.vb) {
+    if constexpr (std::is_same<T, float>::value)
+      return c.p == 2 ? prolong_p<2, T, true>(b, c.J, target, src, j, st)
+                      : prolong_p<3, T, true>(b, c.J, target, src, j, st);
+    return hipErrorInvalidValue;
+  }
+  return c.p == 2 ? prolong_p<2, T, false>(b, c.J, target, src, j, st)
+                  : prolong_p<3, T, false>(b, c.J, target, src, j, st);
 }
 
 // inverse transform: coarse copy, coarse kernel, one launch per finer level
@@ -375,8 +408,6 @@ static hipError_t inverse_t(const Batch& b, const LaunchCfg& c, hipStream_t st) 
 
 hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as_double, int src, int j,
                           hipStream_t st) {
-  // the basis is read in the tile precision, which must be the one it is stored in
-  if (src == 3 && (as_double != 0) != (c.prec == 0)) return hipErrorInvalidValue;
   if (as_double) return prolong_t<double>(b, c, target, src, j, st);
   return prolong_t<float>(b, c, target, src, j, st);
 }

@@ -93,6 +93,7 @@ void fill_geometry(SolveDev& s, const mra_grid_desc* g, int32_t prec) {
   s.p = g->p;
   s.N = 1 << g->J;
   s.prec = prec_bulk(prec);
+  s.vb32 = prec == MRA_FP32;
   s.adjacent_zone = g->adjacent_zone;
   s.tile = tile_edge(s.J, s.p, s.prec);
   s.ntx = s.N / s.tile;
@@ -165,8 +166,8 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.omega = L.take<double>(Nf);
   s.V = nullptr;
   s.V32 = nullptr;
-  if (s.prec == 0) s.V = L.take<double>((size_t)(s.m + 1) * Nf);
-  else s.V32 = L.take<float>((size_t)(s.m + 1) * Nf);
+  if (s.vb32) s.V32 = L.take<float>((size_t)(s.m + 1) * Nf);
+  else s.V = L.take<double>((size_t)(s.m + 1) * Nf);
   s.w = L.take<double>(Nf);
   s.H = L.take<double>((size_t)(s.m + 1) * s.m);
   s.hpart = L.take<double>(2 * (kMaxM + 1));
@@ -499,6 +500,7 @@ int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t p
   solve_layout(L, s);
   h->dev = reinterpret_cast<SolveDev*>(arena);
   h->cfg = LaunchCfg{s.J, s.p, s.prec, m};
+  h->cfg.vb = s.vb32;
   (void)hipGetDevice(&h->device);
   h->diag_rows.resize((size_t)s.N * 5);
   const size_t Nf = (size_t)s.N * s.N;
@@ -611,11 +613,11 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
   for (int t = 0; t < maxs; ++t) {
     // group the solves still running by launch configuration
     // (vorticity solves first: a scalar's step reads its partner's step)
-    std::map<std::tuple<int, int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
+    std::map<std::tuple<int, int, int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > t) {
         const LaunchCfg& c = solves[i]->cfg;
-        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton, c.jac)].push_back(solves[i]);
+        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton, c.jac, c.vb)].push_back(solves[i]);
       }
     for (auto& kv : groups) {
       auto& v = kv.second;
@@ -736,7 +738,7 @@ int32_t mra_solve_ptrs_get(mra_solve h, mra_solve_ptrs* out) {
   out->index_packed = s.index_packed;
   out->index_fine = s.index_fine;
   out->n_active = s.n_active;
-  out->krylov_V = s.prec == 0 ? (void*)s.V : (void*)s.V32;
+  out->krylov_V = s.vb32 ? (void*)s.V32 : (void*)s.V;
   out->hessenberg = s.H;
   out->scalars = s.scal;
   out->control = s.ctrl;
@@ -817,7 +819,7 @@ int32_t mra_time_kernel(mra_solve* solves, int32_t n, int32_t which, int32_t rep
     if (!solves[i]) return MRA_E_ARG;
     const LaunchCfg& c0 = solves[0]->cfg;
     const LaunchCfg& ci = solves[i]->cfg;
-    if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m) return MRA_E_ARG;
+    if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m || ci.vb != c0.vb) return MRA_E_ARG;
     b.s[i] = solves[i]->dev;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -33,6 +33,7 @@ struct SolveDev {
   // geometry / numbers
   int J, j0, p, N;
   int prec;                 // 0 -> double bulk fields, 1 -> float bulk fields
+  int vb32;                 // 1 -> Krylov basis stored in FP32 (precision MRA_FP32)
   int m;                    // Krylov dimension
   int adjacent_zone;
   int smag_mode;
@@ -50,8 +51,8 @@ struct SolveDev {
   unsigned long long* umax; // bits of max|u| (non-negative doubles order as integers)
   // Krylov (FP64 arithmetic)
   double* omega;            // [Nf] active values
-  double* V;                // [(m+1)][Nf] basis, FP64 precision (null in mixed precision)
-  float* V32;               // [(m+1)][Nf] basis, mixed precision (null in FP64)
+  double* V;                // [(m+1)][Nf] basis in FP64 (null when stored in FP32)
+  float* V32;               // [(m+1)][Nf] basis in FP32, precision MRA_FP32 only (else null)
   double* w;                // [Nf]
   double* H;                // [(m+1)][m]
   double* hpart;            // [3][kMaxM+1] Gram-Schmidt coefficients of the current column
@@ -209,19 +210,12 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
-// The Krylov basis is stored in the precision of the bulk fields: FP64 in
-// FP64 solves, FP32 in mixed precision (the products already take the basis
-// vectors rounded to FP32, and every sum over the basis stays FP64).
+// The Krylov basis is stored in FP64, or in FP32 for solves of precision
+// MRA_FP32 (every sum over it stays FP64 either way; the FP32 products take
+// the basis vectors rounded to FP32 in both cases).
 template <typename TV> __device__ inline TV* vbasis(const SolveDev& s);
 template <> __device__ inline double* vbasis<double>(const SolveDev& s) { return s.V; }
 template <> __device__ inline float* vbasis<float>(const SolveDev& s) { return s.V32; }
-__device__ inline double vb_load(const SolveDev& s, size_t idx) {
-  return s.V32 ? (double)glb(s.V32)[idx] : glb(s.V)[idx];
-}
-__device__ inline void vb_store(const SolveDev& s, size_t idx, double v) {
-  if (s.V32) glb(s.V32)[idx] = (float)v;
-  else glb(s.V)[idx] = v;
-}
 
 // ------------------------------------------------- Krylov reductions
 constexpr double kBreakdown = 1e-13;
@@ -341,6 +335,7 @@ struct LaunchCfg {
   int integ = 0;  // 0 exponential Rosenbrock-Euler, 1 theta-scheme by Newton-GMRES
   int newton = 0; // Newton iterations per step (integ 1)
   int jac = 0;    // Jacobian of the Krylov products: 0 eddy viscosity frozen, 1 exact
+  int vb = 0;     // Krylov basis stored in FP32 (precision MRA_FP32); FP64 otherwise
 };
 
 hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);

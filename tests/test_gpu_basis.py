@@ -4,8 +4,9 @@ column, whichever Gram-Schmidt path the column took: the second pass runs
 only where the first lost more than half of ||w||^2 (Kahan's twice-is-enough
 test), and the skipped columns must still be orthogonal to rounding level.
 The subdiagonal of the Hessenberg matrix holds the norms taken before
-normalisation, so it is positive.  Mixed precision stores the basis in FP32,
-so its orthonormality is checked at that precision's bar."""
+normalisation, so it is positive.  Precision MRA_FP32 stores the basis in
+FP32, so its orthonormality is checked at that precision's bar, and its steps
+are checked against the FP64 oracle at the mixed-precision bar."""
 import dataclasses
 
 import numpy as np
@@ -13,6 +14,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import krylov as ok, mra as om, ops as oo
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -35,13 +37,16 @@ CASES = {
 }
 
 
+PRECS = {"fp64": "MRA_FP64", "mixed": "MRA_MIXED", "fp32": "MRA_FP32"}
+
+
 @pytest.mark.parametrize("case", sorted(CASES))
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", sorted(PRECS))
 def test_basis_orthonormal(M, case, prec):
     pb = CASES[case]()
     m_ = 30
     w0 = W.initial_field(pb)
-    pr = M.MRA_FP64 if prec == "fp64" else M.MRA_MIXED
+    pr = getattr(M, PRECS[prec])
     s = M.Solve(M.grid_desc(pb.J, pb.p, pb.eps), M.flow_desc(pb.nu0, pb.cs), pr, m_, pb.dt,
                 torch.from_numpy(w0).to(DEV))
     print(f"{case} {prec}: 2 steps, m = {m_}", flush=True)
@@ -57,15 +62,39 @@ def test_basis_orthonormal(M, case, prec):
     k = int(ctrl[0])
     assert ctrl[2] == 0 and k == m_                        # no breakdown at these sizes
     nf = s.N * s.N
-    vdt = torch.float64 if prec == "fp64" else torch.float32     # mixed precision stores the basis in FP32
+    vdt = torch.float32 if prec == "fp32" else torch.float64     # MRA_FP32 stores the basis in FP32
     V = s._arena_view(p.krylov_V, (m_ + 1) * nf, vdt).view(m_ + 1, nf)[:k, :na].cpu().numpy().astype(np.float64)
     G = V @ V.T
     err = np.abs(G - np.eye(k)).max()
     print(f"  N_a {na}, max |V^T V - I| = {err:.2e}")
-    # FP64: rounding of the Gram-Schmidt sums; FP32 storage: each entry rounded
-    # to 2^-24 relative, so an inner product of unit vectors moves by ~2^-23
-    assert err <= (1e-12 if prec == "fp64" else 1e-6)
+    # FP64 storage: rounding of the Gram-Schmidt sums; FP32 storage: each entry
+    # rounded to 2^-24 relative, so an inner product of unit vectors moves by ~2^-23
+    assert err <= (1e-6 if prec == "fp32" else 1e-12)
     H = s._arena_view(p.hessenberg, (m_ + 1) * m_, torch.float64).view(m_ + 1, m_).cpu().numpy()
     sub = np.array([H[j + 1, j] for j in range(k)])
     assert np.all(np.isfinite(H[:k + 1, :k])) and np.all(sub > 0)
     s.close()
+
+
+def test_fp32_basis_steps_match_oracle(M):
+    """Two steps of a 512^2 Fujiwhara solve with the basis stored in FP32
+    against the FP64 oracle, at the mixed-precision bar (1e-5 relative L2)."""
+    pb = W.fujiwhara_pair(1000)
+    w0 = W.initial_field(pb)
+    out = {}
+    for name in ("MRA_MIXED", "MRA_FP32"):
+        s = M.Solve(M.grid_desc(pb.J, pb.p, pb.eps), M.flow_desc(pb.nu0, pb.cs), getattr(M, name), pb.m, pb.dt,
+                    torch.from_numpy(w0).to(DEV))
+        s.step(2)
+        out[name] = s.read()[0].cpu().numpy()
+        s.close()
+    g = ok.Grid(J=pb.J, p=pb.p, eps=pb.eps)
+    fl = oo.Flow(nu0=pb.nu0, cs=pb.cs)
+    st = ok.init_state(w0, g)
+    for _ in range(2):
+        st = ok.step(st, g, fl, pb.m, pb.dt)
+    ref = om.prolong(st.omega_M, st.index_fine, pb.J, pb.p)
+    for name, d in out.items():
+        rel = np.linalg.norm(d - ref) / np.linalg.norm(ref)
+        print(f"{name}: 2 steps at 512^2 vs the FP64 oracle, rel L2 {rel:.2e}")
+        assert rel <= 1e-5
