@@ -80,8 +80,70 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   }
 }
 
-// Stage 2: h1 from A; w1 = w - V_j h1 (not stored); h2 = V_j^T w1 and
-// ||w1||^2 partials (buffer B).
+// End of column j, shared by stages 2 and 3.  h1 holds the first-pass
+// coefficients; h holds the second-pass ones h2 (zeros when the pass was
+// skipped) and ||w1||^2 at j + 1; nav = ||A v_j||.  h_{j+1,j} comes from
+// Pythagoras, ||w1||^2 - ||h2||^2 (V_j orthonormal, h2 = V_j^T w1), before
+// the update, so V_{j+1} = (w - V_j h1 - V_j h2) / h_{j+1,j} is written
+// normalised in one pass (w1 is rebuilt from w with the same operations in
+// the same order as the second pass took them).  In CGS2 h2 is a
+// rounding-level correction, so no cancellation arises.  A breakdown
+// (h_{j+1,j} <= 1e-13 ||A v_j||) or a non-finite value ends the basis.
+// Block 0 writes column j of H and the control words.
+template <typename TV, int MJ, bool REORTH>
+__device__ __forceinline__ void gs_finish(const Batch& b, const SolveDev& s, int j, int na, int nb,
+                                          const double* h1, const double* h, double nav, double* inv_sh) {
+  if (threadIdx.x == 0) {
+    double h2sq = 0.0;
+    for (int i = 0; i <= j; ++i) h2sq += h[i] * h[i];
+    const double nrm = sqrt(fmax(h[j + 1] - h2sq, 0.0));
+    const bool bad = !isfinite(nrm) || !isfinite(nav);
+    const bool brk = bad || nrm <= kBreakdown * nav;
+    *inv_sh = brk ? 0.0 : 1.0 / nrm;
+    if (MRA_BX(b) == 0) {
+      s.H[(j + 1) * s.m + j] = nrm;
+      if (bad) { s.ctrl[C_STATUS] = 5; s.ctrl[C_MEFF] = 0; }
+      else if (brk) s.ctrl[C_MEFF] = j + 1;
+      if (brk) s.ctrl[C_DONE] = 1;
+    }
+  }
+  __syncthreads();
+  if (MRA_BX(b) == 0)
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) s.H[i * s.m + j] = h1[i] + h[i];
+  if (j + 1 >= s.m) return;          // the last column: no further basis vector
+  const double inv = *inv_sh;
+  const size_t Nf = (size_t)s.N * s.N;
+  const auto* W = glb(s.w);
+  const auto* V = glb(vbasis<TV>(s));
+  auto* Vn = glb(vbasis<TV>(s) + (size_t)(j + 1) * Nf);
+  for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
+    const Chunk c = chunk_of(na, ch);
+    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
+      double t = W[k];
+      TV v[MJ];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) v[i] = V[i * Nf + k];
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i <= j) t -= h1[i] * (double)v[i];
+      if constexpr (REORTH) {
+#pragma unroll
+        for (int i = 0; i < MJ; ++i)
+          if (i <= j) t -= h[i] * (double)v[i];
+      }
+      Vn[k] = (TV)(inv == 0.0 ? 0.0 : t * inv);
+    }
+  }
+}
+
+// Stage 2: h1 and ||w||^2 from A.  Selective reorthogonalisation ("twice is
+// enough"): when the first pass keeps at least half of ||w||^2, w1 = w - V_j h1
+// is orthogonal to V_j to rounding, ||w1||^2 = ||w||^2 - ||h1||^2 has no
+// cancellation, and the stage ends the column itself (h2 = 0).  Otherwise it
+// takes the second pass: h2 = V_j^T w1 and ||w1||^2 partials (buffer B), and
+// stage 3 ends the column.  Every block takes the same decision from the same
+// sums, so no block signals another.
 template <typename TV, int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
@@ -91,24 +153,28 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
   const int nb = nchunks(na);
   if ((int)MRA_BX(b) >= nb) return;
   __shared__ double h[kMaxM + 2];
+  __shared__ double z[kMaxM + 2];
+  __shared__ double inv_sh;
   reduce_partials(part_buf(s, 0), nb, j + 2, h);
-  // selective reorthogonalisation ("twice is enough"): when the first pass
-  // keeps at least half of ||w||^2, w1 is orthogonal to V_j to rounding and
-  // the second pass is skipped; ||w1||^2 = ||w||^2 - ||h1||^2 has no
-  // cancellation in that case.  Every block takes the same decision.
   double h1sq = 0.0;
   for (int i = 0; i <= j; ++i) h1sq += h[i] * h[i];
   const double w1sq = h[j + 1] - h1sq;
   const bool once = w1sq >= 0.5 * h[j + 1];
+  const double nav = sqrt(h[j + 1]);
   if (MRA_BX(b) == 0) {
     for (int i = threadIdx.x; i <= j; i += blockDim.x) s.hpart[i] = h[i];
     if (threadIdx.x == 0) {
-      s.scal[S_NRMAV] = sqrt(h[j + 1]);
-      s.scal[S_W1SQ] = w1sq;
+      s.scal[S_NRMAV] = nav;
       s.ctrl[C_REORTH] = once ? 0 : 1;
     }
   }
-  if (once) return;
+  if (once) {
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) z[i] = 0.0;
+    if (threadIdx.x == 0) z[j + 1] = w1sq;
+    __syncthreads();
+    gs_finish<TV, MJ, false>(b, s, j, na, nb, h, z, nav, &inv_sh);
+    return;
+  }
   const size_t Nf = (size_t)s.N * s.N;
   auto* W = glb(s.w);
   const auto* V = glb(vbasis<TV>(s));
@@ -131,7 +197,7 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
         if (i <= j) acc[i] += (double)v[i] * t;
       acc[MJ] += t * t;
     }
-    // slot layout: h2[0 .. j], then ||w||^2 at j + 1 (static register indices)
+    // slot layout: h2[0 .. j], then ||w1||^2 at j + 1 (static register indices)
 #pragma unroll
     for (int i = 0; i < MJ; ++i)
       if (i == j + 1) acc[i] = acc[MJ];
@@ -140,80 +206,23 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
   }
 }
 
-// Stage 3: h2 and ||w1||^2 from B; H[:j+1, j] = h1 + h2; the next basis
-// vector V_{j+1} = (w1 - V_j h2) / h_{j+1,j}.  The norm of w1 - V_j h2 is taken
-// from Pythagoras, ||w1||^2 - ||h2||^2 (V_j orthonormal, h2 = V_j^T w1), before the
-// update, so the stage writes V_{j+1} normalised in the same pass.  In CGS2
-// h2 is a rounding-level correction, so no cancellation arises.  When stage 2
-// found the second pass unnecessary (C_REORTH = 0), h2 = 0 and only h1 is
-// applied.  A breakdown
-// (h_{j+1,j} <= 1e-13 ||A v_j||) or a non-finite value ends the basis.
+// Stage 3, only where stage 2 took the second pass (C_REORTH = 1): h2 and
+// ||w1||^2 from B, then the end of the column.
 template <typename TV, int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
-  if (s.ctrl[C_DONE]) return;
+  if (s.ctrl[C_DONE] || !s.ctrl[C_REORTH]) return;
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
   if ((int)MRA_BX(b) >= nb) return;
   __shared__ double h[kMaxM + 2];
-  __shared__ double inv_sh;
-  const bool reorth = s.ctrl[C_REORTH] != 0;
-  if (reorth) {
-    reduce_partials(part_buf(s, 1), nb, j + 2, h);
-  } else {                           // one pass sufficed: h2 = 0, ||w1||^2 from stage 2
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) h[i] = 0.0;
-    if (threadIdx.x == 0) h[j + 1] = s.scal[S_W1SQ];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double h2sq = 0.0;
-    for (int i = 0; i <= j; ++i) h2sq += h[i] * h[i];
-    const double nrm = sqrt(fmax(h[j + 1] - h2sq, 0.0));
-    const double nav = s.scal[S_NRMAV];
-    const bool bad = !isfinite(nrm) || !isfinite(nav);
-    const bool brk = bad || nrm <= kBreakdown * nav;
-    inv_sh = brk ? 0.0 : 1.0 / nrm;
-    if (MRA_BX(b) == 0) {
-      s.H[(j + 1) * s.m + j] = nrm;
-      if (bad) { s.ctrl[C_STATUS] = 5; s.ctrl[C_MEFF] = 0; }
-      else if (brk) s.ctrl[C_MEFF] = j + 1;
-      if (brk) s.ctrl[C_DONE] = 1;
-    }
-  }
-  __syncthreads();
-  if (MRA_BX(b) == 0)
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) s.H[i * s.m + j] = s.hpart[i] + h[i];
-  if (j + 1 >= s.m) return;          // the last column: no further basis vector
-  const double inv = inv_sh;
-  const size_t Nf = (size_t)s.N * s.N;
-  const auto* W = glb(s.w);
-  const auto* V = glb(vbasis<TV>(s));
-  auto* Vn = glb(vbasis<TV>(s) + (size_t)(j + 1) * Nf);
-  // the once-orthogonalised w1 is rebuilt from w with h1 (the same operations
-  // in the same order as stage 2), so stage 2 need not store it
   __shared__ double h1[kMaxM + 2];
+  __shared__ double inv_sh;
+  reduce_partials(part_buf(s, 1), nb, j + 2, h);
   for (int i = threadIdx.x; i <= j; i += blockDim.x) h1[i] = s.hpart[i];
   __syncthreads();
-  for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
-    const Chunk c = chunk_of(na, ch);
-    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
-      double t = W[k];
-      TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
-#pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i <= j) v[i] = V[i * Nf + k];
-#pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i <= j) t -= h1[i] * (double)v[i];
-      if (reorth) {
-#pragma unroll
-        for (int i = 0; i < MJ; ++i)
-          if (i <= j) t -= h[i] * (double)v[i];
-      }
-      Vn[k] = (TV)(inv == 0.0 ? 0.0 : t * inv);
-    }
-  }
+  gs_finish<TV, MJ, true>(b, s, j, na, nb, h1, h, s.scal[S_NRMAV], &inv_sh);
 }
 
 // Grid of the reductions, blocks per solve (blocks loop over chunks): at
