@@ -169,35 +169,62 @@ __device__ inline int lat_origin(int x0) {
 // get the x-prediction of the y-predictions, the canonical order, and every
 // y-prediction is computed once per column instead of once per neighbour.
 // Active nodes then take their value.
+// Ranks of this thread's nodes of level L that are new at L (-1 for the
+// nodes of coarser levels and for slots past the lattice).
+template <int S> struct Ranks {
+  int k[S];
+};
+template <int J, int P, int L>
+__host__ __device__ constexpr int lat_slots() {
+  constexpr int B = (1 << J) < kFineTile ? (1 << J) : kFineTile;
+  constexpr int n = lat_count(J, P, B, 0, L);
+  return (n * n + 255) / 256;
+}
+template <int J, int P, int L>
+__device__ __forceinline__ Ranks<lat_slots<J, P, L>()> level_ranks(const SolveDev& s, int x0, int y0) {
+  constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile;
+  constexpr int SH = J - L, SV = 1 << SH;
+  constexpr int n = lat_count(J, P, B, 0, L), NN = n * n, SLOTS = lat_slots<J, P, L>();
+  const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
+  const auto* __restrict__ rank = glb(s.rank);
+  Ranks<SLOTS> r;
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    r.k[i] = -1;
+    if (q < NN) {
+      const int iy = q / n, ix = q - iy * n;
+      const int x = ox + (ix << SH), y = oy + (iy << SH);
+      if ((x | y) & SV) r.k[i] = rank[(y & NM) * N + (x & NM)];
+    }
+  }
+  return r;
+}
+
+// kin: this level's ranks, loaded while the previous level was swept; the
+// ranks of the next level are loaded here in turn, so a rank load is never
+// on the path between two levels.
 template <int P, typename T, int J, int L, bool FB>
 __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLatMax], T* half, int cur, int x0,
-                                                 int y0, int src, double inv, double* Vd, float* Vf, T* f) {
+                                                 int y0, int src, double inv, double* Vd, float* Vf, T* f,
+                                                 const Ranks<lat_slots<J, P, L>()>& kin) {
 #pragma clang fp contract(off)
-  constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile;
+  constexpr int N = 1 << J, B = N < kFineTile ? N : kFineTile;
   constexpr int SH = J - L, SV = 1 << SH;  // node spacing of level L (fine units)
   constexpr int n = lat_count(J, P, B, 0, L), pn = lat_count(J, P, B, 0, L - 1);
-  constexpr int NN = n * n, SLOTS = (NN + 255) / 256;
+  constexpr int NN = n * n, SLOTS = lat_slots<J, P, L>();
   constexpr int NH = n * pn;
   static_assert(NN <= kLatMax && SLOTS <= 4, "lattice of one level exceeds the tile buffer");
   static_assert(NH <= kLatMax, "half-predicted lattice exceeds its buffer");
   const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
   const int pox = lat_origin<J, P, L - 1>(x0), poy = lat_origin<J, P, L - 1>(y0);
-  const auto* __restrict__ rank = glb(s.rank);
   const T* prev = buf[cur];
   T* nxt = buf[cur ^ 1];
-  // a thread's nodes of this level: ranks first, then the values of the
-  // active ones (their latency hides behind pass 1)
+  // the values of this level's active nodes (their latency hides behind
+  // pass 1), then the next level's ranks
   int ks[SLOTS];
 #pragma unroll
-  for (int i = 0; i < SLOTS; ++i) {
-    const int q = threadIdx.x + 256 * i;
-    ks[i] = -1;
-    if (q < NN) {
-      const int iy = q / n, ix = q - iy * n;
-      const int x = ox + (ix << SH), y = oy + (iy << SH);
-      if ((x | y) & SV) ks[i] = rank[(y & NM) * N + (x & NM)];
-    }
-  }
+  for (int i = 0; i < SLOTS; ++i) ks[i] = kin.k[i];
   // FB: the basis is stored in FP32 (precision MRA_FP32).  For src 3 its
   // entries are loaded raw, so that no conversion waits for a load before the
   // next one is issued
@@ -217,6 +244,9 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
       if (ks[i] >= 0) av[i] = active_value(s, src, ks[i], inv, Vd);
     }
   }
+  constexpr int LN = L < J ? L + 1 : L;
+  Ranks<lat_slots<J, P, LN>()> knext;
+  if constexpr (L < J) knext = level_ranks<J, P, LN>(s, x0, y0);
   // pass 1: level-L rows of the level-(L - 1) columns
   for (int q = threadIdx.x; q < NH; q += 256) {
     const int iy = q / pn, c = q - iy * pn;
@@ -266,7 +296,7 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
   }
   if constexpr (L < J) {
     __syncthreads();
-    prolong_level_ct<P, T, J, L + 1, FB>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vd, Vf, f);
+    prolong_level_ct<P, T, J, L + 1, FB>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vd, Vf, f, knext);
   }
 }
 
@@ -292,6 +322,7 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
   const bool has0 = (int)threadIdx.x < pn * pn;
   int x0n = 0, y0n = 0, k0n = 0;
   double raw = 0.0;
+  const auto k1 = level_ranks<J, P, J0 + 1>(s, x0, y0);   // first swept level, in flight meanwhile
   if (has0) {
     const int q = threadIdx.x;
     const int iy = q / pn, ix = q - iy * pn;
@@ -315,7 +346,7 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     buf[0][threadIdx.x] = (T)a;
   }
   __syncthreads();
-  prolong_level_ct<P, T, J, J0 + 1, FB>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f);
+  prolong_level_ct<P, T, J, J0 + 1, FB>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f, k1);
 }
 
 template <int P, typename T>
