@@ -533,7 +533,8 @@ int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, do
   if (m < 1 || m > kMaxM) return MRA_E_SIZE;
   if (!(dt > 0.0) || !std::isfinite(dt) || !(kappa0 >= 0.0) || !std::isfinite(kappa0)) return MRA_E_ARG;
   if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return MRA_E_ARG;
-  const int32_t prec = partner->host.prec == 0 ? MRA_FP64 : MRA_MIXED;
+  // the scalar takes its partner's precision, basis storage included
+  const int32_t prec = partner->host.prec == 0 ? MRA_FP64 : (partner->host.vb32 ? MRA_FP32 : MRA_MIXED);
   size_t need = 0;
   mra_solve_footprint(g, prec, m, &need);
   if (arena_bytes < need) return MRA_E_NOMEM;
@@ -555,6 +556,7 @@ int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, do
   if (eddy) s.nu = partner->host.nu;
   h->dev = reinterpret_cast<SolveDev*>(arena);
   h->cfg = LaunchCfg{s.J, s.p, s.prec, m, 1};
+  h->cfg.vb = s.vb32;
   h->partner = partner;
   partner->riders += 1;
   h->steps = partner->steps;   // the next scalar step follows the partner's next step

@@ -98,3 +98,50 @@ def test_fp32_basis_steps_match_oracle(M):
         rel = np.linalg.norm(d - ref) / np.linalg.norm(ref)
         print(f"{name}: 2 steps at 512^2 vs the FP64 oracle, rel L2 {rel:.2e}")
         assert rel <= 1e-5
+
+
+def test_fp32_basis_theta_step_matches_oracle(M):
+    """The theta-scheme's GMRES and Newton updates read the FP32 basis too:
+    two Crank-Nicolson steps (two Newton iterations each) against the FP64
+    oracle at the mixed-precision bar."""
+    from oracle import implicit as oi
+    pb = W.plain_pair()
+    w0 = W.initial_field(pb)
+    s = M.Solve(M.grid_desc(pb.J, pb.p, pb.eps), M.flow_desc(pb.nu0, pb.cs), M.MRA_FP32, pb.m, pb.dt,
+                torch.from_numpy(w0).to(DEV))
+    s.set_integrator(M.MRA_THETA_NEWTON, 0.5, 2)
+    s.step(2)
+    dense = s.read()[0].cpu().numpy()
+    s.close()
+    g = ok.Grid(J=pb.J, p=pb.p, eps=pb.eps)
+    fl = oo.Flow(nu0=pb.nu0, cs=pb.cs)
+    st = ok.init_state(w0, g)
+    for _ in range(2):
+        st = oi.theta_step(st, g, fl, pb.m, pb.dt, 0.5, 2)
+    ref = om.prolong(st.omega_M, st.index_fine, pb.J, pb.p)
+    rel = np.linalg.norm(dense - ref) / np.linalg.norm(ref)
+    print(f"MRA_FP32 theta steps vs the FP64 oracle: rel L2 {rel:.2e}")
+    assert rel <= 1e-5
+
+
+def test_fp32_basis_partner_carries_a_scalar(M):
+    """A passive scalar takes its partner's precision: coupled to a solve
+    whose basis is FP32 it stores its own basis in FP32 too (the arena the
+    binding sizes from the partner's precision fits), and it sees the same
+    flow to rounding as with a mixed-precision partner."""
+    pb = W.plain_pair()
+    w0 = torch.from_numpy(W.initial_field(pb)).to(DEV)
+    r0 = torch.from_numpy(W.vapor_field(pb.N)).to(DEV)
+    out = {}
+    for name in ("MRA_MIXED", "MRA_FP32"):
+        s = M.Solve(M.grid_desc(pb.J, pb.p, pb.eps), M.flow_desc(pb.nu0, pb.cs), getattr(M, name), pb.m, pb.dt, w0)
+        sc = M.ScalarSolve(s, M.grid_desc(pb.J, pb.p, 1e-3), 10, pb.dt, r0)
+        for _ in range(3):
+            M.solve_batch([s, sc], [1, 1])
+        out[name] = sc.read()[0].cpu().numpy()
+        assert int(sc.read()[1]["status"]) == 0
+        sc.close()
+        s.close()
+    rel = np.linalg.norm(out["MRA_FP32"] - out["MRA_MIXED"]) / np.linalg.norm(out["MRA_MIXED"])
+    print(f"scalar with an FP32-basis partner vs a mixed one, 3 steps: rel L2 {rel:.2e}")
+    assert rel <= 1e-6
