@@ -538,7 +538,7 @@ def run_families(args) -> int:
     solves = []
     with torch.cuda.stream(stream):
         for pb in pbs:
-            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m,
+            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_MIXED, pb.m,
                                   pb.dt, torch.from_numpy(W.initial_field(pb)).to(dev), stream=stream))
     d0 = [s.read(dense=False, stream=stream)[1] for s in solves]
     cs = [[(v.cx, v.cy) for v in pb.vortices] for pb in pbs]
