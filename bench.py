@@ -362,6 +362,65 @@ def run_vapor(args) -> int:
     return 0
 
 
+def run_condensation(args) -> int:
+    """Vapor condensation (Section 2.6's moving interface) at 512^2 in calm
+    air: a batch of circular patches of radii 0.6 .. 1.3 (D_v = 1e-3, rate 1,
+    kappa = 2 D_v) riding one vorticity solve at rest, dt = 0.1 to t = 80 as in
+    the section's figure.  Reports the scalars' active-point evaluations per
+    second, and for the R0 = 1 patch the squared radius sqrt(A / pi)^2 at
+    t = 40 and 80 against the curvature law R0^2 - 2 kappa t and the extremes
+    of r (the section's point: no oscillation at the interface)."""
+    import torch
+    import workloads as W
+    import paper_1604_08159_amd as m
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    J, dt, kappa = 9, 0.1, 2 * W.COND_DV
+    N = 1 << J
+    radii = [0.6 + 0.1 * i for i in range(args.cond_batch)]
+    with torch.cuda.stream(stream):
+        v = m.Solve(m.grid_desc(J, 2, 1e-3), m.flow_desc(1e-4, 0.17), m.MRA_MIXED, 20, dt,
+                    torch.zeros((N, N), dtype=torch.float64, device=dev), stream=stream)
+        scs = []
+        for R0 in radii:
+            r0 = torch.from_numpy(W.vapor_patch(N, R0)).to(dev)
+            sc = m.ScalarSolve(v, m.grid_desc(J, 2, 1e-4), 20, dt, r0, kappa0=kappa, eddy=False, stream=stream)
+            sc.set_condensation(1.0, stream=stream)
+            scs.append(sc)
+    handles = [v] + scs
+    i1 = min(range(len(radii)), key=lambda i: abs(radii[i] - 1.0))
+    h = 2 * np.pi / N
+    r_init, _ = scs[i1].read(stream=stream)
+    R2 = {0.0: h * h * float(r_init.sum()) / np.pi}
+    ev0 = sum(sc.scalars()["evals"] for sc in scs)
+    wall, half = 0.0, args.cond_steps // 2
+    ext = [float(r_init.min()), float(r_init.max())]
+    for k in range(2):
+        stream.synchronize()
+        t0 = time.perf_counter()
+        m.solve_batch(handles, [half] * len(handles), stream=stream)
+        stream.synchronize()
+        wall += time.perf_counter() - t0
+        r, _ = scs[i1].read(stream=stream)
+        R2[(k + 1) * half * dt] = h * h * float(r.sum()) / np.pi
+        ext = [min(ext[0], float(r.min())), max(ext[1], float(r.max()))]
+    ev1 = sum(sc.scalars()["evals"] for sc in scs)
+    nas = [int(sc.read(dense=False, stream=stream)[1]["n_active"]) for sc in scs]
+    law = {t: R2[0.0] - 2 * kappa * t for t in R2}
+    print(json.dumps({"workload": f"vapor condensation, 512^2, calm air, {len(scs)} patches of radius "
+                                  f"{radii[0]:.1f}..{radii[-1]:.1f}, D_v={W.COND_DV}, dt={dt}, {2 * half} steps "
+                                  f"(t = {2 * half * dt:g}), mixed precision",
+                      "metric": "active-pt RHS evals/s", "value": (ev1 - ev0) / wall,
+                      "ms_per_step": wall / (2 * half) * 1e3, "mean_active_points": sum(nas) / len(nas),
+                      "R0_1_patch_R2": {f"{t:g}": R2[t] for t in R2},
+                      "curvature_law_R2": {f"{t:g}": law[t] for t in law},
+                      "r_min_max": ext}))
+    for sc in scs:
+        sc.close()
+    v.close()
+    return 0
+
+
 def run_three(args) -> int:
     """The three-vortex Re = 37440 configuration at 2048^2 (6-point DD, m = 30,
     noise everywhere at first, so nearly every node is active): a batch of
@@ -575,10 +634,12 @@ def run_families(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["fujiwhara", "ensemble", "serving", "vapor", "three2048", "longrun",
-                                           "implicit", "families", "serving_spec"],
+                                           "implicit", "families", "serving_spec", "condensation"],
                     default="fujiwhara")
     ap.add_argument("--batch3", type=int, default=2)
     ap.add_argument("--steps3", type=int, default=10)
+    ap.add_argument("--cond-batch", type=int, default=8)
+    ap.add_argument("--cond-steps", type=int, default=800)
     ap.add_argument("--prec3", choices=["mixed", "fp32"], default="mixed",
                     help="three2048: fp32 stores the Krylov basis in FP32")
     ap.add_argument("--long-steps", type=int, default=2000)
@@ -616,6 +677,8 @@ def main() -> int:
         return run_serving(args)
     if args.workload == "vapor":
         return run_vapor(args)
+    if args.workload == "condensation":
+        return run_condensation(args)
     if args.workload == "three2048":
         return run_three(args)
     if args.workload == "serving_spec":

@@ -239,6 +239,24 @@ int32_t mra_solve_track(mra_solve s, int32_t k, double* centres, void* stream);
 int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, double dt, double kappa0,
                         int32_t eddy, const double* r0_dense, void* arena, size_t arena_bytes,
                         void* stream, mra_solve* out);
+
+/* ------------------------------------------------------------------------
+ * Vapor condensation (Section 2.6, the moving air-vapor interface).  The
+ * loss of vapor there is the variational derivative of the functional
+ * int 1/2 r^2 (r - 1)^2 + D_v |grad r|^2, read as its gradient flow (the
+ * sign under which a vapor patch shrinks, as the section's experiment
+ * describes).  mra_scalar_set_condensation sets the rate c >= 0 of the
+ * reaction part: the scalar's right-hand side gains -c f'(r) at every active
+ * node, f'(r) = r (r - 1) (2 r - 1), and its Krylov products the
+ * linearisation -c f''(r_n) v, f''(r) = 6 r^2 - 6 r + 1, at the state r_n of
+ * the step's start (exponential Rosenbrock-Euler), both in FP64.  The
+ * section's functional has c = 1; its gradient term is the scalar's
+ * diffusion with the constant kappa0 = 2 D_v (eddy = 0).  c = 0 (the default)
+ * is pure transport.  The rate is written in stream order on `stream`, so
+ * steps enqueued after the call use it.  Errors: MRA_E_ARG for a null handle
+ * or a negative or non-finite rate; MRA_E_UNSUPPORTED for a vorticity solve.
+ * ------------------------------------------------------------------------ */
+int32_t mra_scalar_set_condensation(mra_solve s, double rate, void* stream);
 int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* stream);
 int32_t mra_solve_read(mra_solve s, double* omega_dense_out, double* diag_out, void* stream);
 int32_t mra_solve_ptrs_get(mra_solve s, mra_solve_ptrs* out);

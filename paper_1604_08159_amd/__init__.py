@@ -240,6 +240,12 @@ class ScalarSolve(Solve):
         _check("mra_scalar_init", st)
         self.handle = h
 
+    def set_condensation(self, rate: float, stream=None) -> None:
+        """Vapor condensation at rate c (mra_scalar_set_condensation): the
+        right-hand side gains -c r (r - 1) (2 r - 1); 0 turns it off."""
+        _check("mra_scalar_set_condensation",
+               lib().mra_scalar_set_condensation(self.handle, float(rate), _stream(stream)))
+
 
 KERNELS = {"jvp": 0, "fft_rows": 1, "fft_cols": 2, "fft_rows_inv": 3, "prolong_finest": 4,
            "forward": 5, "rhs": 6}

@@ -62,6 +62,7 @@ EXPORTS = {
     "mra_solve_destroy": (C.c_int32, [C.c_void_p]),
     "mra_solve_set_integrator": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p]),
     "mra_solve_set_jacobian": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "mra_scalar_set_condensation": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
     "mra_time_kernel": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_float)]),
 }

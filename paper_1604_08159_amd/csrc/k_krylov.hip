@@ -512,12 +512,15 @@ hipError_t launch_gmres(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   return hipGetLastError();
 }
 
-__global__ void k_set_theta(Batch b, double theta) {
-  if (threadIdx.x == 0) MRA_SOLVE(b).scal[S_THETA] = theta;
+// One device scalar of every solve of b (the theta of the theta-scheme, the
+// condensation rate of a scalar), written in stream order.
+__global__ void k_set_scal(Batch b, int idx, double value) {
+  if (threadIdx.x == 0) MRA_SOLVE(b).scal[idx] = value;
 }
 
-hipError_t launch_set_theta(const Batch& b, double theta, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_theta, dim3((1) * b.n), dim3(64), 0, st, b, theta);
+hipError_t launch_set_scal(const Batch& b, int idx, double value, hipStream_t st) {
+  if (idx < 0 || idx >= S_NSCAL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_set_scal, dim3((1) * b.n), dim3(64), 0, st, b, idx, value);
   return hipGetLastError();
 }
 

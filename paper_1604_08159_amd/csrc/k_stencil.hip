@@ -399,9 +399,11 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
 // Passive scalar (Section 3.6): L v~ = -[D1_x(u v~) + D1_y(v v~)]
 // + 1/2 [L(kappa v~) + kappa L v~ - v~ L kappa] at the active nodes of one
 // tile, with u, v (and the diffusivity kappa, stored in s.nu) the fields the
-// scalar was coupled to.  The operator is linear in the scalar, so the same
-// kernel gives its residual (v~ = Pi(r), check_done = 0) and its products
-// with the Arnoldi vectors.
+// scalar was coupled to.  The same kernel gives the residual (v~ = Pi(r),
+// check_done = 0) and the products with the Arnoldi vectors.  Condensation
+// (Section 2.6, rate c = scal[S_COND], 0 when off) adds -c f'(r) to the
+// residual, f(r) = 1/2 r^2 (r - 1)^2, and its linearisation -c f''(r_n) v~ to
+// the products, in FP64 from the active values r_n of the step's start.
 template <int P, typename T, int TS>
 __global__ void __launch_bounds__(256) k_scalar(Batch b, int check_done) {
   using G = Geo<P>;
@@ -465,6 +467,8 @@ __global__ void __launch_bounds__(256) k_scalar(Batch b, int check_done) {
   }
   __syncthreads();
   double* out = s.out_jvp;
+  const double cond = s.scal[S_COND];
+  const auto* om = glb(s.omega);
 #pragma unroll
   for (int i = 0; i < NO; ++i) {
     const int q = threadIdx.x + 256 * i;
@@ -477,14 +481,22 @@ __global__ void __launch_bounds__(256) k_scalar(Batch b, int check_done) {
     const T nv = nu[rn * Wn + cn_];
     const T diff = T(0.5) * ih2 * (lap5<P, T>(cn, Wn, rn, cn_) + nv * lap5<P, T>(vt, Ww, ra, ca) -
                                    vv * lap5<P, T>(nu, Wn, rn, cn_));
-    out[k] = (double)(adv + diff);
+    double o = (double)(adv + diff);
+    if (cond != 0.0) {
+      const double rk = om[k];
+      o -= check_done ? cond * ((6.0 * rk * rk - 6.0 * rk + 1.0) * (double)vv)
+                      : cond * (rk * (rk - 1.0) * (2.0 * rk - 1.0));
+    }
+    out[k] = o;
   }
 }
 
 template <int P, typename T, int TS>
 static hipError_t scalar_ts(const Batch& b, int N, int check_done, hipStream_t st) {
   const int nt = (N / TS) * (N / TS);
-  const size_t lds = jvp_lds_elems<P, T>(TS) * sizeof(T);
+  using G = Geo<P>;
+  const size_t Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
+  const size_t lds = (3 * Ww * Ww + 2 * Wn * Wn) * sizeof(T);   // v~, both fluxes; kappa, kappa v~
   hipLaunchKernelGGL((k_scalar<P, T, TS>), dim3(nt * b.n), dim3(256), lds, st, b, check_done);
   return hipGetLastError();
 }

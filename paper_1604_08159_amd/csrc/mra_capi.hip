@@ -786,9 +786,16 @@ int32_t mra_solve_set_integrator(mra_solve h, int32_t integrator, double theta, 
   if (integrator == MRA_THETA_NEWTON && h->riders > 0) return MRA_E_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   drop_graphs_of(h);
-  if (integrator == MRA_THETA_NEWTON) MRA_TRY(launch_set_theta(one(h->dev), theta, st));
+  if (integrator == MRA_THETA_NEWTON) MRA_TRY(launch_set_scal(one(h->dev), S_THETA, theta, st));
   h->cfg.integ = integrator;
   h->cfg.newton = integrator == MRA_THETA_NEWTON ? newton_iters : 0;
+  return MRA_OK;
+}
+
+int32_t mra_scalar_set_condensation(mra_solve h, double rate, void* stream) {
+  if (!h || !(rate >= 0.0) || !std::isfinite(rate)) return MRA_E_ARG;
+  if (h->cfg.kind != 1) return MRA_E_UNSUPPORTED;
+  MRA_TRY(launch_set_scal(one(h->dev), S_COND, rate, static_cast<hipStream_t>(stream)));
   return MRA_OK;
 }
 

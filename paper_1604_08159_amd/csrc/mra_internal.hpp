@@ -27,7 +27,7 @@ constexpr int kTwN = 2048;          // twiddle table size (largest FFT length)
 enum Ctrl : int { C_MEFF = 0, C_DONE = 1, C_STATUS = 2, C_CNT0 = 4, C_CNT1 = 5, C_CNT2 = 6,
                   C_CNT3 = 7, C_REORTH = 8, C_NCTRL = 16 };
 enum Scal : int { S_BETA = 0, S_INV = 1, S_NRMAV = 2, S_UMAX = 3, S_T = 4, S_EVALS = 5, S_STEPS = 6,
-                  S_THETA = 7, S_NSCAL = 16 };
+                  S_THETA = 7, S_COND = 8, S_NSCAL = 16 };
 
 struct SolveDev {
   // geometry / numbers
@@ -382,7 +382,7 @@ hipError_t launch_update(const Batch& b, const LaunchCfg& c, hipStream_t st);
 hipError_t launch_newton_rhs(const Batch& b, const LaunchCfg& c, int first, hipStream_t st);
 hipError_t launch_gmres(const Batch& b, const LaunchCfg& c, hipStream_t st);
 hipError_t launch_newton_update(const Batch& b, const LaunchCfg& c, int last, hipStream_t st);
-hipError_t launch_set_theta(const Batch& b, double theta, hipStream_t st);
+hipError_t launch_set_scal(const Batch& b, int idx, double value, hipStream_t st);
 hipError_t launch_reset_ctrl(const Batch& b, hipStream_t st);
 hipError_t launch_clear_done(const Batch& b, hipStream_t st);
 

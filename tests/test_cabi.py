@@ -81,3 +81,4 @@ def test_size_queries_and_argument_checks(lib):
                                C.byref(C.c_void_p())) == 1
     assert lib.mra_solve_set_integrator(None, 1, 0.5, 2, None) == 1
     assert lib.mra_solve_set_jacobian(None, 1) == 1
+    assert lib.mra_scalar_set_condensation(None, 1.0, None) == 1

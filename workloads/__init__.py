@@ -109,6 +109,24 @@ def vapor_field(N: int, sharpness: float = 8.0, length: float = TWO_PI) -> np.nd
     return np.repeat(r, N, axis=1)
 
 
+# Vapor condensation (Section 2.6's moving interface): the section gives the
+# functional and a shrinking circular patch but no sizes, so the recipe is
+# dimensionless: a patch of radius R0 = 1 centred in the periodic square,
+# D_v = 1e-3 (interface width 2 sqrt(2 D_v) ~ 0.09, seven 512^2 nodes), times
+# t = 40 and 80 as in the section's figure.
+COND_DV = 1e-3
+
+
+def vapor_patch(N: int, R0: float = 1.0, D_v: float = COND_DV, length: float = TWO_PI) -> np.ndarray:
+    """Circular vapor patch: 1 inside a circle of radius R0 at the centre of
+    the periodic square, 0 outside, joined by the profile
+    1/2 (1 - tanh(d / (2 sqrt(2 D_v)))) of the signed distance d to the circle
+    (the planar front of the condensation flow with kappa = 2 D_v)."""
+    x = np.arange(N) * (length / N) - length / 2
+    d = np.hypot(x[None, :], x[:, None]) - R0
+    return 0.5 * (1.0 - np.tanh(d / (2.0 * np.sqrt(2.0 * D_v))))
+
+
 def random_field(N: int, seed: int, smooth: int = 0) -> np.ndarray:
     """Seeded N(0,1) field, optionally box-smoothed `smooth` times (periodic)."""
     rng = np.random.default_rng(seed)
