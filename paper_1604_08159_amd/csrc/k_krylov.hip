@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(256) k_gmres(Batch b) {
     const int i = q / k, j = q - i * k;
     double v = 0.0;
     if (i == k) {
-      if (j == k - 1) v = -a * s.H[i * m + j];      // h_{k+1,k}, stored by the last stage
+      if (j == k - 1) v = -a * s.H[i * m + j];      // h_{k+1,k}, stored where the column ended
     } else if (i <= j + 1) {
       v = (i == j ? 1.0 : 0.0) - a * s.H[i * m + j];
     }
