@@ -107,7 +107,8 @@ template <int P, typename T>
 __host__ __device__ inline size_t jvp_lds_elems(int TS, bool exact = false) {
   using G = Geo<P>;
   const size_t Ww = TS + 2 * G::R1, Wn = TS + 2 * P;
-  return exact ? 4 * Ww * Ww + 4 * Wn * Wn : 4 * Ww * Ww + 2 * Wn * Wn;
+  // frozen: v~, both fluxes, nu_e, and psi~ sharing its buffer with nu_e v~
+  return exact ? 4 * Ww * Ww + 4 * Wn * Wn : 4 * Ww * Ww + Wn * Wn;
 }
 
 template <int P, typename T, int TS>
@@ -276,8 +277,9 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   T* fb = fa + Ww * Ww;
   T* nu = fb + Ww * Ww;
   T* cn = nu + Wn * Wn;
-  // frozen Jacobian: psi~ (Ww region), whose D1 gives u~ and v~ in place
-  T* ps = cn + Wn * Wn;
+  // frozen Jacobian: psi~ (Ww region), whose D1 gives u~ and v~ in place; it
+  // is dead once the fluxes are formed, so nu_e v~ (cn) takes its buffer
+  T* ps = cn;
   // exact Jacobian: w~ (Ww region), nu' and nu' w~ (Wn regions)
   T* wl = cn + Wn * Wn;
   T* np = wl + Ww * Ww;
@@ -355,6 +357,7 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
     }
   }
   constexpr int on = G::R1 - P;
+  if constexpr (!EX) __syncthreads();   // every flux has read psi~ before cn overwrites it
   for (int q = threadIdx.x; q < Wn * Wn; q += blockDim.x) {
     const int r = q / Wn, c = q - r * Wn;
     cn[q] = nu[q] * vt[(r + on) * Ww + c + on];
