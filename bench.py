@@ -211,7 +211,18 @@ def run_ensemble(args) -> int:
     import workloads as W
     import paper_1604_08159_amd as m
     from paper_1604_08159_amd import MRA_FP64, MRA_MIXED, serve
+    from paper_1604_08159_amd import autotune
     probs = W.ensemble(args.solves, steps=args.ens_steps)
+    # tile autotuning for the ensemble's grid sizes (outside the timed region)
+    ta = time.perf_counter()
+    sizes = sorted({pb.J for pb in probs})
+    tuned = {}
+    for J in sizes:      # each size tuned at the batch it runs at (up to 16 resident solves)
+        nJ = min(16, sum(pb.J == J for pb in probs))
+        tuned.update(autotune.autotune([(J, 2, MRA_MIXED)], cache=args.tune_cache or None,
+                                       nsolves=nJ, steps=6, warmup=2))
+    tune_s = time.perf_counter() - ta
+    log("autotune: " + ", ".join(f"J={J} tile {tuned[autotune._key(J, 2, MRA_MIXED)]['tile']}" for J in sizes))
     reqs = serve.requests_from_problems([(0.0, pb) for pb in probs], W.initial_field)
     srv = serve.Server(hbm_budget=args.hbm_gb << 30, prec=MRA_MIXED, round_steps=args.round_steps,
                        progress=progress_printer())
@@ -249,7 +260,15 @@ def run_ensemble(args) -> int:
                                              "sec_per_step_by_J": per_step,
                                              "note": "one warmed solve per size timed over 8 steps, "
                                                      "applied to every solve's step count"},
+                      "autotune": {"tiles": {str(J): tuned[autotune._key(J, 2, MRA_MIXED)]["tile"] for J in sizes},
+                                   "ms_per_step_by_tile": {str(J): tuned[autotune._key(J, 2, MRA_MIXED)]["ms_per_step"]
+                                                           for J in sizes},
+                                   "seconds": tune_s,
+                                   "note": "per size, a batch of up to 16 two-vortex solves, 6 steps per "
+                                           "candidate, before the run"},
                       "cpu_baseline": cpu}))
+    for J in sizes:
+        m.tune_set_tile(J, 2, MRA_MIXED, 0)
     return 0
 
 
@@ -638,6 +657,7 @@ def main() -> int:
                     default="fujiwhara")
     ap.add_argument("--batch3", type=int, default=2)
     ap.add_argument("--steps3", type=int, default=10)
+    ap.add_argument("--tune-cache", default="", help="ensemble: JSON cache of the tile autotuner")
     ap.add_argument("--cond-batch", type=int, default=8)
     ap.add_argument("--cond-steps", type=int, default=800)
     ap.add_argument("--prec3", choices=["mixed", "fp32"], default="mixed",

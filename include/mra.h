@@ -257,6 +257,26 @@ int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, do
  * or a negative or non-finite rate; MRA_E_UNSUPPORTED for a vorticity solve.
  * ------------------------------------------------------------------------ */
 int32_t mra_scalar_set_condensation(mra_solve s, double rate, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Tile autotuning.  The stencil kernels (residual, Jacobian-vector products,
+ * scalar transport) work on square tiles of the finest grid staged in LDS;
+ * the edge trades halo re-reads (larger tiles read fewer halo nodes) against
+ * LDS per block (smaller tiles fit more blocks per CU).  By default it is 32,
+ * 16 for FP64 with the 6-point rule, never more than N.
+ * mra_tune_set_tile sets the edge (8, 16 or 32) that solves and residual
+ * workspaces laid out from now on take for (J, p, precision); tile 0 restores
+ * the default.  A solve keeps the tile it was created with, and solve_batch
+ * groups solves by tile, so solves of either tile can share a call.
+ * Errors: MRA_E_ARG for J outside 3..11, p outside {2, 3}, an unknown
+ * precision, a tile other than 0, 8, 16, 32, a tile larger than N, or the
+ * 32-tile of FP64 with the 6-point rule.  mra_tune_get_tile writes the edge
+ * a new solve of (J, p, precision) would take.  The table is process-wide;
+ * the Python autotuner (paper_1604_08159_amd/autotune.py) times the
+ * candidates on the GPU and keeps the choices in a JSON cache.
+ * ------------------------------------------------------------------------ */
+int32_t mra_tune_set_tile(int32_t J, int32_t p, int32_t prec, int32_t tile);
+int32_t mra_tune_get_tile(int32_t J, int32_t p, int32_t prec, int32_t* tile);
 int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* stream);
 int32_t mra_solve_read(mra_solve s, double* omega_dense_out, double* diag_out, void* stream);
 int32_t mra_solve_ptrs_get(mra_solve s, mra_solve_ptrs* out);

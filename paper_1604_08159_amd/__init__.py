@@ -125,6 +125,18 @@ def solve_footprint(g: GridDesc, prec: int, m: int) -> int:
     return n.value
 
 
+def tune_set_tile(J: int, p: int, prec: int, tile: int) -> None:
+    """Stencil tile edge (8, 16 or 32; 0: the default) that solves of
+    (J, p, prec) created from now on take (mra_tune_set_tile)."""
+    _check("mra_tune_set_tile", lib().mra_tune_set_tile(J, p, prec, tile))
+
+
+def tune_get_tile(J: int, p: int, prec: int) -> int:
+    t = C.c_int32()
+    _check("mra_tune_get_tile", lib().mra_tune_get_tile(J, p, prec, C.byref(t)))
+    return t.value
+
+
 DIAG_KEYS = ("t", "energy", "enstrophy", "palinstrophy", "gamma", "max_abs", "n_active", "status")
 
 

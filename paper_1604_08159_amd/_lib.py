@@ -63,6 +63,8 @@ EXPORTS = {
     "mra_solve_set_integrator": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p]),
     "mra_solve_set_jacobian": (C.c_int32, [C.c_void_p, C.c_int32]),
     "mra_scalar_set_condensation": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
+    "mra_tune_set_tile": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "mra_tune_get_tile": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     "mra_time_kernel": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_float)]),
 }

@@ -507,7 +507,8 @@ static hipError_t scalar_ts(const Batch& b, int N, int check_done, hipStream_t s
 template <int P, typename T>
 static hipError_t scalar_t(const Batch& b, const LaunchCfg& c, int check_done, hipStream_t st) {
   const int N = 1 << c.J;
-  const int TS = tile_edge(c.J, c.p, c.prec);
+  const int TS = c.tile;     // the tile the solves were laid out with
+  if (!tile_valid(c.J, c.p, c.prec, TS)) return hipErrorInvalidValue;
   if (TS == 32) return scalar_ts<P, T, 32>(b, N, check_done, st);
   if (TS == 16) return scalar_ts<P, T, 16>(b, N, check_done, st);
   return scalar_ts<P, T, 8>(b, N, check_done, st);
@@ -553,7 +554,8 @@ static hipError_t rhs_ts(const Batch& b, int N, bool jvp, bool exact, hipStream_
 template <int P, typename T>
 static hipError_t rhs_t(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {
   const int N = 1 << c.J;
-  const int TS = tile_edge(c.J, c.p, c.prec);
+  const int TS = c.tile;     // the tile the solves were laid out with
+  if (!tile_valid(c.J, c.p, c.prec, TS)) return hipErrorInvalidValue;
   const bool exact = jvp && c.jac == 1;
   if (TS == 32) return rhs_ts<P, T, 32>(b, N, jvp, exact, st);
   if (TS == 16) return rhs_ts<P, T, 16>(b, N, jvp, exact, st);

@@ -2,6 +2,7 @@
 // sequence of launches of one exponential step, HIP-graph capture of that
 // step, batching of solves, read-back and diagnostics.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -72,6 +73,11 @@ int32_t check_flow(const mra_flow_desc* f) {
 
 int prec_bulk(int32_t prec) { return prec == MRA_FP64 ? 0 : 1; }
 
+// Tile edges set by mra_tune_set_tile, per (J, p - 2, bulk precision); 0 keeps
+// the default rule.  Read when a solve or workspace is laid out.
+static std::atomic<int> g_tile_set[kMaxJ + 1][2][2];
+
+
 // Simple bump allocator over a caller buffer (null base = size query).
 struct Layout {
   char* base;
@@ -95,7 +101,7 @@ void fill_geometry(SolveDev& s, const mra_grid_desc* g, int32_t prec) {
   s.prec = prec_bulk(prec);
   s.vb32 = prec == MRA_FP32;
   s.adjacent_zone = g->adjacent_zone;
-  s.tile = tile_edge(s.J, s.p, s.prec);
+  s.tile = tile_choice(s.J, s.p, s.prec);
   s.ntx = s.N / s.tile;
   s.length = g->length;
   s.h = g->length / s.N;
@@ -316,6 +322,14 @@ hipError_t capture(const Batch& b, const LaunchCfg& c, hipStream_t st, hipGraph_
 
 }  // namespace
 
+int mra::tile_choice(int J, int p, int prec) {
+  if (J >= 0 && J <= kMaxJ && (p == 2 || p == 3) && (prec == 0 || prec == 1)) {
+    const int t = g_tile_set[J][p - 2][prec].load(std::memory_order_relaxed);
+    if (t != 0) return t;
+  }
+  return tile_edge(J, p, prec);
+}
+
 extern "C" {
 
 const char* mra_status_str(int32_t st) {
@@ -368,6 +382,7 @@ int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const v
   SolveDev* dev = reinterpret_cast<SolveDev*>(ws);
   const bool dbl = s.prec == 0;
   LaunchCfg c{s.J, s.p, s.prec, 0};
+  c.tile = s.tile;
   s.mask = mask;
   s.index_packed = index_packed;
   s.index_fine = index_fine;
@@ -445,6 +460,7 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
   }
   const int dbl = s.prec == 0;
   LaunchCfg c{s.J, s.p, s.prec, 0};
+  c.tile = s.tile;
   MRA_TRY(launch_write_desc(dev, s, st));
   Batch b = one(dev);
   MRA_TRY(launch_reset_ctrl(b, st));
@@ -501,6 +517,7 @@ int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t p
   h->dev = reinterpret_cast<SolveDev*>(arena);
   h->cfg = LaunchCfg{s.J, s.p, s.prec, m};
   h->cfg.vb = s.vb32;
+  h->cfg.tile = s.tile;
   (void)hipGetDevice(&h->device);
   h->diag_rows.resize((size_t)s.N * 5);
   const size_t Nf = (size_t)s.N * s.N;
@@ -557,6 +574,7 @@ int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, do
   h->dev = reinterpret_cast<SolveDev*>(arena);
   h->cfg = LaunchCfg{s.J, s.p, s.prec, m, 1};
   h->cfg.vb = s.vb32;
+  h->cfg.tile = s.tile;
   h->partner = partner;
   partner->riders += 1;
   h->steps = partner->steps;   // the next scalar step follows the partner's next step
@@ -615,11 +633,12 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
   for (int t = 0; t < maxs; ++t) {
     // group the solves still running by launch configuration
     // (vorticity solves first: a scalar's step reads its partner's step)
-    std::map<std::tuple<int, int, int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
+    std::map<std::tuple<int, int, int, int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > t) {
         const LaunchCfg& c = solves[i]->cfg;
-        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton, c.jac, c.vb)].push_back(solves[i]);
+        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton, c.jac, c.vb, c.tile)]
+            .push_back(solves[i]);
       }
     for (auto& kv : groups) {
       auto& v = kv.second;
@@ -792,6 +811,20 @@ int32_t mra_solve_set_integrator(mra_solve h, int32_t integrator, double theta, 
   return MRA_OK;
 }
 
+int32_t mra_tune_set_tile(int32_t J, int32_t p, int32_t prec, int32_t tile) {
+  if (J < 3 || J > kMaxJ || (p != 2 && p != 3) || prec < 0 || prec > 2) return MRA_E_ARG;
+  const int bulk = prec_bulk(prec);
+  if (tile != 0 && !tile_valid(J, p, bulk, tile)) return MRA_E_ARG;
+  g_tile_set[J][p - 2][bulk].store(tile, std::memory_order_relaxed);
+  return MRA_OK;
+}
+
+int32_t mra_tune_get_tile(int32_t J, int32_t p, int32_t prec, int32_t* tile) {
+  if (!tile || J < 3 || J > kMaxJ || (p != 2 && p != 3) || prec < 0 || prec > 2) return MRA_E_ARG;
+  *tile = tile_choice(J, p, prec_bulk(prec));
+  return MRA_OK;
+}
+
 int32_t mra_scalar_set_condensation(mra_solve h, double rate, void* stream) {
   if (!h || !(rate >= 0.0) || !std::isfinite(rate)) return MRA_E_ARG;
   if (h->cfg.kind != 1) return MRA_E_UNSUPPORTED;
@@ -828,7 +861,8 @@ int32_t mra_time_kernel(mra_solve* solves, int32_t n, int32_t which, int32_t rep
     if (!solves[i]) return MRA_E_ARG;
     const LaunchCfg& c0 = solves[0]->cfg;
     const LaunchCfg& ci = solves[i]->cfg;
-    if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m || ci.vb != c0.vb) return MRA_E_ARG;
+    if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m || ci.vb != c0.vb || ci.tile != c0.tile)
+      return MRA_E_ARG;
     b.s[i] = solves[i]->dev;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -200,6 +200,16 @@ __host__ __device__ inline int tile_edge(int J, int p, int prec) {
   const int N = 1 << J;
   return N < t ? N : t;
 }
+// Whether a stencil tile edge can serve (J, p, bulk precision): 8, 16 or 32,
+// at most N, and not the excluded 32-tile of FP64 with the 6-point rule.
+inline bool tile_valid(int J, int p, int prec, int t) {
+  if (t != 8 && t != 16 && t != 32) return false;
+  if (t > (1 << J)) return false;
+  return !(prec == 0 && p == 3 && t == 32);
+}
+// The tile a new solve takes: the one set by mra_tune_set_tile for its
+// (J, p, bulk precision), else tile_edge.
+int tile_choice(int J, int p, int prec);
 
 // Solve buffers are device (global) memory, but their pointers reach the
 // kernels through the solve descriptor, where the compiler cannot tell and
@@ -336,6 +346,7 @@ struct LaunchCfg {
   int newton = 0; // Newton iterations per step (integ 1)
   int jac = 0;    // Jacobian of the Krylov products: 0 eddy viscosity frozen, 1 exact
   int vb = 0;     // Krylov basis stored in FP32 (precision MRA_FP32); FP64 otherwise
+  int tile = 0;   // stencil tile edge of the solves (their SolveDev tile)
 };
 
 hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);

@@ -82,3 +82,33 @@ def test_size_queries_and_argument_checks(lib):
     assert lib.mra_solve_set_integrator(None, 1, 0.5, 2, None) == 1
     assert lib.mra_solve_set_jacobian(None, 1) == 1
     assert lib.mra_scalar_set_condensation(None, 1.0, None) == 1
+
+
+def test_tile_table_host_logic():
+    """mra_tune_set_tile / mra_tune_get_tile on the host: defaults, the
+    precisions that share bulk storage, the accepted edges, and that the
+    footprint of a new solve follows the table (its tile-count array)."""
+    import paper_1604_08159_amd as m
+    from paper_1604_08159_amd import autotune as at
+    assert m.tune_get_tile(9, 2, m.MRA_MIXED) == 32
+    assert m.tune_get_tile(9, 3, m.MRA_FP64) == 16
+    assert m.tune_get_tile(3, 2, m.MRA_MIXED) == 8
+    g = m.grid_desc(9, 2, 1e-4)
+    f32 = m.solve_footprint(g, m.MRA_MIXED, 20)
+    try:
+        m.tune_set_tile(9, 2, m.MRA_MIXED, 16)
+        assert m.tune_get_tile(9, 2, m.MRA_MIXED) == 16 and m.tune_get_tile(9, 2, m.MRA_FP32) == 16
+        assert m.tune_get_tile(9, 2, m.MRA_FP64) == 32
+        assert m.solve_footprint(g, m.MRA_MIXED, 20) > f32          # four times the tile counts
+    finally:
+        m.tune_set_tile(9, 2, m.MRA_MIXED, 0)
+    assert m.tune_get_tile(9, 2, m.MRA_MIXED) == 32
+    for bad in [(9, 3, m.MRA_FP64, 32), (4, 2, m.MRA_MIXED, 32), (9, 2, m.MRA_MIXED, 12), (2, 2, m.MRA_MIXED, 8),
+                (12, 2, m.MRA_MIXED, 16), (9, 4, m.MRA_MIXED, 16), (9, 2, 3, 16)]:
+        with pytest.raises(m.MraError) as e:
+            m.tune_set_tile(*bad)
+        assert e.value.status == 1
+    assert at.valid_tiles(9, 3, m.MRA_FP64) == (8, 16)
+    assert at.valid_tiles(4, 2, m.MRA_MIXED) == (8, 16)
+    assert at.valid_tiles(11, 3, m.MRA_MIXED) == (8, 16, 32)
+    assert at._parse_key(at._key(10, 3, 2)) == (10, 3, 2)
