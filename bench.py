@@ -204,6 +204,34 @@ def progress_printer(every: float = 10.0):
     return cb
 
 
+def tune_tiles(Js, cache: str = "") -> dict:
+    """Tile autotuning for the grid sizes of a workload (outside any timed
+    region): each size J (with its count in Js) is tuned at the batch it runs
+    at, up to 16 resident solves, 6 steps per candidate.  Returns the choices
+    and timings for the JSON line."""
+    import collections
+    from paper_1604_08159_amd import MRA_MIXED, autotune
+    ta = time.perf_counter()
+    counts = collections.Counter(Js)
+    tuned = {}
+    for J in sorted(counts):
+        tuned.update(autotune.autotune([(J, 2, MRA_MIXED)], cache=cache or None,
+                                       nsolves=min(16, counts[J]), steps=6, warmup=2))
+    out = {"tiles": {str(J): tuned[autotune._key(J, 2, MRA_MIXED)]["tile"] for J in sorted(counts)},
+           "ms_per_step_by_tile": {str(J): tuned[autotune._key(J, 2, MRA_MIXED)]["ms_per_step"]
+                                   for J in sorted(counts)},
+           "seconds": time.perf_counter() - ta,
+           "note": "per size, a batch of up to 16 two-vortex solves, 6 steps per candidate, before the run"}
+    log("autotune: " + ", ".join(f"J={J} tile {t}" for J, t in out["tiles"].items()))
+    return out
+
+
+def untune_tiles(tuned: dict) -> None:
+    import paper_1604_08159_amd as m
+    for J in tuned["tiles"]:
+        m.tune_set_tile(int(J), 2, m.MRA_MIXED, 0)
+
+
 def run_ensemble(args) -> int:
     """Batched ensemble: two-vortex solves of sizes 128^2..1024^2, mixed
     precision, all resident, advanced by the continuous-batching server."""
@@ -211,18 +239,8 @@ def run_ensemble(args) -> int:
     import workloads as W
     import paper_1604_08159_amd as m
     from paper_1604_08159_amd import MRA_FP64, MRA_MIXED, serve
-    from paper_1604_08159_amd import autotune
     probs = W.ensemble(args.solves, steps=args.ens_steps)
-    # tile autotuning for the ensemble's grid sizes (outside the timed region)
-    ta = time.perf_counter()
-    sizes = sorted({pb.J for pb in probs})
-    tuned = {}
-    for J in sizes:      # each size tuned at the batch it runs at (up to 16 resident solves)
-        nJ = min(16, sum(pb.J == J for pb in probs))
-        tuned.update(autotune.autotune([(J, 2, MRA_MIXED)], cache=args.tune_cache or None,
-                                       nsolves=nJ, steps=6, warmup=2))
-    tune_s = time.perf_counter() - ta
-    log("autotune: " + ", ".join(f"J={J} tile {tuned[autotune._key(J, 2, MRA_MIXED)]['tile']}" for J in sizes))
+    tuned = tune_tiles([pb.J for pb in probs], args.tune_cache)
     reqs = serve.requests_from_problems([(0.0, pb) for pb in probs], W.initial_field)
     srv = serve.Server(hbm_budget=args.hbm_gb << 30, prec=MRA_MIXED, round_steps=args.round_steps,
                        progress=progress_printer())
@@ -260,15 +278,9 @@ def run_ensemble(args) -> int:
                                              "sec_per_step_by_J": per_step,
                                              "note": "one warmed solve per size timed over 8 steps, "
                                                      "applied to every solve's step count"},
-                      "autotune": {"tiles": {str(J): tuned[autotune._key(J, 2, MRA_MIXED)]["tile"] for J in sizes},
-                                   "ms_per_step_by_tile": {str(J): tuned[autotune._key(J, 2, MRA_MIXED)]["ms_per_step"]
-                                                           for J in sizes},
-                                   "seconds": tune_s,
-                                   "note": "per size, a batch of up to 16 two-vortex solves, 6 steps per "
-                                           "candidate, before the run"},
+                      "autotune": tuned,
                       "cpu_baseline": cpu}))
-    for J in sizes:
-        m.tune_set_tile(J, 2, MRA_MIXED, 0)
+    untune_tiles(tuned)
     return 0
 
 
@@ -280,6 +292,7 @@ def run_serving(args) -> int:
     from paper_1604_08159_amd import MRA_MIXED, serve
     timed = W.serving_requests(args.requests, rate=args.rate, J_range=(6, args.max_J),
                                steps_range=(args.min_steps, args.max_steps))
+    tuned = tune_tiles([pb.J for _, pb in timed], args.tune_cache)
     reqs = serve.requests_from_problems(timed, W.initial_field)
     srv = serve.Server(hbm_budget=args.hbm_gb << 30, prec=MRA_MIXED, round_steps=args.round_steps,
                        progress=progress_printer())
@@ -293,7 +306,8 @@ def run_serving(args) -> int:
     print(json.dumps({"workload": f"serving: {args.requests} requests, Poisson arrivals at {args.rate}/s, "
                                   f"finest 64^2..{1 << args.max_J}^2, {args.min_steps}-{args.max_steps} steps",
                       **summ, "offered_req_per_s": offered,
-                      "achieved_req_per_s": summ["solves_per_s"]}))
+                      "achieved_req_per_s": summ["solves_per_s"], "autotune": tuned}))
+    untune_tiles(tuned)
     return 0
 
 
