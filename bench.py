@@ -217,8 +217,8 @@ def tune_tiles(Js, cache: str = "") -> dict:
     for J in sorted(counts):
         tuned.update(autotune.autotune([(J, 2, MRA_MIXED)], cache=cache or None,
                                        nsolves=min(16, counts[J]), steps=6, warmup=2))
-    out = {"tiles": {str(J): tuned[autotune._key(J, 2, MRA_MIXED)]["tile"] for J in sorted(counts)},
-           "ms_per_step_by_tile": {str(J): tuned[autotune._key(J, 2, MRA_MIXED)]["ms_per_step"]
+    out = {"tiles": {str(J): tuned[autotune.entry_key(J, 2, MRA_MIXED)]["tile"] for J in sorted(counts)},
+           "ms_per_step_by_tile": {str(J): tuned[autotune.entry_key(J, 2, MRA_MIXED)]["ms_per_step"]
                                    for J in sorted(counts)},
            "seconds": time.perf_counter() - ta,
            "note": "per size, a batch of up to 16 two-vortex solves, 6 steps per candidate, before the run"}

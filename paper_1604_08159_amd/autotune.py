@@ -20,7 +20,7 @@ import json
 import math
 import os
 import time
-from typing import Dict, Iterable, Optional, Sequence, Tuple
+from typing import Dict, Iterable, Optional, Tuple
 
 import torch
 
@@ -72,11 +72,11 @@ def time_tile(J: int, p: int, prec: int, tile: int, nsolves: int = 4, steps: int
         tune_set_tile(J, p, prec, prev if prev in valid_tiles(J, p, prec) else 0)
 
 
-def _key(J: int, p: int, prec: int) -> str:
+def entry_key(J: int, p: int, prec: int) -> str:
     return f"J{J}_p{p}_prec{prec}"
 
 
-def _parse_key(k: str) -> Tuple[int, int, int]:
+def parse_entry_key(k: str) -> Tuple[int, int, int]:
     j, p, prec = k.split("_")
     return int(j[1:]), int(p[1:]), int(prec[4:])
 
@@ -93,7 +93,7 @@ def autotune(configs: Iterable[Tuple[int, int, int]], cache: Optional[str] = Non
         if data.get("device") == name:
             entries = dict(data.get("entries", {}))
     for J, p, prec in configs:
-        k = _key(J, p, prec)
+        k = entry_key(J, p, prec)
         if k not in entries:
             ms = {str(t): time_tile(J, p, prec, t, device=device, **timing) for t in valid_tiles(J, p, prec)}
             best = min(ms, key=ms.get)
@@ -115,7 +115,7 @@ def apply_cache(cache: str, device: str = "cuda:0") -> int:
         return 0
     n = 0
     for k, e in data.get("entries", {}).items():
-        J, p, prec = _parse_key(k)
+        J, p, prec = parse_entry_key(k)
         tune_set_tile(J, p, prec, int(e["tile"]))
         n += 1
     return n

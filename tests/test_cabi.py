@@ -111,4 +111,4 @@ def test_tile_table_host_logic():
     assert at.valid_tiles(9, 3, m.MRA_FP64) == (8, 16)
     assert at.valid_tiles(4, 2, m.MRA_MIXED) == (8, 16)
     assert at.valid_tiles(11, 3, m.MRA_MIXED) == (8, 16, 32)
-    assert at._parse_key(at._key(10, 3, 2)) == (10, 3, 2)
+    assert at.parse_entry_key(at.entry_key(10, 3, 2)) == (10, 3, 2)
