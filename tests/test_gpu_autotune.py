@@ -1,7 +1,8 @@
 """Tile autotuning on the GPU: the stencil tile edge changes only how tiles
 are staged in LDS, never a node's arithmetic, so solves laid out with tiles
 8, 16 and 32 step bit-identically (FP64 and mixed); solves of different tiles
-share a solve_batch call and each equals itself stepped alone; the autotuner
+share a solve_batch call and each equals itself stepped alone; a condensing
+scalar steps bit-identically whatever its and its partner's tiles; the autotuner
 times the candidates, applies its choice and round-trips its JSON cache."""
 import json
 
@@ -84,3 +85,24 @@ def test_autotuner_choice_and_cache(M, tmp_path):
     again = at.autotune([(7, 2, M.MRA_MIXED)], cache=cache)
     assert again["J7_p2_prec2"] == data["entries"]["J7_p2_prec2"]
     M.tune_set_tile(7, 2, M.MRA_MIXED, 0)
+
+
+def test_scalar_tiles_step_bit_identically(M):
+    """A passive scalar (with condensation) laid out with tile 16 or 32 on a
+    partner of either tile steps bit-identically."""
+    pb = W.fujiwhara_pair(1004, J=7)
+    r0 = torch.from_numpy(W.vapor_patch(pb.N, 1.0, 0.005)).to(DEV)
+    out = []
+    for tv, ts in ((32, 32), (16, 32), (32, 16)):
+        v = _solve(M, pb, M.MRA_MIXED, tv)
+        M.tune_set_tile(pb.J, pb.p, M.MRA_MIXED, ts)
+        try:
+            s = M.ScalarSolve(v, M.grid_desc(pb.J, pb.p, 1e-3), 10, pb.dt, r0, kappa0=0.01, eddy=False)
+        finally:
+            M.tune_set_tile(pb.J, pb.p, M.MRA_MIXED, 0)
+        s.set_condensation(1.0)
+        M.solve_batch([v, s], [3, 3])
+        out.append(s.read()[0].cpu().numpy())
+        s.close()
+        v.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
