@@ -61,11 +61,14 @@ enum {
   MRA_E_UNSUPPORTED = 6
 };
 
-enum { MRA_FP64 = 0, MRA_FP32 = 1, MRA_MIXED = 2 };   /* MIXED: FP32 bulk fields,
-                                                         FP64 Krylov / regrid.
-                                                         FP32 (solves): as MIXED, but
-                                                         the Krylov basis is stored
-                                                         in FP32 (its sums stay FP64) */
+/* Precision.  MRA_FP64: every field and sum in FP64.  MRA_MIXED: the bulk
+ * fields of the Jacobian-vector products (Pi of the Arnoldi vectors, their
+ * Poisson solve, the product stencil, and the base fields w~, u, v, nu_e they
+ * read) are FP32; the residual F itself (its Pi, Poisson solve and stencil,
+ * once per step), the Krylov basis and its sums, the Hessenberg exponential
+ * or solve, the update and the regrid are FP64.  MRA_FP32 (solves): as
+ * MIXED, with the Krylov basis stored in FP32 (its sums stay FP64). */
+enum { MRA_FP64 = 0, MRA_FP32 = 1, MRA_MIXED = 2 };
 enum { MRA_FORWARD = 1, MRA_INVERSE = -1, MRA_PROLONG = 2 };
 enum { MRA_EXPONENTIAL = 0, MRA_THETA_NEWTON = 1 };   /* time integrator of a solve */
 enum { MRA_JAC_FROZEN = 0, MRA_JAC_EXACT = 1 };        /* Jacobian of its Krylov products */
@@ -163,6 +166,9 @@ int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir,
  * vel_dense_or_null: if non-NULL receives the velocity of w~ as [2][N][N]
  *   (u then v; element type of prec), caller-owned.
  * prec: element type of the dense fields (FP64, or FP32 for FP32/MIXED).
+ *   With FP32 fields the residual F is still evaluated in FP64 (its Pi,
+ *   Poisson solve and stencil) and the FP32 base fields of the product are
+ *   its values rounded; only J v runs in FP32.
  * ------------------------------------------------------------------------ */
 int32_t mra_rhs_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes);
 int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec,

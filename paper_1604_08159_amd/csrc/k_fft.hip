@@ -249,10 +249,11 @@ template <typename T>
 __device__ inline const T* poisson_src(const SolveDev& s, int src) {
   if (src == 0) return reinterpret_cast<const T*>(s.wt);
   if (src == 1) return reinterpret_cast<const T*>(s.vt);
+  if (src == 3) return reinterpret_cast<const T*>(s.res64);
   return reinterpret_cast<const T*>(s.dense64);
 }
 // velocity outputs: src 0 -> (u, v), src 1 -> (u_v, v_v), or psi~ alone in u_v
-// when only the stream function is formed, src 2 -> FP64 pair
+// when only the stream function is formed, src 2 and 3 -> the FP64 pair
 template <typename T>
 __device__ inline T* poisson_dst(const SolveDev& s, int src, int comp) {
   if (src == 0) return reinterpret_cast<T*>(comp == 0 ? s.u : s.v);
@@ -433,12 +434,12 @@ static hipError_t poisson_t(const Batch& b, const LaunchCfg& c, int src, int pas
 }
 
 hipError_t launch_poisson(const Batch& b, const LaunchCfg& c, int src, hipStream_t st) {
-  if (src == 2 || c.prec == 0) return poisson_t<double>(b, c, src, -1, st);
+  if (src >= 2 || c.prec == 0) return poisson_t<double>(b, c, src, -1, st);
   return poisson_t<float>(b, c, src, -1, st);
 }
 
 hipError_t launch_poisson_pass(const Batch& b, const LaunchCfg& c, int src, int pass, hipStream_t st) {
-  if (src == 2 || c.prec == 0) return poisson_t<double>(b, c, src, pass, st);
+  if (src >= 2 || c.prec == 0) return poisson_t<double>(b, c, src, pass, st);
   return poisson_t<float>(b, c, src, pass, st);
 }
 

@@ -17,6 +17,8 @@
 // the active list through the dense rank map); tiles without an active node
 // skip the residual.  The residual kernel also stores nu_e on the whole grid:
 // the Jacobian-vector products of the step reuse it (frozen) with u and v.
+#include <type_traits>
+
 #include "mra_internal.hpp"
 
 namespace mra {
@@ -111,9 +113,15 @@ __host__ __device__ inline size_t jvp_lds_elems(int TS, bool exact = false) {
   return exact ? 4 * Ww * Ww + 4 * Wn * Wn : 4 * Ww * Ww + Wn * Wn;
 }
 
-template <int P, typename T, int TS>
+// R64: the residual of a solve whose bulk fields are FP32, evaluated in FP64
+// from the FP64 prolongation res64 and its FP64 velocity vel64 (u, then v).
+// Such a kernel also leaves the FP32 copies of w~, u, v (rounded) and nu_e in
+// the bulk fields, which the Jacobian-vector products of the step read.
+template <int P, typename T, int TS, bool R64 = false>
 __global__ void __launch_bounds__(256) k_rhs(Batch b) {
+  static_assert(!R64 || sizeof(T) == 8, "the FP32-bulk residual runs in FP64");
   using G = Geo<P>;
+  using TB = typename std::conditional<R64, float, T>::type;   // bulk field type
   extern __shared__ unsigned char smem[];
   const SolveDev& s = MRA_SOLVE(b);
   const int N = s.N, ntx = s.ntx;
@@ -126,16 +134,32 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   T* ww = nu + Wn * Wn;
   T* cn = ww + Ww * Ww;
   {
+    const T* gu = R64 ? reinterpret_cast<const T*>(s.vel64) : reinterpret_cast<const T*>(s.u);
+    const T* gv = R64 ? reinterpret_cast<const T*>(s.vel64 + (size_t)N * N) : reinterpret_cast<const T*>(s.v);
+    const T* gw = R64 ? reinterpret_cast<const T*>(s.res64) : reinterpret_cast<const T*>(s.wt);
     Region<Wu, T> ru, rv;
     Region<Ww, T> rw;
-    ru.fetch(reinterpret_cast<const T*>(s.u), x0 - G::HU, y0 - G::HU, N);
-    rv.fetch(reinterpret_cast<const T*>(s.v), x0 - G::HU, y0 - G::HU, N);
-    rw.fetch(reinterpret_cast<const T*>(s.wt), x0 - G::R1, y0 - G::R1, N);
+    ru.fetch(gu, x0 - G::HU, y0 - G::HU, N);
+    rv.fetch(gv, x0 - G::HU, y0 - G::HU, N);
+    rw.fetch(gw, x0 - G::R1, y0 - G::R1, N);
     ru.put(uu);
     rv.put(vv);
     rw.put(ww);
   }
   __syncthreads();
+  if constexpr (R64) {
+    // the FP32 fields of the products: every tile writes its own nodes
+    TB* bw = reinterpret_cast<TB*>(s.wt);
+    TB* bu = reinterpret_cast<TB*>(s.u);
+    TB* bv = reinterpret_cast<TB*>(s.v);
+    for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+      const int r = q / TS, c = q - r * TS;
+      const size_t o = (size_t)(y0 + r) * N + x0 + c;
+      bw[o] = (TB)ww[(r + G::R1) * Ww + c + G::R1];
+      bu[o] = (TB)uu[(r + G::HU) * Wu + c + G::HU];
+      bv[o] = (TB)vv[(r + G::HU) * Wu + c + G::HU];
+    }
+  }
   const T ih = T(1.0 / s.h), ih2 = T(1.0 / (s.h * s.h));
   // nu_e on the Wn region
   const T cs2 = T((s.cs * s.h) * (s.cs * s.h));
@@ -157,10 +181,10 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   }
   __syncthreads();
   // store nu_e of the tile for the Jacobian-vector products
-  T* gn = reinterpret_cast<T*>(s.nu);
+  TB* gn = reinterpret_cast<TB*>(s.nu);
   for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
     const int r = q / TS, c = q - r * TS;
-    gn[(y0 + r) * N + x0 + c] = nu[(r + P) * Wn + c + P];
+    gn[(y0 + r) * N + x0 + c] = (TB)nu[(r + P) * Wn + c + P];
   }
   if (s.tile_count[tile] == 0) return;
   __syncthreads();
@@ -538,8 +562,14 @@ template <int P, typename T, int TS>
 static hipError_t rhs_ts(const Batch& b, int N, bool jvp, bool exact, hipStream_t st) {
   const int nt = (N / TS) * (N / TS);
   if (!jvp) {
-    const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
-    hipLaunchKernelGGL((k_rhs<P, T, TS>), dim3((nt) * b.n), dim3(256), lds, st, b);
+    if constexpr (sizeof(T) == 4) {
+      // FP32 bulk fields: the residual itself runs in FP64 (k_rhs R64)
+      const size_t lds = rhs_lds_elems<P, double>(TS) * sizeof(double);
+      hipLaunchKernelGGL((k_rhs<P, double, TS, true>), dim3((nt) * b.n), dim3(256), lds, st, b);
+    } else {
+      const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
+      hipLaunchKernelGGL((k_rhs<P, T, TS>), dim3((nt) * b.n), dim3(256), lds, st, b);
+    }
   } else if (!exact) {
     const size_t lds = jvp_lds_elems<P, T>(TS) * sizeof(T);
     hipLaunchKernelGGL((k_jvp<P, T, TS, false>), dim3((nt) * b.n), dim3(256), lds, st, b);

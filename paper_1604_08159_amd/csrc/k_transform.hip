@@ -28,6 +28,7 @@ template <typename T>
 __device__ inline T* dense_target(const SolveDev& s, int target) {
   if (target == 0) return reinterpret_cast<T*>(s.wt);
   if (target == 1) return reinterpret_cast<T*>(s.vt);
+  if (target == 3) return reinterpret_cast<T*>(s.res64);
   return reinterpret_cast<T*>(s.dense64);
 }
 

@@ -149,8 +149,14 @@ void rhs_layout(Layout& L, SolveDev& s) {
   s.vt = L.take<char>(Nf * esz);
   s.uv = L.take<char>(Nf * esz);
   s.vv = L.take<char>(Nf * esz);
-  s.spec = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 2 * esz);
-  s.spec2 = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 2 * esz);
+  // the residual of FP32 bulk fields runs in FP64: its prolongation, velocity
+  // and FP64 spectra
+  s.spec = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 16);
+  s.spec2 = L.take<char>((size_t)(s.N / 2 + 1) * s.N * 16);
+  if (s.prec != 0) {
+    s.res64 = L.take<double>(Nf);
+    s.vel64 = L.take<double>(2 * Nf);
+  }
   s.out_rhs = L.take<double>(Nf);
 }
 
@@ -194,6 +200,10 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.diag = L.take<double>((size_t)s.N * 5);
   s.out_rhs = s.w;
   s.out_jvp = s.w;
+  // FP32 bulk fields: the FP64 prolongation of the residual lives in the
+  // basis storage ((m + 1) N^2 elements, m >= 1), which a step writes only
+  // after the residual (V_0 = F / beta is written by the first product's Pi)
+  if (s.prec != 0) s.res64 = s.V ? s.V : reinterpret_cast<double*>(s.V32);
 }
 
 Batch one(const SolveDev* d) {
@@ -202,6 +212,19 @@ Batch one(const SolveDev* d) {
   b.s[0] = d;
   b.n = 1;
   return b;
+}
+
+// The residual F(omega) at the active nodes, with u, v and nu_e of Pi(omega)
+// left in the bulk fields for the Jacobian-vector products.  FP64 solves
+// prolong, solve the Poisson equation and evaluate the stencil in their own
+// fields; solves with FP32 bulk fields do all three in FP64 (res64, vel64)
+// and the stencil kernel leaves the FP32 copies that the products read.
+hipError_t enqueue_residual(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  hipError_t e;
+  const bool dbl = c.prec == 0;
+  if ((e = launch_prolong(b, c, dbl ? 0 : 3, 1, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_poisson(b, c, dbl ? 0 : 3, st)) != hipSuccess) return e;
+  return launch_rhs(b, c, st);
 }
 
 // One exponential step of passive scalars: the operator is linear in the
@@ -235,9 +258,7 @@ hipError_t enqueue_theta_step(const Batch& b, const LaunchCfg& c, hipStream_t st
   const int dbl = c.prec == 0;
   hipError_t e;
   for (int it = 0; it < c.newton; ++it) {
-    if ((e = launch_prolong(b, c, 0, dbl, 0, 0, st)) != hipSuccess) return e;
-    if ((e = launch_poisson(b, c, 0, st)) != hipSuccess) return e;
-    if ((e = launch_rhs(b, c, st)) != hipSuccess) return e;
+    if ((e = enqueue_residual(b, c, st)) != hipSuccess) return e;
     if ((e = launch_newton_rhs(b, c, it == 0, st)) != hipSuccess) return e;
     if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
     for (int j = 0; j < c.m; ++j) {
@@ -263,9 +284,7 @@ hipError_t enqueue_step(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   const int dbl = c.prec == 0;
   hipError_t e;
   // residual F at omega
-  if ((e = launch_prolong(b, c, 0, dbl, 0, 0, st)) != hipSuccess) return e;
-  if ((e = launch_poisson(b, c, 0, st)) != hipSuccess) return e;
-  if ((e = launch_rhs(b, c, st)) != hipSuccess) return e;
+  if ((e = enqueue_residual(b, c, st)) != hipSuccess) return e;
   if ((e = launch_norm0(b, c, st)) != hipSuccess) return e;
   // Arnoldi
   for (int j = 0; j < c.m; ++j) {
@@ -361,20 +380,23 @@ int32_t mra_transform_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* byt
   return MRA_OK;
 }
 
-int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const void* in, void* out,
-                      uint8_t* mask, int32_t* index_packed, int32_t* index_fine, int64_t* n_active,
-                      void* ws, size_t ws_bytes, void* stream) {
+// Argument checks of mra_transform.
+static int32_t check_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const void* in, void* out,
+                               uint8_t* mask, int32_t* index_packed, int32_t* index_fine, int64_t* n_active) {
   int32_t r = check_grid(g);
   if (r != MRA_OK) return r;
-  if (prec < 0 || prec > 2 || !in || !out || !ws) return MRA_E_ARG;
+  if (prec < 0 || prec > 2 || !in || !out) return MRA_E_ARG;
   if (dir != MRA_FORWARD && dir != MRA_INVERSE && dir != MRA_PROLONG) return MRA_E_ARG;
   if (dir == MRA_FORWARD && mask && (!index_packed || !index_fine || !n_active)) return MRA_E_ARG;
   if (dir == MRA_PROLONG && (!mask || !index_fine || !n_active)) return MRA_E_ARG;
-  size_t need = 0;
-  mra_transform_ws_bytes(g, prec, &need);
-  if (ws_bytes < need) return MRA_E_NOMEM;
-  if ((r = ensure_init()) != MRA_OK) return r;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  return MRA_OK;
+}
+
+// The launches of a transform whose workspace (device address ws, already
+// checked to be large enough) holds the descriptor and the scratch arrays.
+static int32_t transform_enqueue(const mra_grid_desc* g, int32_t prec, int32_t dir, const void* in, void* out,
+                                 uint8_t* mask, int32_t* index_packed, int32_t* index_fine, int64_t* n_active,
+                                 void* ws, hipStream_t st) {
   SolveDev s;
   fill_geometry(s, g, prec);
   Layout L(ws);
@@ -410,6 +432,20 @@ int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const v
     MRA_TRY(launch_prolong(b, c, dbl ? 2 : 0, dbl ? 1 : 0, 0, 0, st));
   }
   return MRA_OK;
+}
+
+int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const void* in, void* out,
+                      uint8_t* mask, int32_t* index_packed, int32_t* index_fine, int64_t* n_active,
+                      void* ws, size_t ws_bytes, void* stream) {
+  int32_t r = check_transform(g, prec, dir, in, out, mask, index_packed, index_fine, n_active);
+  if (r != MRA_OK) return r;
+  if (!ws) return MRA_E_ARG;
+  size_t need = 0;
+  mra_transform_ws_bytes(g, prec, &need);
+  if (ws_bytes < need) return MRA_E_NOMEM;
+  if ((r = ensure_init()) != MRA_OK) return r;
+  return transform_enqueue(g, prec, dir, in, out, mask, index_packed, index_fine, n_active, ws,
+                           static_cast<hipStream_t>(stream));
 }
 
 int32_t mra_rhs_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes) {
@@ -465,9 +501,7 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
   Batch b = one(dev);
   MRA_TRY(launch_reset_ctrl(b, st));
   MRA_TRY(launch_rank_from_index(b, c, st));
-  MRA_TRY(launch_prolong(b, c, 0, dbl, 0, 0, st));
-  MRA_TRY(launch_poisson(b, c, 0, st));
-  MRA_TRY(launch_rhs(b, c, st));
+  MRA_TRY(enqueue_residual(b, c, st));
   if (v_active) {
     MRA_TRY(launch_prolong(b, c, 1, dbl, 2, 0, st));
     MRA_TRY(launch_poisson(b, c, 1, st));

@@ -70,7 +70,9 @@ struct SolveDev {
   void* vv;
   void* spec;               // complex half spectrum [(N/2+1)][N]: omega, then u
   void* spec2;              // the v spectrum, same shape
-  double* vel64;            // FP64 velocity [2][Nf] of dense64 (diagnostics)
+  double* vel64;            // FP64 velocity [2][Nf] of dense64 (diagnostics), and of res64
+  double* res64;            // FP32-bulk solves: Pi(omega) in FP64 for the residual [Nf] (it
+                            // shares the Krylov basis storage, which a step fills only later)
   double* dense64;          // FP64 regrid field [Nf]; F(omega_n) during Newton iterations
   double* packed64;         // FP64 packed pyramid [Nf]; omega_n during Newton iterations
   double* out_rhs;          // residual at the active nodes [Nf]
@@ -352,8 +354,8 @@ struct LaunchCfg {
 hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);
 
 // transforms
-// Pi into target (0 wt, 1 vt, 2 dense64) from src (0 omega, 1 the next
-// Arnoldi vector V_j, 2 vin); as_double selects the element type.
+// Pi into target (0 wt, 1 vt, 2 dense64, 3 res64) from src (0 omega, 1 the
+// next Arnoldi vector V_j, 2 vin); as_double selects the element type.
 hipError_t launch_prolong(const Batch& b, const LaunchCfg& c, int target, int as_double, int src, int j,
                           hipStream_t st);
 hipError_t launch_forward(const Batch& b, const LaunchCfg& c, int src /*0 dense64 (fp64), 1 wt*/,
@@ -366,11 +368,14 @@ hipError_t launch_reset_max(const Batch& b, hipStream_t st);
 
 // Poisson
 hipError_t fft_init_tables(hipStream_t st);
-hipError_t launch_poisson(const Batch& b, const LaunchCfg& c, int src /*0 wt->(u,v), 1 vt->(uv,vv), 2 dense64->vel64 (fp64)*/,
+hipError_t launch_poisson(const Batch& b, const LaunchCfg& c,
+                          int src /*0 wt->(u,v), 1 vt->(uv,vv), 2 dense64->vel64, 3 res64->vel64 (fp64)*/,
                           hipStream_t st);
 hipError_t launch_poisson_pass(const Batch& b, const LaunchCfg& c, int src, int pass, hipStream_t st);
 
 // stencils
+// The residual: FP64 solves from wt, u, v; FP32-bulk solves in FP64 from res64
+// and vel64, also writing the FP32 wt, u, v and nu_e that their products read.
 hipError_t launch_rhs(const Batch& b, const LaunchCfg& c, hipStream_t st);
 hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st);
 // passive-scalar operator at the active nodes (check_done: skip once the basis is complete)

@@ -6,7 +6,8 @@ non-default stream).
   solves in mixed precision, 2 steps; solve 0 against the FP64 oracle.
 * 2048^2 three vortices + noise, 6-point DD, eps 1e-4: F and J v at every
   active node against the oracle (mixed precision), and one m = 30 step in
-  FP64 and mixed precision against each other.
+  FP64 and mixed precision against each other (the oracle's own m = 30 steps
+  of this shape run at 512^2 and 1024^2 in test_gpu_configs.py).
 """
 import math
 
@@ -74,16 +75,10 @@ def three2048():
     return pb, w0, mask, fi
 
 
-def fp32_flux_bound(umax, wmax, h, p):
-    """A-priori FP32 rounding bound of the flux derivative D1(u w): the
-    operands carry relative errors of a few 2^-24 (the velocity from an FP32
-    FFT about ten), and the D1 stencil sum amplifies them by 2 sum|a_n| / h."""
-    from oracle import dd
-    amp = 2 * sum(abs(float(c)) for c in dd.d1_coeffs(p)) / h
-    return 16 * 2.0 ** -24 * amp * umax * wmax
-
-
 def test_three2048_rhs_and_jvp_match_oracle(M, three2048):
+    """Mixed precision at 2048^2, 6-point DD, every node active: the residual
+    (evaluated in FP64 from the FP32-rounded state) and the FP32 product within
+    the stated 2e-5 of their scales."""
     pb, w0, mask, fi = three2048
     h = 2 * math.pi / pb.N
     omega = w0.ravel()[fi].astype(np.float32).astype(np.float64)
@@ -102,20 +97,13 @@ def test_three2048_rhs_and_jvp_match_oracle(M, three2048):
     M.collocation_rhs(g, gf, M.MRA_MIXED, mk, fk, nk, _t(omega), None, out)
     errF = np.abs(out.cpu().numpy() - F).max() / sc
     v = W.random_field(pb.N, 77, smooth=2).ravel()[fi].astype(np.float32).astype(np.float64)
-    Jv = oo.jvp(om.prolong(v, fi, pb.J, pb.p), base, h, pb.p, fl).ravel()[fi]
+    vt = om.prolong(v, fi, pb.J, pb.p)
+    Jv = oo.jvp(vt, base, h, pb.p, fl).ravel()[fi]
     M.collocation_rhs(g, gf, M.MRA_MIXED, mk, fk, nk, _t(omega), _t(v), out)
     errJ = np.abs(out.cpu().numpy() - Jv).max() / np.abs(Jv).max()
-    umax = max(np.abs(base["u"]).max(), np.abs(base["v"]).max())
-    tolF = max(2e-5, fp32_flux_bound(umax, np.abs(wt).max(), h, pb.p) / sc)
-    vt = om.prolong(v, fi, pb.J, pb.p)
-    psv = oo.poisson(vt, h, pb.p)
-    uvmax = max(np.abs(oo.d1(psv, 0, h, pb.p)).max(), np.abs(oo.d1(psv, 1, h, pb.p)).max())
-    tolJ = max(2e-5, (fp32_flux_bound(uvmax, np.abs(wt).max(), h, pb.p) +
-                      fp32_flux_bound(umax, np.abs(vt).max(), h, pb.p)) / np.abs(Jv).max())
-    print(f"2048^2 p=3 N_a={n} ({n / pb.N ** 2:.1%} active): F err {errF:.2e} (bar {tolF:.1e}), "
-          f"Jv err {errJ:.2e} (bar {tolJ:.1e})")
-    assert errF <= tolF
-    assert errJ <= tolJ
+    print(f"2048^2 p=3 N_a={n} ({n / pb.N ** 2:.1%} active): F err {errF:.2e}, J v err {errJ:.2e} (bar 2e-5)")
+    assert errF <= 2e-5
+    assert errJ <= 2e-5
 
 
 def test_three2048_step_fp64_vs_mixed(M, three2048):
