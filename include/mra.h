@@ -29,8 +29,9 @@
  *   - Every pointer argument named *_dev, and every array argument unless
  *     stated otherwise, is DEVICE memory owned by the caller.  The library
  *     never allocates or frees device memory; it keeps only small constant
- *     tables in module memory (set up by mra_init) and, per solve handle, a
- *     small host object plus captured HIP graphs.
+ *     tables and the 5 MiB workspace of mra_transform_noalloc in module
+ *     memory (set up by mra_init) and, per solve handle, a small host object
+ *     plus captured HIP graphs.
  *   - `stream` is a hipStream_t (NULL = default stream).  Every call is
  *     asynchronous on it except mra_solve_read, which synchronises it.
  *   - Argument and size errors are returned before anything is launched.
@@ -147,6 +148,25 @@ int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir,
                       const void* in, void* out,
                       uint8_t* mask, int32_t* index_packed, int32_t* index_fine,
                       int64_t* n_active, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * mra_transform_noalloc -- mra_transform for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same arguments without the workspace, the same
+ * kernels and the same results bit for bit.  The workspace is a
+ * library-owned array in module memory of 5 MiB per device, held from the
+ * first call on a device until the process ends; the call itself allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).  Grids up to
+ * J = 10 only: a larger J returns MRA_E_SIZE before anything is launched.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents (each call initialises what it reads), so calls on one device
+ * must not overlap: issue them on one stream, or order them by events or
+ * synchronisation; calls that overlap race.  Other errors as mra_transform.
+ * ------------------------------------------------------------------------ */
+int32_t mra_transform_noalloc(const mra_grid_desc* g, int32_t prec, int32_t dir,
+                              const void* in, void* out,
+                              uint8_t* mask, int32_t* index_packed, int32_t* index_fine,
+                              int64_t* n_active, void* stream);
 
 /* ------------------------------------------------------------------------
  * collocation_rhs -- residual F(omega) or the Jacobian-vector product J v at

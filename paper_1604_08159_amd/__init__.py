@@ -101,6 +101,18 @@ def mra_transform(g: GridDesc, prec: int, direction: int, inp: torch.Tensor, out
     _check("mra_transform", st)
 
 
+def mra_transform_noalloc(g: GridDesc, prec: int, direction: int, inp: torch.Tensor, out: torch.Tensor,
+                          mask: Optional[torch.Tensor] = None, index_packed: Optional[torch.Tensor] = None,
+                          index_fine: Optional[torch.Tensor] = None, n_active: Optional[torch.Tensor] = None,
+                          stream=None) -> None:
+    """mra_transform without a workspace argument: the library's own
+    per-device workspace serves (grids up to J = 10; calls on one device must
+    not overlap)."""
+    st = lib().mra_transform_noalloc(C.byref(g), prec, direction, _ptr(inp), _ptr(out), _ptr(mask),
+                                     _ptr(index_packed), _ptr(index_fine), _ptr(n_active), _stream(stream))
+    _check("mra_transform_noalloc", st)
+
+
 def rhs_ws_bytes(g: GridDesc, prec: int) -> int:
     n = C.c_size_t()
     _check("mra_rhs_ws_bytes", lib().mra_rhs_ws_bytes(C.byref(g), prec, C.byref(n)))

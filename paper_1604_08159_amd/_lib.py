@@ -43,6 +43,8 @@ EXPORTS = {
     "mra_transform": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_size_t, C.c_void_p]),
+    "mra_transform_noalloc": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mra_rhs_ws_bytes": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.POINTER(C.c_size_t)]),
     "collocation_rhs": (C.c_int32, [C.POINTER(GridDesc), C.POINTER(FlowDesc), C.c_int32, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

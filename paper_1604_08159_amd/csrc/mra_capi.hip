@@ -16,6 +16,14 @@
 
 using namespace mra;
 
+// Workspace of mra_transform_noalloc: one per device, in module memory, for
+// grids up to kScratchMaxJ (the transform's descriptor, max|u|, compaction
+// offsets, rank map and tile counts: about 4.1 MB at J = 10).  Every call on a
+// device shares it, so such calls must not overlap on that device.
+constexpr int kScratchMaxJ = 10;
+constexpr size_t kScratchBytes = (size_t)5 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 struct mra_solve_s {
   SolveDev host;          // pointers into the arena
   SolveDev* dev = nullptr;
@@ -34,6 +42,7 @@ namespace {
 
 std::mutex g_mu;
 bool g_init[64] = {};
+void* g_scratch[64] = {};   // per device: the address of `scratch` on that device
 
 #define MRA_TRY(expr)                                   \
   do {                                                  \
@@ -47,6 +56,11 @@ int32_t ensure_init() {
   if (dev < 0 || dev >= 64) return MRA_E_DEVICE;
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_init[dev]) return MRA_OK;
+  // the device copy of the no-allocation workspace: its address on this
+  // device (the host-side name of the array is not a device address)
+  void* sp = nullptr;
+  if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) return MRA_E_DEVICE;
+  g_scratch[dev] = sp;
   MRA_TRY(fft_init_tables(nullptr));
   MRA_TRY(hipDeviceSynchronize());
   g_init[dev] = true;
@@ -380,7 +394,7 @@ int32_t mra_transform_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* byt
   return MRA_OK;
 }
 
-// Argument checks of mra_transform.
+// Argument checks shared by mra_transform and mra_transform_noalloc.
 static int32_t check_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const void* in, void* out,
                                uint8_t* mask, int32_t* index_packed, int32_t* index_fine, int64_t* n_active) {
   int32_t r = check_grid(g);
@@ -445,6 +459,21 @@ int32_t mra_transform(const mra_grid_desc* g, int32_t prec, int32_t dir, const v
   if (ws_bytes < need) return MRA_E_NOMEM;
   if ((r = ensure_init()) != MRA_OK) return r;
   return transform_enqueue(g, prec, dir, in, out, mask, index_packed, index_fine, n_active, ws,
+                           static_cast<hipStream_t>(stream));
+}
+
+int32_t mra_transform_noalloc(const mra_grid_desc* g, int32_t prec, int32_t dir, const void* in, void* out,
+                              uint8_t* mask, int32_t* index_packed, int32_t* index_fine, int64_t* n_active,
+                              void* stream) {
+  int32_t r = check_transform(g, prec, dir, in, out, mask, index_packed, index_fine, n_active);
+  if (r != MRA_OK) return r;
+  size_t need = 0;
+  mra_transform_ws_bytes(g, prec, &need);
+  if (g->J > kScratchMaxJ || need > kScratchBytes) return MRA_E_SIZE;
+  if ((r = ensure_init()) != MRA_OK) return r;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MRA_E_DEVICE;
+  return transform_enqueue(g, prec, dir, in, out, mask, index_packed, index_fine, n_active, g_scratch[dev],
                            static_cast<hipStream_t>(stream));
 }
 

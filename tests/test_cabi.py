@@ -112,3 +112,37 @@ def test_tile_table_host_logic():
     assert at.valid_tiles(4, 2, m.MRA_MIXED) == (8, 16)
     assert at.valid_tiles(11, 3, m.MRA_MIXED) == (8, 16, 32)
     assert at.parse_entry_key(at.entry_key(10, 3, 2)) == (10, 3, 2)
+
+
+def test_noalloc_transform_host_checks(lib):
+    """mra_transform_noalloc on the host: every grid up to J = 10 fits its
+    5 MiB per-device workspace whatever the tile table holds, a larger grid
+    is refused with MRA_E_SIZE and null arrays with MRA_E_ARG, both before
+    anything touches the GPU."""
+    import paper_1604_08159_amd as m
+    n = C.c_size_t()
+    limit = 5 << 20
+    try:
+        for J in range(3, 11):
+            for p in (2, 3):
+                if J <= (2 if p == 2 else 3):
+                    continue
+                for prec in (0, 1, 2):
+                    for tile in (0, 8, 16, 32):
+                        if tile and (tile > (1 << J) or (prec == 0 and p == 3 and tile == 32)):
+                            continue
+                        m.tune_set_tile(J, p, prec, tile)
+                        assert lib.mra_transform_ws_bytes(C.byref(_grid(J, p)), prec, C.byref(n)) == 0
+                        assert n.value <= limit, (J, p, prec, tile, n.value)
+                        m.tune_set_tile(J, p, prec, 0)
+    finally:
+        for J in range(3, 11):
+            for p in (2, 3):
+                for prec in (0, 2):
+                    if J > (2 if p == 2 else 3):
+                        m.tune_set_tile(J, p, prec, 0)
+    buf = C.c_void_p(0x1000)     # never dereferenced: the size check comes first
+    assert lib.mra_transform_noalloc(C.byref(_grid(11, 2)), 0, 1, buf, buf, None, None, None, None, None) == 2
+    assert lib.mra_transform_noalloc(C.byref(_grid(11, 3)), 2, 2, buf, buf, buf, None, buf, buf, None) == 2
+    assert lib.mra_transform_noalloc(C.byref(_grid(6, 2)), 0, 1, None, None, None, None, None, None, None) == 1
+    assert lib.mra_transform_noalloc(C.byref(_grid(6, 2)), 0, 7, buf, buf, None, None, None, None, None) == 1
