@@ -1,18 +1,35 @@
 """Benchmark of the wavelet-collocation vortex step on one MI355X.
 
-Workload: the Fujiwhara pair at Re = 5000 on a 512 x 512 finest grid
-(J = 9), 4-point DD, threshold 1e-4, Krylov dimension 20, dt = 0.01; a batch
-of 24 solves whose radii and separations are drawn from seeds 1000..1023.
-One step = one exponential Rosenbrock-Euler step of every solve of the batch
-(residual, 20 Jacobian-vector products, Arnoldi, phi_1, update and FP64
-regrid), launched together through solve_batch and replayed as a HIP graph.
+Headline workload: the three-vortex Re = 37440 configuration at its full
+size, 2048 x 2048 finest grid (J = 11), 6-point DD, threshold 1e-4,
+Smagorinsky Cs = 0.17, Krylov dimension 30, dt = 0.002, seeded white-noise
+vorticity of amplitude 1e-3 (nearly every node active at first); a batch of
+two solves (noise seeds 37440, 37441) in mixed precision.  One step = one
+exponential Rosenbrock-Euler step of every solve of the batch (residual,
+30 Jacobian-vector products, Arnoldi, phi_1, update and FP64 regrid),
+launched together through solve_batch and replayed as a HIP graph.
 
 Metric: active-point residual evaluations per second, summed over the batch
-((1 + m_eff) N_a per solve and step, counted on the device).  Also reported:
-the roofline fraction of the dominant kernel (HIP events on the launching
-stream) and the FP64 CPU oracle timed on a bounded sample on the host cores.
+((1 + m_eff) N_a per solve and step, counted on the device).  Also reported
+in the same JSON line:
+  roofline        the dominant kernel of the step (largest share of one
+                  step's GPU time, from per-phase HIP events inside a step)
+                  against 8 TB/s, with algorithmic bytes per launch from the
+                  per-unit byte model of each kernel (kernel_bytes), and the
+                  same for every other kernel of the step;
+  rhs_pipeline    the HBM fraction of the residual and product kernels
+                  together: (B_F + m B_Jv) / (t_F + m t_Jv) / 8 TB/s;
+  cpu_baseline    the FP64 CPU oracle on a bounded sample of the same
+                  workload (one residual and three products at 2048^2, one
+                  core), whose outputs also give the accuracy of the GPU's
+                  residual and product against the oracle;
+  sub-records     the 512^2 Fujiwhara batch of 24 (with its accuracy against
+                  the oracle after the timed steps and its 2000-step drift),
+                  the 256-solve ensemble (solves/s against the FP64 per-solve
+                  GPU path and the oracle), and the serving configuration's
+                  request mix (p50 / p99 latency at 70% of capacity).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec mixed|fp64]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
 """
 from __future__ import annotations
 
@@ -22,6 +39,7 @@ import math
 import os
 import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -32,38 +50,112 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 CALIB_BYTES = 64 << 20          # plain device copy of known size (PMC byte-counter scale)
-KERNEL_SOURCES = {"jvp": "k_stencil.hip", "rhs": "k_stencil.hip", "fft_rows": "k_fft.hip",
-                  "fft_cols": "k_fft.hip", "fft_rows_inv": "k_fft.hip", "prolong_finest": "k_transform.hip",
-                  "forward": "k_transform.hip"}
+KERNEL_SOURCES = {"jvp": "k_stencil.hip", "res_stencil": "k_stencil.hip", "prolong": "k_transform.hip",
+                  "res_prolong": "k_transform.hip", "fft_rows": "k_fft.hip", "fft_cols": "k_fft.hip",
+                  "fft_rows_inv": "k_fft.hip", "res_fft_rows": "k_fft.hip", "res_fft_cols": "k_fft.hip",
+                  "res_fft_rows_inv": "k_fft.hip", "gram_schmidt": "k_krylov.hip"}
 SEEDS = list(range(1000, 1024))   # 24 resident solves: the throughput-optimal batch on one MI355X
 METRIC = "active-pt RHS evals/s"
+ORACLE_ENV = {"OMP_NUM_THREADS": "1", "OPENBLAS_NUM_THREADS": "1", "MKL_NUM_THREADS": "1",
+              "NUMEXPR_NUM_THREADS": "1"}
 
 
-def kernel_bytes(name: str, N: int, na: int, tiles_active_frac: float, nbatch: int, esz: int) -> float:
-    """Algorithmic HBM bytes of one launch of a step kernel for the batch."""
+def kernel_bytes(phase: str, N: int, na: float, phi_t: float, esz: int, m: int) -> float:
+    """Algorithmic HBM bytes of one launch of a step phase for ONE solve: the
+    per-unit byte model of each kernel (what the method must move), with N_f
+    terms at the bulk element size esz (4 for FP32 fields, 8 for FP64):
+      Pi                 esz N_f written + 12 N_a (FP64 value + int32 index)
+      Poisson pass       2 esz N_f (read + write of the real-field equivalent)
+      product stencil    6 esz N_f phi_t (v~, psi_v, w~, u, v, nu_e on the
+                         tiles holding an active node) + 12 N_a (FP64 out + index)
+      residual stencil   2 esz N_f phi_t (w~, psi) + 12 N_a
+      Gram-Schmidt       16 m (m+1) N_a + 64 m N_a per step for CGS2 with the
+                         second pass in every column, per column: that over m
+                         (gs_bytes gives the passes a step actually took)
+    The residual of a solve with FP32 bulk fields runs in FP64 (esz 8 for its
+    phases).  The dense int32 rank map that the kernels read is implementation
+    traffic and is reported apart (rank_map_bytes)."""
     nf = N * N
-    if name == "jvp":
-        # psi~, v~, w~, u, v, nu_e on active tiles + rank map; J v out (FP64)
-        per = (6 * esz + 4) * nf * tiles_active_frac + 8 * na
-    elif name == "rhs":
-        # u, v, w~ in; nu_e out; rank map; F out (FP64)
-        per = (4 * esz + 4) * nf + 8 * na
-    elif name == "fft_rows":
-        per = esz * nf + 2 * esz * (N // 2 + 1) * N
-    elif name == "fft_rows_inv":
-        # the products' pass: psi~ alone
-        per = esz * nf + 2 * esz * (N // 2 + 1) * N
-    elif name == "fft_cols":
-        # spectrum in, psi~ spectrum out
-        per = 2 * (2 * esz * (N // 2 + 1) * N)
-    elif name == "prolong_finest":
-        lev = 3 * nf // 4
-        per = lev * (1 + esz)          # mask byte + written value (inputs are re-read coarse values)
-    elif name == "forward":
-        per = nf * (8 + 8)
-    else:
-        raise KeyError(name)
-    return per * nbatch
+    if phase in ("prolong", "res_prolong", "regrid_prolong"):
+        return esz * nf + 12 * na
+    if phase in ("fft_rows", "fft_cols", "fft_rows_inv", "res_fft_rows", "res_fft_cols", "res_fft_rows_inv"):
+        return 2 * esz * nf
+    if phase == "jvp":
+        return 6 * esz * nf * phi_t + 12 * na
+    if phase == "res_stencil":
+        return 2 * esz * nf * phi_t + 12 * na
+    if phase == "gram_schmidt":
+        return (16 * m * (m + 1) * na + 64 * m * na) / m
+    raise KeyError(phase)
+
+
+def gs_bytes(N_a: float, m: int, reorth, vsz: int = 8) -> float:
+    """Bytes of the Gram-Schmidt of one step as the selective CGS2 runs it:
+    column j reads the basis V_0..V_j (vsz bytes per entry) and w (FP64) once
+    for its first pass, once more where it takes the second pass (reorth),
+    and once to form V_{j+1}, which it writes (no V_{j+1} for the last
+    column)."""
+    tot = 0.0
+    for j in range(m):
+        rd = (j + 1) * vsz + 8
+        last = j == m - 1
+        tot += rd * (1 + (1 if j in reorth else 0) + (0 if last else 1)) + (0 if last else vsz)
+    return tot * N_a
+
+
+# launches of each phase in one step (the rest run once)
+PER_COLUMN = ("prolong", "fft_rows", "fft_cols", "fft_rows_inv", "jvp", "gram_schmidt")
+RESIDUAL = ("res_prolong", "res_fft_rows", "res_fft_cols", "res_fft_rows_inv", "res_stencil")
+MODELLED = RESIDUAL + PER_COLUMN
+
+
+def roofline_from_profile(prof: dict, N: int, na: float, phi_t: float, nbatch: int, bulk_esz: int, m: int,
+                          residual_esz: int = 8, gs_step_bytes: float = None) -> dict:
+    """Per-kernel achieved bandwidth from one profiled step (GPU ms per phase,
+    summed over the step): algorithmic bytes per launch / average launch time.
+    gs_step_bytes: the Gram-Schmidt bytes of the profiled step over the batch
+    (gs_bytes); else CGS2 with every second pass."""
+    step_ms = sum(prof.values())
+    out = {}
+    for ph in MODELLED:
+        launches = m if ph in PER_COLUMN else 1
+        esz = residual_esz if ph in RESIDUAL else bulk_esz
+        if ph == "gram_schmidt":
+            esz = 8
+        nbytes = kernel_bytes(ph, N, na, phi_t, esz, m) * nbatch
+        if ph == "gram_schmidt" and gs_step_bytes is not None:
+            nbytes = gs_step_bytes / m
+        avg = prof[ph] / launches
+        gbs = nbytes / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+        out[ph] = {"launches_per_step": launches, "avg_launch_ms": avg, "share_of_step": prof[ph] / step_ms,
+                   "algorithmic_bytes_per_launch": nbytes, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def rhs_pipeline(kern: dict, m: int) -> dict:
+    """HBM fraction of the residual and product kernels together:
+    (B_F + m B_Jv) / (t_F + m t_Jv) against the peak."""
+    bf = sum(kern[p]["algorithmic_bytes_per_launch"] for p in RESIDUAL)
+    tf = sum(kern[p]["avg_launch_ms"] for p in RESIDUAL)
+    prod = ("prolong", "fft_rows", "fft_cols", "fft_rows_inv", "jvp")
+    bj = sum(kern[p]["algorithmic_bytes_per_launch"] for p in prod)
+    tj = sum(kern[p]["avg_launch_ms"] for p in prod)
+    gbs = (bf + m * bj) / ((tf + m * tj) * 1e-3) / 1e9
+    return {"bytes_F": bf, "ms_F": tf, "bytes_Jv": bj, "ms_Jv": tj, "achieved_gbs": gbs,
+            "frac": gbs / HBM_PEAK_GBS,
+            "kernels": "residual: Pi, 3 Poisson passes, stencil (FP64); product: Pi, 3 Poisson passes, stencil"}
+
+
+def active_tile_fraction(solves, N: int, ts: int = 32) -> float:
+    """Fraction of the stencil tiles holding an active node, over the batch."""
+    import torch
+    fr = []
+    for s in solves:
+        _, _, _, fi = s.active_set()
+        f = fi.long()
+        t = ((f // N) // ts) * (N // ts) + (f % N) // ts
+        fr.append(torch.unique(t).numel() / (N // ts) ** 2)
+    return sum(fr) / len(fr)
 
 
 def measured_traffic(kernel: str):
@@ -82,7 +174,7 @@ def measured_traffic(kernel: str):
 
 
 def fp64_per_solve(m, W, dev, steps: int) -> dict:
-    """The same workload, one solve at a time, all bulk fields in FP64."""
+    """The 512^2 Fujiwhara workload, one solve at a time, all bulk fields in FP64."""
     import torch
     stream = torch.cuda.Stream(device=dev)
     pb = W.fujiwhara_pair(SEEDS[0])
@@ -103,51 +195,70 @@ def fp64_per_solve(m, W, dev, steps: int) -> dict:
             "solves_per_s_at_2000_steps": 1.0 / (wall / steps * 2000)}
 
 
-def accuracy_vs_fp64(m, W, dev, solve, seed: int, steps: int) -> dict:
-    """Mixed-precision solve against the same solve run with FP64 bulk fields
-    for the same number of steps: relative L2 of the vorticity field and the
-    relative differences of energy and enstrophy."""
-    import torch
-    stream = torch.cuda.Stream(device=dev)
-    pb = W.fujiwhara_pair(seed)
-    with torch.cuda.stream(stream):
-        w0 = torch.from_numpy(W.initial_field(pb)).to(dev)
-        ref = m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), m.MRA_FP64, pb.m, pb.dt, w0,
-                      stream=stream)
-    ref.step(steps, stream=stream)
-    a, da = ref.read(stream=stream)
-    b, db = solve.read(stream=stream)
-    stream.synchronize()
-    ref.close()
-    rel = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a))
-    return {"seed": seed, "steps": steps, "rel_l2_vorticity": rel,
-            "rel_energy": abs(da["energy"] - db["energy"]) / da["energy"],
-            "rel_enstrophy": abs(da["enstrophy"] - db["enstrophy"]) / da["enstrophy"],
-            "n_active_fp64": int(da["n_active"]), "n_active_mixed": int(db["n_active"]),
-            "tolerance": 1e-5, "within": rel <= 1e-5}
+def compare_fields(a, b, da: dict, db: dict) -> dict:
+    """Relative L2 of two dense vorticity fields and the relative differences
+    of energy and enstrophy (a is the reference)."""
+    rel = float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(a)))
+    return {"rel_l2_vorticity": rel, "rel_energy": abs(da["energy"] - db["energy"]) / da["energy"],
+            "rel_enstrophy": abs(da["enstrophy"] - db["enstrophy"]) / da["enstrophy"]}
 
 
-def cpu_baseline(steps: int) -> dict:
-    """The FP64 oracle on one solve of the batch, single-threaded, timed here."""
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
-               NUMEXPR_NUM_THREADS="1")
-    code = (
-        "import json,sys,time; sys.path.insert(0, %r)\n"
-        "import workloads as W\n"
-        "from oracle import krylov as ok, ops as oo\n"
-        "pb = W.fujiwhara_pair(%d)\n"
-        "g = ok.Grid(J=pb.J, p=pb.p, eps=pb.eps); fl = oo.Flow(nu0=pb.nu0, cs=pb.cs)\n"
-        "st = ok.init_state(W.initial_field(pb), g)\n"
-        "ev = 0; t0 = time.perf_counter()\n"
-        "for _ in range(%d):\n"
-        "    na = st.omega_M.size; st = ok.step(st, g, fl, pb.m, pb.dt); ev += (1 + st.last_m_eff) * na\n"
-        "dt = time.perf_counter() - t0\n"
-        "print(json.dumps({'evals': ev, 'sec': dt}))\n" % (ROOT, SEEDS[0], steps))
-    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
-    r = json.loads(out.stdout.strip().splitlines()[-1])
-    return {"value": r["evals"] / r["sec"], "unit": "active-pt RHS evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of one 512^2 Fujiwhara solve (seed {SEEDS[0]}), FP64 NumPy/SciPy, "
-                      f"{r['sec']:.1f} s"}
+def start_oracle(code: str) -> subprocess.Popen:
+    """An oracle run in a single-threaded child process (it overlaps the GPU legs)."""
+    env = dict(os.environ, **ORACLE_ENV)
+    return subprocess.Popen([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE,
+                            stderr=subprocess.PIPE, text=True)
+
+
+def finish_oracle(pr: subprocess.Popen) -> dict:
+    out, err = pr.communicate()
+    if pr.returncode != 0:
+        raise RuntimeError("oracle run failed: " + err[-2000:])
+    return json.loads(out.strip().splitlines()[-1])
+
+
+ORACLE_THREE = """
+import json, sys, time, dataclasses
+sys.path.insert(0, {root!r})
+import numpy as np
+import workloads as W
+from oracle import krylov as ok, ops as oo
+pb = dataclasses.replace(W.three_vortex(), noise_seed={seed})
+g = ok.Grid(J=pb.J, p=pb.p, eps=pb.eps); fl = oo.Flow(nu0=pb.nu0, cs=pb.cs)
+st = ok.init_state(W.initial_field(pb), g)
+op = ok.Operator(g, fl, st.index_fine)
+t0 = time.perf_counter()
+F = op.F(st.omega_M)
+v = F / np.linalg.norm(F)
+outs = []
+for _ in range({nprod}):
+    w = op.Av(v)
+    outs.append((v, w))
+    v = w / np.linalg.norm(w)
+sec = time.perf_counter() - t0
+np.save({d!r} + "/omega.npy", st.omega_M); np.save({d!r} + "/fi.npy", st.index_fine)
+np.save({d!r} + "/mask.npy", st.mask); np.save({d!r} + "/F.npy", F)
+np.save({d!r} + "/v.npy", outs[0][0]); np.save({d!r} + "/Av.npy", outs[0][1])
+print(json.dumps({{"evals": (1 + {nprod}) * int(st.omega_M.size), "sec": sec, "n_active": int(st.omega_M.size)}}))
+"""
+
+ORACLE_PAIR = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import workloads as W
+from oracle import krylov as ok, mra as om, ops as oo
+pb = W.fujiwhara_pair({seed})
+g = ok.Grid(J=pb.J, p=pb.p, eps=pb.eps); fl = oo.Flow(nu0=pb.nu0, cs=pb.cs)
+st = ok.init_state(W.initial_field(pb), g)
+ev = 0; t0 = time.perf_counter()
+for _ in range({steps}):
+    na = st.omega_M.size; st = ok.step(st, g, fl, pb.m, pb.dt); ev += (1 + st.last_m_eff) * na
+sec = time.perf_counter() - t0
+ref = om.prolong(st.omega_M, st.index_fine, pb.J, pb.p)
+np.save({d!r} + "/pair_ref.npy", ref); np.save({d!r} + "/pair_mask.npy", st.mask)
+print(json.dumps({{"evals": ev, "sec": sec, "n_active": int(st.omega_M.size), "diag": ok.diagnostics(ref, g)}}))
+"""
 
 
 def ensemble_cpu_baseline(probs, steps: int = 2) -> dict:
@@ -232,7 +343,7 @@ def untune_tiles(tuned: dict) -> None:
         m.tune_set_tile(int(J), 2, m.MRA_MIXED, 0)
 
 
-def run_ensemble(args) -> int:
+def ensemble_leg(args, with_cpu: bool = True) -> dict:
     """Batched ensemble: two-vortex solves of sizes 128^2..1024^2, mixed
     precision, all resident, advanced by the continuous-batching server."""
     import torch
@@ -269,8 +380,8 @@ def run_ensemble(args) -> int:
         s.close()
         log(f"fp64 per-solve J={J}: {per_step[J] * 1e3:.2f} ms/step")
     fp64_total = sum(per_step[pb.J] * pb.steps for pb in probs)
-    cpu = None if args.no_cpu else ensemble_cpu_baseline(probs)
-    print(json.dumps({"workload": f"ensemble of {len(probs)} two-vortex solves, finest 128^2..1024^2, "
+    cpu = ensemble_cpu_baseline(probs) if with_cpu else None
+    out = ({"workload": f"ensemble of {len(probs)} two-vortex solves, finest 128^2..1024^2, "
                                   f"{args.ens_steps} steps each, mixed precision, one GPU",
                       "metric": "ensemble solves/s", "value": summ["solves_per_s"], "wall_s": wall,
                       "active_pt_evals_per_s": summ["active_pt_evals_per_s"], "failed": summ["failed"],
@@ -279,8 +390,13 @@ def run_ensemble(args) -> int:
                                              "note": "one warmed solve per size timed over 8 steps, "
                                                      "applied to every solve's step count"},
                       "autotune": tuned,
-                      "cpu_baseline": cpu}))
+                      "cpu_baseline": cpu})
     untune_tiles(tuned)
+    return out
+
+
+def run_ensemble(args) -> int:
+    print(json.dumps(ensemble_leg(args, not args.no_cpu)))
     return 0
 
 
@@ -311,7 +427,7 @@ def run_serving(args) -> int:
     return 0
 
 
-def run_serving_spec(args) -> int:
+def serving_spec_leg(args) -> dict:
     """The serving configuration's request mix (1-3 vortices, finest 64^2..2048^2
     log-uniform over levels, 200-2000 steps, Re 1e3..4e4) on a bounded sample:
     capacity from a closed-loop run (every request queued at once), then
@@ -342,11 +458,15 @@ def run_serving_spec(args) -> int:
     torch.cuda.synchronize()
     wall70 = time.perf_counter() - t0
     at70 = serve.summarize(recs70, wall70)
-    print(json.dumps({"workload": f"serving configuration mix: 1-3 vortices, finest 64^2..2048^2, 200-2000 steps, "
+    return ({"workload": f"serving configuration mix: 1-3 vortices, finest 64^2..2048^2, 200-2000 steps, "
                                   f"{n} requests per run, mixed precision",
                       "metric": "solves/s and p50/p99 latency",
                       "capacity_closed_loop": cap, "offered_req_per_s_at_70pct": rate, "at_70pct_of_capacity": at70,
-                      "configured_rate_req_per_s": 50.0}))
+                      "configured_rate_req_per_s": 50.0})
+
+
+def run_serving_spec(args) -> int:
+    print(json.dumps(serving_spec_leg(args)))
     return 0
 
 
@@ -482,7 +602,7 @@ def run_three(args) -> int:
     nas = [int(s.read(dense=False, stream=stream)[1]["n_active"]) for s in solves]
     N = pbs[0].N
     k_ms = m.time_kernel(solves, "jvp", 10, stream=stream)
-    nbytes = kernel_bytes("jvp", N, int(sum(nas) / len(nas)), 1.0, len(solves), 4)
+    nbytes = kernel_bytes("jvp", N, sum(nas) / len(nas), 1.0, 4, pbs[0].m) * len(solves)
     print(json.dumps({"workload": f"three vortices Re=37440 + noise, finest 2048^2 (J=11), 6-point DD, eps=1e-4, "
                                   f"m=30, dt=0.002; batch of {len(solves)}, mixed precision"
                                   f"{' (Krylov basis in FP32)' if args.prec3 == 'fp32' else ''}, {args.steps3} steps",
@@ -664,11 +784,321 @@ def run_families(args) -> int:
     return 0
 
 
+def make_batch(m, W, dev, stream, pbs, prec):
+    import torch
+    solves = []
+    with torch.cuda.stream(stream):
+        for pb in pbs:
+            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m, pb.dt,
+                                  torch.from_numpy(W.initial_field(pb)).to(dev), stream=stream))
+    return solves
+
+
+def timed_batch(m, solves, stream, warmup: int, steps: int) -> dict:
+    """warmup untimed steps, then `steps` timed steps of the batch (graph
+    replay), bracketed by device synchronisation."""
+    import torch
+    n = len(solves)
+    m.solve_batch(solves, [warmup] * n, stream=stream)
+    stream.synchronize()
+    ev0 = sum(s.scalars()["evals"] for s in solves)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.solve_batch(solves, [steps] * n, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev1 = sum(s.scalars()["evals"] for s in solves)
+    diags = [s.read(dense=False, stream=stream)[1] for s in solves]
+    if any(d["status"] != 0 for d in diags):
+        raise RuntimeError(f"a solve reported status {[d['status'] for d in diags]}")
+    return {"value": (ev1 - ev0) / wall, "wall": wall, "ms_per_step": wall / steps * 1e3,
+            "n_active": [int(d["n_active"]) for d in diags]}
+
+
+def step_roofline(m, solves, stream, N: int, m_kry: int, bulk_esz: int) -> dict:
+    """Per-phase GPU time of one more step (mra_step_profile) turned into
+    achieved bandwidth per kernel, the dominant kernel and the fraction of the
+    residual and product pipeline."""
+    phi_t = active_tile_fraction(solves, N)
+    nas = [int(s.read(dense=False, stream=stream)[1]["n_active"]) for s in solves]   # the profiled step's N_a
+    na = sum(nas) / len(nas)
+    prof = m.step_profile(solves, stream=stream)
+    reorth = [s.reorth_columns(stream=stream) for s in solves]
+    gsb = sum(gs_bytes(a, m_kry, set(r)) for a, r in zip(nas, reorth))
+    kern = roofline_from_profile(prof, N, na, phi_t, len(solves), bulk_esz, m_kry, gs_step_bytes=gsb)
+    kern["gram_schmidt"]["second_pass_columns"] = [len(r) for r in reorth]
+    kern["gram_schmidt"]["full_cgs2_bytes_per_launch"] = kernel_bytes("gram_schmidt", N, na, phi_t, 8, m_kry) * len(solves)
+    step_ms = sum(prof.values())
+    dom = max(kern, key=lambda k: kern[k]["avg_launch_ms"] * kern[k]["launches_per_step"])
+    # phases with no byte model (phi_1, update, regrid, norm) keep their share
+    others = {k: {"ms_per_step": v, "share_of_step": v / step_ms} for k, v in prof.items() if k not in kern}
+    return {"phi_t": phi_t, "n_active_mean": na, "profile_ms": prof, "step_ms_profiled": step_ms,
+            "kernels": kern, "other_phases": others, "dominant": dom,
+            "rhs_pipeline": rhs_pipeline(kern, m_kry)}
+
+
+def copy_ceiling(dev) -> float:
+    """Plain device copy: the byte-counter scale of profiled runs (64 MiB) and,
+    timed, the practical streaming ceiling of this device (1 GiB)."""
+    import torch
+    cal_a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    cal_b = torch.empty_like(cal_a)
+    cal_b.copy_(cal_a)
+    torch.cuda.synchronize()
+    big_a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    big_b = torch.empty_like(big_a)
+    big_b.copy_(big_a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        big_b.copy_(big_a)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * big_a.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del cal_a, cal_b, big_a, big_b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def three_leg(args, m, W, dev, tmpdir: str) -> dict:
+    """The headline: the three-vortex configuration at 2048^2, a batch of
+    args.batch3 solves (noise seeds 37440 + i), mixed precision."""
+    import dataclasses
+    import torch
+    stream = torch.cuda.Stream(device=dev)
+    pbs = [dataclasses.replace(W.three_vortex(), noise_seed=37440 + i) for i in range(args.batch3)]
+    pb = pbs[0]
+    solves = make_batch(m, W, dev, stream, pbs, m.MRA_MIXED)
+    log(f"three-vortex 2048^2 batch of {len(solves)}: {args.warmup} + {args.steps} steps")
+    t = timed_batch(m, solves, stream, args.warmup, args.steps)
+    rl = step_roofline(m, solves, stream, pb.N, pb.m, 4)
+    k_jvp = m.time_kernel(solves, "jvp", 10, stream=stream)
+    out = {"timed": t, "roofline": rl, "jvp_back_to_back_ms": k_jvp}
+    if args.no_compare:
+        for s in solves:
+            s.close()
+        return out
+    # mixed against the FP64 GPU path over the same steps (warm-up, timed, profiled)
+    nst = args.warmup + args.steps + 1
+    ref = make_batch(m, W, dev, stream, [pb], m.MRA_FP64)[0]
+    ref.step(nst, stream=stream)
+    a, da = ref.read(stream=stream)
+    b, db = solves[0].read(stream=stream)
+    _, ma, _, _ = ref.active_set()
+    _, mb, _, _ = solves[0].active_set()
+    out["mixed_vs_fp64_gpu"] = {"steps": nst, **compare_fields(a.cpu().numpy(), b.cpu().numpy(), da, db),
+                                "mask_flips": int((ma != mb).sum()), "n_active_fp64": int(da["n_active"])}
+    ref.close()
+    for s in solves:
+        s.close()
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def three_oracle_accuracy(m, W, dev, tmpdir: str) -> dict:
+    """The mixed path's residual and product at 2048^2 against the FP64 oracle
+    on the same FP64 inputs (the initial state of seed 37440 and a unit-norm
+    Krylov-like vector), from the oracle's cpu_baseline sample."""
+    import torch
+    pb = W.three_vortex()
+    ld = lambda n: np.load(os.path.join(tmpdir, n + ".npy"))
+    omega, fi, mask, F, v, Av = ld("omega"), ld("fi"), ld("mask"), ld("F"), ld("v"), ld("Av")
+    n = fi.size
+    g, f = m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs)
+    t = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)
+    mk, fk, nk = t(mask, torch.uint8), t(fi, torch.int32), t(np.array([n]), torch.int64)
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    m.collocation_rhs(g, f, m.MRA_MIXED, mk, fk, nk, t(omega), None, out)
+    eF = float(np.abs(out.cpu().numpy() - F).max() / np.abs(F).max())
+    m.collocation_rhs(g, f, m.MRA_MIXED, mk, fk, nk, t(omega), t(v), out)
+    eJ = float(np.abs(out.cpu().numpy() - Av).max() / np.abs(Av).max())
+    return {"residual_max_rel": eF, "product_max_rel": eJ, "n_active": n, "tolerance": 2e-5,
+            "within": eF <= 2e-5 and eJ <= 2e-5,
+            "note": "max |GPU - oracle| / max |oracle| at every active node of 2048^2; the product takes the "
+                    "FP64 vector rounded to FP32, the residual runs in FP64"}
+
+
+def pair_leg(args, m, W, dev, tmpdir: str, orc: dict) -> dict:
+    """The 512^2 Fujiwhara batch of 24 in mixed precision, with its accuracy
+    against the FP64 oracle after the warm-up and timed steps."""
+    import torch
+    stream = torch.cuda.Stream(device=dev)
+    pbs = [W.fujiwhara_pair(sd) for sd in SEEDS[:args.batch]]
+    solves = make_batch(m, W, dev, stream, pbs, m.MRA_MIXED)
+    log(f"Fujiwhara 512^2 batch of {len(solves)}: {args.warmup} + {args.steps} steps")
+    t = timed_batch(m, solves, stream, args.warmup, args.steps)
+    dense, diag = solves[0].read(stream=stream)
+    _, mask, _, _ = solves[0].active_set()
+    ref = np.load(os.path.join(tmpdir, "pair_ref.npy"))
+    rmask = np.load(os.path.join(tmpdir, "pair_mask.npy"))
+    acc = {"seed": SEEDS[0], "steps": args.warmup + args.steps,
+           **compare_fields(ref, dense.cpu().numpy(), orc["diag"], diag),
+           "mask_flips": int((mask.cpu().numpy() != rmask).sum()), "n_active_oracle": orc["n_active"],
+           "n_active_mixed": int(diag["n_active"]), "tolerance": 1e-5}
+    acc["within"] = acc["rel_l2_vorticity"] <= 1e-5
+    rl = step_roofline(m, solves, stream, pbs[0].N, pbs[0].m, 4)
+    for s in solves:
+        s.close()
+    return {"workload": f"Fujiwhara pair Re=5000, finest 512^2 (J=9), 4-point DD, eps=1e-4, m=20, dt=0.01; "
+                        f"batch of {len(pbs)} seeded solves, mixed precision",
+            "metric": METRIC, "value": t["value"], "ms_per_step": t["ms_per_step"], "steps": args.steps,
+            "mean_active_points": sum(t["n_active"]) / len(t["n_active"]),
+            "accuracy_vs_oracle": acc,
+            "roofline_dominant": {"kernel": rl["dominant"], **rl["kernels"][rl["dominant"]]},
+            "jvp": rl["kernels"]["jvp"], "rhs_pipeline": rl["rhs_pipeline"], "phi_t": rl["phi_t"],
+            "fp64_per_solve_gpu": fp64_per_solve(m, W, dev, max(10, args.steps // 2)),
+            "cpu_baseline": {"value": orc["evals"] / orc["sec"], "unit": METRIC, "cores": 1, "kind": "oracle",
+                             "sample": f"{args.warmup + args.steps} steps of seed {SEEDS[0]}, {orc['sec']:.1f} s"}}
+
+
+def drift_leg(m, W, dev, steps: int, every: int = 100) -> dict:
+    """Mixed precision against FP64 over the Fujiwhara configuration's full
+    length for one seed, both on the GPU (the FP64 GPU path is pinned to the
+    oracle by the parity tests: 2.4e-15 over the plain configuration's 100
+    steps), and beside it the method's own sensitivity: an FP64 run whose
+    initial field carries a relative perturbation of 1e-10 (about what the
+    mixed precision leaves after a few dozen steps) against the same
+    unperturbed FP64 run.  Thresholding is discontinuous: once a perturbation
+    moves one detail across tau the two runs carry different active sets.
+    Every `every` steps: relative L2 of both pairs and their mask flips."""
+    import torch
+    pb = W.fujiwhara_pair(SEEDS[0])
+    w0 = W.initial_field(pb)
+    rng = np.random.default_rng(7)
+    w0p = w0 * (1.0 + 1e-10 * rng.standard_normal(w0.shape))
+    stream = torch.cuda.Stream(device=dev)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        mk = lambda prec, w: m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m,
+                                     pb.dt, torch.from_numpy(w).to(dev), stream=stream)
+        ref, mix, per = mk(m.MRA_FP64, w0), mk(m.MRA_MIXED, w0), mk(m.MRA_FP64, w0p)
+    curve = []
+    first_flip = {"mixed": None, "perturbed_fp64": None}
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        m.solve_batch([ref, mix, per], [k] * 3, stream=stream)
+        done += k
+        fields = {}
+        for name, s in (("fp64", ref), ("mixed", mix), ("perturbed_fp64", per)):
+            dense, diag = s.read(stream=stream)
+            _, mask, _, _ = s.active_set()
+            fields[name] = (dense.cpu().numpy(), diag, mask.cpu().numpy())
+        a, da, ma = fields["fp64"]
+        row = {"step": done}
+        for name in ("mixed", "perturbed_fp64"):
+            b, db, mb = fields[name]
+            flips = int((ma != mb).sum())
+            row[name] = {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(a)), "mask_flips": flips}
+            if flips and first_flip[name] is None:
+                first_flip[name] = done
+        curve.append(row)
+    a, da, ma = fields["fp64"]
+    b, db, mb = fields["mixed"]
+    c, dc, mc = fields["perturbed_fp64"]
+    for s in (ref, mix, per):
+        s.close()
+    return {"seed": SEEDS[0], "steps": steps, "reference": "the FP64 GPU path", **compare_fields(a, b, da, db),
+            "mask_flips": int((ma != mb).sum()), "n_active_fp64": int(da["n_active"]),
+            "n_active_mixed": int(db["n_active"]),
+            "perturbed_fp64_vs_fp64": {"perturbation": "relative 1e-10 N(0,1) on the initial field",
+                                       **compare_fields(a, c, da, dc), "mask_flips": int((ma != mc).sum())},
+            "first_flip_by": first_flip, "every": every, "curve": curve, "seconds": time.perf_counter() - t0}
+
+
+def run_fujiwhara(args) -> int:
+    """The 512^2 Fujiwhara batch alone, with its oracle accuracy and baseline."""
+    import torch
+    import paper_1604_08159_amd as m
+    import workloads as W
+    tmp = tempfile.TemporaryDirectory(prefix="mra_bench_")
+    orc = start_oracle(ORACLE_PAIR.format(root=ROOT, seed=SEEDS[0], steps=args.warmup + args.steps, d=tmp.name))
+    r = finish_oracle(orc)
+    print(json.dumps(pair_leg(args, m, W, torch.device("cuda:0"), tmp.name, r)))
+    tmp.cleanup()
+    return 0
+
+
+def run_default(args) -> int:
+    """The headline line: the three-vortex 2048^2 batch, with the roofline of
+    its step, the oracle beside it, and the sub-records of the other
+    configurations."""
+    import torch
+    import paper_1604_08159_amd as m
+    import workloads as W
+    T0 = time.perf_counter()
+    dev = torch.device("cuda:0")
+    tmp = tempfile.TemporaryDirectory(prefix="mra_bench_")
+    orc3 = orc2 = None
+    if not args.no_cpu:
+        orc3 = start_oracle(ORACLE_THREE.format(root=ROOT, seed=37440, nprod=3, d=tmp.name))
+        orc2 = start_oracle(ORACLE_PAIR.format(root=ROOT, seed=SEEDS[0], steps=args.warmup + args.steps,
+                                               d=tmp.name))
+    ceiling = copy_ceiling(dev)
+    three = three_leg(args, m, W, dev, tmp.name)
+    t, rl = three["timed"], three["roofline"]
+    dom = rl["dominant"]
+    kd = rl["kernels"][dom]
+    out = {
+        "metric": METRIC, "value": t["value"], "unit": METRIC, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "three Gaussian vortices at Re=37440 plus seeded white noise of amplitude 1e-3, "
+                               "finest 2048^2 (J=11), 6-point DD, eps=1e-4, Cs=0.17, m=30, dt=0.002; "
+                               f"batch of {args.batch3} solves (noise seeds 37440..{37440 + args.batch3 - 1}), "
+                               "mixed precision (FP32 products, FP64 residual, Krylov and regrid)",
+                   "batch": args.batch3, "finest_points": 1 << 22,
+                   "mean_active_points": sum(t["n_active"]) / len(t["n_active"]),
+                   "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": kd["frac"], "traffic": measured_traffic(dom),
+                     "avg_launch_ms": kd["avg_launch_ms"], "launches_per_step": kd["launches_per_step"],
+                     "algorithmic_bytes_per_launch": kd["algorithmic_bytes_per_launch"],
+                     "share_of_step": kd["share_of_step"], "active_tile_fraction": rl["phi_t"],
+                     "mean_active_points": rl["n_active_mean"],
+                     "timing": "HIP events after every phase of one step on the step's stream (mra_step_profile)",
+                     "copy_ceiling_gbs": ceiling, "frac_of_copy_ceiling": kd["achieved_gbs"] / ceiling},
+        "rhs_pipeline": rl["rhs_pipeline"],
+        "kernels": rl["kernels"], "other_phases": rl["other_phases"],
+        "jvp_back_to_back_ms": three["jvp_back_to_back_ms"],
+        "finest_pt_evals_per_s": t["value"] * (1 << 22) / (sum(t["n_active"]) / len(t["n_active"])),
+        "mixed_vs_fp64_gpu": three.get("mixed_vs_fp64_gpu"),
+    }
+    log("three-vortex leg done")
+    if orc3 is not None:
+        r3 = finish_oracle(orc3)
+        out["cpu_baseline"] = {"value": r3["evals"] / r3["sec"], "unit": METRIC, "cores": 1, "kind": "oracle",
+                               "sample": f"one residual and 3 Jacobian-vector products of the FP64 oracle at "
+                                         f"2048^2 on the initial state of noise seed 37440 "
+                                         f"({r3['n_active']} active nodes), one core, {r3['sec']:.1f} s"}
+        out["accuracy_vs_oracle"] = three_oracle_accuracy(m, W, dev, tmp.name)
+    if not args.no_sub:
+        r2 = finish_oracle(orc2) if orc2 is not None else None
+        if r2 is not None:
+            out["fujiwhara512"] = pair_leg(args, m, W, dev, tmp.name, r2)
+        out["drift_fujiwhara512"] = drift_leg(m, W, dev, args.long_steps)
+        log("drift leg done")
+        out["ensemble"] = ensemble_leg(args, not args.no_cpu)
+        log("ensemble leg done")
+        out["serving"] = serving_spec_leg(args)
+        log("serving leg done")
+    tmp.cleanup()
+    out["bench_wall_s"] = time.perf_counter() - T0
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["fujiwhara", "ensemble", "serving", "vapor", "three2048", "longrun",
-                                           "implicit", "families", "serving_spec", "condensation"],
-                    default="fujiwhara")
+    ap.add_argument("--workload", choices=["default", "fujiwhara", "ensemble", "serving", "vapor", "three2048",
+                                           "longrun", "implicit", "families", "serving_spec", "condensation"],
+                    default="default",
+                    help="default: the three-vortex 2048^2 headline with every sub-record")
+    ap.add_argument("--no-sub", action="store_true", help="default workload: the headline only")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="default workload: skip the FP64 GPU comparison run (kernel profiles of the step)")
     ap.add_argument("--batch3", type=int, default=2)
     ap.add_argument("--steps3", type=int, default=10)
     ap.add_argument("--tune-cache", default="", help="ensemble: JSON cache of the tile autotuner")
@@ -678,7 +1108,7 @@ def main() -> int:
                     help="three2048: fp32 stores the Krylov basis in FP32")
     ap.add_argument("--long-steps", type=int, default=2000)
     ap.add_argument("--fam-steps", type=int, default=0, help="0: up to 37.5 h")
-    ap.add_argument("--spec-requests", type=int, default=40)
+    ap.add_argument("--spec-requests", type=int, default=24)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--newton", type=int, default=2)
     ap.add_argument("--jacobian", choices=["frozen", "exact"], default="frozen")
@@ -692,15 +1122,12 @@ def main() -> int:
     ap.add_argument("--min-steps", type=int, default=20)
     ap.add_argument("--max-steps", type=int, default=200)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", choices=["mixed", "fp64", "fp32"], default="mixed",
                     help="fp32: mixed with the Krylov basis stored in FP32")
     ap.add_argument("--batch", type=int, default=len(SEEDS))
-    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--kernel", default="jvp")
-    ap.add_argument("--no-fp64-compare", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: --gpus must be 1 (independent solves shard across GPUs by a host router)"}))
@@ -724,122 +1151,9 @@ def main() -> int:
     if args.workload == "longrun":
         return run_longrun(args)
 
-    import torch
-    import paper_1604_08159_amd as m
-    import workloads as W
-
-    dev = torch.device("cuda:0")
-    prec = {"mixed": m.MRA_MIXED, "fp64": m.MRA_FP64, "fp32": m.MRA_FP32}[args.prec]
-    stream = torch.cuda.Stream(device=dev)
-    seeds = [SEEDS[i % len(SEEDS)] + 100 * (i // len(SEEDS)) for i in range(args.batch)]
-    pbs = [W.fujiwhara_pair(s) for s in seeds]
-    solves = []
-    with torch.cuda.stream(stream):
-        for pb in pbs:
-            w0 = torch.from_numpy(W.initial_field(pb)).to(dev)
-            solves.append(m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m,
-                                  pb.dt, w0, stream=stream))
-    n = len(solves)
-    m.solve_batch(solves, [args.warmup] * n, stream=stream)
-    stream.synchronize()
-    ev0 = sum(s.scalars()["evals"] for s in solves)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    m.solve_batch(solves, [args.steps] * n, stream=stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev1 = sum(s.scalars()["evals"] for s in solves)
-    value = (ev1 - ev0) / wall
-
-    # state after the timed region
-    nas = []
-    for s in solves:
-        _, diag = s.read(dense=False, stream=stream)
-        nas.append(int(diag["n_active"]))
-        if diag["status"] != 0:
-            print(json.dumps({"error": f"solve reported status {diag['status']}"}))
-            return 1
-    N = 1 << pbs[0].J
-    esz = 8 if prec == m.MRA_FP64 else 4
-
-    # dominant kernel: HIP events around back-to-back launches of the same
-    # launch configuration, on the stream the step runs on
-    reps = 50
-    k_ms = m.time_kernel(solves, args.kernel, reps, stream=stream)
-    # fraction of stencil tiles holding an active node (the stencil skips the rest)
-    ts = 32
-    act_tiles = []
-    for s in solves:
-        _, mask, ip, fi = s.active_set()
-        f = fi.long()
-        t = ((f // N) // ts) * (N // ts) + (f % N) // ts
-        act_tiles.append(torch.unique(t).numel() / (N // ts) ** 2)
-    frac_t = sum(act_tiles) / len(act_tiles)
-    nbytes = kernel_bytes(args.kernel, N, int(sum(nas) / len(nas)), frac_t, n, esz)
-    achieved = nbytes / (k_ms * 1e-3) / 1e9
-
-    # plain copy of known size: the byte-counter scale of profiled runs, and
-    # (timed) the practical streaming ceiling of this device
-    cal_a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
-    cal_b = torch.empty_like(cal_a)
-    cal_b.copy_(cal_a)
-    torch.cuda.synchronize()
-    big_a = torch.empty(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB, far beyond the caches
-    big_b = torch.empty_like(big_a)
-    big_b.copy_(big_a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        big_b.copy_(big_a)
-    e1.record()
-    e1.synchronize()
-    copy_gbs = 2 * big_a.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del cal_a, cal_b, big_a, big_b
-    compare = None
-    accuracy = None
-    if not args.no_fp64_compare and prec != m.MRA_FP64:
-        compare = fp64_per_solve(m, W, dev, max(10, args.steps // 10))
-        accuracy = accuracy_vs_fp64(m, W, dev, solves[0], seeds[0], args.warmup + args.steps)
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "active-pt RHS evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == m.MRA_FP64 else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"Fujiwhara pair Re=5000, finest 512^2 (J=9), 4-point DD, eps=1e-4, m=20, "
-                               f"dt=0.01; batch of {n} seeded solves",
-                   "batch": n, "finest_points": N * N, "mean_active_points": sum(nas) / len(nas),
-                   "precision": args.prec, "parallelism": "none (1 GPU)"},
-        "roofline": {"bound": "hbm", "kernel": args.kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.kernel),
-                     "avg_launch_ms": k_ms, "algorithmic_bytes_per_launch": nbytes,
-                     "active_tile_fraction": frac_t,
-                     "copy_ceiling_gbs": copy_gbs, "frac_of_copy_ceiling": achieved / copy_gbs},
-        "finest_pt_evals_per_s": value * N * N / (sum(nas) / len(nas)),
-    }
-    step_s = wall / args.steps
-    out["ensemble"] = {"solves_per_s_at_2000_steps": n / (step_s * 2000),
-                       "note": "batch solves/s if each solve ran the configuration's 2000 steps"}
-    if compare is not None:
-        out["fp64_per_solve_gpu"] = compare
-    if accuracy is not None:
-        out["fp32_vs_fp64"] = accuracy
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
-    for s in solves:
-        s.close()
-    print(json.dumps(out))
-    return 0
+    if args.workload == "fujiwhara":
+        return run_fujiwhara(args)
+    return run_default(args)
 
 
 if __name__ == "__main__":

@@ -108,7 +108,9 @@ typedef struct {
   double* scalars;           /* [16] FP64: [0] beta, [2] ||A v_last||, [4] t,
                                 [5] active-point residual evaluations so far
                                 (sum over steps of (1 + m_eff) N_a), [6] steps */
-  int32_t* control;          /* [16] int: m_eff, done, status, ...               */
+  int32_t* control;          /* [16] int: [0] m_eff, [1] done, [2] status; [9], [10]
+                                the Arnoldi columns of the last step that took the
+                                second Gram-Schmidt pass (bit j of word j / 32)  */
 } mra_solve_ptrs;
 
 const char* mra_status_str(int32_t status);
@@ -213,9 +215,14 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
  *   step.  The first call captures one step into a HIP graph on `stream`;
  *   later calls replay it.
  * solve_batch: advances solves[i] by nsteps[i] steps; solves of equal
- *   (J, p, precision, m, integrator, Newton iterations, Jacobian) share every
- *   kernel launch.  Results are bit for bit
- *   those of krylov_step on each solve alone.
+ *   (J, p, precision, m, integrator, Newton iterations, Jacobian, tile) share
+ *   every kernel launch (up to 64 solves per launch).  On a non-default
+ *   stream one step of the whole call, whatever its grid sizes, is one
+ *   captured HIP graph launch: each group of equal configuration is a branch
+ *   of the graph, the branches run concurrently, and passive scalars' branches
+ *   follow their partners'.  A graph is captured once per composition of the
+ *   call (which solves, in which groups) and replayed while it stays the
+ *   same.  Results are bit for bit those of krylov_step on each solve alone.
  * mra_solve_read: synchronises `stream`; omega_dense_out (device double
  *   [N][N], may be NULL) receives Pi(omega_M); diag_out (HOST double[8],
  *   may be NULL) receives t, energy, enstrophy, palinstrophy, circulation,
@@ -367,6 +374,20 @@ int32_t mra_solve_set_jacobian(mra_solve s, int32_t jacobian);
  * work buffers are overwritten: call it between steps. */
 int32_t mra_time_kernel(mra_solve* solves, int32_t n, int32_t which, int32_t reps, void* stream,
                         float* avg_ms);
+
+/* Profiling hook: advances the batch `solves` (n solves of one launch
+ * configuration, exponential integrator, vorticity solves) by ONE step with
+ * the launches of krylov_step / solve_batch, issued directly (not from a
+ * graph) with a HIP event on `stream` after every phase, and writes the GPU
+ * time of each phase, summed over the step, to ms_out[0 .. 16]: the
+ * residual's Pi, its three Poisson passes (rows, columns, inverse rows) and
+ * its stencil; ||F||; the m products' Pi, their three Poisson passes and their
+ * stencil; the m Gram-Schmidt columns; phi_1; the update; the regrid's Pi, its
+ * forward transform, and its threshold, compaction and gather.  n_out >= 17.
+ * Synchronises `stream`.  Errors: MRA_E_ARG (bad handles, mixed
+ * configurations, n_out too small), MRA_E_UNSUPPORTED (passive scalars, the
+ * theta-scheme). */
+int32_t mra_step_profile(mra_solve* solves, int32_t n, void* stream, double* ms_out, int32_t n_out);
 
 #ifdef __cplusplus
 }

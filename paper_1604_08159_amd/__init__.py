@@ -223,12 +223,29 @@ class Solve:
                 self._arena_view(p.index_packed, na, torch.int32).clone(),
                 self._arena_view(p.index_fine, na, torch.int32).clone())
 
-    def scalars(self) -> Dict[str, float]:
-        """t, steps and the active-point residual evaluations counted on the device."""
+    def scalars(self, stream=None) -> Dict[str, float]:
+        """t, steps and the active-point residual evaluations counted on the
+        device: after all work on the device, or, with `stream`, after the work
+        enqueued on that stream (the solve's stream) only."""
         p = self.ptrs()
-        torch.cuda.synchronize(self.arena.device)
-        v = self._arena_view(p.scalars, 16, torch.float64).cpu().tolist()
+        view = self._arena_view(p.scalars, 16, torch.float64)
+        if stream is None:
+            torch.cuda.synchronize(self.arena.device)
+            v = view.cpu().tolist()
+        else:
+            with torch.cuda.stream(stream):
+                v = view.cpu().tolist()
         return {"t": v[4], "evals": v[5], "steps": v[6], "beta": v[0]}
+
+    def reorth_columns(self, stream=None) -> List[int]:
+        """The Arnoldi columns of the last step that took the second
+        Gram-Schmidt pass."""
+        p = self.ptrs()
+        view = self._arena_view(p.control, 16, torch.int32)
+        with torch.cuda.stream(stream or torch.cuda.current_stream()):
+            c = view.cpu().tolist()
+        bits = (c[9] & 0xFFFFFFFF) | ((c[10] & 0xFFFFFFFF) << 32)
+        return [j for j in range(64) if bits >> j & 1]
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -282,6 +299,21 @@ def time_kernel(solves: Sequence[Solve], which: str, reps: int, stream=None) -> 
     ms = C.c_float()
     _check("mra_time_kernel", lib().mra_time_kernel(hs, n, KERNELS[which], reps, _stream(stream), C.byref(ms)))
     return ms.value
+
+
+STEP_PHASES = ("res_prolong", "res_fft_rows", "res_fft_cols", "res_fft_rows_inv", "res_stencil", "norm0",
+               "prolong", "fft_rows", "fft_cols", "fft_rows_inv", "jvp", "gram_schmidt", "phi1", "update",
+               "regrid_prolong", "regrid_forward", "regrid_mask")
+
+
+def step_profile(solves: Sequence[Solve], stream=None) -> Dict[str, float]:
+    """One step of the batch with a HIP event after every phase
+    (mra_step_profile): GPU milliseconds per phase, summed over the step."""
+    n = len(solves)
+    hs = (C.c_void_p * n)(*[s.handle for s in solves])
+    out = (C.c_double * len(STEP_PHASES))()
+    _check("mra_step_profile", lib().mra_step_profile(hs, n, _stream(stream), out, len(STEP_PHASES)))
+    return dict(zip(STEP_PHASES, list(out)))
 
 
 def solve_batch(solves: Sequence[Solve], nsteps: Sequence[int], stream=None) -> None:

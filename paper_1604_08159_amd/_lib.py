@@ -69,6 +69,8 @@ EXPORTS = {
     "mra_tune_get_tile": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     "mra_time_kernel": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_float)]),
+    "mra_step_profile": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.POINTER(C.c_double),
+                                     C.c_int32]),
 }
 
 

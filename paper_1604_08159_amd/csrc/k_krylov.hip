@@ -166,6 +166,7 @@ __global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
     if (threadIdx.x == 0) {
       s.scal[S_NRMAV] = nav;
       s.ctrl[C_REORTH] = once ? 0 : 1;
+      if (!once) s.ctrl[C_RBITS0 + (j >> 5)] |= 1 << (j & 31);
     }
   }
   if (once) {

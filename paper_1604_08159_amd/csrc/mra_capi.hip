@@ -353,6 +353,74 @@ hipError_t capture(const Batch& b, const LaunchCfg& c, hipStream_t st, hipGraph_
   return hipSuccess;
 }
 
+// One launch of a batch step: up to kMaxBatch solves of one configuration.
+struct StepChunk {
+  Batch b;
+  LaunchCfg c;
+};
+
+// Side streams of the graph captures (per device, default priority); a
+// captured graph does not refer to them once it is instantiated.
+constexpr int kSideStreams = 16;
+hipStream_t g_side[64][kSideStreams] = {};
+
+hipError_t side_stream(int i, hipStream_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipStream_t& s = g_side[dev][i % kSideStreams];
+  if (!s && (e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
+  *out = s;
+  return hipSuccess;
+}
+
+// Captures one step of every chunk into one graph.  A single chunk is
+// captured on `st` itself.  Several chunks become parallel branches: each is
+// enqueued on a side stream that waits for a fork event of `st`, and `st`
+// waits for each branch's join event before the capture ends.  Passive
+// scalars read their partner's step, so their chunks fork only after every
+// vorticity chunk has joined.
+hipError_t capture_chunks(const std::vector<StepChunk>& chunks, hipStream_t st, hipGraph_t* g,
+                          hipGraphExec_t* x) {
+  if (chunks.size() == 1) return capture(chunks[0].b, chunks[0].c, st, g, x);
+  std::vector<hipEvent_t> evs;
+  auto new_event = [&](hipEvent_t* e) -> hipError_t {
+    hipError_t r = hipEventCreateWithFlags(e, hipEventDisableTiming);
+    if (r == hipSuccess) evs.push_back(*e);
+    return r;
+  };
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t e1 = hipSuccess;
+  int next_side = 0;
+  for (int kind = 0; kind <= 1 && e1 == hipSuccess; ++kind) {
+    hipEvent_t fork;
+    if ((e1 = new_event(&fork)) != hipSuccess || (e1 = hipEventRecord(fork, st)) != hipSuccess) break;
+    for (const StepChunk& ch : chunks) {
+      if (ch.c.kind != kind) continue;
+      hipStream_t sd;
+      hipEvent_t join;
+      if ((e1 = side_stream(next_side++, &sd)) != hipSuccess || (e1 = hipStreamWaitEvent(sd, fork, 0)) != hipSuccess ||
+          (e1 = enqueue_step(ch.b, ch.c, sd)) != hipSuccess || (e1 = new_event(&join)) != hipSuccess ||
+          (e1 = hipEventRecord(join, sd)) != hipSuccess || (e1 = hipStreamWaitEvent(st, join, 0)) != hipSuccess)
+        break;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(st, &graph);
+  for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return e1 != hipSuccess ? e1 : e2;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) { (void)hipGraphDestroy(graph); return e; }
+  *g = graph;
+  *x = exec;
+  return hipSuccess;
+}
+
 }  // namespace
 
 int mra::tile_choice(int J, int p, int prec) {
@@ -694,8 +762,9 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
   for (int i = 0; i < n; ++i) maxs = std::max(maxs, nsteps[i]);
   const bool use_graph = st && graphs_enabled();
   for (int t = 0; t < maxs; ++t) {
-    // group the solves still running by launch configuration
-    // (vorticity solves first: a scalar's step reads its partner's step)
+    // the solves still running, grouped by launch configuration (vorticity
+    // solves first: a scalar's step reads its partner's step) and cut into
+    // launches of at most kMaxBatch solves
     std::map<std::tuple<int, int, int, int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > t) {
@@ -703,41 +772,61 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
         groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton, c.jac, c.vb, c.tile)]
             .push_back(solves[i]);
       }
+    std::vector<StepChunk> chunks;
+    std::vector<const void*> key;   // the composition: each launch's handles, then a null separator
     for (auto& kv : groups) {
       auto& v = kv.second;
+      // groups in order, vorticity first: a scalar is ready once its
+      // partner's step of this round is counted
       for (mra_solve h : v) {
         if (!scalar_step_ready(h)) return MRA_E_ARG;
         h->steps += 1;
       }
       for (size_t o = 0; o < v.size(); o += kMaxBatch) {
-        Batch b;
-        std::memset(&b, 0, sizeof(b));
-        b.n = (int)std::min<size_t>(kMaxBatch, v.size() - o);
-        std::vector<const void*> key;
-        for (int k = 0; k < b.n; ++k) {
-          b.s[k] = v[o + k]->dev;
+        StepChunk ch;
+        std::memset(&ch.b, 0, sizeof(ch.b));
+        ch.b.n = (int)std::min<size_t>(kMaxBatch, v.size() - o);
+        for (int k = 0; k < ch.b.n; ++k) {
+          ch.b.s[k] = v[o + k]->dev;
           key.push_back(v[o + k]);
         }
-        const LaunchCfg& c = v[o]->cfg;
-        if (!use_graph) {
-          MRA_TRY(enqueue_step(b, c, st));
-          continue;
-        }
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_batch_graphs.find({key, st});
-        if (it == g_batch_graphs.end()) {
-          // bounded cache: a serving loop changes the batch composition often
-          if (g_batch_graphs.size() >= kMaxCachedGraphs) {
-            MRA_TRY(hipDeviceSynchronize());   // cached graphs may be in flight on any stream
-            drop_batch_graphs();
-          }
-          GraphEntry ge;
-          MRA_TRY(capture(b, c, st, &ge.g, &ge.x));
-          it = g_batch_graphs.emplace(std::make_pair(key, st), ge).first;
-        }
-        MRA_TRY(hipGraphLaunch(it->second.x, st));
+        key.push_back(nullptr);
+        ch.c = v[o]->cfg;
+        chunks.push_back(ch);
       }
     }
+    if (!use_graph) {
+      for (const StepChunk& ch : chunks) MRA_TRY(enqueue_step(ch.b, ch.c, st));
+      continue;
+    }
+    // one graph per composition: every launch of the step is a branch of it,
+    // so a step of the whole batch, whatever its sizes, is one graph launch
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_batch_graphs.find({key, st});
+    if (it == g_batch_graphs.end()) {
+      // bounded cache: a serving loop changes the batch composition often.
+      // Drop this stream's graphs first (after the stream's work), and all
+      // graphs only if it holds none.
+      if (g_batch_graphs.size() >= kMaxCachedGraphs) {
+        MRA_TRY(hipStreamSynchronize(st));
+        bool dropped = false;
+        for (auto d = g_batch_graphs.begin(); d != g_batch_graphs.end();) {
+          if (d->first.second != st) { ++d; continue; }
+          if (d->second.x) (void)hipGraphExecDestroy(d->second.x);
+          if (d->second.g) (void)hipGraphDestroy(d->second.g);
+          d = g_batch_graphs.erase(d);
+          dropped = true;
+        }
+        if (!dropped) {
+          MRA_TRY(hipDeviceSynchronize());   // cached graphs may be in flight on any stream
+          drop_batch_graphs();
+        }
+      }
+      GraphEntry ge;
+      MRA_TRY(capture_chunks(chunks, st, &ge.g, &ge.x));
+      it = g_batch_graphs.emplace(std::make_pair(key, st), ge).first;
+    }
+    MRA_TRY(hipGraphLaunch(it->second.x, st));
   }
   return MRA_OK;
 }
@@ -834,11 +923,11 @@ int32_t mra_solve_ptrs_get(mra_solve h, mra_solve_ptrs* out) {
 static void drop_graphs_of(mra_solve h) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    bool synced = false;
     for (auto it = g_batch_graphs.begin(); it != g_batch_graphs.end();) {
       const auto& key = it->first.first;
       if (std::find(key.begin(), key.end(), static_cast<const void*>(h)) == key.end()) { ++it; continue; }
-      if (!synced) { (void)hipDeviceSynchronize(); synced = true; }
+      // the graph was launched only on its key's stream: wait for that stream
+      (void)hipStreamSynchronize(it->first.second);
       if (it->second.x) (void)hipGraphExecDestroy(it->second.x);
       if (it->second.g) (void)hipGraphDestroy(it->second.g);
       it = g_batch_graphs.erase(it);
@@ -910,6 +999,85 @@ int32_t mra_solve_destroy(mra_solve h) {
   drop_graphs_of(h);
   if (h->partner) h->partner->riders -= 1;
   delete h;
+  return MRA_OK;
+}
+
+// Phases of one exponential step, in launch order, for mra_step_profile.
+enum StepPhase : int { P_RES_PI = 0, P_RES_FFT_ROWS, P_RES_FFT_COLS, P_RES_FFT_INV, P_RES_STENCIL, P_NORM0,
+                       P_PI, P_FFT_ROWS, P_FFT_COLS, P_FFT_INV, P_JVP, P_GS, P_PHI1, P_UPDATE, P_REGRID_PI,
+                       P_REGRID_FWD, P_REGRID_MASK, P_NPHASE };
+
+int32_t mra_step_profile(mra_solve* solves, int32_t n, void* stream, double* ms_out, int32_t n_out) {
+  if (!solves || n < 1 || n > kMaxBatch || !ms_out || n_out < P_NPHASE) return MRA_E_ARG;
+  Batch b;
+  std::memset(&b, 0, sizeof(b));
+  b.n = n;
+  for (int i = 0; i < n; ++i) {
+    if (!solves[i]) return MRA_E_ARG;
+    const LaunchCfg& c0 = solves[0]->cfg;
+    const LaunchCfg& ci = solves[i]->cfg;
+    if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m || ci.vb != c0.vb ||
+        ci.tile != c0.tile || ci.kind != c0.kind || ci.integ != c0.integ || ci.jac != c0.jac)
+      return MRA_E_ARG;
+    b.s[i] = solves[i]->dev;
+  }
+  const LaunchCfg& c = solves[0]->cfg;
+  if (c.kind != 0 || c.integ != 0) return MRA_E_UNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<hipEvent_t> ev;
+  std::vector<int> phase;   // phase of the launches between event i - 1 and event i
+  auto mark = [&](int ph) -> hipError_t {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    ev.push_back(e);
+    phase.push_back(ph);
+    return hipEventRecord(e, st);
+  };
+  auto run = [&]() -> hipError_t {
+    hipError_t e;
+    const bool dbl = c.prec == 0;
+    const int rsrc = dbl ? 0 : 3;
+    if ((e = mark(-1)) != hipSuccess) return e;
+    // the launches of enqueue_step (exponential integrator), phase by phase
+    if ((e = launch_prolong(b, c, rsrc, 1, 0, 0, st)) != hipSuccess || (e = mark(P_RES_PI)) != hipSuccess) return e;
+    for (int pass = 0; pass < 3; ++pass)
+      if ((e = launch_poisson_pass(b, c, rsrc, pass, st)) != hipSuccess || (e = mark(P_RES_FFT_ROWS + pass)) != hipSuccess)
+        return e;
+    if ((e = launch_rhs(b, c, st)) != hipSuccess || (e = mark(P_RES_STENCIL)) != hipSuccess) return e;
+    if ((e = launch_norm0(b, c, st)) != hipSuccess || (e = mark(P_NORM0)) != hipSuccess) return e;
+    for (int j = 0; j < c.m; ++j) {
+      if ((e = launch_prolong(b, c, 1, dbl, j == 0 ? 1 : 3, j, st)) != hipSuccess || (e = mark(P_PI)) != hipSuccess)
+        return e;
+      for (int pass = 0; pass < 3; ++pass)
+        if ((e = launch_poisson_pass(b, c, 1, pass, st)) != hipSuccess || (e = mark(P_FFT_ROWS + pass)) != hipSuccess)
+          return e;
+      if ((e = launch_jvp(b, c, st)) != hipSuccess || (e = mark(P_JVP)) != hipSuccess) return e;
+      if ((e = launch_arnoldi(b, c, j, st)) != hipSuccess || (e = mark(P_GS)) != hipSuccess) return e;
+    }
+    if ((e = launch_phi1(b, c, st)) != hipSuccess || (e = mark(P_PHI1)) != hipSuccess) return e;
+    if ((e = launch_update(b, c, st)) != hipSuccess || (e = mark(P_UPDATE)) != hipSuccess) return e;
+    if ((e = launch_prolong(b, c, 2, 1, 0, 0, st)) != hipSuccess || (e = mark(P_REGRID_PI)) != hipSuccess) return e;
+    if ((e = launch_reset_max(b, st)) != hipSuccess || (e = launch_forward(b, c, 0, 0, st)) != hipSuccess ||
+        (e = mark(P_REGRID_FWD)) != hipSuccess)
+      return e;
+    if ((e = launch_threshold(b, c, 1, st)) != hipSuccess || (e = launch_gather(b, c, st)) != hipSuccess ||
+        (e = mark(P_REGRID_MASK)) != hipSuccess)
+      return e;
+    return hipEventSynchronize(ev.back());
+  };
+  hipError_t e = run();
+  for (int i = 0; i < P_NPHASE; ++i) ms_out[i] = 0.0;
+  if (e == hipSuccess) {
+    for (size_t i = 1; i < ev.size(); ++i) {
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, ev[i - 1], ev[i])) != hipSuccess) break;
+      ms_out[phase[i]] += ms;
+    }
+  }
+  for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return MRA_E_DEVICE;
+  for (int i = 0; i < n; ++i) solves[i]->steps += 1;
   return MRA_OK;
 }
 

@@ -24,8 +24,11 @@ constexpr int kCoarseLevels = 6;    // levels <= this are prolonged by one block
 constexpr int kTwN = 2048;          // twiddle table size (largest FFT length)
 
 // Control words (int) and scalars (double) of a solve.
+// C_RBITS0/1: the Arnoldi columns of the current step that took the second
+// Gram-Schmidt pass (bit j of word j / 32), for the byte accounting of
+// profiles; cleared when the step's first basis vector is formed.
 enum Ctrl : int { C_MEFF = 0, C_DONE = 1, C_STATUS = 2, C_CNT0 = 4, C_CNT1 = 5, C_CNT2 = 6,
-                  C_CNT3 = 7, C_REORTH = 8, C_NCTRL = 16 };
+                  C_CNT3 = 7, C_REORTH = 8, C_RBITS0 = 9, C_RBITS1 = 10, C_NCTRL = 16 };
 enum Scal : int { S_BETA = 0, S_INV = 1, S_NRMAV = 2, S_UMAX = 3, S_T = 4, S_EVALS = 5, S_STEPS = 6,
                   S_THETA = 7, S_COND = 8, S_NSCAL = 16 };
 
@@ -332,6 +335,8 @@ __device__ inline double first_scale(const SolveDev& s, int bx) {
       if (!ok) s.ctrl[C_STATUS] = 5;
       s.ctrl[C_DONE] = zero ? 1 : 0;
       s.ctrl[C_MEFF] = zero ? 0 : s.m;
+      s.ctrl[C_RBITS0] = 0;
+      s.ctrl[C_RBITS1] = 0;
     }
     inv_sh = zero ? 0.0 : 1.0 / nrm;
   }

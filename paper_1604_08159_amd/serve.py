@@ -5,12 +5,15 @@ library's kernels through solve_batch.  Requests (initial vortices, grid,
 Reynolds number, step count) arrive over time; a request is admitted as soon
 as its arena fits in the HBM budget (footprint from mra_solve_footprint) and
 stays resident -- active set, Krylov basis, dense work fields -- until its
-last step.  All resident solves advance together in rounds: solves of equal
-(J, p, precision, m) share every kernel launch and a captured step graph,
-and each such group runs on its own stream so that groups overlap on the
-device.  A solve finishes in the round in which its step count is reached;
-its result is read back, its latency recorded and its arena released, which
-may admit waiting requests.
+last step.  Resident solves of equal (J, p, m) form a group with a stream of
+its own; a group advances in rounds of a few steps (one solve_batch call, so
+its solves share every kernel launch and a captured step graph), and groups
+run independently of each other: there is no barrier across groups.  The
+host polls each group's completion event; when a round ends it retires the
+group's finished solves (result read back, latency recorded, arena
+released), admits the requests that now fit, and starts the group's next
+round, so a small request never waits for a large group's round, and
+requests that arrive while others run join as soon as memory allows.
 
 Results do not depend on the mix: kernels and reductions are per solve, so a
 solve gives bit-identical results alone and inside any batch.
@@ -89,8 +92,12 @@ class Server:
     def _admit(self, r: Request, rec: Record, now: float) -> None:
         st = self._stream(r)
         with torch.cuda.stream(st):
-            w0 = torch.from_numpy(r.omega0).to(self.dev, non_blocking=False)
+            # an asynchronous copy from pinned memory on the group's stream: the
+            # host does not wait for a round of that group still in flight
+            host = torch.from_numpy(r.omega0).pin_memory()
+            w0 = host.to(self.dev, non_blocking=True)
             s = Solve(grid_desc(r.J, r.p, r.eps), flow_desc(r.nu0, r.cs), self.prec, r.m, r.dt, w0, stream=st)
+        s._staging = (host, w0)          # alive until the copy and the init have run
         self.used += s.nbytes
         rec.admitted = now
         self.live[r.rid] = (s, r, rec, 0)
@@ -103,16 +110,20 @@ class Server:
         rec.diag = diag
         rec.n_active = int(diag["n_active"])
         rec.status = int(diag["status"])
-        rec.evals = s.scalars()["evals"]
+        rec.evals = s.scalars(stream=st)["evals"]
         rec.omega = dense
         self.used -= s.nbytes
         s.close()
         return rec
 
+    def _event(self):
+        return torch.cuda.Event()
+
     def run(self, requests: Sequence[Request], realtime: bool = True) -> List[Record]:
         """Serve the requests (sorted by arrival); returns their records.  A
         request whose footprint alone exceeds the budget is rejected
-        (status -1) without affecting the others."""
+        (status -1) without affecting the others.  realtime=False: arrival
+        times only order the queue (a virtual clock advances with them)."""
         records: Dict[int, Record] = {r.rid: Record(r.rid, r.J, r.steps, r.arrival) for r in requests}
         done: List[Record] = []
         ok = []
@@ -126,41 +137,54 @@ class Server:
         pending = collections.deque(sorted(ok, key=lambda r: r.arrival))
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if realtime else None
-        vclock = 0.0
+        vclock = [0.0]
+        now = (lambda: clock()) if realtime else (lambda: vclock[0])
+        # per group: the round in flight, as (event, solve ids, steps)
+        inflight: Dict[Tuple[int, int, int], Tuple[object, List[int], int]] = {}
         while pending or self.live:
-            now = clock() if realtime else vclock
+            progressed = False
+            # retire: every group whose round has ended
+            for key in list(inflight):
+                ev, rids, k = inflight[key]
+                if not ev.query():
+                    continue
+                del inflight[key]
+                progressed = True
+                for i in rids:
+                    s, r, rec, d = self.live[i]
+                    self.live[i] = (s, r, rec, d + k)
+                for i in [i for i in rids if self.live[i][3] >= self.live[i][1].steps]:
+                    done.append(self._retire(i, now()))
             # admission: FIFO, while the head fits in the remaining budget
-            # (realtime=False: arrival times only order the queue)
-            while pending and (not realtime or pending[0].arrival <= now):
+            while pending and (not realtime or pending[0].arrival <= now()):
                 r = pending[0]
                 if self.used + self.footprint(r) > self.budget and self.live:
                     break
                 pending.popleft()
                 if not realtime:
-                    vclock = max(vclock, r.arrival)
-                self._admit(r, records[r.rid], now if realtime else vclock)
-            if not self.live:
-                if realtime and pending:
-                    time.sleep(max(0.0, min(0.002, pending[0].arrival - clock())))
-                continue
-            # one round: every group advances together on its own stream
+                    vclock[0] = max(vclock[0], r.arrival)
+                self._admit(r, records[r.rid], now())
+                progressed = True
+            # launch: the next round of every idle group
             groups: Dict[Tuple[int, int, int], List[int]] = collections.defaultdict(list)
             for rid, (s, r, rec, k) in self.live.items():
                 groups[(r.J, r.p, r.m)].append(rid)
             for key, rids in groups.items():
+                if key in inflight:
+                    continue
                 k = min(self.round_steps, min(self.live[i][1].steps - self.live[i][3] for i in rids))
-                solves = [self.live[i][0] for i in rids]
-                solve_batch(solves, [k] * len(solves), stream=self.streams[key])
-                for i in rids:
-                    s, r, rec, d = self.live[i]
-                    self.live[i] = (s, r, rec, d + k)
-            for st in self.streams.values():
-                st.synchronize()
-            now = clock() if realtime else vclock
-            for rid in [i for i, (s, r, rec, d) in self.live.items() if d >= r.steps]:
-                done.append(self._retire(rid, now))
-            if self.progress:
+                st = self.streams[key]
+                solve_batch([self.live[i][0] for i in rids], [k] * len(rids), stream=st)
+                ev = self._event()
+                ev.record(st)
+                inflight[key] = (ev, list(rids), k)
+                progressed = True
+            if self.progress and progressed:
                 self.progress(len(done), len(self.live), len(pending))
+            if not progressed:
+                # nothing ended, arrived or started: wait a little for a round or an arrival
+                if realtime or inflight:
+                    time.sleep(0.0002)
         return done
 
 
@@ -174,11 +198,17 @@ def summarize(records: Sequence[Record], wall: float) -> Dict[str, float]:
         i = min(len(lat) - 1, max(0, int(round(q * (len(lat) - 1)))))
         return lat[i]
 
+    by_size = {}
+    for J in sorted({r.J for r in served}):
+        lj = sorted(r.latency for r in served if r.J == J)
+        q = lambda f: lj[min(len(lj) - 1, max(0, int(round(f * (len(lj) - 1)))))]
+        by_size[str(1 << J)] = {"requests": len(lj), "p50_latency_s": q(0.50), "p99_latency_s": q(0.99)}
     return {"requests": len(records), "wall_s": wall, "solves_per_s": len(served) / wall if wall > 0 else 0.0,
             "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "max_latency_s": lat[-1] if lat else 0.0,
             "active_pt_evals_per_s": sum(r.evals for r in records) / wall if wall > 0 else 0.0,
             "failed": sum(1 for r in records if r.status > 0),
-            "rejected": sum(1 for r in records if r.status < 0)}
+            "rejected": sum(1 for r in records if r.status < 0),
+            "latency_by_finest_size": by_size}
 
 
 def requests_from_problems(timed_problems, omega_fn) -> List[Request]:

@@ -303,3 +303,50 @@ def test_stream_batch_equals_alone(M):
         assert np.array_equal(s.read(stream=st)[0].cpu().numpy(), a)
     for s in solves:
         s.close()
+
+
+def test_uneven_stream_batch_equals_alone(M):
+    """Solves of three grid sizes, two precisions and a passive scalar advanced
+    by one solve_batch call on a stream: each step of the whole batch is one
+    captured graph whose branches are the configuration groups (the scalar's
+    branch after its partner's).  Uneven step counts change the composition
+    mid-call.  Every solve is bit-identical to the same solve stepped alone."""
+    pbs = [W.fujiwhara_pair(3000, J=5), W.fujiwhara_pair(3001, J=6), W.fujiwhara_pair(3002, J=7),
+           W.fujiwhara_pair(3003, J=6)]
+    precs = [M.MRA_MIXED, M.MRA_MIXED, M.MRA_FP64, M.MRA_MIXED]
+    steps = [3, 2, 3, 3]
+    st = torch.cuda.Stream(device=DEV)
+
+    def make(pb, prec):
+        with torch.cuda.stream(st):
+            return M.Solve(M.grid_desc(pb.J, pb.p, pb.eps), M.flow_desc(pb.nu0, pb.cs), prec, 8, pb.dt,
+                           _t(W.initial_field(pb)), stream=st)
+
+    def scalar(partner, pb):
+        with torch.cuda.stream(st):
+            return M.ScalarSolve(partner, M.grid_desc(pb.J, pb.p, 1e-3), 8, pb.dt,
+                                 _t(W.vapor_field(pb.N, 4.0)), eddy=True, stream=st)
+
+    alone = []
+    for pb, prec, k in zip(pbs, precs, steps):
+        s = make(pb, prec)
+        sc = scalar(s, pb) if pb is pbs[3] else None
+        for _ in range(k):
+            s.step(1, stream=st)
+            if sc is not None:
+                sc.step(1, stream=st)
+        alone.append(s.read(stream=st)[0].cpu().numpy())
+        if sc is not None:
+            alone.append(sc.read(stream=st)[0].cpu().numpy())
+            sc.close()
+        s.close()
+    solves = [make(pb, prec) for pb, prec in zip(pbs, precs)]
+    sc = scalar(solves[3], pbs[3])
+    handles = solves + [sc]
+    M.solve_batch(handles, steps + [steps[3]], stream=st)
+    got = [h.read(stream=st)[0].cpu().numpy() for h in solves] + [sc.read(stream=st)[0].cpu().numpy()]
+    for i, (g_, a) in enumerate(zip(got, alone)):
+        assert np.array_equal(g_, a), f"solve {i} differs"
+    sc.close()
+    for s in solves:
+        s.close()

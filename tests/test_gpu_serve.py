@@ -60,3 +60,23 @@ def test_budget_admission_and_rejection(S):
     assert all(r.status == 0 for r in recs if r.status >= 0)
     summ = S.summarize(recs, 1.0)
     assert summ["rejected"] >= 1 and summ["failed"] == 0
+
+
+def test_staggered_arrivals_tight_budget_equal_alone(S):
+    """Poisson-like arrivals on the wall clock and a budget of about two
+    solves: requests are admitted while others are resident and mid-run
+    (no barrier across groups), and each result is still bit-identical to
+    the request served alone."""
+    timed = W.serving_requests(8, seed=11, rate=40.0, J_range=(5, 7), steps_range=(10, 40))
+    reqs = S.requests_from_problems(timed, W.initial_field)
+    big = max(S.Server(1).footprint(r) for r in reqs)
+    srv = S.Server(hbm_budget=2 * big, round_steps=4, keep_results=True)
+    recs = {r.rid: r for r in srv.run(reqs, realtime=True)}
+    assert all(r.status == 0 for r in recs.values())
+    # some request was admitted while another one was resident and unfinished
+    overlap = [(a.rid, b.rid) for a in recs.values() for b in recs.values()
+               if a.rid != b.rid and b.admitted < a.admitted < b.finished]
+    assert overlap, "no request joined while another was running"
+    for q in reqs:
+        alone = S.Server(hbm_budget=8 << 30, round_steps=7, keep_results=True).run([q], realtime=False)[0]
+        assert torch.equal(recs[q.rid].omega, alone.omega), q.rid

@@ -29,7 +29,7 @@ class FakeSolve:
     def read(self, dense=True, stream=None):
         return None, {"n_active": 10.0, "status": 0.0}
 
-    def scalars(self):
+    def scalars(self, stream=None):
         return {"evals": 21.0 * 10 * self.steps}
 
     def close(self):
@@ -53,6 +53,16 @@ class FakeStream:
         pass
 
 
+class FakeEvent:
+    """A round's completion event: the fake batch has run when it is recorded."""
+
+    def record(self, stream=None):
+        pass
+
+    def query(self):
+        return True
+
+
 @pytest.fixture
 def fakes(monkeypatch):
     FakeSolve.live = FakeSolve.peak = FakeSolve.bytes_live = FakeSolve.peak_bytes = 0
@@ -63,11 +73,15 @@ def fakes(monkeypatch):
     monkeypatch.setattr(serve.torch.cuda, "Stream", lambda device=None: FakeStream())
     monkeypatch.setattr(serve.torch.cuda, "stream", lambda st: contextlib.nullcontext())
     monkeypatch.setattr(serve.torch, "from_numpy", lambda a: a)          # host arrays stay put
+    monkeypatch.setattr(serve.Server, "_event", lambda self: FakeEvent())
     yield
 
 
 class _Host(np.ndarray):
     def to(self, *a, **k):
+        return self
+
+    def pin_memory(self):
         return self
 
 
@@ -119,3 +133,31 @@ def test_summary_percentiles():
     s = serve.summarize(recs, 2.0)
     assert s["p50_latency_s"] == 3.0 and s["p99_latency_s"] == 10.0 and s["max_latency_s"] == 10.0
     assert s["solves_per_s"] == 2.5 and s["active_pt_evals_per_s"] == 12.5
+
+
+def test_groups_advance_without_a_barrier(fakes, monkeypatch):
+    """A large group's round still in flight does not hold a small group
+    back: the small request runs all its rounds and is retired first, and a
+    request arriving meanwhile (queued behind the budget) is admitted as soon
+    as the small one's arena is released."""
+    class SlowEvent(FakeEvent):
+        def __init__(self, slow):
+            self.slow, self.left = slow, 40 if slow else 0
+
+        def query(self):
+            if self.left > 0:
+                self.left -= 1
+                return False
+            return True
+
+    srv = serve.Server(hbm_budget=1700, round_steps=20, device="cpu")
+    # the event recorded after a J = 8 round (the last batch launched) takes 40 polls
+    monkeypatch.setattr(srv, "_event", lambda: SlowEvent(BATCHES[-1][0] == 8))
+    reqs = [_req(0, 0.0, 8, 20), _req(1, 0.0, 6, 60), _req(2, 0.0, 6, 20)]
+    recs = srv.run(reqs, realtime=False)
+    order = [r.rid for r in recs]
+    assert order.index(1) < order.index(0) and order.index(2) < order.index(0)
+    # the J = 6 rounds (3 for request 1, 1 for request 2) ran while the J = 8 round was in flight
+    j6 = [b for b in BATCHES if b[0] == 6]
+    assert sum(k for _, n, k in j6 if n >= 1) >= 60 and BATCHES.index((8, 1, 20)) < BATCHES.index(j6[-1])
+    assert all(r.status == 0 for r in recs) and FakeSolve.live == 0
