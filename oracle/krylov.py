@@ -69,10 +69,17 @@ def regrid(dense: np.ndarray, g: Grid):
 
 class Operator:
     """F and A = R J Pi at a fixed active set; J at frozen eddy viscosity, or
-    the exact Jacobian (exact=True)."""
+    the exact Jacobian (exact=True).  adapted=True: the level-adapted
+    evaluation of adapted.py (outer derivatives at each active node's local
+    level; frozen-viscosity Jacobian only)."""
 
-    def __init__(self, g: Grid, fl: ops.Flow, index_fine: np.ndarray, exact: bool = False):
-        self.g, self.fl, self.fi, self.exact = g, fl, index_fine, exact
+    def __init__(self, g: Grid, fl: ops.Flow, index_fine: np.ndarray, exact: bool = False,
+                 adapted: bool = False):
+        assert not (exact and adapted)
+        self.g, self.fl, self.fi, self.exact, self.adapted = g, fl, index_fine, exact, adapted
+        if adapted:
+            from . import adapted as ad
+            self.lam = ad.local_level(index_fine, g.J, g.p)
 
     def dense(self, vals):
         return mra.prolong(vals, self.fi, self.g.J, self.g.p)
@@ -80,10 +87,16 @@ class Operator:
     def F(self, omega_M):
         w = self.dense(omega_M)
         self.base = ops.base_fields(w, self.g.h, self.g.p, self.fl)
+        if self.adapted:
+            from . import adapted as ad
+            return ad.rhs(w, self.base, self.fi, self.lam, self.g.h, self.g.p, self.fl)
         return ops.rhs(w, self.g.h, self.g.p, self.fl, self.base).ravel()[self.fi]
 
     def Av(self, v):
         vt = self.dense(v)
+        if self.adapted:
+            from . import adapted as ad
+            return ad.jvp(vt, self.base, self.fi, self.lam, self.g.h, self.g.p, self.fl)
         f = ops.jvp_exact if self.exact else ops.jvp
         return f(vt, self.base, self.g.h, self.g.p, self.fl).ravel()[self.fi]
 
@@ -130,8 +143,8 @@ def init_state(omega0: np.ndarray, g: Grid) -> State:
 
 
 def step(st: State, g: Grid, fl: ops.Flow, m: int, dt: float, do_regrid: bool = True,
-         exact: bool = False) -> State:
-    op = Operator(g, fl, st.index_fine, exact)
+         exact: bool = False, adapted: bool = False) -> State:
+    op = Operator(g, fl, st.index_fine, exact, adapted)
     F = op.F(st.omega_M)
     V, H, m_eff, beta = arnoldi_mgs(op.Av, F, m)
     om = st.omega_M.copy()
