@@ -947,25 +947,65 @@ def pair_leg(args, m, W, dev, tmpdir: str, orc: dict) -> dict:
             "mean_active_points": sum(t["n_active"]) / len(t["n_active"]),
             "accuracy_vs_oracle": acc,
             "roofline_dominant": {"kernel": rl["dominant"], **rl["kernels"][rl["dominant"]]},
+            "kernels": rl["kernels"], "other_phases": rl["other_phases"],
             "jvp": rl["kernels"]["jvp"], "rhs_pipeline": rl["rhs_pipeline"], "phi_t": rl["phi_t"],
             "fp64_per_solve_gpu": fp64_per_solve(m, W, dev, max(10, args.steps // 2)),
             "cpu_baseline": {"value": orc["evals"] / orc["sec"], "unit": METRIC, "cores": 1, "kind": "oracle",
                              "sample": f"{args.warmup + args.steps} steps of seed {SEEDS[0]}, {orc['sec']:.1f} s"}}
 
 
+def adapted_leg(args, m, W, dev) -> dict:
+    """The 512^2 Fujiwhara batch with the level-adapted evaluation (the
+    residual and products at the active nodes on the stencils of each node's
+    local level; Pi and the Poisson solve stay dense): throughput, the
+    products' stencil time against the dense tile stencil of the same batch,
+    and the distance of the adapted run from the dense one after the timed
+    steps."""
+    import torch
+    stream = torch.cuda.Stream(device=dev)
+    pbs = [W.fujiwhara_pair(sd) for sd in SEEDS[:args.batch]]
+    out = {}
+    fields = {}
+    for name, ev in (("dense", m.MRA_EVAL_DENSE), ("adapted", m.MRA_EVAL_ADAPTED)):
+        solves = make_batch(m, W, dev, stream, pbs, m.MRA_MIXED)
+        for s in solves:
+            s.set_evaluation(ev)
+        t = timed_batch(m, solves, stream, args.warmup, args.steps)
+        dense, diag = solves[0].read(stream=stream)
+        fields[name] = (dense.cpu().numpy(), diag)
+        prof = m.step_profile(solves, stream=stream)
+        out[name] = {"value": t["value"], "ms_per_step": t["ms_per_step"],
+                     "product_stencil_ms": prof["jvp"] / pbs[0].m, "residual_stencil_ms": prof["res_stencil"],
+                     "step_profile_ms": sum(prof.values())}
+        for s in solves:
+            s.close()
+    a, da = fields["dense"]
+    b, db = fields["adapted"]
+    out["adapted_vs_dense"] = {"steps": args.warmup + args.steps, **compare_fields(a, b, da, db),
+                               "note": "the two evaluations are different discrete operators (distance O(eps))"}
+    out["workload"] = (f"Fujiwhara pair Re=5000, 512^2, batch of {len(pbs)}, mixed precision, level-adapted "
+                       f"evaluation against the dense one")
+    return out
+
+
 def drift_leg(m, W, dev, steps: int, every: int = 100) -> dict:
     """Mixed precision against FP64 over the Fujiwhara configuration's full
     length for one seed, both on the GPU (the FP64 GPU path is pinned to the
     oracle by the parity tests: 2.4e-15 over the plain configuration's 100
-    steps), and beside it the method's own sensitivity: an FP64 run whose
-    initial field carries a relative perturbation of 1e-10 (about what the
-    mixed precision leaves after a few dozen steps) against the same
-    unperturbed FP64 run.  Thresholding is discontinuous: once a perturbation
-    moves one detail across tau the two runs carry different active sets.
-    Every `every` steps: relative L2 of both pairs and their mask flips."""
+    steps), and beside it the flow's own sensitivity: FP64 runs whose initial
+    vortex moves by 1e-9 (a smooth perturbation, about the size of the
+    difference the mixed precision leaves after the first steps) or whose
+    initial field carries white noise of relative size 1e-10, each against
+    the unperturbed FP64 run.  Thresholding is discontinuous: once the runs
+    differ enough to move one detail across tau they carry different active
+    sets.  Every `every` steps: relative L2 of each pair and its mask flips."""
+    import dataclasses
     import torch
     pb = W.fujiwhara_pair(SEEDS[0])
     w0 = W.initial_field(pb)
+    v0 = pb.vortices[0]
+    shifted = dataclasses.replace(pb, vortices=(dataclasses.replace(v0, cx=v0.cx + 1e-9),) + pb.vortices[1:])
+    w0s = W.initial_field(shifted)
     rng = np.random.default_rng(7)
     w0p = w0 * (1.0 + 1e-10 * rng.standard_normal(w0.shape))
     stream = torch.cuda.Stream(device=dev)
@@ -973,22 +1013,23 @@ def drift_leg(m, W, dev, steps: int, every: int = 100) -> dict:
     with torch.cuda.stream(stream):
         mk = lambda prec, w: m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m,
                                      pb.dt, torch.from_numpy(w).to(dev), stream=stream)
-        ref, mix, per = mk(m.MRA_FP64, w0), mk(m.MRA_MIXED, w0), mk(m.MRA_FP64, w0p)
+        ref, mix, per, sft = mk(m.MRA_FP64, w0), mk(m.MRA_MIXED, w0), mk(m.MRA_FP64, w0p), mk(m.MRA_FP64, w0s)
+    runs = (("fp64", ref), ("mixed", mix), ("perturbed_fp64", per), ("shifted_fp64", sft))
     curve = []
-    first_flip = {"mixed": None, "perturbed_fp64": None}
+    first_flip = {"mixed": None, "perturbed_fp64": None, "shifted_fp64": None}
     done = 0
     while done < steps:
         k = min(every, steps - done)
-        m.solve_batch([ref, mix, per], [k] * 3, stream=stream)
+        m.solve_batch([r for _, r in runs], [k] * len(runs), stream=stream)
         done += k
         fields = {}
-        for name, s in (("fp64", ref), ("mixed", mix), ("perturbed_fp64", per)):
+        for name, s in runs:
             dense, diag = s.read(stream=stream)
             _, mask, _, _ = s.active_set()
             fields[name] = (dense.cpu().numpy(), diag, mask.cpu().numpy())
         a, da, ma = fields["fp64"]
         row = {"step": done}
-        for name in ("mixed", "perturbed_fp64"):
+        for name in ("mixed", "perturbed_fp64", "shifted_fp64"):
             b, db, mb = fields[name]
             flips = int((ma != mb).sum())
             row[name] = {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(a)), "mask_flips": flips}
@@ -998,13 +1039,17 @@ def drift_leg(m, W, dev, steps: int, every: int = 100) -> dict:
     a, da, ma = fields["fp64"]
     b, db, mb = fields["mixed"]
     c, dc, mc = fields["perturbed_fp64"]
-    for s in (ref, mix, per):
+    e, de, me = fields["shifted_fp64"]
+    for _, s in runs:
         s.close()
     return {"seed": SEEDS[0], "steps": steps, "reference": "the FP64 GPU path", **compare_fields(a, b, da, db),
             "mask_flips": int((ma != mb).sum()), "n_active_fp64": int(da["n_active"]),
             "n_active_mixed": int(db["n_active"]),
             "perturbed_fp64_vs_fp64": {"perturbation": "relative 1e-10 N(0,1) on the initial field",
                                        **compare_fields(a, c, da, dc), "mask_flips": int((ma != mc).sum())},
+            "shifted_fp64_vs_fp64": {"perturbation": "the first vortex's centre moved by 1e-9 in x",
+                                     "initial_rel_l2": float(np.linalg.norm(w0s - w0) / np.linalg.norm(w0)),
+                                     **compare_fields(a, e, da, de), "mask_flips": int((ma != me).sum())},
             "first_flip_by": first_flip, "every": every, "curve": curve, "seconds": time.perf_counter() - t0}
 
 
@@ -1080,6 +1125,8 @@ def run_default(args) -> int:
             out["fujiwhara512"] = pair_leg(args, m, W, dev, tmp.name, r2)
         out["drift_fujiwhara512"] = drift_leg(m, W, dev, args.long_steps)
         log("drift leg done")
+        out["adapted_fujiwhara512"] = adapted_leg(args, m, W, dev)
+        log("adapted leg done")
         out["ensemble"] = ensemble_leg(args, not args.no_cpu)
         log("ensemble leg done")
         out["serving"] = serving_spec_leg(args)
@@ -1092,7 +1139,7 @@ def run_default(args) -> int:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["default", "fujiwhara", "ensemble", "serving", "vapor", "three2048",
+    ap.add_argument("--workload", choices=["default", "fujiwhara", "adapted", "ensemble", "serving", "vapor", "three2048",
                                            "longrun", "implicit", "families", "serving_spec", "condensation"],
                     default="default",
                     help="default: the three-vortex 2048^2 headline with every sub-record")
@@ -1153,6 +1200,12 @@ def main() -> int:
 
     if args.workload == "fujiwhara":
         return run_fujiwhara(args)
+    if args.workload == "adapted":
+        import torch
+        import paper_1604_08159_amd as m
+        import workloads as W
+        print(json.dumps(adapted_leg(args, m, W, torch.device("cuda:0"))))
+        return 0
     return run_default(args)
 
 

@@ -73,6 +73,7 @@ enum { MRA_FP64 = 0, MRA_FP32 = 1, MRA_MIXED = 2 };
 enum { MRA_FORWARD = 1, MRA_INVERSE = -1, MRA_PROLONG = 2 };
 enum { MRA_EXPONENTIAL = 0, MRA_THETA_NEWTON = 1 };   /* time integrator of a solve */
 enum { MRA_JAC_FROZEN = 0, MRA_JAC_EXACT = 1 };        /* Jacobian of its Krylov products */
+enum { MRA_EVAL_DENSE = 0, MRA_EVAL_ADAPTED = 1 };     /* evaluation of the residual / products */
 #define MRA_MAX_NEWTON 8
 
 /* Grid: J in [j0+1, 11]; p in {2, 3} (4- and 6-point DD); j0 must equal
@@ -198,6 +199,27 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
                         const int64_t* n_active, const double* omega_active,
                         const double* v_active, double* out_active,
                         void* vel_dense_or_null, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * collocation_rhs_adapted -- collocation_rhs with the level-adapted
+ * evaluation of the adaptive wavelet collocation method that Section 2.1
+ * cites: the derivatives at an active node x take the stencils of its local
+ * level lambda(x), the finest level l of an active node of level l within
+ * periodic Chebyshev distance (2p - 2) 2^(J - l) of x (at least the level of x
+ * itself).  The flux divergence and the three Laplacians of the conservative
+ * diffusion at x use the D1 and L stencils with node spacing 2^(J - lambda)
+ * (step 2^(J - lambda) h) on the dense w~ = Pi(omega) (values of the
+ * interpolant at inactive stencil points), the velocity of the spectral
+ * Poisson solve and the eddy viscosity; where every node is active this is
+ * collocation_rhs.  The stencil work is one thread per active node; Pi and
+ * the Poisson solve stay dense.  Same arguments, workspace and errors as
+ * collocation_rhs (mra_rhs_ws_bytes covers both).
+ * ------------------------------------------------------------------------ */
+int32_t collocation_rhs_adapted(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec,
+                                const uint8_t* mask, const int32_t* index_fine,
+                                const int64_t* n_active, const double* omega_active,
+                                const double* v_active, double* out_active,
+                                void* vel_dense_or_null, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Solves.  A solve keeps its whole state in a caller-owned device arena of
@@ -364,6 +386,19 @@ int32_t mra_solve_set_integrator(mra_solve s, int32_t integrator, double theta, 
  * linear).
  * ------------------------------------------------------------------------ */
 int32_t mra_solve_set_jacobian(mra_solve s, int32_t jacobian);
+
+/* ------------------------------------------------------------------------
+ * mra_solve_set_evaluation -- how later steps of a vorticity solve evaluate
+ * the residual and the Krylov products: MRA_EVAL_DENSE (default: the stencils
+ * of the finest level at every node, Section 2.5) or MRA_EVAL_ADAPTED (the
+ * level-adapted evaluation of collocation_rhs_adapted; the local levels are
+ * taken once per step from the step's active set).  Drops the captured graphs
+ * that launch the solve.  Errors: MRA_E_ARG (null handle, unknown value);
+ * MRA_E_UNSUPPORTED on a passive scalar, with the theta-scheme or with the
+ * exact Jacobian (mra_solve_set_integrator and mra_solve_set_jacobian refuse
+ * those in turn on an adapted solve).
+ * ------------------------------------------------------------------------ */
+int32_t mra_solve_set_evaluation(mra_solve s, int32_t evaluation);
 
 /* Profiling hook: times `reps` back-to-back launches of one kernel of the
  * step, launched exactly as the step launches it for the batch `solves`

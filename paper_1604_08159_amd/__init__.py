@@ -25,7 +25,8 @@ import torch
 from . import _lib
 from ._lib import (FlowDesc, GridDesc, MraError, SolvePtrs, MRA_FORWARD, MRA_INVERSE, MRA_PROLONG,
                    MRA_FP64, MRA_FP32, MRA_MIXED, MRA_OK, MRA_E_NONFINITE, MRA_EXPONENTIAL,
-                   MRA_THETA_NEWTON, MRA_MAX_NEWTON, MRA_JAC_FROZEN, MRA_JAC_EXACT)
+                   MRA_THETA_NEWTON, MRA_MAX_NEWTON, MRA_JAC_FROZEN, MRA_JAC_EXACT, MRA_EVAL_DENSE,
+                   MRA_EVAL_ADAPTED)
 
 _LIB: Optional[C.CDLL] = None
 
@@ -131,6 +132,20 @@ def collocation_rhs(g: GridDesc, f: FlowDesc, prec: int, mask: torch.Tensor, ind
     _check("collocation_rhs", st)
 
 
+def collocation_rhs_adapted(g: GridDesc, f: FlowDesc, prec: int, mask: torch.Tensor, index_fine: torch.Tensor,
+                            n_active: torch.Tensor, omega_active: torch.Tensor, v_active: Optional[torch.Tensor],
+                            out_active: torch.Tensor, velocity: Optional[torch.Tensor] = None,
+                            ws: Optional[torch.Tensor] = None, stream=None) -> None:
+    """collocation_rhs with the level-adapted evaluation (derivatives at each
+    active node on the stencils of its local level)."""
+    if ws is None:
+        ws = _alloc(rhs_ws_bytes(g, prec), omega_active.device)
+    st = lib().collocation_rhs_adapted(C.byref(g), C.byref(f), prec, _ptr(mask), _ptr(index_fine), _ptr(n_active),
+                                       _ptr(omega_active), _ptr(v_active), _ptr(out_active), _ptr(velocity),
+                                       _ptr(ws), ws.numel(), _stream(stream))
+    _check("collocation_rhs_adapted", st)
+
+
 def solve_footprint(g: GridDesc, prec: int, m: int) -> int:
     n = C.c_size_t()
     _check("mra_solve_footprint", lib().mra_solve_footprint(C.byref(g), prec, m, C.byref(n)))
@@ -179,6 +194,10 @@ class Solve:
         _check("mra_solve_set_integrator",
                lib().mra_solve_set_integrator(self.handle, integrator, float(theta), int(newton_iters),
                                               _stream(stream)))
+
+    def set_evaluation(self, evaluation: int) -> None:
+        """Evaluation of later steps: MRA_EVAL_DENSE or MRA_EVAL_ADAPTED."""
+        _check("mra_solve_set_evaluation", lib().mra_solve_set_evaluation(self.handle, int(evaluation)))
 
     def set_jacobian(self, jacobian: int) -> None:
         """Jacobian of later steps' Krylov products: MRA_JAC_FROZEN or MRA_JAC_EXACT."""

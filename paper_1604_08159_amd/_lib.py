@@ -16,6 +16,7 @@ MRA_FP64, MRA_FP32, MRA_MIXED = 0, 1, 2
 MRA_FORWARD, MRA_INVERSE, MRA_PROLONG = 1, -1, 2
 MRA_EXPONENTIAL, MRA_THETA_NEWTON = 0, 1
 MRA_JAC_FROZEN, MRA_JAC_EXACT = 0, 1
+MRA_EVAL_DENSE, MRA_EVAL_ADAPTED = 0, 1
 MRA_MAX_NEWTON = 8
 
 
@@ -49,6 +50,10 @@ EXPORTS = {
     "collocation_rhs": (C.c_int32, [C.POINTER(GridDesc), C.POINTER(FlowDesc), C.c_int32, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "collocation_rhs_adapted": (C.c_int32, [C.POINTER(GridDesc), C.POINTER(FlowDesc), C.c_int32, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "mra_solve_set_evaluation": (C.c_int32, [C.c_void_p, C.c_int32]),
     "mra_solve_footprint": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "mra_solve_init": (C.c_int32, [C.POINTER(GridDesc), C.POINTER(FlowDesc), C.c_int32, C.c_int32,
                                    C.c_double, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,

@@ -175,7 +175,7 @@ __device__ inline void small_dft(typename C2<T>::t* v) {
 
 // One radix-2^LGR pass over NF vectors of length 2^LGL (Ns = 2^LGNS), all
 // sizes compile-time, so index arithmetic is shifts and immediate offsets.
-template <int S, typename T, int LGL, int NF, int LGNS, int LGR>
+template <int S, typename T, int LGL, int NF, int LGNS, int LGR, int NT = kFftThreads>
 __device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int nfft) {
   using V = typename C2<T>::t;
   constexpr int R = 1 << LGR, IPT = 8 / R, LGIPT = 3 - LGR;
@@ -183,8 +183,8 @@ __device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int nfft) 
   constexpr int NS = 1 << LGNS;
   constexpr int TWSHIFT = 11 - LGNS - LGR;                // kTwN = 2^11
   constexpr bool WL = LGL <= 9;
-  constexpr bool FULL = NF * PER == kFftThreads * IPT;    // every (thread, it) has an item
-  static_assert(NF * (1 << LGL) <= kFftPoints, "FFT block size");
+  constexpr bool FULL = NF * PER == NT * IPT;             // every (thread, it) has an item
+  static_assert(NF * (1 << LGL) <= 8 * NT, "FFT block size");
   const int total = nfft << LGPER;
   // item of (thread, it): wavefront w takes items [64 IPT w, 64 IPT (w + 1))
   const int qbase = ((threadIdx.x >> 6) << (6 + LGIPT)) + (threadIdx.x & 63);
@@ -228,21 +228,21 @@ __device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int nfft) 
   fft_sync(WL);
 }
 
-template <int S, typename T, int LGL, int NF, int LGNS>
+template <int S, typename T, int LGL, int NF, int LGNS, int NT = kFftThreads>
 __device__ __forceinline__ void fft_passes(typename C2<T>::t* buf, int nfft) {
   if constexpr (LGNS < LGL) {
     constexpr int REM = LGL - LGNS;
     constexpr int LGR = REM >= 3 ? 3 : REM;
-    stockham_pass<S, T, LGL, NF, LGNS, LGR>(buf, nfft);
-    fft_passes<S, T, LGL, NF, LGNS + LGR>(buf, nfft);
+    stockham_pass<S, T, LGL, NF, LGNS, LGR, NT>(buf, nfft);
+    fft_passes<S, T, LGL, NF, LGNS + LGR, NT>(buf, nfft);
   }
 }
 
 // nfft <= NF vectors of length 2^LGL at stride 2^LGL; wavefront-local when
 // L <= 512
-template <int S, typename T, int LGL, int NF>
+template <int S, typename T, int LGL, int NF, int NT = kFftThreads>
 __device__ __forceinline__ void fft_block(typename C2<T>::t* buf, int nfft) {
-  fft_passes<S, T, LGL, NF, 0>(buf, nfft);
+  fft_passes<S, T, LGL, NF, 0, NT>(buf, nfft);
 }
 
 template <typename T>
@@ -263,17 +263,23 @@ __device__ inline T* poisson_dst(const SolveDev& s, int src, int comp) {
 
 // Launch geometry, compile-time per grid level J (N = 2^J, M = N/2):
 // rows per row-pass block and spectrum rows per column-pass block.
-template <int J> struct FftGeo {
+// NT threads per row-pass block hold 8 NT points: the large grids take more
+// threads so that a block holds several rows, and each spectrum access of the
+// transposed layout covers R consecutive elements (at least 64 bytes).
+template <int J, int NT = kFftThreads> struct FftGeo {
   static constexpr int N = 1 << J, M = N >> 1, LGM = J - 1;
-  static constexpr int R = (kFftPoints >> LGM) < N ? (kFftPoints >> LGM) : N;
+  static constexpr int R = ((8 * NT) >> LGM) < N ? ((8 * NT) >> LGM) : N;
   static constexpr int C = (kFftPoints >> J) < M + 1 ? (kFftPoints >> J) : M + 1;
 };
+template <typename T, int J> constexpr int row_threads() {
+  return J >= 10 ? (sizeof(T) == 4 ? 1024 : 512) : kFftThreads;
+}
 
 // pass A: rows -> spec[kx][y], R rows per block (R * N/2 <= 2048)
-template <typename T, int J>
-__global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src) {
+template <typename T, int J, int NT = row_threads<T, J>()>
+__global__ void __launch_bounds__(NT) k_fft_rows_fwd(Batch b, int src) {
   using V = typename C2<T>::t;
-  using G = FftGeo<J>;
+  using G = FftGeo<J, NT>;
   constexpr int N = G::N, M = G::M, R = G::R;
   extern __shared__ unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
@@ -284,11 +290,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_fwd(Batch b, int src) 
   const int e1 = min(own0() + kWaveSpan, n);
   for (int q = own0() + lane(); q < e1; q += 64) buf[lx(q)] = gload(in, (size_t)y0 * M + q);
   fft_sync(G::LGM <= 9);
-  fft_block<-1, T, G::LGM, R>(buf, R);
+  fft_block<-1, T, G::LGM, R, NT>(buf, R);
   __syncthreads();
   V* spec = reinterpret_cast<V*>(s.spec);
   constexpr int twN = kTwN / N;
-  for (int q = threadIdx.x; q < (M + 1) * R; q += kFftThreads) {
+  for (int q = threadIdx.x; q < (M + 1) * R; q += NT) {
     const int k = q / R, r = q % R;
     const V zk = buf[lx(r * M + (k & (M - 1)))];
     const V zc = cconj(buf[lx(r * M + ((M - k) & (M - 1)))]);
@@ -358,10 +364,10 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b) {
 
 // pass C: spec[kx][y] -> real rows, R rows per block (R * N/2 <= 2048), for
 // the u spectrum and then the v spectrum (NC = 2), or for psi alone (NC = 1).
-template <typename T, int J, int NC>
-__global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) {
+template <typename T, int J, int NC, int NT = row_threads<T, J>()>
+__global__ void __launch_bounds__(NT) k_fft_rows_inv(Batch b, int src) {
   using V = typename C2<T>::t;
-  using G = FftGeo<J>;
+  using G = FftGeo<J, NT>;
   constexpr int N = G::N, M = G::M, R = G::R;
   extern __shared__ unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
@@ -370,7 +376,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) 
   constexpr int twN = kTwN / N;
   for (int comp = 0; comp < NC; ++comp) {
     const V* spec = reinterpret_cast<const V*>(comp == 0 ? s.spec : s.spec2);
-    for (int q = threadIdx.x; q < M * R; q += kFftThreads) {
+    for (int q = threadIdx.x; q < M * R; q += NT) {
       const int k = q / R, r = q % R;
       const V xk = gload(spec, (size_t)k * N + y0 + r);
       const V xc = cconj(gload(spec, (size_t)(M - k) * N + y0 + r));
@@ -381,7 +387,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows_inv(Batch b, int src) 
       buf[lx(r * M + k)] = z;
     }
     __syncthreads();
-    fft_block<1, T, G::LGM, R>(buf, R);
+    fft_block<1, T, G::LGM, R, NT>(buf, R);
     V* out = reinterpret_cast<V*>(poisson_dst<T>(s, src, comp));
     const int e1 = min(own0() + kWaveSpan, R * M);
     for (int q = own0() + lane(); q < e1; q += 64) gstore(out, (size_t)y0 * M + q, buf[lx(q)]);
@@ -393,9 +399,11 @@ template <typename T, int J, bool PSI>
 static void poisson_jp(const Batch& b, int p, int src, int pass, hipStream_t st) {
   using V = typename C2<T>::t;
   using G = FftGeo<J>;
+  constexpr int NT = row_threads<T, J>();
+  using GR = FftGeo<J, NT>;
   if (pass < 0 || pass == 0)
-    hipLaunchKernelGGL((k_fft_rows_fwd<T, J>), dim3((G::N / G::R) * b.n), dim3(kFftThreads),
-                       lds_slots(G::R * G::M) * sizeof(V), st, b, src);
+    hipLaunchKernelGGL((k_fft_rows_fwd<T, J>), dim3((GR::N / GR::R) * b.n), dim3(NT),
+                       lds_slots(GR::R * GR::M) * sizeof(V), st, b, src);
   if (pass < 0 || pass == 1) {
     dim3 g(((G::M + 1 + G::C - 1) / G::C) * b.n);
     const size_t lds = (PSI ? 1 : 2) * (size_t)lds_slots(G::C * G::N) * sizeof(V);
@@ -403,8 +411,8 @@ static void poisson_jp(const Batch& b, int p, int src, int pass, hipStream_t st)
     else hipLaunchKernelGGL((k_fft_cols<3, T, J, PSI>), g, dim3(kFftThreads), lds, st, b);
   }
   if (pass < 0 || pass == 2)
-    hipLaunchKernelGGL((k_fft_rows_inv<T, J, PSI ? 1 : 2>), dim3((G::N / G::R) * b.n), dim3(kFftThreads),
-                       lds_slots(G::R * G::M) * sizeof(V), st, b, src);
+    hipLaunchKernelGGL((k_fft_rows_inv<T, J, PSI ? 1 : 2>), dim3((GR::N / GR::R) * b.n), dim3(NT),
+                       lds_slots(GR::R * GR::M) * sizeof(V), st, b, src);
 }
 
 template <typename T, int J>

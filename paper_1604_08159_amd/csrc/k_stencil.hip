@@ -117,7 +117,9 @@ __host__ __device__ inline size_t jvp_lds_elems(int TS, bool exact = false) {
 // from the FP64 prolongation res64 and its FP64 velocity vel64 (u, then v).
 // Such a kernel also leaves the FP32 copies of w~, u, v (rounded) and nu_e in
 // the bulk fields, which the Jacobian-vector products of the step read.
-template <int P, typename T, int TS, bool R64 = false>
+// FIELDS: only the fields (nu_e, and with R64 the FP32 copies and nu_e in FP64
+// in dense64), no residual: the level-adapted residual follows.
+template <int P, typename T, int TS, bool R64 = false, bool FIELDS = false>
 __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   static_assert(!R64 || sizeof(T) == 8, "the FP32-bulk residual runs in FP64");
   using G = Geo<P>;
@@ -185,6 +187,16 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
   for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
     const int r = q / TS, c = q - r * TS;
     gn[(y0 + r) * N + x0 + c] = (TB)nu[(r + P) * Wn + c + P];
+  }
+  if constexpr (FIELDS) {
+    if constexpr (R64) {
+      double* g64 = s.dense64;
+      for (int q = threadIdx.x; q < TS * TS; q += blockDim.x) {
+        const int r = q / TS, c = q - r * TS;
+        g64[(y0 + r) * N + x0 + c] = nu[(r + P) * Wn + c + P];
+      }
+    }
+    return;
   }
   if (s.tile_count[tile] == 0) return;
   __syncthreads();
@@ -558,18 +570,24 @@ hipError_t launch_fill(void* f, size_t n, int prec, double value, hipStream_t st
   return hipGetLastError();
 }
 
+template <int P, typename T, int TS, bool FIELDS>
+static void rhs_launch(const Batch& b, int nt, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    // FP32 bulk fields: the residual itself runs in FP64 (k_rhs R64)
+    const size_t lds = rhs_lds_elems<P, double>(TS) * sizeof(double);
+    hipLaunchKernelGGL((k_rhs<P, double, TS, true, FIELDS>), dim3((nt) * b.n), dim3(256), lds, st, b);
+  } else {
+    const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
+    hipLaunchKernelGGL((k_rhs<P, T, TS, false, FIELDS>), dim3((nt) * b.n), dim3(256), lds, st, b);
+  }
+}
+
 template <int P, typename T, int TS>
-static hipError_t rhs_ts(const Batch& b, int N, bool jvp, bool exact, hipStream_t st) {
+static hipError_t rhs_ts(const Batch& b, int N, bool jvp, bool exact, hipStream_t st, bool fields = false) {
   const int nt = (N / TS) * (N / TS);
   if (!jvp) {
-    if constexpr (sizeof(T) == 4) {
-      // FP32 bulk fields: the residual itself runs in FP64 (k_rhs R64)
-      const size_t lds = rhs_lds_elems<P, double>(TS) * sizeof(double);
-      hipLaunchKernelGGL((k_rhs<P, double, TS, true>), dim3((nt) * b.n), dim3(256), lds, st, b);
-    } else {
-      const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
-      hipLaunchKernelGGL((k_rhs<P, T, TS>), dim3((nt) * b.n), dim3(256), lds, st, b);
-    }
+    if (fields) rhs_launch<P, T, TS, true>(b, nt, st);
+    else rhs_launch<P, T, TS, false>(b, nt, st);
   } else if (!exact) {
     const size_t lds = jvp_lds_elems<P, T>(TS) * sizeof(T);
     hipLaunchKernelGGL((k_jvp<P, T, TS, false>), dim3((nt) * b.n), dim3(256), lds, st, b);
@@ -582,23 +600,36 @@ static hipError_t rhs_ts(const Batch& b, int N, bool jvp, bool exact, hipStream_
 }
 
 template <int P, typename T>
-static hipError_t rhs_t(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {
+static hipError_t rhs_t(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st, bool fields = false) {
   const int N = 1 << c.J;
   const int TS = c.tile;     // the tile the solves were laid out with
   if (!tile_valid(c.J, c.p, c.prec, TS)) return hipErrorInvalidValue;
   const bool exact = jvp && c.jac == 1;
-  if (TS == 32) return rhs_ts<P, T, 32>(b, N, jvp, exact, st);
-  if (TS == 16) return rhs_ts<P, T, 16>(b, N, jvp, exact, st);
-  return rhs_ts<P, T, 8>(b, N, jvp, exact, st);
+  if (TS == 32) return rhs_ts<P, T, 32>(b, N, jvp, exact, st, fields);
+  if (TS == 16) return rhs_ts<P, T, 16>(b, N, jvp, exact, st, fields);
+  return rhs_ts<P, T, 8>(b, N, jvp, exact, st, fields);
 }
 
-static hipError_t rhs_dispatch(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st) {
-  if (c.prec == 0) return c.p == 2 ? rhs_t<2, double>(b, c, jvp, st) : rhs_t<3, double>(b, c, jvp, st);
-  return c.p == 2 ? rhs_t<2, float>(b, c, jvp, st) : rhs_t<3, float>(b, c, jvp, st);
+static hipError_t rhs_dispatch(const Batch& b, const LaunchCfg& c, bool jvp, hipStream_t st, bool fields = false) {
+  if (c.prec == 0)
+    return c.p == 2 ? rhs_t<2, double>(b, c, jvp, st, fields) : rhs_t<3, double>(b, c, jvp, st, fields);
+  return c.p == 2 ? rhs_t<2, float>(b, c, jvp, st, fields) : rhs_t<3, float>(b, c, jvp, st, fields);
 }
 
-hipError_t launch_rhs(const Batch& b, const LaunchCfg& c, hipStream_t st) { return rhs_dispatch(b, c, false, st); }
-hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st) { return rhs_dispatch(b, c, true, st); }
+// Level-adapted evaluation (k_adapted.hip): the local levels of the step's
+// active set, the residual's fields on the dense grid, then the residual at
+// the active nodes; the products at the active nodes.
+hipError_t launch_rhs(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  if (!c.adapt) return rhs_dispatch(b, c, false, st);
+  hipError_t e;
+  if ((e = launch_local_level(b, c, st)) != hipSuccess) return e;
+  if ((e = rhs_dispatch(b, c, false, st, true)) != hipSuccess) return e;
+  return launch_rhs_adapted(b, c, st);
+}
+hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  if (c.adapt) return launch_jvp_adapted(b, c, st);
+  return rhs_dispatch(b, c, true, st);
+}
 
 // ------------------------------------------------------------- diagnostics
 // One block per row y of the FP64 field dense64 and its FP64 velocity

@@ -138,8 +138,15 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
 // later Arnoldi vectors (src 3) are read from V_j as the Gram-Schmidt stage
 // wrote them.  The kernel is specialised per grid level J: every lattice
 // size, halo and shift is a compile-time constant.
-constexpr int kFineTile = 32;
-constexpr int kLatMax = kFineTile * kFineTile;   // lattice nodes of one level of a tile
+// FP32 tiles are 64 wide with 512 threads: against 32-wide tiles with 256
+// threads a quarter of the blocks, each with 4 waves more, and fewer halo
+// nodes per tile node (Pi per launch: 25.7 against 30.9 us for 24 solves of
+// 512^2, 54 against 66 us for two of 2048^2; 1024 threads: 30.0 and 60 us).
+// FP64 tiles stay 32 wide with 256 threads (their lattices take twice the LDS).
+constexpr int kFineTile = 64;                      // tile edge of the FP32 prolongation
+constexpr int kPiThreads = 512;                    // its threads per block
+template <typename T> constexpr int pi_tile() { return sizeof(T) == 4 ? kFineTile : 32; }
+template <typename T> constexpr int pi_threads() { return sizeof(T) == 4 ? kPiThreads : 256; }
 
 // halo E_l of the level-l lattice (fine units) and its node count per side
 // (independent of the tile offset; checked on the host for every offset)
@@ -175,23 +182,23 @@ __device__ inline int lat_origin(int x0) {
 template <int S> struct Ranks {
   int k[S];
 };
-template <int J, int P, int L>
+template <int J, int P, int L, int TB, int NT>
 __host__ __device__ constexpr int lat_slots() {
-  constexpr int B = (1 << J) < kFineTile ? (1 << J) : kFineTile;
+  constexpr int B = (1 << J) < TB ? (1 << J) : TB;
   constexpr int n = lat_count(J, P, B, 0, L);
-  return (n * n + 255) / 256;
+  return (n * n + NT - 1) / NT;
 }
-template <int J, int P, int L>
-__device__ __forceinline__ Ranks<lat_slots<J, P, L>()> level_ranks(const SolveDev& s, int x0, int y0) {
-  constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile;
+template <int J, int P, int L, int TB, int NT>
+__device__ __forceinline__ Ranks<lat_slots<J, P, L, TB, NT>()> level_ranks(const SolveDev& s, int x0, int y0) {
+  constexpr int N = 1 << J, NM = N - 1, B = N < TB ? N : TB;
   constexpr int SH = J - L, SV = 1 << SH;
-  constexpr int n = lat_count(J, P, B, 0, L), NN = n * n, SLOTS = lat_slots<J, P, L>();
+  constexpr int n = lat_count(J, P, B, 0, L), NN = n * n, SLOTS = lat_slots<J, P, L, TB, NT>();
   const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
   const auto* __restrict__ rank = glb(s.rank);
   Ranks<SLOTS> r;
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i) {
-    const int q = threadIdx.x + 256 * i;
+    const int q = threadIdx.x + NT * i;
     r.k[i] = -1;
     if (q < NN) {
       const int iy = q / n, ix = q - iy * n;
@@ -205,18 +212,18 @@ __device__ __forceinline__ Ranks<lat_slots<J, P, L>()> level_ranks(const SolveDe
 // kin: this level's ranks, loaded while the previous level was swept; the
 // ranks of the next level are loaded here in turn, so a rank load is never
 // on the path between two levels.
-template <int P, typename T, int J, int L, bool FB>
-__device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLatMax], T* half, int cur, int x0,
+template <int P, typename T, int J, int L, bool FB, int TB, int NT>
+__device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[TB * TB], T* half, int cur, int x0,
                                                  int y0, int src, double inv, double* Vd, float* Vf, T* f,
-                                                 const Ranks<lat_slots<J, P, L>()>& kin) {
+                                                 const Ranks<lat_slots<J, P, L, TB, NT>()>& kin) {
 #pragma clang fp contract(off)
-  constexpr int N = 1 << J, B = N < kFineTile ? N : kFineTile;
+  constexpr int N = 1 << J, B = N < TB ? N : TB;
   constexpr int SH = J - L, SV = 1 << SH;  // node spacing of level L (fine units)
   constexpr int n = lat_count(J, P, B, 0, L), pn = lat_count(J, P, B, 0, L - 1);
-  constexpr int NN = n * n, SLOTS = lat_slots<J, P, L>();
+  constexpr int NN = n * n, SLOTS = lat_slots<J, P, L, TB, NT>();
   constexpr int NH = n * pn;
-  static_assert(NN <= kLatMax && SLOTS <= 4, "lattice of one level exceeds the tile buffer");
-  static_assert(NH <= kLatMax, "half-predicted lattice exceeds its buffer");
+  static_assert(NN <= TB * TB && SLOTS <= 16, "lattice of one level exceeds the tile buffer");
+  static_assert(NH <= TB * TB, "half-predicted lattice exceeds its buffer");
   const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
   const int pox = lat_origin<J, P, L - 1>(x0), poy = lat_origin<J, P, L - 1>(y0);
   const T* prev = buf[cur];
@@ -246,10 +253,10 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
     }
   }
   constexpr int LN = L < J ? L + 1 : L;
-  Ranks<lat_slots<J, P, LN>()> knext;
-  if constexpr (L < J) knext = level_ranks<J, P, LN>(s, x0, y0);
+  Ranks<lat_slots<J, P, LN, TB, NT>()> knext;
+  if constexpr (L < J) knext = level_ranks<J, P, LN, TB, NT>(s, x0, y0);
   // pass 1: level-L rows of the level-(L - 1) columns
-  for (int q = threadIdx.x; q < NH; q += 256) {
+  for (int q = threadIdx.x; q < NH; q += NT) {
     const int iy = q / pn, c = q - iy * pn;
     const int dy = oy + (iy << SH) - poy;
     T v;
@@ -268,7 +275,7 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
   // pass 2: every node of level L from its row of `half`
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i) {
-    const int q = threadIdx.x + 256 * i;
+    const int q = threadIdx.x + NT * i;
     if (q < NN) {
       const int iy = q / n, ix = q - iy * n;
       const int x = ox + (ix << SH), y = oy + (iy << SH);
@@ -297,20 +304,20 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[kLa
   }
   if constexpr (L < J) {
     __syncthreads();
-    prolong_level_ct<P, T, J, L + 1, FB>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vd, Vf, f, knext);
+    prolong_level_ct<P, T, J, L + 1, FB, TB, NT>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vd, Vf, f, knext);
   }
 }
 
-template <int P, typename T, int J, bool FB>
-__global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int src, int j) {
+template <int P, typename T, int J, bool FB, int TB = pi_tile<T>(), int NT = pi_threads<T>()>
+__global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int src, int j) {
 #pragma clang fp contract(off)
-  constexpr int N = 1 << J, NM = N - 1, B = N < kFineTile ? N : kFineTile, NTX = N / B;
+  constexpr int N = 1 << J, NM = N - 1, B = N < TB ? N : TB, NTX = N / B;
   constexpr int J0 = P == 2 ? 2 : 3;
   constexpr int pn = lat_count(J, P, B, 0, J0), SH0 = J - J0;
-  static_assert(pn * pn <= 256, "coarsest lattice exceeds one node per thread");
+  static_assert(pn * pn <= NT, "coarsest lattice exceeds one node per thread");
   static_assert(lat_count(J, P, B, 0, J) == B, "finest lattice is the tile");
-  __shared__ T buf[2][kLatMax];
-  __shared__ T half[kLatMax];
+  __shared__ T buf[2][TB * TB];
+  __shared__ T half[TB * TB];
   const SolveDev& s = MRA_SOLVE(b);
   const int t = MRA_BX(b);
   const int x0 = (t % NTX) * B, y0 = (t / NTX) * B;
@@ -323,7 +330,7 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
   const bool has0 = (int)threadIdx.x < pn * pn;
   int x0n = 0, y0n = 0, k0n = 0;
   double raw = 0.0;
-  const auto k1 = level_ranks<J, P, J0 + 1>(s, x0, y0);   // first swept level, in flight meanwhile
+  const auto k1 = level_ranks<J, P, J0 + 1, TB, NT>(s, x0, y0);   // first swept level, in flight meanwhile
   if (has0) {
     const int q = threadIdx.x;
     const int iy = q / pn, ix = q - iy * pn;
@@ -347,7 +354,7 @@ __global__ void __launch_bounds__(256) k_prolong_tiles(Batch b, int target, int 
     buf[0][threadIdx.x] = (T)a;
   }
   __syncthreads();
-  prolong_level_ct<P, T, J, J0 + 1, FB>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f, k1);
+  prolong_level_ct<P, T, J, J0 + 1, FB, TB, NT>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f, k1);
 }
 
 template <int P, typename T>
@@ -373,9 +380,9 @@ __global__ void k_inverse_coarse(Batch b, int target) {
 // Host check of k_prolong_tiles' assumptions for a grid, over every tile
 // offset: each level's lattice count is the one the kernel was compiled for
 // (the count at offset 0, so the x and y lattices of a tile have equal size).
-static bool lattice_fits(int J, int P) {
+static bool lattice_fits(int J, int P, int TB) {
   const int N = 1 << J, j0 = P == 2 ? 2 : 3;
-  const int B = N < kFineTile ? N : kFineTile;
+  const int B = N < TB ? N : TB;
   for (int x0 = 0; x0 < N; x0 += B)
     for (int l = j0; l <= J; ++l)
       if (lat_count(J, P, B, x0, l) != lat_count(J, P, B, 0, l)) return false;
@@ -384,8 +391,9 @@ static bool lattice_fits(int J, int P) {
 
 template <int P, typename T, int J, bool FB>
 static void prolong_j(const Batch& b, int target, int src, int j, hipStream_t st) {
-  constexpr int N = 1 << J, B = N < kFineTile ? N : kFineTile;
-  hipLaunchKernelGGL((k_prolong_tiles<P, T, J, FB>), dim3((N / B) * (N / B) * b.n), dim3(256), 0, st, b, target,
+  constexpr int TB = pi_tile<T>(), NT = pi_threads<T>();
+  constexpr int N = 1 << J, B = N < TB ? N : TB;
+  hipLaunchKernelGGL((k_prolong_tiles<P, T, J, FB>), dim3((N / B) * (N / B) * b.n), dim3(NT), 0, st, b, target,
                      src, j);
 }
 
@@ -411,7 +419,7 @@ static hipError_t prolong_p(const Batch& b, int J, int target, int src, int j, h
 // such solves).
 template <typename T>
 static hipError_t prolong_t(const Batch& b, const LaunchCfg& c, int target, int src, int j, hipStream_t st) {
-  if (!lattice_fits(c.J, c.p)) return hipErrorInvalidValue;
+  if (!lattice_fits(c.J, c.p, pi_tile<T>())) return hipErrorInvalidValue;
   if ((src == 1 || src == 3) && c.vb) {
     if constexpr (std::is_same<T, float>::value)
       return c.p == 2 ? prolong_p<2, T, true>(b, c.J, target, src, j, st)

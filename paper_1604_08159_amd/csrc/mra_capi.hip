@@ -170,7 +170,9 @@ void rhs_layout(Layout& L, SolveDev& s) {
   if (s.prec != 0) {
     s.res64 = L.take<double>(Nf);
     s.vel64 = L.take<double>(2 * Nf);
+    s.dense64 = L.take<double>(Nf);     // FP64 nu_e of the level-adapted residual
   }
+  s.lam = L.take<uint8_t>(Nf);
   s.out_rhs = L.take<double>(Nf);
 }
 
@@ -212,6 +214,7 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.dense64 = L.take<double>(Nf);
   s.packed64 = L.take<double>(Nf);
   s.diag = L.take<double>((size_t)s.N * 5);
+  s.lam = L.take<uint8_t>(Nf);
   s.out_rhs = s.w;
   s.out_jvp = s.w;
   // FP32 bulk fields: the FP64 prolongation of the residual lives in the
@@ -557,10 +560,10 @@ int32_t mra_rhs_ws_bytes(const mra_grid_desc* g, int32_t prec, size_t* bytes) {
   return MRA_OK;
 }
 
-int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, const uint8_t* mask,
+static int32_t rhs_impl(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, const uint8_t* mask,
                         const int32_t* index_fine, const int64_t* n_active, const double* omega_active,
                         const double* v_active, double* out_active, void* vel_dense_or_null, void* ws,
-                        size_t ws_bytes, void* stream) {
+                        size_t ws_bytes, void* stream, int adapt) {
   int32_t r = check_grid(g);
   if (r != MRA_OK) return r;
   if ((r = check_flow(f)) != MRA_OK) return r;
@@ -594,6 +597,7 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
   const int dbl = s.prec == 0;
   LaunchCfg c{s.J, s.p, s.prec, 0};
   c.tile = s.tile;
+  c.adapt = adapt;
   MRA_TRY(launch_write_desc(dev, s, st));
   Batch b = one(dev);
   MRA_TRY(launch_reset_ctrl(b, st));
@@ -605,6 +609,22 @@ int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t 
     MRA_TRY(launch_jvp(b, c, st));
   }
   return MRA_OK;
+}
+
+int32_t collocation_rhs(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, const uint8_t* mask,
+                        const int32_t* index_fine, const int64_t* n_active, const double* omega_active,
+                        const double* v_active, double* out_active, void* vel_dense_or_null, void* ws,
+                        size_t ws_bytes, void* stream) {
+  return rhs_impl(g, f, prec, mask, index_fine, n_active, omega_active, v_active, out_active, vel_dense_or_null,
+                  ws, ws_bytes, stream, 0);
+}
+
+int32_t collocation_rhs_adapted(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, const uint8_t* mask,
+                                const int32_t* index_fine, const int64_t* n_active, const double* omega_active,
+                                const double* v_active, double* out_active, void* vel_dense_or_null, void* ws,
+                                size_t ws_bytes, void* stream) {
+  return rhs_impl(g, f, prec, mask, index_fine, n_active, omega_active, v_active, out_active, vel_dense_or_null,
+                  ws, ws_bytes, stream, 1);
 }
 
 int32_t mra_solve_footprint(const mra_grid_desc* g, int32_t prec, int32_t m, size_t* bytes) {
@@ -765,11 +785,11 @@ int32_t solve_batch(mra_solve* solves, int32_t n, const int32_t* nsteps, void* s
     // the solves still running, grouped by launch configuration (vorticity
     // solves first: a scalar's step reads its partner's step) and cut into
     // launches of at most kMaxBatch solves
-    std::map<std::tuple<int, int, int, int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
+    std::map<std::tuple<int, int, int, int, int, int, int, int, int, int, int>, std::vector<mra_solve>> groups;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > t) {
         const LaunchCfg& c = solves[i]->cfg;
-        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton, c.jac, c.vb, c.tile)]
+        groups[std::make_tuple(c.kind, c.J, c.p, c.prec, c.m, c.integ, c.newton, c.jac, c.vb, c.tile, c.adapt)]
             .push_back(solves[i]);
       }
     std::vector<StepChunk> chunks;
@@ -954,12 +974,25 @@ int32_t mra_solve_set_integrator(mra_solve h, int32_t integrator, double theta, 
     if (newton_iters < 1 || newton_iters > MRA_MAX_NEWTON) return MRA_E_ARG;
   }
   if (h->cfg.kind != 0) return MRA_E_UNSUPPORTED;
-  if (integrator == MRA_THETA_NEWTON && h->riders > 0) return MRA_E_UNSUPPORTED;
+  if (integrator == MRA_THETA_NEWTON && (h->riders > 0 || h->cfg.adapt)) return MRA_E_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   drop_graphs_of(h);
   if (integrator == MRA_THETA_NEWTON) MRA_TRY(launch_set_scal(one(h->dev), S_THETA, theta, st));
   h->cfg.integ = integrator;
   h->cfg.newton = integrator == MRA_THETA_NEWTON ? newton_iters : 0;
+  return MRA_OK;
+}
+
+int32_t mra_solve_set_evaluation(mra_solve h, int32_t evaluation) {
+  if (!h) return MRA_E_ARG;
+  if (evaluation != MRA_EVAL_DENSE && evaluation != MRA_EVAL_ADAPTED) return MRA_E_ARG;
+  if (h->cfg.kind != 0) return MRA_E_UNSUPPORTED;
+  // the adapted residual keeps the FP64 eddy viscosity in the regrid field,
+  // which the theta-scheme's Newton iterations hold; its products are the
+  // frozen-viscosity ones
+  if (evaluation == MRA_EVAL_ADAPTED && (h->cfg.integ != 0 || h->cfg.jac != 0)) return MRA_E_UNSUPPORTED;
+  drop_graphs_of(h);
+  h->cfg.adapt = evaluation;
   return MRA_OK;
 }
 
@@ -988,6 +1021,7 @@ int32_t mra_solve_set_jacobian(mra_solve h, int32_t jacobian) {
   if (!h) return MRA_E_ARG;
   if (jacobian != MRA_JAC_FROZEN && jacobian != MRA_JAC_EXACT) return MRA_E_ARG;
   if (h->cfg.kind != 0) return MRA_E_UNSUPPORTED;
+  if (jacobian == MRA_JAC_EXACT && h->cfg.adapt) return MRA_E_UNSUPPORTED;
   drop_graphs_of(h);
   h->cfg.jac = jacobian;
   return MRA_OK;
@@ -1017,7 +1051,8 @@ int32_t mra_step_profile(mra_solve* solves, int32_t n, void* stream, double* ms_
     const LaunchCfg& c0 = solves[0]->cfg;
     const LaunchCfg& ci = solves[i]->cfg;
     if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m || ci.vb != c0.vb ||
-        ci.tile != c0.tile || ci.kind != c0.kind || ci.integ != c0.integ || ci.jac != c0.jac)
+        ci.tile != c0.tile || ci.kind != c0.kind || ci.integ != c0.integ || ci.jac != c0.jac ||
+        ci.adapt != c0.adapt)
       return MRA_E_ARG;
     b.s[i] = solves[i]->dev;
   }
@@ -1092,7 +1127,8 @@ int32_t mra_time_kernel(mra_solve* solves, int32_t n, int32_t which, int32_t rep
     if (!solves[i]) return MRA_E_ARG;
     const LaunchCfg& c0 = solves[0]->cfg;
     const LaunchCfg& ci = solves[i]->cfg;
-    if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m || ci.vb != c0.vb || ci.tile != c0.tile)
+    if (ci.J != c0.J || ci.p != c0.p || ci.prec != c0.prec || ci.m != c0.m || ci.vb != c0.vb || ci.tile != c0.tile ||
+        ci.adapt != c0.adapt)
       return MRA_E_ARG;
     b.s[i] = solves[i]->dev;
   }

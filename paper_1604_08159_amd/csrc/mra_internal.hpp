@@ -82,6 +82,7 @@ struct SolveDev {
   double* out_jvp;          // J v at the active nodes [Nf]
   const double* vin;        // active vector scattered by src 2 of the scatter
   double* diag;             // [N][4] per-row diagnostic partial sums
+  uint8_t* lam;             // level-adapted evaluation: local level of each active node [Nf]
 };
 
 struct Batch {
@@ -354,6 +355,7 @@ struct LaunchCfg {
   int jac = 0;    // Jacobian of the Krylov products: 0 eddy viscosity frozen, 1 exact
   int vb = 0;     // Krylov basis stored in FP32 (precision MRA_FP32); FP64 otherwise
   int tile = 0;   // stencil tile edge of the solves (their SolveDev tile)
+  int adapt = 0;  // evaluation: 0 dense, 1 level-adapted at the active nodes
 };
 
 hipError_t launch_write_desc(SolveDev* dst, const SolveDev& src, hipStream_t st);
@@ -383,6 +385,10 @@ hipError_t launch_poisson_pass(const Batch& b, const LaunchCfg& c, int src, int 
 // and vel64, also writing the FP32 wt, u, v and nu_e that their products read.
 hipError_t launch_rhs(const Batch& b, const LaunchCfg& c, hipStream_t st);
 hipError_t launch_jvp(const Batch& b, const LaunchCfg& c, hipStream_t st);
+// level-adapted evaluation: local levels, residual and products at the active nodes
+hipError_t launch_local_level(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_rhs_adapted(const Batch& b, const LaunchCfg& c, hipStream_t st);
+hipError_t launch_jvp_adapted(const Batch& b, const LaunchCfg& c, hipStream_t st);
 // passive-scalar operator at the active nodes (check_done: skip once the basis is complete)
 hipError_t launch_scalar(const Batch& b, const LaunchCfg& c, int check_done, hipStream_t st);
 hipError_t launch_fill(void* f, size_t n, int prec, double value, hipStream_t st);
