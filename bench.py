@@ -70,8 +70,9 @@ def kernel_bytes(phase: str, N: int, na: float, phi_t: float, esz: int, m: int) 
                          tiles holding an active node) + 12 N_a (FP64 out + index)
       residual stencil   2 esz N_f phi_t (w~, psi) + 12 N_a
       Gram-Schmidt       16 m (m+1) N_a + 64 m N_a per step for CGS2 with the
-                         second pass in every column, per column: that over m
-                         (gs_bytes gives the passes a step actually took)
+                         second pass in every column and every pass reading
+                         the basis twice, per column: that over m (gs_bytes
+                         gives what the delayed second pass reads, about half)
     The residual of a solve with FP32 bulk fields runs in FP64 (esz 8 for its
     phases).  The dense int32 rank map that the kernels read is implementation
     traffic and is reported apart (rank_map_bytes)."""
@@ -89,17 +90,15 @@ def kernel_bytes(phase: str, N: int, na: float, phi_t: float, esz: int, m: int) 
     raise KeyError(phase)
 
 
-def gs_bytes(N_a: float, m: int, reorth, vsz: int = 8) -> float:
-    """Bytes of the Gram-Schmidt of one step as the selective CGS2 runs it:
-    column j reads the basis V_0..V_j (vsz bytes per entry) and w (FP64) once
-    for its first pass, once more where it takes the second pass (reorth),
-    and once to form V_{j+1}, which it writes (no V_{j+1} for the last
-    column)."""
+def gs_bytes(N_a: float, m: int, vsz: int = 8) -> float:
+    """Bytes of the Gram-Schmidt of one step as the delayed-reorthogonalisation
+    CGS2 runs it: column j reads slots 0..j of the basis (vsz bytes per entry)
+    and w (FP64) twice, once per stage, and writes v_j (j > 0) and r_{j+1}
+    (j < m - 1).  Every column gets its second pass within these two reads."""
     tot = 0.0
     for j in range(m):
         rd = (j + 1) * vsz + 8
-        last = j == m - 1
-        tot += rd * (1 + (1 if j in reorth else 0) + (0 if last else 1)) + (0 if last else vsz)
+        tot += 2 * rd + vsz * ((1 if j > 0 else 0) + (1 if j < m - 1 else 0))
     return tot * N_a
 
 
@@ -114,7 +113,7 @@ def roofline_from_profile(prof: dict, N: int, na: float, phi_t: float, nbatch: i
     """Per-kernel achieved bandwidth from one profiled step (GPU ms per phase,
     summed over the step): algorithmic bytes per launch / average launch time.
     gs_step_bytes: the Gram-Schmidt bytes of the profiled step over the batch
-    (gs_bytes); else CGS2 with every second pass."""
+    (gs_bytes); else the CGS2 model of kernel_bytes."""
     step_ms = sum(prof.values())
     out = {}
     for ph in MODELLED:
@@ -824,11 +823,10 @@ def step_roofline(m, solves, stream, N: int, m_kry: int, bulk_esz: int) -> dict:
     nas = [int(s.read(dense=False, stream=stream)[1]["n_active"]) for s in solves]   # the profiled step's N_a
     na = sum(nas) / len(nas)
     prof = m.step_profile(solves, stream=stream)
-    reorth = [s.reorth_columns(stream=stream) for s in solves]
-    gsb = sum(gs_bytes(a, m_kry, set(r)) for a, r in zip(nas, reorth))
+    gsb = sum(gs_bytes(a, m_kry) for a in nas)
     kern = roofline_from_profile(prof, N, na, phi_t, len(solves), bulk_esz, m_kry, gs_step_bytes=gsb)
-    kern["gram_schmidt"]["second_pass_columns"] = [len(r) for r in reorth]
-    kern["gram_schmidt"]["full_cgs2_bytes_per_launch"] = kernel_bytes("gram_schmidt", N, na, phi_t, 8, m_kry) * len(solves)
+    kern["gram_schmidt"]["cgs2_two_reads_per_pass_bytes_per_launch"] = \
+        kernel_bytes("gram_schmidt", N, na, phi_t, 8, m_kry) * len(solves)
     step_ms = sum(prof.values())
     dom = max(kern, key=lambda k: kern[k]["avg_launch_ms"] * kern[k]["launches_per_step"])
     # phases with no byte model (phi_1, update, regrid, norm) keep their share

@@ -104,14 +104,14 @@ typedef struct {
   int32_t* index_fine;       /* [N*N], first N_a valid                           */
   int64_t* n_active;         /* device scalar                                    */
   void* krylov_V;            /* [(m+1)][N*N] Arnoldi basis: double, or float for
-                                precision MRA_FP32 (sums over it are FP64)      */
+                                precision MRA_FP32 (sums over it are FP64); after
+                                a step rows 0 .. m_eff-1 hold the orthonormal
+                                basis, the next row a work vector              */
   double* hessenberg;        /* [(m+1)][m] FP64                                  */
-  double* scalars;           /* [16] FP64: [0] beta, [2] ||A v_last||, [4] t,
+  double* scalars;           /* [16] FP64: [0] beta, [4] t,
                                 [5] active-point residual evaluations so far
                                 (sum over steps of (1 + m_eff) N_a), [6] steps */
-  int32_t* control;          /* [16] int: [0] m_eff, [1] done, [2] status; [9], [10]
-                                the Arnoldi columns of the last step that took the
-                                second Gram-Schmidt pass (bit j of word j / 32)  */
+  int32_t* control;          /* [16] int: [0] m_eff, [1] done, [2] status        */
 } mra_solve_ptrs;
 
 const char* mra_status_str(int32_t status);
@@ -231,8 +231,9 @@ int32_t collocation_rhs_adapted(const mra_grid_desc* g, const mra_flow_desc* f, 
  *   thresholded to the first active set; the host handle is written to *out.
  * krylov_step: nsteps exponential Rosenbrock-Euler steps
  *   omega_M <- omega_M + dt beta V_m phi_1(dt H_m) e_1, with Arnoldi
- *   (classical Gram-Schmidt with a second pass where the first loses more
- *   than half of ||A v_j||^2, happy breakdown h_{j+1,j} <= 1e-13 ||A v_j||, beta = 0 -> no update) and
+ *   (classical Gram-Schmidt with a second pass for every column, delayed to
+ *   the next column's reads of the basis (DCGS2); happy breakdown
+ *   h_{j+1,j} <= 1e-13 ||A v_j||, beta = 0 -> no update) and
  *   an FP64 regrid (Pi, forward transform, threshold, gather) after each
  *   step.  The first call captures one step into a HIP graph on `stream`;
  *   later calls replay it.
@@ -351,7 +352,7 @@ int32_t mra_solve_destroy(mra_solve s);
  * (I - theta dt J(w_k)) d = -G(w_k), w_{k+1} = w_k + d, with J the Jacobian at
  * eddy viscosity frozen at w_k (the exponential step's operator) and each
  * linear system solved by one GMRES(m) cycle from a zero guess: the Arnoldi
- * process of J from -G (CGS2, the same breakdown rule), then the least-squares
+ * process of J from -G (the same Gram-Schmidt and breakdown rule), then the least-squares
  * problem on I~ - theta dt H (Givens rotations).  Each step ends with the
  * FP64 regrid.  No extra arena memory.  theta and newton_iters are ignored for
  * MRA_EXPONENTIAL.  Takes effect for steps enqueued after the call (theta is

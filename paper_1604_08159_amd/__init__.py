@@ -256,16 +256,6 @@ class Solve:
                 v = view.cpu().tolist()
         return {"t": v[4], "evals": v[5], "steps": v[6], "beta": v[0]}
 
-    def reorth_columns(self, stream=None) -> List[int]:
-        """The Arnoldi columns of the last step that took the second
-        Gram-Schmidt pass."""
-        p = self.ptrs()
-        view = self._arena_view(p.control, 16, torch.int32)
-        with torch.cuda.stream(stream or torch.cuda.current_stream()):
-            c = view.cpu().tolist()
-        bits = (c[9] & 0xFFFFFFFF) | ((c[10] & 0xFFFFFFFF) << 32)
-        return [j for j in range(64) if bits >> j & 1]
-
     def close(self) -> None:
         if getattr(self, "handle", None):
             _check("mra_solve_destroy", lib().mra_solve_destroy(self.handle))   # refused while scalars ride on it

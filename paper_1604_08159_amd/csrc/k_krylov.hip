@@ -1,6 +1,6 @@
 // Krylov part of the time steps, in FP64 arithmetic (the basis is stored in
 // FP64, or in FP32 for precision MRA_FP32): Arnoldi with classical
-// Gram-Schmidt and a selective reorthogonalisation (CGS2); for the
+// Gram-Schmidt and a reorthogonalisation delayed by one column (DCGS2); for the
 // exponential Rosenbrock-Euler
 // step phi_1(dt H) e_1 from the exponential of the augmented Hessenberg
 // matrix and the update omega_M += dt beta V y; for the theta-scheme the
@@ -28,8 +28,40 @@ namespace mra {
 // at once (MJ >= j + 1 register slots, MJ fixed at compile time from m), so a
 // chunk costs one dependent global round per element instead of one per group
 // of basis vectors.
+//
+// Classical Gram-Schmidt with the reorthogonalisation delayed by one column
+// (DCGS2: Swirydowicz, Langou, Ananthan, Yang and Thomas, "Low
+// synchronization Gram-Schmidt and GMRES algorithms", 2020; Bielich et al.,
+// 2022).  Every column gets its second pass, as in CGS2, but the second pass
+// of column j - 1 shares the reads of the basis with the first pass of column
+// j, so a column costs two passes over the basis, not three or four.  Slot j
+// of the basis holds r_j, the residual of the first pass of column j - 1 (not
+// normalised and not yet reorthogonalised; for j = 0 the normalised v_0), and
+// the product w = A r_j is taken of it.  Column j:
+//   stage 1 (k_gs_dot)   g = V_{<j}^T w, c = r_j^T w, ||w||^2;
+//   stage 2 (k_gs_update), with s = V_{<j}^T r_j and ||r_j||^2 from the
+//     previous column's stage 2:
+//       alpha = ||r_j - V s|| = sqrt(||r_j||^2 - ||s||^2)      (Pythagoras)
+//       column j - 1 of H: h^(j-1) + s, and H[j][j-1] = alpha     (final)
+//       v_j = (r_j - V s) / alpha
+//       A v_j = (w - V_{<=j} u) / alpha,  u = H[0..j][0..j-1] s   (Arnoldi)
+//       h^(j) = V_{<=j}^T A v_j: (g_i - u_i) / alpha for i < j,
+//               (kappa - u_j) / alpha at j, kappa = (c - s^T g) / alpha
+//       r_{j+1} = A v_j - V_{<=j} h^(j) = (w - V g - kappa v_j) / alpha
+//     and on the fly the partials of V_{<=j}^T r_{j+1} and ||r_{j+1}||^2;
+//   after the last column, k_gs_last ends column m - 1 from those partials.
+// A breakdown of column j - 1 (alpha <= 1e-13 ||A v_{j-1}||, with
+// ||A v_{j-1}||^2 = ||h^(j-1)||^2 + ||r_j||^2) or a non-finite value ends the
+// basis at column j's stage 2 (m_eff = j).  The oracle's Arnoldi uses
+// modified Gram-Schmidt; in exact arithmetic the two give the same basis and
+// Hessenberg matrix.
+//
+// Partials: stage 1 writes buffer 0; stage 2 of column j reads buffer
+// 1 + ((j - 1) & 1) and writes 1 + (j & 1), so no kernel overwrites partials
+// that a block of the same kernel is still reading.  The first-pass
+// coefficients h^(j) wait in hpart slot j & 1 until the next column ends them.
 
-// ||F||^2 partials (buffer B).
+// ||F||^2 partials (buffer 1).
 __global__ void __launch_bounds__(256) k_norm0(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
   const int na = (int)*s.n_active;
@@ -44,7 +76,7 @@ __global__ void __launch_bounds__(256) k_norm0(Batch b) {
   }
 }
 
-// Stage 1: h1 = V_j^T w and ||w||^2 (= ||A v_j||^2) partials (buffer A).
+// Stage 1: V_{<=j}^T w (slot j holding r_j) and ||w||^2 partials (buffer 0).
 template <typename TV, int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
@@ -71,7 +103,7 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
         if (i <= j) acc[i] += (double)v[i] * wk;
       acc[MJ] += wk * wk;
     }
-    // slot layout: h1[0 .. j], then ||w||^2 at j + 1 (static register indices)
+    // slot layout: g[0 .. j - 1], c at j, ||w||^2 at j + 1 (static register indices)
 #pragma unroll
     for (int i = 0; i < MJ; ++i)
       if (i == j + 1) acc[i] = acc[MJ];
@@ -80,150 +112,189 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   }
 }
 
-// End of column j, shared by stages 2 and 3.  h1 holds the first-pass
-// coefficients; h holds the second-pass ones h2 (zeros when the pass was
-// skipped) and ||w1||^2 at j + 1; nav = ||A v_j||.  h_{j+1,j} comes from
-// Pythagoras, ||w1||^2 - ||h2||^2 (V_j orthonormal, h2 = V_j^T w1), before
-// the update, so V_{j+1} = (w - V_j h1 - V_j h2) / h_{j+1,j} is written
-// normalised in one pass (w1 is rebuilt from w with the same operations in
-// the same order as the second pass took them).  In CGS2 h2 is a
-// rounding-level correction, so no cancellation arises.  A breakdown
-// (h_{j+1,j} <= 1e-13 ||A v_j||) or a non-finite value ends the basis.
-// Block 0 writes column j of H and the control words.
-template <typename TV, int MJ, bool REORTH>
-__device__ __forceinline__ void gs_finish(const Batch& b, const SolveDev& s, int j, int na, int nb,
-                                          const double* h1, const double* h, double nav, double* inv_sh) {
-  if (threadIdx.x == 0) {
-    double h2sq = 0.0;
-    for (int i = 0; i <= j; ++i) h2sq += h[i] * h[i];
-    const double nrm = sqrt(fmax(h[j + 1] - h2sq, 0.0));
-    const bool bad = !isfinite(nrm) || !isfinite(nav);
-    const bool brk = bad || nrm <= kBreakdown * nav;
-    *inv_sh = brk ? 0.0 : 1.0 / nrm;
-    if (MRA_BX(b) == 0) {
-      s.H[(j + 1) * s.m + j] = nrm;
-      if (bad) { s.ctrl[C_STATUS] = 5; s.ctrl[C_MEFF] = 0; }
-      else if (brk) s.ctrl[C_MEFF] = j + 1;
-      if (brk) s.ctrl[C_DONE] = 1;
-    }
+// The end of column jj - 1 from the partials of V_{<jj}^T r_jj and
+// ||r_jj||^2 (in sb, ||r_jj||^2 at jj) and its first-pass coefficients
+// (hpart slot (jj - 1) & 1): alpha, and the breakdown and non-finite tests
+// against ||A v_{jj-1}||.  Thread 0; *brk when the basis ends at column
+// jj - 1, *bad when a value is not finite.
+__device__ inline double end_column(const SolveDev& s, int jj, const double* sb, bool* brk, bool* bad) {
+  const double* hp = s.hpart + (size_t)((jj - 1) & 1) * (kMaxM + 1);
+  double ss = 0.0, hh = 0.0;
+  for (int i = 0; i < jj; ++i) {
+    ss += sb[i] * sb[i];
+    hh += hp[i] * hp[i];
   }
-  __syncthreads();
-  if (MRA_BX(b) == 0)
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) s.H[i * s.m + j] = h1[i] + h[i];
-  if (j + 1 >= s.m) return;          // the last column: no further basis vector
-  const double inv = *inv_sh;
-  const size_t Nf = (size_t)s.N * s.N;
-  const auto* W = glb(s.w);
-  const auto* V = glb(vbasis<TV>(s));
-  auto* Vn = glb(vbasis<TV>(s) + (size_t)(j + 1) * Nf);
-  for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
-    const Chunk c = chunk_of(na, ch);
-    for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
-      double t = W[k];
-      TV v[MJ];
-#pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i <= j) v[i] = V[i * Nf + k];
-#pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i <= j) t -= h1[i] * (double)v[i];
-      if constexpr (REORTH) {
-#pragma unroll
-        for (int i = 0; i < MJ; ++i)
-          if (i <= j) t -= h[i] * (double)v[i];
-      }
-      Vn[k] = (TV)(inv == 0.0 ? 0.0 : t * inv);
+  const double a = sb[jj];
+  *bad = !isfinite(a) || !isfinite(ss) || !isfinite(hh);
+  const double al = *bad ? 0.0 : sqrt(fmax(a - ss, 0.0));
+  *brk = *bad || al <= kBreakdown * sqrt(hh + a);
+  return al;
+}
+
+// Block 0: column jj - 1 of H made final (h^(jj-1) + s, subdiagonal alpha)
+// and, if the basis ends there, the control words (m_eff = jj, or 0 with
+// status 5 for a non-finite value).
+__device__ inline void write_column(const SolveDev& s, int jj, const double* sb, double alpha, bool brk, bool bad) {
+  const double* hp = s.hpart + (size_t)((jj - 1) & 1) * (kMaxM + 1);
+  const int m = s.m;
+  for (int i = threadIdx.x; i < jj; i += blockDim.x) s.H[i * m + jj - 1] = hp[i] + sb[i];
+  if (threadIdx.x == 0) {
+    s.H[jj * m + jj - 1] = alpha;
+    if (bad) {
+      s.ctrl[C_STATUS] = 5;
+      s.ctrl[C_MEFF] = 0;
+    } else if (brk && jj < s.ctrl[C_MEFF]) {
+      s.ctrl[C_MEFF] = jj;
     }
+    if (brk) s.ctrl[C_DONE] = 1;
   }
 }
 
-// Stage 2: h1 and ||w||^2 from A.  Selective reorthogonalisation ("twice is
-// enough"): when the first pass keeps at least half of ||w||^2, w1 = w - V_j h1
-// is orthogonal to V_j to rounding, ||w1||^2 = ||w||^2 - ||h1||^2 has no
-// cancellation, and the stage ends the column itself (h2 = 0).  Otherwise it
-// takes the second pass: h2 = V_j^T w1 and ||w1||^2 partials (buffer B), and
-// stage 3 ends the column.  Every block takes the same decision from the same
-// sums, so no block signals another.
+// Stage 2 (see above).
 template <typename TV, int MJ, int JC>
-__global__ void __launch_bounds__(256) k_gs_axpy_dot(Batch b, int jrt) {
+__global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
   if (s.ctrl[C_DONE]) return;
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
   if ((int)MRA_BX(b) >= nb) return;
-  __shared__ double h[kMaxM + 2];
-  __shared__ double z[kMaxM + 2];
-  __shared__ double inv_sh;
-  reduce_partials(part_buf(s, 0), nb, j + 2, h);
-  double h1sq = 0.0;
-  for (int i = 0; i <= j; ++i) h1sq += h[i] * h[i];
-  const double w1sq = h[j + 1] - h1sq;
-  const bool once = w1sq >= 0.5 * h[j + 1];
-  const double nav = sqrt(h[j + 1]);
+  const int m = s.m;
+  __shared__ double ga[kMaxM + 2];               // g[0 .. j - 1], c, ||w||^2
+  __shared__ double sb[kMaxM + 2];               // s[0 .. j - 1], ||r_j||^2
+  __shared__ double Hs[(kMaxM + 1) * kMaxM];     // H[0..j][0..j-1], column j - 1 made final
+  __shared__ double u[kMaxM + 1];
+  __shared__ double sc[3];                       // alpha, kappa, 1 / alpha
+  __shared__ int brk_sh, bad_sh;
+  // columns 0 .. j - 2 of H are final (earlier stage-2 kernels wrote them)
+  for (int q = threadIdx.x; q < (j + 1) * j; q += blockDim.x) {
+    const int r = q / j, cidx = q - r * j;
+    Hs[q] = cidx < j - 1 ? s.H[r * m + cidx] : 0.0;
+  }
+  reduce_partials(part_buf(s, 0), nb, j + 2, ga);
+  if (j > 0) reduce_partials(part_buf(s, 1 + ((j + 1) & 1)), nb, j + 1, sb);
+  if (threadIdx.x == 0) {
+    double al = 1.0;
+    bool brk = false, bad = false;
+    if (j > 0) al = end_column(s, j, sb, &brk, &bad);
+    bad |= !isfinite(ga[j + 1]);        // the product of r_j
+    sc[0] = al;
+    sc[2] = al > 0.0 ? 1.0 / al : 0.0;
+    brk_sh = brk || bad;
+    bad_sh = bad;
+  }
+  __syncthreads();
   if (MRA_BX(b) == 0) {
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) s.hpart[i] = h[i];
-    if (threadIdx.x == 0) {
-      s.scal[S_NRMAV] = nav;
-      s.ctrl[C_REORTH] = once ? 0 : 1;
-      if (!once) s.ctrl[C_RBITS0 + (j >> 5)] |= 1 << (j & 31);
+    if (j > 0) write_column(s, j, sb, sc[0], brk_sh, bad_sh);
+    else if (bad_sh && threadIdx.x == 0) {
+      s.ctrl[C_STATUS] = 5;
+      s.ctrl[C_MEFF] = 0;
+      s.ctrl[C_DONE] = 1;
     }
   }
-  if (once) {
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) z[i] = 0.0;
-    if (threadIdx.x == 0) z[j + 1] = w1sq;
-    __syncthreads();
-    gs_finish<TV, MJ, false>(b, s, j, na, nb, h, z, nav, &inv_sh);
-    return;
+  if (brk_sh) return;
+  // column j - 1 of the staged H made final, then u = H[0..j][0..j-1] s
+  if (j > 0) {
+    const double* hp = s.hpart + (size_t)((j - 1) & 1) * (kMaxM + 1);
+    for (int r = threadIdx.x; r <= j; r += blockDim.x)
+      Hs[r * j + j - 1] = r < j ? hp[r] + sb[r] : sc[0];
   }
+  __syncthreads();
+  for (int r = threadIdx.x; r <= j; r += blockDim.x) {
+    double t = 0.0;
+    for (int i = r > 0 ? r - 1 : 0; i < j; ++i) t += Hs[r * j + i] * sb[i];
+    u[r] = t;
+  }
+  if (threadIdx.x == 0) {
+    double sg = 0.0;
+    for (int i = 0; i < j; ++i) sg += sb[i] * ga[i];
+    sc[1] = (ga[j] - sg) * sc[2];
+  }
+  __syncthreads();
+  // first-pass coefficients of column j, kept until the next column ends it
+  if (MRA_BX(b) == 0) {
+    double* hc = s.hpart + (size_t)(j & 1) * (kMaxM + 1);
+    for (int r = threadIdx.x; r <= j; r += blockDim.x) hc[r] = ((r < j ? ga[r] : sc[1]) - u[r]) * sc[2];
+  }
+  const double ia = sc[2], kap = sc[1];
   const size_t Nf = (size_t)s.N * s.N;
-  auto* W = glb(s.w);
-  const auto* V = glb(vbasis<TV>(s));
+  const auto* W = glb(s.w);
+  auto* V = glb(vbasis<TV>(s));
+  auto* Vj = V + (size_t)j * Nf;
+  auto* Vn = V + (size_t)(j + 1) * Nf;
+  const bool store_next = j + 1 < m;
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     double acc[MJ + 1];
 #pragma unroll
     for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
-      double t = W[k];
+      // the coefficients sb, ga are read from LDS in every trip: held in
+      // registers across the loop they would take 4 more per basis vector
+      // beside the loaded entries and the sums, and cut the waves per SIMD
+      asm volatile("" ::: "memory");
+      const double wk = W[k];
       TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) v[i] = V[i * Nf + k];
+      double rj = 0.0;
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) t -= h[i] * (double)v[i];
+        if (i == j) rj = (double)v[i];
+      double t = rj;
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) acc[i] += (double)v[i] * t;
-      acc[MJ] += t * t;
+        if (i < j) t -= sb[i] * (double)v[i];
+      // v_j as stored (j = 0: v_0 itself, already final)
+      const TV vjs = j > 0 ? (TV)(t * ia) : (TV)rj;
+      const double vj = (double)vjs;
+      double q = wk;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i < j) q -= ga[i] * (double)v[i];
+      q -= kap * vj;
+      const TV rns = (TV)(q * ia);
+      const double rn = (double)rns;
+      if (j > 0) Vj[k] = vjs;
+      if (store_next) Vn[k] = rns;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i < j) acc[i] += (double)v[i] * rn;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i == j) acc[i] += vj * rn;
+      acc[MJ] += rn * rn;
     }
-    // slot layout: h2[0 .. j], then ||w1||^2 at j + 1 (static register indices)
+    // slot layout: V_{<=j}^T r_{j+1} at 0 .. j, ||r_{j+1}||^2 at j + 1
 #pragma unroll
     for (int i = 0; i < MJ; ++i)
       if (i == j + 1) acc[i] = acc[MJ];
-    block_sums_store<MJ + 1>(acc, j + 2, part_buf(s, 1) + (size_t)ch * (kMaxM + 2));
+    block_sums_store<MJ + 1>(acc, j + 2, part_buf(s, 1 + (j & 1)) + (size_t)ch * (kMaxM + 2));
     __syncthreads();
   }
 }
 
-// Stage 3, only where stage 2 took the second pass (C_REORTH = 1): h2 and
-// ||w1||^2 from B, then the end of the column.
-template <typename TV, int MJ, int JC>
-__global__ void __launch_bounds__(256) k_gs_axpy_next(Batch b, int jrt) {
-  const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
+// The end of the last column m - 1: the second-pass coefficients of r_m and
+// ||r_m||^2 from its stage 2 (r_m itself is not stored).  One block per solve.
+__global__ void __launch_bounds__(256) k_gs_last(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
-  if (s.ctrl[C_DONE] || !s.ctrl[C_REORTH]) return;
+  if (s.ctrl[C_DONE]) return;
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
-  if ((int)MRA_BX(b) >= nb) return;
-  __shared__ double h[kMaxM + 2];
-  __shared__ double h1[kMaxM + 2];
-  __shared__ double inv_sh;
-  reduce_partials(part_buf(s, 1), nb, j + 2, h);
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) h1[i] = s.hpart[i];
+  const int jj = s.m;
+  __shared__ double sb[kMaxM + 2];
+  __shared__ double al_sh;
+  __shared__ int brk_sh, bad_sh;
+  reduce_partials(part_buf(s, 1 + ((jj + 1) & 1)), nb, jj + 1, sb);
+  if (threadIdx.x == 0) {
+    bool brk, bad;
+    al_sh = end_column(s, jj, sb, &brk, &bad);
+    brk_sh = brk;
+    bad_sh = bad;
+  }
   __syncthreads();
-  gs_finish<TV, MJ, true>(b, s, j, na, nb, h1, h, s.scal[S_NRMAV], &inv_sh);
+  write_column(s, jj, sb, al_sh, brk_sh, bad_sh);
 }
 
 // Grid of the reductions, blocks per solve (blocks loop over chunks): at
@@ -249,8 +320,7 @@ hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st) {
 template <typename TV, int MJ, int JC>
 static void arnoldi_mj(const Batch& b, dim3 g, int j, hipStream_t st) {
   hipLaunchKernelGGL((k_gs_dot<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL((k_gs_axpy_dot<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL((k_gs_axpy_next<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
+  hipLaunchKernelGGL((k_gs_update<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
 }
 
 // Columns j < kFixedCols run kernels instantiated for that column (exactly
@@ -274,6 +344,7 @@ hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t
   if (j >= c.m || c.m > kMaxM) return hipErrorInvalidValue;
   if (c.vb) arnoldi_t<float>(b, c, g, j, st);
   else arnoldi_t<double>(b, c, g, j, st);
+  if (j == c.m - 1) hipLaunchKernelGGL(k_gs_last, dim3(b.n), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -200,7 +200,7 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.H = L.take<double>((size_t)(s.m + 1) * s.m);
   s.hpart = L.take<double>(2 * (kMaxM + 1));
   s.y = L.take<double>(kMaxM + 1);
-  s.partials = L.take<double>((size_t)2 * kPartSlots * (kMaxM + 2));
+  s.partials = L.take<double>((size_t)3 * kPartSlots * (kMaxM + 2));
   s.wt = L.take<char>(Nf * esz);
   s.u = L.take<char>(Nf * esz);
   s.v = L.take<char>(Nf * esz);

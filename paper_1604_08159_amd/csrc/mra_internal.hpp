@@ -24,12 +24,9 @@ constexpr int kCoarseLevels = 6;    // levels <= this are prolonged by one block
 constexpr int kTwN = 2048;          // twiddle table size (largest FFT length)
 
 // Control words (int) and scalars (double) of a solve.
-// C_RBITS0/1: the Arnoldi columns of the current step that took the second
-// Gram-Schmidt pass (bit j of word j / 32), for the byte accounting of
-// profiles; cleared when the step's first basis vector is formed.
 enum Ctrl : int { C_MEFF = 0, C_DONE = 1, C_STATUS = 2, C_CNT0 = 4, C_CNT1 = 5, C_CNT2 = 6,
-                  C_CNT3 = 7, C_REORTH = 8, C_RBITS0 = 9, C_RBITS1 = 10, C_NCTRL = 16 };
-enum Scal : int { S_BETA = 0, S_INV = 1, S_NRMAV = 2, S_UMAX = 3, S_T = 4, S_EVALS = 5, S_STEPS = 6,
+                  C_CNT3 = 7, C_NCTRL = 16 };
+enum Scal : int { S_BETA = 0, S_INV = 1, S_UMAX = 3, S_T = 4, S_EVALS = 5, S_STEPS = 6,
                   S_THETA = 7, S_COND = 8, S_NSCAL = 16 };
 
 struct SolveDev {
@@ -58,9 +55,9 @@ struct SolveDev {
   float* V32;               // [(m+1)][Nf] basis in FP32, precision MRA_FP32 only (else null)
   double* w;                // [Nf]
   double* H;                // [(m+1)][m]
-  double* hpart;            // [3][kMaxM+1] Gram-Schmidt coefficients of the current column
+  double* hpart;            // [2][kMaxM+1] first-pass Gram-Schmidt coefficients, by column parity
   double* y;                // [kMaxM + 1]
-  double* partials;         // [2][kRedBlocks][kMaxM + 2]
+  double* partials;         // [3][kRedBlocks][kMaxM + 2]
   double* scal;             // [S_NSCAL]
   int* ctrl;                // [C_NCTRL]
   // dense fields (element type by prec)
@@ -259,9 +256,10 @@ __device__ inline Chunk chunk_of(int na, int ch) {
   return c;
 }
 
-// Partial-sum buffers: stage 1 and 3 write A, the residual norm and stage 2
-// write B, so that a kernel never overwrites partials another block of the
-// same kernel is still reading.  One slot of kMaxM + 2 sums per chunk.
+// Partial-sum buffers: the Gram-Schmidt's first stage writes buffer 0, the
+// residual norm buffer 1, and the second stage of column j buffer
+// 1 + (j & 1), so that a kernel never overwrites partials another block of
+// the same kernel is still reading.  One slot of kMaxM + 2 sums per chunk.
 constexpr int kWavesPerBlock = 4;
 constexpr int kPartSlots = kRedBlocks;
 __device__ inline double* part_buf(const SolveDev& s, int which) {
@@ -319,8 +317,8 @@ __device__ inline void block_sums_store(double (&acc)[NA], int cnt, double* out)
 // The scaling of the first basis vector: beta = ||F|| from the partials of
 // k_norm0 (buffer B).  Every block computes the same value; block 0 records
 // beta and starts the basis (C_MEFF = m, or 0 and C_DONE when F = 0 or is not
-// finite).  Returns 1 / beta, or 0.  Later basis vectors are scaled by the
-// last Gram-Schmidt stage, which writes them normalised.
+// finite).  Returns 1 / beta, or 0.  Later basis vectors are normalised by
+// the Gram-Schmidt stage of the column after theirs.
 __device__ inline double first_scale(const SolveDev& s, int bx) {
   __shared__ double tot[2];
   __shared__ double inv_sh;
@@ -336,8 +334,6 @@ __device__ inline double first_scale(const SolveDev& s, int bx) {
       if (!ok) s.ctrl[C_STATUS] = 5;
       s.ctrl[C_DONE] = zero ? 1 : 0;
       s.ctrl[C_MEFF] = zero ? 0 : s.m;
-      s.ctrl[C_RBITS0] = 0;
-      s.ctrl[C_RBITS1] = 0;
     }
     inv_sh = zero ? 0.0 : 1.0 / nrm;
   }

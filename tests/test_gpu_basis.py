@@ -1,9 +1,9 @@
 """The Arnoldi basis the GPU builds is orthonormal over the active set, at
 full size and in both precisions.  This holds at any size and for every
-column, whichever Gram-Schmidt path the column took: the second pass runs
-only where the first lost more than half of ||w||^2 (Kahan's twice-is-enough
-test), and the skipped columns must still be orthogonal to rounding level.
-The subdiagonal of the Hessenberg matrix holds the norms taken before
+column: each column's second Gram-Schmidt pass is taken in the next column's
+reads of the basis, and the last column's from the partial sums of its own
+update, so every stored vector must be orthogonal to rounding level.  The
+subdiagonal of the Hessenberg matrix holds the norms taken before
 normalisation, so it is positive.  Precision MRA_FP32 stores the basis in
 FP32, so its orthonormality is checked at that precision's bar, and its steps
 are checked against the FP64 oracle at the mixed-precision bar."""
