@@ -173,10 +173,42 @@ __device__ inline void small_dft(typename C2<T>::t* v) {
   }
 }
 
+// The twiddle w = exp(-2 pi i k / (Ns R)) of each item of each pass, loaded
+// from the table when a block starts (beside its data loads) instead of at
+// each pass, where it would add one dependent load to every pass.  The
+// passes of both signs use the same entries (the inverse takes conj(w)).
+template <typename T, int LGL, int LGNS> struct TwSet {
+  static constexpr int REM = LGL - LGNS, LGR = REM >= 3 ? 3 : REM, IPT = 8 >> LGR;
+  typename C2<T>::t w[IPT];
+  TwSet<T, LGL, LGNS + LGR> next;
+};
+template <typename T, int LGL> struct TwSet<T, LGL, LGL> {};
+
+template <typename T, int LGL, int NF, int LGNS, int NT = kFftThreads>
+__device__ __forceinline__ void load_twiddles(TwSet<T, LGL, LGNS>& ts, int nfft) {
+  if constexpr (LGNS < LGL) {
+    using S_ = TwSet<T, LGL, LGNS>;
+    constexpr int LGR = S_::LGR, IPT = S_::IPT, LGIPT = 3 - LGR;
+    constexpr int LGPER = LGL - LGR, PER = 1 << LGPER, NS = 1 << LGNS;
+    constexpr int TWSHIFT = 11 - LGNS - LGR;
+    constexpr bool FULL = NF * PER == NT * IPT;
+    if constexpr (LGNS > 0) {
+      const int total = nfft << LGPER;
+      const int qbase = ((threadIdx.x >> 6) << (6 + LGIPT)) + (threadIdx.x & 63);
+#pragma unroll
+      for (int it = 0; it < IPT; ++it) {
+        const int q = qbase + (it << 6);
+        if (FULL || q < total) ts.w[it] = C2<T>::tw(((q & (PER - 1)) & (NS - 1)) << TWSHIFT);
+      }
+    }
+    load_twiddles<T, LGL, NF, LGNS + LGR, NT>(ts.next, nfft);
+  }
+}
+
 // One radix-2^LGR pass over NF vectors of length 2^LGL (Ns = 2^LGNS), all
 // sizes compile-time, so index arithmetic is shifts and immediate offsets.
 template <int S, typename T, int LGL, int NF, int LGNS, int LGR, int NT = kFftThreads>
-__device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int nfft) {
+__device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int nfft, const TwSet<T, LGL, LGNS>& ts) {
   using V = typename C2<T>::t;
   constexpr int R = 1 << LGR, IPT = 8 / R, LGIPT = 3 - LGR;
   constexpr int LGPER = LGL - LGR, PER = 1 << LGPER;      // items per vector
@@ -199,8 +231,11 @@ __device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int nfft) 
 #pragma unroll
         for (int r = 0; r < R; ++r) v[it][r] = buf[lx(base + r * PER)];
       } else {
-        // twiddles w^r, w = exp(-2 pi i k / (Ns R)): one table load, then powers
-        const V w1 = C2<T>::tw((j & (NS - 1)) << TWSHIFT);
+        // twiddles w^r, w = exp(-2 pi i k / (Ns R)): one preloaded entry, then
+        // powers.  The empty asm keeps the powers here: formed when the entry
+        // arrives they would hold R - 1 more values per pass across the block
+        V w1 = ts.w[it];
+        asm volatile("" : "+v"(w1.x), "+v"(w1.y));
         v[it][0] = buf[lx(base)];
         V wr = w1;
 #pragma unroll
@@ -229,20 +264,20 @@ __device__ __forceinline__ void stockham_pass(typename C2<T>::t* buf, int nfft) 
 }
 
 template <int S, typename T, int LGL, int NF, int LGNS, int NT = kFftThreads>
-__device__ __forceinline__ void fft_passes(typename C2<T>::t* buf, int nfft) {
+__device__ __forceinline__ void fft_passes(typename C2<T>::t* buf, int nfft, const TwSet<T, LGL, LGNS>& ts) {
   if constexpr (LGNS < LGL) {
     constexpr int REM = LGL - LGNS;
     constexpr int LGR = REM >= 3 ? 3 : REM;
-    stockham_pass<S, T, LGL, NF, LGNS, LGR, NT>(buf, nfft);
-    fft_passes<S, T, LGL, NF, LGNS + LGR, NT>(buf, nfft);
+    stockham_pass<S, T, LGL, NF, LGNS, LGR, NT>(buf, nfft, ts);
+    fft_passes<S, T, LGL, NF, LGNS + LGR, NT>(buf, nfft, ts.next);
   }
 }
 
 // nfft <= NF vectors of length 2^LGL at stride 2^LGL; wavefront-local when
-// L <= 512
+// L <= 512.  ts: the twiddles of (LGL, NF, NT, nfft) from load_twiddles.
 template <int S, typename T, int LGL, int NF, int NT = kFftThreads>
-__device__ __forceinline__ void fft_block(typename C2<T>::t* buf, int nfft) {
-  fft_passes<S, T, LGL, NF, 0, NT>(buf, nfft);
+__device__ __forceinline__ void fft_block(typename C2<T>::t* buf, int nfft, const TwSet<T, LGL, 0>& ts) {
+  fft_passes<S, T, LGL, NF, 0, NT>(buf, nfft, ts);
 }
 
 template <typename T>
@@ -287,18 +322,43 @@ __global__ void __launch_bounds__(NT) k_fft_rows_fwd(Batch b, int src) {
   const int y0 = MRA_BX(b) * R;
   const V* in = reinterpret_cast<const V*>(poisson_src<T>(s, src));
   constexpr int n = R * M;
+  constexpr int twN = kTwN / N;
+  constexpr int PL = kWaveSpan / 64, PO = ((M + 1) * R + NT - 1) / NT;
+  // the row data and the twiddles of every pass are all in flight before the
+  // first is waited for
   const int e1 = min(own0() + kWaveSpan, n);
-  for (int q = own0() + lane(); q < e1; q += 64) buf[lx(q)] = gload(in, (size_t)y0 * M + q);
+  V d[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int q = own0() + lane() + u * 64;
+    if (q < e1) d[u] = gload(in, (size_t)y0 * M + q);
+  }
+  TwSet<T, G::LGM, 0> ts;
+  load_twiddles<T, G::LGM, R, 0, NT>(ts, R);
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int q = own0() + lane() + u * 64;
+    if (q < e1) buf[lx(q)] = d[u];
+  }
   fft_sync(G::LGM <= 9);
-  fft_block<-1, T, G::LGM, R, NT>(buf, R);
+  fft_block<-1, T, G::LGM, R, NT>(buf, R, ts);
   __syncthreads();
   V* spec = reinterpret_cast<V*>(s.spec);
-  constexpr int twN = kTwN / N;
-  for (int q = threadIdx.x; q < (M + 1) * R; q += NT) {
+  // the twiddles of the split into the real transform, loaded together
+  V tk[PO];
+#pragma unroll
+  for (int u = 0; u < PO; ++u) {
+    const int q = threadIdx.x + u * NT;
+    if (q < (M + 1) * R) tk[u] = C2<T>::tw((q / R) * twN);
+  }
+#pragma unroll
+  for (int u = 0; u < PO; ++u) {
+    const int q = threadIdx.x + u * NT;
+    if (q >= (M + 1) * R) break;
     const int k = q / R, r = q % R;
     const V zk = buf[lx(r * M + (k & (M - 1)))];
     const V zc = cconj(buf[lx(r * M + ((M - k) & (M - 1)))]);
-    const V e = cmul(csub(zk, zc), C2<T>::tw(k * twN));
+    const V e = cmul(csub(zk, zc), tk[u]);
     V x;
     x.x = T(0.5) * (zk.x + zc.x + e.y);
     x.y = T(0.5) * (zk.y + zc.y - e.x);
@@ -326,39 +386,79 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_cols(Batch b) {
   V* specU = reinterpret_cast<V*>(s.spec);
   V* specV = reinterpret_cast<V*>(s.spec2);
   constexpr bool wl = J <= 9;
+  constexpr int PL = kWaveSpan / 64;
   const int e1 = min(own0() + kWaveSpan, nr * N);
-  for (int q = own0() + lane(); q < e1; q += 64) A[lx(q)] = specU[(size_t)k0 * N + q];
+  // the spectrum rows and the twiddles of every pass are all in flight before
+  // the first is waited for
+  V d[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int q = own0() + lane() + u * 64;
+    if (q < e1) d[u] = gload(specU, (size_t)k0 * N + q);
+  }
+  TwSet<T, J, 0> ts;
+  load_twiddles<T, J, C, 0>(ts, nr);
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int q = own0() + lane() + u * 64;
+    if (q < e1) A[lx(q)] = d[u];
+  }
   fft_sync(wl);
-  fft_block<-1, T, J, C>(A, nr);
+  fft_block<-1, T, J, C>(A, nr, ts);
   const T h2n = T(-s.h * s.h / ((double)N * (double)N));
   const T ih = T(1.0 / s.h);
-  for (int q = own0() + lane(); q < e1; q += 64) {
+  // the symbols of this thread's elements, loaded together
+  T s1x[PL], s1y[PL], s0y[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int q = own0() + lane() + u * 64;
+    if (q < e1) {
+      s1x[u] = C2<T>::sym(P, 1, N + k0 + (q >> J));
+      s1y[u] = C2<T>::sym(P, 1, N + (q & (N - 1)));
+      if constexpr (!PSI) s0y[u] = C2<T>::sym(P, 0, N + (q & (N - 1)));
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int q = own0() + lane() + u * 64;
+    if (q >= e1) break;
     const int r = q >> J, ky = q & (N - 1);
     const int kx = k0 + r;
-    const T den = C2<T>::sym(P, 1, N + kx) + C2<T>::sym(P, 1, N + ky);
+    const T den = s1x[u] + s1y[u];
     const T g = (kx == 0 && ky == 0) ? T(0) : h2n / den;
-    const T sy = C2<T>::sym(P, 0, N + ky) * ih;
     const V z = A[lx(q)];
     const V ps = V{z.x * g, z.y * g};
     A[lx(q)] = ps;
-    if constexpr (!PSI) Bv[lx(q)] = V{-sy * ps.y, sy * ps.x};   // i s1(ky) psi_hat
+    if constexpr (!PSI) {
+      const T sy = s0y[u] * ih;
+      Bv[lx(q)] = V{-sy * ps.y, sy * ps.x};   // i s1(ky) psi_hat
+    }
   }
   fft_sync(wl);
   if constexpr (PSI) {
-    fft_block<1, T, J, C>(A, nr);
+    fft_block<1, T, J, C>(A, nr, ts);
     for (int q = own0() + lane(); q < e1; q += 64) specU[(size_t)k0 * N + q] = A[lx(q)];
     return;
   }
-  fft_block<1, T, J, C>(Bv, nr);
+  fft_block<1, T, J, C>(Bv, nr, ts);
   for (int q = own0() + lane(); q < e1; q += 64) specU[(size_t)k0 * N + q] = Bv[lx(q)];
   fft_sync(wl);
-  for (int q = own0() + lane(); q < e1; q += 64) {
-    const T sx = C2<T>::sym(P, 0, N + k0 + (q >> J)) * ih;
+  T s0x[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int q = own0() + lane() + u * 64;
+    if (q < e1) s0x[u] = C2<T>::sym(P, 0, N + k0 + (q >> J));
+  }
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int q = own0() + lane() + u * 64;
+    if (q >= e1) break;
+    const T sx = s0x[u] * ih;
     const V z = A[lx(q)];
     Bv[lx(q)] = V{sx * z.y, -sx * z.x};                    // -i s1(kx) psi_hat
   }
   fft_sync(wl);
-  fft_block<1, T, J, C>(Bv, nr);
+  fft_block<1, T, J, C>(Bv, nr, ts);
   for (int q = own0() + lane(); q < e1; q += 64) specV[(size_t)k0 * N + q] = Bv[lx(q)];
 }
 
@@ -374,20 +474,50 @@ __global__ void __launch_bounds__(NT) k_fft_rows_inv(Batch b, int src) {
   const SolveDev& s = MRA_SOLVE(b);
   const int y0 = MRA_BX(b) * R;
   constexpr int twN = kTwN / N;
+  constexpr int NP = (M / 2 + 1) * R, PP = (NP + NT - 1) / NT;
+  TwSet<T, G::LGM, 0> ts;
+  load_twiddles<T, G::LGM, R, 0, NT>(ts, R);
   for (int comp = 0; comp < NC; ++comp) {
     const V* spec = reinterpret_cast<const V*>(comp == 0 ? s.spec : s.spec2);
-    for (int q = threadIdx.x; q < M * R; q += NT) {
+    // z_k = X_k + conj X_{M-k} + i tw_k (X_k - conj X_{M-k}): the pair (k,
+    // M - k) gives z_k and z_{M-k} from the same two loads, so every entry of
+    // the spectrum is read once; all of this thread's pairs are loaded first
+    V xa[PP], xb[PP], ta[PP], tb[PP];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+      const int q = threadIdx.x + u * NT;
+      if (q < NP) {
+        const int k = q / R, r = q % R;
+        xa[u] = gload(spec, (size_t)k * N + y0 + r);
+        xb[u] = gload(spec, (size_t)(M - k) * N + y0 + r);
+        ta[u] = C2<T>::tw(k * twN);
+        tb[u] = C2<T>::tw(((M - k) & (M - 1)) * twN);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+      const int q = threadIdx.x + u * NT;
+      if (q >= NP) break;
       const int k = q / R, r = q % R;
-      const V xk = gload(spec, (size_t)k * N + y0 + r);
-      const V xc = cconj(gload(spec, (size_t)(M - k) * N + y0 + r));
-      const V e = cmulc(csub(xk, xc), C2<T>::tw(k * twN));
-      V z;
-      z.x = xk.x + xc.x - e.y;
-      z.y = xk.y + xc.y + e.x;
-      buf[lx(r * M + k)] = z;
+      {
+        const V xc = cconj(xb[u]);
+        const V e = cmulc(csub(xa[u], xc), ta[u]);
+        V z;
+        z.x = xa[u].x + xc.x - e.y;
+        z.y = xa[u].y + xc.y + e.x;
+        buf[lx(r * M + k)] = z;
+      }
+      if (k > 0 && k < M / 2) {
+        const V xc = cconj(xa[u]);
+        const V e = cmulc(csub(xb[u], xc), tb[u]);
+        V z;
+        z.x = xb[u].x + xc.x - e.y;
+        z.y = xb[u].y + xc.y + e.x;
+        buf[lx(r * M + M - k)] = z;
+      }
     }
     __syncthreads();
-    fft_block<1, T, G::LGM, R, NT>(buf, R);
+    fft_block<1, T, G::LGM, R, NT>(buf, R, ts);
     V* out = reinterpret_cast<V*>(poisson_dst<T>(s, src, comp));
     const int e1 = min(own0() + kWaveSpan, R * M);
     for (int q = own0() + lane(); q < e1; q += 64) gstore(out, (size_t)y0 * M + q, buf[lx(q)]);

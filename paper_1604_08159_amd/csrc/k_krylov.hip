@@ -171,8 +171,12 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
     const int r = q / j, cidx = q - r * j;
     Hs[q] = cidx < j - 1 ? s.H[r * m + cidx] : 0.0;
   }
-  reduce_partials(part_buf(s, 0), nb, j + 2, ga);
-  if (j > 0) reduce_partials(part_buf(s, 1 + ((j + 1) & 1)), nb, j + 1, sb);
+  if (j > 0 && 2 * j + 3 <= 64) {
+    reduce_partials2(part_buf(s, 0), j + 2, ga, part_buf(s, 1 + ((j + 1) & 1)), j + 1, sb, nb);
+  } else {
+    reduce_partials<32>(part_buf(s, 0), nb, j + 2, ga);
+    if (j > 0) reduce_partials<32>(part_buf(s, 1 + ((j + 1) & 1)), nb, j + 1, sb);
+  }
   if (threadIdx.x == 0) {
     double al = 1.0;
     bool brk = false, bad = false;
@@ -286,7 +290,7 @@ __global__ void __launch_bounds__(256) k_gs_last(Batch b) {
   __shared__ double sb[kMaxM + 2];
   __shared__ double al_sh;
   __shared__ int brk_sh, bad_sh;
-  reduce_partials(part_buf(s, 1 + ((jj + 1) & 1)), nb, jj + 1, sb);
+  reduce_partials<32>(part_buf(s, 1 + ((jj + 1) & 1)), nb, jj + 1, sb);
   if (threadIdx.x == 0) {
     bool brk, bad;
     al_sh = end_column(s, jj, sb, &brk, &bad);

@@ -35,8 +35,8 @@ __device__ inline T* dense_target(const SolveDev& s, int target) {
 // ------------------------------------------------------- active values
 // The value of active node k in the prolongation of: src 0 the state omega,
 // src 1 the first Arnoldi vector F * inv (inv = 0: no basis), src 2 a caller
-// vector, src 3 the Arnoldi vector V_j, written normalised by the last
-// Gram-Schmidt stage.  Vd is V_j of an FP64 basis; callers read a basis stored
+// vector, src 3 basis slot j (for j > 0 the first-pass residual r_j that the
+// Gram-Schmidt normalises after its product).  Vd is V_j of an FP64 basis; callers read a basis stored
 // in FP32 (Vf) themselves.  Both pointers are taken once per kernel, so no
 // descriptor load is repeated after a store.
 __device__ inline double active_value(const SolveDev& s, int src, int k, double inv, const double* Vd) {
@@ -632,14 +632,12 @@ __global__ void __launch_bounds__(1024) k_scan(Batch b) {
     if (k < nblk) s.block_off[k] = off + loc[q];
   }
   if (threadIdx.x == 0) *s.n_active = total;
-  const int ntiles = s.ntx * s.ntx;
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) s.tile_count[t] = 0;
 }
 
 __global__ void __launch_bounds__(kScanBlock) k_compact(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
   const int Nf = s.N * s.N;
-  const int J = s.J, j0 = s.j0, N = s.N, T = s.tile, ntx = s.ntx;
+  const int J = s.J, j0 = s.j0;
   const int base = MRA_BX(b) * (kScanBlock * kScanItems) + threadIdx.x * kScanItems;
   int m[kScanItems];
   int cnt = 0;
@@ -661,13 +659,37 @@ __global__ void __launch_bounds__(kScanBlock) k_compact(Batch b) {
       s.index_packed[pos] = i;
       s.index_fine[pos] = f;
       s.rank[f] = pos;
-      const int x = f & (N - 1), y = f >> J;
-      atomicAdd(&s.tile_count[(y / T) * ntx + x / T], 1);
       ++pos;
     } else {
       s.rank[f] = -1;
     }
   }
+}
+
+// Active nodes per stencil tile, from the rank map: one block per tile, a
+// plain count (no atomics, so no contention on the counters of full tiles).
+__global__ void __launch_bounds__(256) k_tile_count(Batch b) {
+  const SolveDev& s = MRA_SOLVE(b);
+  const int T = s.tile, ntx = s.ntx, N = s.N;
+  const auto* rank = glb(s.rank);
+  __shared__ int part[4];
+  for (int t = MRA_BX(b); t < ntx * ntx; t += MRA_GX(b)) {
+    const int x0 = (t % ntx) * T, y0 = (t / ntx) * T;
+    int c = 0;
+    for (int q = threadIdx.x; q < T * T; q += blockDim.x) c += rank[(y0 + q / T) * N + x0 + q % T] >= 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) glb(s.tile_count)[t] = part[0] + part[1] + part[2] + part[3];
+    __syncthreads();
+  }
+}
+
+static hipError_t launch_tile_count(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  const int ntx = c.tile > 0 ? (1 << c.J) / c.tile : 1;
+  const int per = ntx * ntx < 2048 ? ntx * ntx : 2048;
+  hipLaunchKernelGGL(k_tile_count, dim3(per * b.n), dim3(256), 0, st, b);
+  return hipGetLastError();
 }
 
 static int grid_blocks(int J);
@@ -687,7 +709,7 @@ hipError_t launch_threshold(const Batch& b, const LaunchCfg& c, int packed_is_do
   hipLaunchKernelGGL(k_mask_count, g, dim3(kScanBlock), 0, st, b);
   hipLaunchKernelGGL(k_scan, dim3((1) * b.n), dim3(1024), 0, st, b);
   hipLaunchKernelGGL(k_compact, g, dim3(kScanBlock), 0, st, b);
-  return hipGetLastError();
+  return launch_tile_count(b, c, st);
 }
 
 // ---------------------------------------------------------------- gather
@@ -709,32 +731,25 @@ hipError_t launch_gather(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   return hipGetLastError();
 }
 
-// rank map and tile flags from a caller-given index list
+// rank map and tile counts from a caller-given index list
 __global__ void __launch_bounds__(256) k_rank_clear(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
   const int Nf = s.N * s.N;
   for (int f = MRA_BX(b) * blockDim.x + threadIdx.x; f < Nf; f += MRA_GX(b) * blockDim.x) s.rank[f] = -1;
-  const int ntiles = s.ntx * s.ntx;
-  for (int t = MRA_BX(b) * blockDim.x + threadIdx.x; t < ntiles; t += MRA_GX(b) * blockDim.x)
-    s.tile_count[t] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_rank_scatter(Batch b) {
   const SolveDev& s = MRA_SOLVE(b);
   const int na = (int)*s.n_active;
-  const int J = s.J, N = s.N, T = s.tile, ntx = s.ntx;
-  for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x) {
-    const int f = s.index_fine[k];
-    s.rank[f] = k;
-    atomicAdd(&s.tile_count[((f >> J) / T) * ntx + (f & (N - 1)) / T], 1);
-  }
+  for (int k = MRA_BX(b) * blockDim.x + threadIdx.x; k < na; k += MRA_GX(b) * blockDim.x)
+    s.rank[s.index_fine[k]] = k;
 }
 
 hipError_t launch_rank_from_index(const Batch& b, const LaunchCfg& c, hipStream_t st) {
   dim3 g((grid_blocks(c.J)) * b.n);
   hipLaunchKernelGGL(k_rank_clear, g, dim3(256), 0, st, b);
   hipLaunchKernelGGL(k_rank_scatter, g, dim3(256), 0, st, b);
-  return hipGetLastError();
+  return launch_tile_count(b, c, st);
 }
 
 }  // namespace mra

@@ -269,7 +269,11 @@ __device__ inline double* part_buf(const SolveDev& s, int which) {
 // totals[i] = sum over the nb slots of buf[slot][i], i < cnt <= kMaxM + 2, in
 // a fixed order (wavefront w adds slots w, w + 4, ... in turn, lane i holds
 // sum i, then the four wavefronts in order): every block that calls this gets
-// bit-identical totals.  totals is in LDS.
+// bit-identical totals.  totals is in LDS.  U slots per lane are in flight at
+// once: the Gram-Schmidt stages take 32 (their sums over up to 512 slots sit
+// in front of every block's pass), kernels where the reduction is a side
+// path keep 8, so that it does not raise their register count.
+template <int U = 8>
 __device__ inline void reduce_partials(const double* buf, int nb, int cnt, double* totals) {
   __shared__ double part[kWavesPerBlock][kMaxM + 2];
   const int stride = kMaxM + 2;
@@ -277,7 +281,7 @@ __device__ inline void reduce_partials(const double* buf, int nb, int cnt, doubl
   const auto* g = glb(buf);
   double t = 0.0;
   if (lane < cnt) {
-#pragma unroll 8
+#pragma unroll U
     for (int q = wid; q < nb; q += kWavesPerBlock) t += g[q * stride + lane];
     part[wid][lane] = t;
   }
@@ -287,6 +291,34 @@ __device__ inline void reduce_partials(const double* buf, int nb, int cnt, doubl
 #pragma unroll
     for (int w = 1; w < kWavesPerBlock; ++w) a += part[w][threadIdx.x];
     totals[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
+// Two reductions in one pass over the slots (cnt_a + cnt_b <= 64): lanes
+// below cnt_a sum buffer a, the next cnt_b lanes buffer b, each in the order
+// of reduce_partials (so the totals are bit-identical to two calls of it).
+__device__ inline void reduce_partials2(const double* bufa, int cnta, double* tota, const double* bufb, int cntb,
+                                        double* totb, int nb) {
+  __shared__ double part[kWavesPerBlock][64];
+  const int stride = kMaxM + 2;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool ina = lane < cnta, inb = !ina && lane < cnta + cntb;
+  const auto* g = glb(ina ? bufa + lane : bufb + (lane - cnta));
+  double t = 0.0;
+  if (ina || inb) {
+#pragma unroll 32
+    for (int q = wid; q < nb; q += kWavesPerBlock) t += g[q * stride];
+    part[wid][lane] = t;
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < cnta + cntb) {
+    double a = part[0][i];
+#pragma unroll
+    for (int w = 1; w < kWavesPerBlock; ++w) a += part[w][i];
+    if (i < cnta) tota[i] = a;
+    else totb[i - cnta] = a;
   }
   __syncthreads();
 }
