@@ -209,13 +209,46 @@ __device__ __forceinline__ Ranks<lat_slots<J, P, L, TB, NT>()> level_ranks(const
   return r;
 }
 
-// kin: this level's ranks, loaded while the previous level was swept; the
-// ranks of the next level are loaded here in turn, so a rank load is never
-// on the path between two levels.
+// Raw source values of a level's new active nodes (before the first basis
+// vector's scale is applied): FP64, or FP32 for a basis stored in FP32.
+template <int S, bool FB> struct RawVals {
+  double d[S];
+  float f[FB ? S : 1];
+};
+template <int S, bool FB>
+__device__ __forceinline__ RawVals<S, FB> level_values(const SolveDev& s, const Ranks<S>& kr, int src,
+                                                       const double* Vd, const float* Vf) {
+  RawVals<S, FB> rv;
+  if (FB && src == 3) {
+    // loaded raw: a conversion next to the load would wait for each in turn
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      rv.f[i] = 0.0f;
+      if (kr.k[i] >= 0) rv.f[i] = glb(Vf)[kr.k[i]];
+    }
+  } else {
+    const double* base = src == 0 ? s.omega : (src == 2 ? s.vin : (src == 3 ? Vd : s.w));
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      rv.d[i] = 0.0;
+      if (kr.k[i] >= 0) rv.d[i] = glb(base)[kr.k[i]];
+    }
+  }
+  return rv;
+}
+
+// The sweep keeps two levels of loads in flight: at level L the values of
+// level L + 1 (whose ranks arrived during level L - 1) and the ranks of level
+// L + 2 are issued before L's passes, so no global load sits on the path
+// between two levels.  kin, vin: ranks and raw values of level L; kn1: ranks
+// of level L + 1.
+template <int J, int L> constexpr int lvl_cap() { return L < J ? L : J; }
 template <int P, typename T, int J, int L, bool FB, int TB, int NT>
 __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[TB * TB], T* half, int cur, int x0,
                                                  int y0, int src, double inv, double* Vd, float* Vf, T* f,
-                                                 const Ranks<lat_slots<J, P, L, TB, NT>()>& kin) {
+                                                 const Ranks<lat_slots<J, P, L, TB, NT>()>& kin,
+                                                 const RawVals<lat_slots<J, P, L, TB, NT>(), FB>& vin,
+                                                 const Ranks<lat_slots<J, P, lvl_cap<J, L + 1>(), TB, NT>()>& kn1) {
 #pragma clang fp contract(off)
   constexpr int N = 1 << J, B = N < TB ? N : TB;
   constexpr int SH = J - L, SV = 1 << SH;  // node spacing of level L (fine units)
@@ -228,33 +261,11 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[TB 
   const int pox = lat_origin<J, P, L - 1>(x0), poy = lat_origin<J, P, L - 1>(y0);
   const T* prev = buf[cur];
   T* nxt = buf[cur ^ 1];
-  // the values of this level's active nodes (their latency hides behind
-  // pass 1), then the next level's ranks
-  int ks[SLOTS];
-#pragma unroll
-  for (int i = 0; i < SLOTS; ++i) ks[i] = kin.k[i];
-  // FB: the basis is stored in FP32 (precision MRA_FP32).  For src 3 its
-  // entries are loaded raw, so that no conversion waits for a load before the
-  // next one is issued
-  double av[SLOTS];
-  float af[SLOTS];
-  if (FB && src == 3) {
-    const auto* Vb = glb(Vf);
-#pragma unroll
-    for (int i = 0; i < SLOTS; ++i) {
-      af[i] = 0.0f;
-      if (ks[i] >= 0) af[i] = Vb[ks[i]];
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < SLOTS; ++i) {
-      av[i] = 0.0;
-      if (ks[i] >= 0) av[i] = active_value(s, src, ks[i], inv, Vd);
-    }
-  }
-  constexpr int LN = L < J ? L + 1 : L;
-  Ranks<lat_slots<J, P, LN, TB, NT>()> knext;
-  if constexpr (L < J) knext = level_ranks<J, P, LN, TB, NT>(s, x0, y0);
+  constexpr int L1 = lvl_cap<J, L + 1>(), L2 = lvl_cap<J, L + 2>();
+  RawVals<lat_slots<J, P, L1, TB, NT>(), FB> vn1;
+  Ranks<lat_slots<J, P, L2, TB, NT>()> kn2;
+  if constexpr (L < J) vn1 = level_values<lat_slots<J, P, L1, TB, NT>(), FB>(s, kn1, src, Vd, Vf);
+  if constexpr (L + 1 < J) kn2 = level_ranks<J, P, L2, TB, NT>(s, x0, y0);
   // pass 1: level-L rows of the level-(L - 1) columns
   for (int q = threadIdx.x; q < NH; q += NT) {
     const int iy = q / pn, c = q - iy * pn;
@@ -291,11 +302,16 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[TB 
         for (int o = 0; o < 2 * P; ++o) cc[o] = row[a + o];
         v = dd_pred<P, T>(cc);
       }
-      if (ks[i] >= 0) {
-        v = (FB && src == 3) ? (T)af[i] : (T)av[i];
-        if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) {
-          if constexpr (FB) glb(Vf)[ks[i]] = (float)av[i];
-          else glb(Vd)[ks[i]] = av[i];
+      if (kin.k[i] >= 0) {
+        if (FB && src == 3) {
+          v = (T)vin.f[i];
+        } else {
+          const double av = src == 1 ? (inv == 0.0 ? 0.0 : vin.d[i] * inv) : vin.d[i];
+          v = (T)av;
+          if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) {
+            if constexpr (FB) glb(Vf)[kin.k[i]] = (float)av;
+            else glb(Vd)[kin.k[i]] = av;
+          }
         }
       }
       if constexpr (L == J) glb(f)[(y0 + q / B) * N + x0 + (q % B)] = v;   // finest lattice = the tile
@@ -304,7 +320,8 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[TB 
   }
   if constexpr (L < J) {
     __syncthreads();
-    prolong_level_ct<P, T, J, L + 1, FB, TB, NT>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vd, Vf, f, knext);
+    prolong_level_ct<P, T, J, L + 1, FB, TB, NT>(s, buf, half, cur ^ 1, x0, y0, src, inv, Vd, Vf, f, kn1, vn1,
+                                                 kn2);
   }
 }
 
@@ -330,7 +347,10 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
   const bool has0 = (int)threadIdx.x < pn * pn;
   int x0n = 0, y0n = 0, k0n = 0;
   double raw = 0.0;
-  const auto k1 = level_ranks<J, P, J0 + 1, TB, NT>(s, x0, y0);   // first swept level, in flight meanwhile
+  // the first two swept levels' ranks, in flight meanwhile
+  const auto k1 = level_ranks<J, P, J0 + 1, TB, NT>(s, x0, y0);
+  Ranks<lat_slots<J, P, lvl_cap<J, J0 + 2>(), TB, NT>()> k2;
+  if constexpr (J0 + 1 < J) k2 = level_ranks<J, P, J0 + 2, TB, NT>(s, x0, y0);
   if (has0) {
     const int q = threadIdx.x;
     const int iy = q / pn, ix = q - iy * pn;
@@ -353,8 +373,9 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
     }
     buf[0][threadIdx.x] = (T)a;
   }
+  const auto v1 = level_values<lat_slots<J, P, J0 + 1, TB, NT>(), FB>(s, k1, src, Vd, Vf);
   __syncthreads();
-  prolong_level_ct<P, T, J, J0 + 1, FB, TB, NT>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f, k1);
+  prolong_level_ct<P, T, J, J0 + 1, FB, TB, NT>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f, k1, v1, k2);
 }
 
 template <int P, typename T>

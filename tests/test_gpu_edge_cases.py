@@ -1,8 +1,9 @@
 """GPU edge cases of the integrators against the FP64 oracle and closed forms:
 the happy breakdown of the Arnoldi process (a single Fourier mode without
-advection spans a one-dimensional Krylov space) in the exponential step and
-in the theta-scheme's GMRES, and the 6-point (p = 3) instantiations of the
-exact-Jacobian products and of the theta-scheme."""
+advection spans a one-dimensional Krylov space; n modes an n-dimensional one)
+in the exponential step and in the theta-scheme's GMRES, and the 6-point
+(p = 3) instantiations of the exact-Jacobian products and of the
+theta-scheme."""
 import dataclasses
 import math
 
@@ -67,6 +68,47 @@ def test_single_mode_breakdown(M, integ):
     sc = s.scalars()
     # one F and one product per step: the basis stopped at one vector
     assert sc["evals"] == 2 * (1 + 1) * N * N
+    s.close()
+
+
+@pytest.mark.parametrize("modes", [(3, 5), (3, 5, 7)])
+@pytest.mark.parametrize("integ", ["exponential", "theta"])
+def test_breakdown_after_several_columns(M, modes, integ):
+    """w = sum_k a_k cos(k x): no advection (u = 0 and w depends on x only),
+    F = nu L w, and every cos(k x) is an eigenvector of L, so the Krylov space
+    of F has the dimension n of the mode set and the Arnoldi process must stop
+    after n columns (the delayed second pass finds the breakdown of column
+    n - 1 one product later).  Each mode then advances by its own closed
+    form, and m_eff = n as in the oracle."""
+    J, N, nu, dt, theta = 4, 16, 0.05, 0.4, 0.5      # 16^2: the residual after n columns is ~1e-15 of ||A v||
+    h = 2 * math.pi / N
+    x = np.arange(N) * h
+    amps = [1.0, 0.5, 0.25, 0.125]
+    row = sum(a * np.cos(k * x) for a, k in zip(amps, modes))
+    w0 = np.repeat(row[None, :], N, axis=0)
+    s = M.Solve(M.grid_desc(J, 2, 0.0), M.flow_desc(nu, 0.0, smag_mode=0), M.MRA_FP64, 10, dt, _t(w0))
+    if integ == "theta":
+        s.set_integrator(M.MRA_THETA_NEWTON, theta, 1)
+    s.step(2)
+    dense, diag = s.read()
+    got = dense.cpu().numpy()
+    want_row = np.zeros(N)
+    for a, k in zip(amps, modes):
+        z = nu * dt * lam_d2_p2(k * h, h)
+        fac = math.exp(z) if integ == "exponential" else (1 + (1 - theta) * z) / (1 - theta * z)
+        want_row += a * fac ** 2 * np.cos(k * x)
+    err = np.abs(got - want_row[None, :]).max()
+    print(f"{integ}, modes {modes}: max |GPU - closed form| {err:.2e}")
+    assert err < 1e-12
+    g = ok.Grid(J=J, p=2, eps=0.0)
+    fl = oo.Flow(nu0=nu, cs=0.0, smag_mode=0)
+    st = ok.init_state(w0, g)
+    for _ in range(2):
+        st = ok.step(st, g, fl, 10, dt) if integ == "exponential" else oi.theta_step(st, g, fl, 10, dt, theta, 1)
+    assert st.last_m_eff == len(modes)
+    ref = om.prolong(st.omega_M, st.index_fine, J, 2)
+    assert np.abs(got - ref).max() < 1e-12
+    assert s.scalars()["evals"] == 2 * (1 + len(modes)) * N * N
     s.close()
 
 
