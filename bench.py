@@ -360,6 +360,24 @@ def ensemble_leg(args, with_cpu: bool = True) -> dict:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     summ = serve.summarize(recs, wall)
+    full_peak = srv.peak_used
+    # the same ensemble with arenas sized for a fraction of N^2 active nodes:
+    # residency, refits and the same results
+    srv2 = serve.Server(hbm_budget=args.hbm_gb << 30, prec=MRA_MIXED, round_steps=args.round_steps,
+                        progress=progress_printer(), capacity_fraction=args.cap_frac)
+    t0 = time.perf_counter()
+    recs2 = srv2.run(reqs, realtime=False)
+    torch.cuda.synchronize()
+    wall2 = time.perf_counter() - t0
+    by_id = {r.rid: r for r in recs}
+    same = all(r.status == 0 and r.diag == by_id[r.rid].diag for r in recs2)
+    cap_rec = {"capacity_fraction": args.cap_frac, "solves_per_s": len(recs2) / wall2, "wall_s": wall2,
+               "peak_resident_bytes": srv2.peak_used, "full_capacity_peak_resident_bytes": full_peak,
+               "refits": srv2.migrations, "diagnostics_identical_to_full_capacity": same,
+               "note": "every solve resident at once in both runs; a solve whose active set outgrows its "
+                       "capacity is moved to a larger arena when its round ends"}
+    log(f"capacity-sized ensemble: peak {srv2.peak_used / 2**30:.2f} GiB against {full_peak / 2**30:.2f} GiB, "
+        f"{srv2.migrations} refits, identical {same}")
     # baseline: the FP64 GPU path, one solve at a time: per grid size, one
     # solve is warmed up (graph captured) and timed over a few steps, and that
     # per-step time is applied to every solve's step count
@@ -388,7 +406,7 @@ def ensemble_leg(args, with_cpu: bool = True) -> dict:
                                              "sec_per_step_by_J": per_step,
                                              "note": "one warmed solve per size timed over 8 steps, "
                                                      "applied to every solve's step count"},
-                      "autotune": tuned,
+                      "autotune": tuned, "capacity_sized": cap_rec,
                       "cpu_baseline": cpu})
     untune_tiles(tuned)
     return out
@@ -1161,6 +1179,8 @@ def main() -> int:
     ap.add_argument("--ens-steps", type=int, default=200)
     ap.add_argument("--round-steps", type=int, default=20)
     ap.add_argument("--hbm-gb", type=int, default=200)
+    ap.add_argument("--cap-frac", type=float, default=0.25,
+                    help="ensemble: active-node capacity of the second run's arenas, as a fraction of N^2")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--max-J", type=int, default=10)

@@ -59,7 +59,9 @@ enum {
   MRA_E_NOMEM = 3,        /* arena / workspace smaller than required             */
   MRA_E_DEVICE = 4,       /* a HIP call failed                                   */
   MRA_E_NONFINITE = 5,    /* a non-finite value was met (status word only)       */
-  MRA_E_UNSUPPORTED = 6
+  MRA_E_UNSUPPORTED = 6,
+  MRA_E_CAPACITY = 7      /* a regrid found more active nodes than the solve's
+                             capacity (status word; see mra_solve_migrate)      */
 };
 
 /* Precision.  MRA_FP64: every field and sum in FP64.  MRA_MIXED: the bulk
@@ -98,12 +100,12 @@ typedef struct mra_solve_s* mra_solve;
 
 /* Device pointers into a solve's arena (for inspection by tests/tools). */
 typedef struct {
-  double* omega_active;      /* [N*N] FP64, first N_a valid                     */
+  double* omega_active;      /* [capacity] FP64, first N_a valid                */
   uint8_t* mask;             /* [N*N] packed layout, 1 = active                  */
-  int32_t* index_packed;     /* [N*N], first N_a valid                           */
-  int32_t* index_fine;       /* [N*N], first N_a valid                           */
-  int64_t* n_active;         /* device scalar                                    */
-  void* krylov_V;            /* [(m+1)][N*N] Arnoldi basis: double, or float for
+  int32_t* index_packed;     /* [capacity], first N_a valid                      */
+  int32_t* index_fine;       /* [capacity], first N_a valid                      */
+  int64_t* n_active;         /* device scalar (0 while the solve is frozen)      */
+  void* krylov_V;            /* [(m+1)][capacity] Arnoldi basis: double, or float for
                                 precision MRA_FP32 (sums over it are FP64); after
                                 a step rows 0 .. m_eff-1 hold the orthonormal
                                 basis, the next row a work vector              */
@@ -111,7 +113,9 @@ typedef struct {
   double* scalars;           /* [16] FP64: [0] beta, [4] t,
                                 [5] active-point residual evaluations so far
                                 (sum over steps of (1 + m_eff) N_a), [6] steps */
-  int32_t* control;          /* [16] int: [0] m_eff, [1] done, [2] status        */
+  int32_t* control;          /* [16] int: [0] m_eff, [1] done, [2] status, [8] 1
+                                while frozen, [9] the N_a a frozen regrid found  */
+  int64_t capacity;          /* entries of the active-length arrays             */
 } mra_solve_ptrs;
 
 const char* mra_status_str(int32_t status);
@@ -229,6 +233,7 @@ int32_t collocation_rhs_adapted(const mra_grid_desc* g, const mra_flow_desc* f, 
  *
  * mra_solve_init: omega0_dense (device, double [N][N]) is transformed and
  *   thresholded to the first active set; the host handle is written to *out.
+ *   The solve's capacity is N*N.
  * krylov_step: nsteps exponential Rosenbrock-Euler steps
  *   omega_M <- omega_M + dt beta V_m phi_1(dt H_m) e_1, with Arnoldi
  *   (classical Gram-Schmidt with a second pass for every column, delayed to
@@ -256,6 +261,48 @@ int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t p
                        int32_t m, double dt, const double* omega0_dense,
                        void* arena, size_t arena_bytes, void* stream, mra_solve* out);
 int32_t krylov_step(mra_solve s, int32_t nsteps, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Capacity.  The active set of the adaptive grid (Section 2.4) is usually a
+ * small part of the N*N nodes; a solve can size its active values, index
+ * lists and Krylov basis for `capacity` active nodes instead of N*N (the
+ * node-indexed fields stay N*N), so that an arena holds what the active set
+ * needs.  capacity 0 means N*N; otherwise 2^(2 j0) <= capacity <= N*N, else
+ * MRA_E_SIZE.
+ *
+ * mra_solve_footprint_cap / mra_solve_init_cap: as mra_solve_footprint and
+ *   mra_solve_init, for that capacity.  Below N*N, mra_solve_init_cap
+ *   synchronises `stream` and checks the first active set: when it exceeds
+ *   the capacity no handle is made, *needed (if not NULL) receives its size
+ *   and the call returns MRA_E_CAPACITY.
+ * When a later regrid finds more active nodes than the capacity, nothing
+ *   beyond it is written: the solve is frozen.  Its state
+ *   stays omega on the previous active set, advanced by the step that
+ *   overflowed; its status word becomes MRA_E_CAPACITY (mra_solve_read
+ *   returns it) and n_active reads 0; later steps leave it unchanged and do
+ *   not advance t.
+ * mra_solve_capacity: the capacity, the active-node count (for a frozen
+ *   solve, the count the regrid needed) and the frozen flag.  Synchronises
+ *   `stream`.
+ * mra_solve_migrate: moves the solve into a new caller-owned arena of
+ *   mra_solve_footprint_cap(capacity) bytes.  A frozen solve completes its
+ *   pending regrid there (the same FP64 field, so the run continues exactly as
+ *   with a larger capacity); any other solve is copied as it is.  The handle
+ *   stays valid and now lives in the new arena, which the caller keeps; the
+ *   old arena is no longer read once the call returns (it synchronises
+ *   `stream`).  The solve's captured graphs are dropped.  Errors: MRA_E_ARG;
+ *   MRA_E_SIZE when the capacity is out of range or below the active (or
+ *   needed) count; MRA_E_NOMEM for a small arena; MRA_E_UNSUPPORTED for a
+ *   passive scalar or a solve that carries one (mra_scalar_init also refuses
+ *   a partner whose capacity is below N*N).
+ * ------------------------------------------------------------------------ */
+int32_t mra_solve_footprint_cap(const mra_grid_desc* g, int32_t prec, int32_t m, int64_t capacity,
+                                size_t* bytes);
+int32_t mra_solve_init_cap(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, int32_t m,
+                           double dt, const double* omega0_dense, int64_t capacity, void* arena,
+                           size_t arena_bytes, void* stream, mra_solve* out, int64_t* needed);
+int32_t mra_solve_capacity(mra_solve s, int64_t* capacity, int64_t* needed, int32_t* frozen, void* stream);
+int32_t mra_solve_migrate(mra_solve s, int64_t capacity, void* arena, size_t arena_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * mra_solve_track -- vortex centres for the separation b(t) of Section 3.2.

@@ -24,7 +24,8 @@ import torch
 
 from . import _lib
 from ._lib import (FlowDesc, GridDesc, MraError, SolvePtrs, MRA_FORWARD, MRA_INVERSE, MRA_PROLONG,
-                   MRA_FP64, MRA_FP32, MRA_MIXED, MRA_OK, MRA_E_NONFINITE, MRA_EXPONENTIAL,
+                   MRA_FP64, MRA_FP32, MRA_MIXED, MRA_OK, MRA_E_NONFINITE, MRA_E_UNSUPPORTED, MRA_E_CAPACITY,
+                   MRA_EXPONENTIAL,
                    MRA_THETA_NEWTON, MRA_MAX_NEWTON, MRA_JAC_FROZEN, MRA_JAC_EXACT, MRA_EVAL_DENSE,
                    MRA_EVAL_ADAPTED)
 
@@ -146,9 +147,11 @@ def collocation_rhs_adapted(g: GridDesc, f: FlowDesc, prec: int, mask: torch.Ten
     _check("collocation_rhs_adapted", st)
 
 
-def solve_footprint(g: GridDesc, prec: int, m: int) -> int:
+def solve_footprint(g: GridDesc, prec: int, m: int, capacity: int = 0) -> int:
+    """Arena bytes of a solve whose active-length arrays hold `capacity`
+    nodes (0: N^2)."""
     n = C.c_size_t()
-    _check("mra_solve_footprint", lib().mra_solve_footprint(C.byref(g), prec, m, C.byref(n)))
+    _check("mra_solve_footprint_cap", lib().mra_solve_footprint_cap(C.byref(g), prec, m, int(capacity), C.byref(n)))
     return n.value
 
 
@@ -168,25 +171,79 @@ DIAG_KEYS = ("t", "energy", "enstrophy", "palinstrophy", "gamma", "max_abs", "n_
 
 
 class Solve:
-    """One solve whose whole state lives in a torch-allocated device arena."""
+    """One solve whose whole state lives in a torch-allocated device arena.
+
+    capacity: active nodes the arena holds (0: N^2).  A solve whose active set
+    outgrows it is moved to an arena `grow` times the needed count (capped at
+    N^2) by step() and solve_batch(), and then runs on exactly as it would
+    have with the larger capacity."""
 
     def __init__(self, g: GridDesc, f: FlowDesc, prec: int, m: int, dt: float, omega0: torch.Tensor,
-                 stream=None, arena: Optional[torch.Tensor] = None):
+                 stream=None, arena: Optional[torch.Tensor] = None, capacity: int = 0, grow: float = 1.5):
         N = 1 << g.J
         if omega0.dtype != torch.float64 or tuple(omega0.shape) != (N, N):
             raise ValueError("omega0 must be a float64 [N, N] device tensor")
         self.g, self.f, self.prec, self.m, self.dt = g, f, prec, m, dt
         self.N = N
-        self.nbytes = solve_footprint(g, prec, m)
-        self.arena = arena if arena is not None else _alloc(self.nbytes, omega0.device)
-        h = C.c_void_p()
-        st = lib().mra_solve_init(C.byref(g), C.byref(f), prec, m, dt, _ptr(omega0.contiguous()),
-                                  _ptr(self.arena), self.arena.numel(), _stream(stream), C.byref(h))
-        _check("mra_solve_init", st)
+        self.capacity = int(capacity) if capacity else N * N
+        self.grow = float(grow)
+        self.migrations = 0
+        w0 = omega0.contiguous()
+        while True:
+            self.nbytes = solve_footprint(g, prec, m, self.capacity)
+            self.arena = arena if arena is not None else _alloc(self.nbytes, omega0.device)
+            h, need = C.c_void_p(), C.c_int64()
+            st = lib().mra_solve_init_cap(C.byref(g), C.byref(f), prec, m, dt, _ptr(w0), self.capacity,
+                                          _ptr(self.arena), self.arena.numel(), _stream(stream), C.byref(h),
+                                          C.byref(need))
+            if st != MRA_E_CAPACITY or arena is not None:
+                break
+            # the first active set is larger than the capacity: a larger arena
+            self.capacity = min(N * N, max(need.value, int(math.ceil(need.value * self.grow))))
+            self.migrations += 1
+        _check("mra_solve_init_cap", st)
         self.handle = h
 
+    def capacity_state(self, stream=None) -> Tuple[int, int, bool]:
+        """(capacity, active or needed node count, frozen); synchronises."""
+        cap, need, frozen = C.c_int64(), C.c_int64(), C.c_int32()
+        _check("mra_solve_capacity", lib().mra_solve_capacity(self.handle, C.byref(cap), C.byref(need),
+                                                               C.byref(frozen), _stream(stream)))
+        return cap.value, need.value, bool(frozen.value)
+
+    def migrate(self, capacity: int, stream=None) -> None:
+        """Move the solve to a new arena of `capacity` active nodes
+        (mra_solve_migrate); a frozen solve completes its regrid there."""
+        nbytes = solve_footprint(self.g, self.prec, self.m, capacity)
+        arena = _alloc(nbytes, self.arena.device)
+        _check("mra_solve_migrate", lib().mra_solve_migrate(self.handle, int(capacity), _ptr(arena), arena.numel(),
+                                                             _stream(stream)))
+        self.arena, self.nbytes, self.capacity = arena, nbytes, int(capacity)
+        self.migrations += 1
+
+    def fit(self, stream=None) -> bool:
+        """If the solve is frozen, move it to a larger arena; returns whether it was."""
+        if self.capacity >= self.N * self.N:
+            return False
+        _, need, frozen = self.capacity_state(stream)
+        if frozen:
+            self.migrate(min(self.N * self.N, max(need, int(math.ceil(need * self.grow)))), stream)
+        return frozen
+
+    def steps_done(self, stream=None) -> int:
+        return int(round(self.scalars(stream=stream)["steps"]))
+
     def step(self, nsteps: int = 1, stream=None) -> None:
-        _check("krylov_step", lib().krylov_step(self.handle, nsteps, _stream(stream)))
+        if self.capacity >= self.N * self.N:
+            _check("krylov_step", lib().krylov_step(self.handle, nsteps, _stream(stream)))
+            return
+        target = self.steps_done(stream) + nsteps
+        while True:
+            done = self.steps_done(stream)
+            if done >= target:
+                return
+            _check("krylov_step", lib().krylov_step(self.handle, target - done, _stream(stream)))
+            self.fit(stream)
 
     def set_integrator(self, integrator: int, theta: float = 0.5, newton_iters: int = 2, stream=None) -> None:
         """Time scheme of later steps: MRA_EXPONENTIAL, or MRA_THETA_NEWTON
@@ -207,7 +264,7 @@ class Solve:
         out = torch.empty((self.N, self.N), dtype=torch.float64, device=self.arena.device) if dense else None
         diag = (C.c_double * 8)()
         st = lib().mra_solve_read(self.handle, _ptr(out), diag, _stream(stream))
-        if st not in (MRA_OK, MRA_E_NONFINITE):
+        if st not in (MRA_OK, MRA_E_NONFINITE, MRA_E_CAPACITY):
             _check("mra_solve_read", st)
         return out, dict(zip(DIAG_KEYS, list(diag)))
 
@@ -281,6 +338,7 @@ class ScalarSolve(Solve):
         self.g, self.f, self.prec, self.m, self.dt = g, partner.f, partner.prec, m, dt
         self.N = N
         self.partner = partner
+        self.capacity, self.grow, self.migrations = N * N, 1.5, 0
         self.nbytes = solve_footprint(g, partner.prec, m)
         self.arena = arena if arena is not None else _alloc(self.nbytes, r0.device)
         h = C.c_void_p()
@@ -325,8 +383,31 @@ def step_profile(solves: Sequence[Solve], stream=None) -> Dict[str, float]:
     return dict(zip(STEP_PHASES, list(out)))
 
 
-def solve_batch(solves: Sequence[Solve], nsteps: Sequence[int], stream=None) -> None:
+def _solve_batch(solves: Sequence[Solve], nsteps: Sequence[int], stream=None) -> None:
     n = len(solves)
     hs = (C.c_void_p * n)(*[s.handle for s in solves])
     ns = (C.c_int32 * n)(*[int(k) for k in nsteps])
     _check("solve_batch", lib().solve_batch(hs, n, ns, _stream(stream)))
+
+
+def solve_batch(solves: Sequence[Solve], nsteps: Sequence[int], stream=None, fit: bool = True) -> None:
+    """Advance solves[i] by nsteps[i] steps in shared launches (solve_batch).
+    Solves below full capacity that freeze on the way are moved to larger
+    arenas and finish their steps (fit=False leaves that to the caller: the
+    call then does not synchronise)."""
+    small = [i for i, s in enumerate(solves) if s.capacity < s.N * s.N]
+    if not fit or not small:
+        _solve_batch(solves, nsteps, stream)
+        return
+    target = {i: solves[i].steps_done(stream) + int(nsteps[i]) for i in small}
+    _solve_batch(solves, nsteps, stream)
+    while True:
+        rest = []
+        for i in small:
+            solves[i].fit(stream)
+            k = target[i] - solves[i].steps_done(stream)
+            if k > 0:
+                rest.append((solves[i], k))
+        if not rest:
+            return
+        _solve_batch([s for s, _ in rest], [k for _, k in rest], stream)

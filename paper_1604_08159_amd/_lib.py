@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmra.so")
 
-MRA_OK, MRA_E_ARG, MRA_E_SIZE, MRA_E_NOMEM, MRA_E_DEVICE, MRA_E_NONFINITE, MRA_E_UNSUPPORTED = range(7)
+MRA_OK, MRA_E_ARG, MRA_E_SIZE, MRA_E_NOMEM, MRA_E_DEVICE, MRA_E_NONFINITE, MRA_E_UNSUPPORTED, MRA_E_CAPACITY = range(8)
 MRA_FP64, MRA_FP32, MRA_MIXED = 0, 1, 2
 MRA_FORWARD, MRA_INVERSE, MRA_PROLONG = 1, -1, 2
 MRA_EXPONENTIAL, MRA_THETA_NEWTON = 0, 1
@@ -33,7 +33,8 @@ class FlowDesc(C.Structure):
 class SolvePtrs(C.Structure):
     _fields_ = [("omega_active", C.c_void_p), ("mask", C.c_void_p), ("index_packed", C.c_void_p),
                 ("index_fine", C.c_void_p), ("n_active", C.c_void_p), ("krylov_V", C.c_void_p),
-                ("hessenberg", C.c_void_p), ("scalars", C.c_void_p), ("control", C.c_void_p)]
+                ("hessenberg", C.c_void_p), ("scalars", C.c_void_p), ("control", C.c_void_p),
+                ("capacity", C.c_int64)]
 
 
 EXPORTS = {
@@ -59,6 +60,14 @@ EXPORTS = {
                                    C.c_double, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                    C.POINTER(C.c_void_p)]),
     "krylov_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "mra_solve_footprint_cap": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_int32, C.c_int64,
+                                            C.POINTER(C.c_size_t)]),
+    "mra_solve_init_cap": (C.c_int32, [C.POINTER(GridDesc), C.POINTER(FlowDesc), C.c_int32, C.c_int32,
+                                       C.c_double, C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p,
+                                       C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]),
+    "mra_solve_capacity": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int32), C.c_void_p]),
+    "mra_solve_migrate": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p]),
     "mra_scalar_init": (C.c_int32, [C.c_void_p, C.POINTER(GridDesc), C.c_int32, C.c_double, C.c_double,
                                     C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),

@@ -38,6 +38,8 @@ struct mra_solve_s {
   int riders = 0;                 // passive scalars riding on this solve
 };
 
+static_assert(kStatusCapacity == MRA_E_CAPACITY, "status word value of a capacity overflow");
+
 namespace {
 
 std::mutex g_mu;
@@ -117,6 +119,7 @@ void fill_geometry(SolveDev& s, const mra_grid_desc* g, int32_t prec) {
   s.adjacent_zone = g->adjacent_zone;
   s.tile = tile_choice(s.J, s.p, s.prec);
   s.ntx = s.N / s.tile;
+  s.cap = s.N * s.N;
   s.length = g->length;
   s.h = g->length / s.N;
   s.eps = g->eps;
@@ -176,9 +179,11 @@ void rhs_layout(Layout& L, SolveDev& s) {
   s.out_rhs = L.take<double>(Nf);
 }
 
-// Arena of a solve.
+// Arena of a solve.  The active-length arrays and the basis vectors hold
+// s.cap entries (at most N^2); everything indexed by grid node holds N^2.
 void solve_layout(Layout& L, SolveDev& s) {
   const size_t Nf = (size_t)s.N * s.N;
+  const size_t cap = (size_t)s.cap;
   const size_t esz = s.prec == 0 ? 8 : 4;
   (void)L.take<SolveDev>(1);
   s.ctrl = L.take<int>(C_NCTRL);
@@ -186,17 +191,17 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.umax = L.take<unsigned long long>(1);
   s.n_active = L.take<int64_t>(1);
   s.mask = L.take<uint8_t>(Nf);
-  s.index_packed = L.take<int32_t>(Nf);
-  s.index_fine = L.take<int32_t>(Nf);
+  s.index_packed = L.take<int32_t>(cap);
+  s.index_fine = L.take<int32_t>(cap);
   s.rank = L.take<int32_t>(Nf);
   s.tile_count = L.take<int32_t>((size_t)s.ntx * s.ntx);
   s.block_off = L.take<int32_t>(nscan_of(s.J));
-  s.omega = L.take<double>(Nf);
+  s.omega = L.take<double>(cap);
   s.V = nullptr;
   s.V32 = nullptr;
-  if (s.vb32) s.V32 = L.take<float>((size_t)(s.m + 1) * Nf);
-  else s.V = L.take<double>((size_t)(s.m + 1) * Nf);
-  s.w = L.take<double>(Nf);
+  if (s.vb32) s.V32 = L.take<float>((size_t)(s.m + 1) * cap);
+  else s.V = L.take<double>((size_t)(s.m + 1) * cap);
+  s.w = L.take<double>(cap);
   s.H = L.take<double>((size_t)(s.m + 1) * s.m);
   s.hpart = L.take<double>(2 * (kMaxM + 1));
   s.y = L.take<double>(kMaxM + 1);
@@ -214,13 +219,17 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.dense64 = L.take<double>(Nf);
   s.packed64 = L.take<double>(Nf);
   s.diag = L.take<double>((size_t)s.N * 5);
-  s.lam = L.take<uint8_t>(Nf);
+  s.lam = L.take<uint8_t>(cap);
   s.out_rhs = s.w;
   s.out_jvp = s.w;
   // FP32 bulk fields: the FP64 prolongation of the residual lives in the
-  // basis storage ((m + 1) N^2 elements, m >= 1), which a step writes only
-  // after the residual (V_0 = F / beta is written by the first product's Pi)
-  if (s.prec != 0) s.res64 = s.V ? s.V : reinterpret_cast<double*>(s.V32);
+  // basis storage ((m + 1) cap elements, m >= 1), which a step writes only
+  // after the residual (V_0 = F / beta is written by the first product's Pi),
+  // when that holds N^2 doubles; else in a buffer of its own
+  if (s.prec != 0) {
+    const size_t vbytes = (size_t)(s.m + 1) * cap * (s.vb32 ? 4 : 8);
+    s.res64 = vbytes >= Nf * 8 ? (s.V ? s.V : reinterpret_cast<double*>(s.V32)) : L.take<double>(Nf);
+  }
 }
 
 Batch one(const SolveDev* d) {
@@ -445,6 +454,7 @@ const char* mra_status_str(int32_t st) {
     case MRA_E_DEVICE: return "HIP error";
     case MRA_E_NONFINITE: return "non-finite value";
     case MRA_E_UNSUPPORTED: return "unsupported";
+    case MRA_E_CAPACITY: return "active set exceeds the solve's capacity";
     default: return "unknown status";
   }
 }
@@ -627,32 +637,58 @@ int32_t collocation_rhs_adapted(const mra_grid_desc* g, const mra_flow_desc* f, 
                   ws, ws_bytes, stream, 1);
 }
 
-int32_t mra_solve_footprint(const mra_grid_desc* g, int32_t prec, int32_t m, size_t* bytes) {
+// capacity 0: N^2; otherwise between the coarsest mesh's node count and N^2
+static int32_t check_capacity(const mra_grid_desc* g, int64_t capacity) {
+  const int64_t nf = (int64_t)1 << (2 * g->J);
+  const int64_t n0 = (int64_t)1 << (2 * g->j0);
+  if (capacity != 0 && (capacity < n0 || capacity > nf)) return MRA_E_SIZE;
+  return MRA_OK;
+}
+
+int32_t mra_solve_footprint_cap(const mra_grid_desc* g, int32_t prec, int32_t m, int64_t capacity,
+                                size_t* bytes) {
   int32_t r = check_grid(g);
   if (r != MRA_OK) return r;
   if (!bytes || prec < 0 || prec > 2) return MRA_E_ARG;
   if (m < 1 || m > kMaxM) return MRA_E_SIZE;
+  if ((r = check_capacity(g, capacity)) != MRA_OK) return r;
   SolveDev s;
   fill_geometry(s, g, prec);
   s.m = m;
+  if (capacity) s.cap = (int)capacity;
   Layout L(nullptr);
   solve_layout(L, s);
   *bytes = L.off + 256;
   return MRA_OK;
 }
 
-int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, int32_t m, double dt,
-                       const double* omega0_dense, void* arena, size_t arena_bytes, void* stream,
-                       mra_solve* out) {
+int32_t mra_solve_footprint(const mra_grid_desc* g, int32_t prec, int32_t m, size_t* bytes) {
+  return mra_solve_footprint_cap(g, prec, m, 0, bytes);
+}
+
+// The launches that turn the FP64 field in s.dense64 into the active set and
+// values of an arena (the regrid without its prolongation).
+static hipError_t enqueue_regrid_from_dense(const Batch& b, const LaunchCfg& c, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_reset_max(b, st)) != hipSuccess || (e = launch_forward(b, c, 0, 0, st)) != hipSuccess ||
+      (e = launch_threshold(b, c, 1, st)) != hipSuccess)
+    return e;
+  return launch_gather(b, c, st);
+}
+
+int32_t mra_solve_init_cap(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, int32_t m, double dt,
+                           const double* omega0_dense, int64_t capacity, void* arena, size_t arena_bytes,
+                           void* stream, mra_solve* out, int64_t* needed) {
   int32_t r = check_grid(g);
   if (r != MRA_OK) return r;
   if ((r = check_flow(f)) != MRA_OK) return r;
   if (!omega0_dense || !arena || !out || prec < 0 || prec > 2) return MRA_E_ARG;
   if (m < 1 || m > kMaxM) return MRA_E_SIZE;
+  if ((r = check_capacity(g, capacity)) != MRA_OK) return r;
   if (!(dt > 0.0) || !std::isfinite(dt)) return MRA_E_ARG;
   if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return MRA_E_ARG;
   size_t need = 0;
-  mra_solve_footprint(g, prec, m, &need);
+  mra_solve_footprint_cap(g, prec, m, capacity, &need);
   if (arena_bytes < need) return MRA_E_NOMEM;
   if ((r = ensure_init()) != MRA_OK) return r;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -663,6 +699,7 @@ int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t p
   fill_flow(s, f);
   s.m = m;
   s.dt = dt;
+  if (capacity) s.cap = (int)capacity;
   Layout L(arena);
   solve_layout(L, s);
   h->dev = reinterpret_cast<SolveDev*>(arena);
@@ -678,12 +715,114 @@ int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t p
       (e = launch_reset_ctrl(b, st)) != hipSuccess ||
       (e = hipMemcpyAsync(s.dense64, omega0_dense, Nf * sizeof(double), hipMemcpyDeviceToDevice, st)) !=
           hipSuccess ||
-      (e = launch_reset_max(b, st)) != hipSuccess || (e = launch_forward(b, h->cfg, 0, 0, st)) != hipSuccess ||
-      (e = launch_threshold(b, h->cfg, 1, st)) != hipSuccess || (e = launch_gather(b, h->cfg, st)) != hipSuccess) {
+      (e = enqueue_regrid_from_dense(b, h->cfg, st)) != hipSuccess) {
     delete h;
     return MRA_E_DEVICE;
   }
+  if (s.cap < (int)Nf) {
+    // the first active set must fit: a solve frozen before its first regrid
+    // would have no previous set to fall back on
+    int ctrl[C_NCTRL];
+    if (hipMemcpyAsync(ctrl, s.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      delete h;
+      return MRA_E_DEVICE;
+    }
+    if (ctrl[C_OVER]) {
+      if (needed) *needed = ctrl[C_NEED];
+      delete h;
+      return MRA_E_CAPACITY;
+    }
+  }
   *out = h;
+  return MRA_OK;
+}
+
+int32_t mra_solve_init(const mra_grid_desc* g, const mra_flow_desc* f, int32_t prec, int32_t m, double dt,
+                       const double* omega0_dense, void* arena, size_t arena_bytes, void* stream,
+                       mra_solve* out) {
+  return mra_solve_init_cap(g, f, prec, m, dt, omega0_dense, 0, arena, arena_bytes, stream, out, nullptr);
+}
+
+int32_t mra_solve_capacity(mra_solve h, int64_t* capacity, int64_t* needed, int32_t* frozen, void* stream) {
+  if (!h || !capacity || !needed || !frozen) return MRA_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int ctrl[C_NCTRL];
+  int64_t na = 0;
+  MRA_TRY(hipMemcpyAsync(ctrl, h->host.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, st));
+  MRA_TRY(hipMemcpyAsync(&na, h->host.n_active, sizeof(na), hipMemcpyDeviceToHost, st));
+  MRA_TRY(hipStreamSynchronize(st));
+  *capacity = h->host.cap;
+  *frozen = ctrl[C_OVER] ? 1 : 0;
+  *needed = ctrl[C_OVER] ? (int64_t)ctrl[C_NEED] : na;
+  return MRA_OK;
+}
+
+static void drop_graphs_of(mra_solve h);
+
+int32_t mra_solve_migrate(mra_solve h, int64_t capacity, void* arena, size_t arena_bytes, void* stream) {
+  if (!h || !arena) return MRA_E_ARG;
+  if (h->cfg.kind != 0 || h->riders) return MRA_E_UNSUPPORTED;
+  if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return MRA_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const SolveDev& o = h->host;
+  mra_grid_desc g{};
+  g.J = o.J;
+  g.j0 = o.j0;
+  g.p = o.p;
+  g.eps = o.eps;
+  g.length = o.length;
+  g.adjacent_zone = o.adjacent_zone;
+  const int32_t prec = o.prec == 0 ? MRA_FP64 : (o.vb32 ? MRA_FP32 : MRA_MIXED);
+  int32_t r = check_capacity(&g, capacity);
+  if (r != MRA_OK) return r;
+  size_t need = 0;
+  mra_solve_footprint_cap(&g, prec, o.m, capacity, &need);
+  if (arena_bytes < need) return MRA_E_NOMEM;
+  // the old arena's state: control words and counters, after its work
+  MRA_TRY(hipStreamSynchronize(st));
+  int ctrl[C_NCTRL];
+  int64_t na = 0;
+  MRA_TRY(hipMemcpy(ctrl, o.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost));
+  MRA_TRY(hipMemcpy(&na, o.n_active, sizeof(na), hipMemcpyDeviceToHost));
+  const bool frozen = ctrl[C_OVER] != 0;
+  const int64_t cap = capacity ? capacity : (int64_t)o.N * o.N;
+  if ((frozen ? (int64_t)ctrl[C_NEED] : na) > cap) return MRA_E_SIZE;
+  drop_graphs_of(h);
+  SolveDev s = o;
+  s.cap = (int)cap;
+  Layout L(arena);
+  solve_layout(L, s);
+  SolveDev* dev = reinterpret_cast<SolveDev*>(arena);
+  LaunchCfg c = h->cfg;
+  Batch b = one(dev);
+  const size_t Nf = (size_t)s.N * s.N;
+  MRA_TRY(launch_write_desc(dev, s, st));
+  MRA_TRY(launch_reset_ctrl(b, st));
+  // time, step and evaluation counters, theta, ...
+  MRA_TRY(hipMemcpyAsync(s.scal, o.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (frozen) {
+    // the pending regrid: the FP64 prolongation of omega on the old set
+    MRA_TRY(launch_prolong(one(h->dev), c, 2, 1, 0, 0, st));
+    MRA_TRY(hipMemcpyAsync(s.dense64, o.dense64, Nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+    MRA_TRY(enqueue_regrid_from_dense(b, c, st));
+  } else {
+    // the state as it is: active set, values and the tile counts
+    MRA_TRY(hipMemcpyAsync(s.n_active, o.n_active, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    MRA_TRY(hipMemcpyAsync(s.mask, o.mask, Nf, hipMemcpyDeviceToDevice, st));
+    MRA_TRY(hipMemcpyAsync(s.rank, o.rank, Nf * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    MRA_TRY(hipMemcpyAsync(s.tile_count, o.tile_count, (size_t)s.ntx * s.ntx * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, st));
+    if (na > 0) {
+      MRA_TRY(hipMemcpyAsync(s.index_packed, o.index_packed, na * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      MRA_TRY(hipMemcpyAsync(s.index_fine, o.index_fine, na * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      MRA_TRY(hipMemcpyAsync(s.omega, o.omega, na * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+  }
+  // the old arena is read until here: the caller may free it on return
+  MRA_TRY(hipStreamSynchronize(st));
+  h->host = s;
+  h->dev = dev;
   return MRA_OK;
 }
 
@@ -691,6 +830,9 @@ int32_t mra_scalar_init(mra_solve partner, const mra_grid_desc* g, int32_t m, do
                         int32_t eddy, const double* r0_dense, void* arena, size_t arena_bytes, void* stream,
                         mra_solve* out) {
   if (!partner || partner->cfg.kind != 0) return MRA_E_ARG;
+  // a scalar holds pointers into its partner's arena, which a move to a
+  // larger one would leave behind
+  if (partner->host.cap != partner->host.N * partner->host.N) return MRA_E_UNSUPPORTED;
   // a scalar step reads the partner's flow at the start of its step, which a
   // Newton step overwrites with the flow at its last iterate
   if (partner->cfg.integ != 0) return MRA_E_UNSUPPORTED;
@@ -890,6 +1032,7 @@ int32_t mra_solve_read(mra_solve h, double* omega_dense_out, double* diag_out, v
     diag_out[6] = (double)na;
     diag_out[7] = (double)ctrl[C_STATUS];
   }
+  if (ctrl[C_STATUS] == kStatusCapacity) return MRA_E_CAPACITY;
   return ctrl[C_STATUS] == 0 ? MRA_OK : MRA_E_NONFINITE;
 }
 
@@ -935,6 +1078,7 @@ int32_t mra_solve_ptrs_get(mra_solve h, mra_solve_ptrs* out) {
   out->hessenberg = s.H;
   out->scalars = s.scal;
   out->control = s.ctrl;
+  out->capacity = s.cap;
   return MRA_OK;
 }
 

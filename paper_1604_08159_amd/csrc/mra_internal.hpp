@@ -24,8 +24,11 @@ constexpr int kCoarseLevels = 6;    // levels <= this are prolonged by one block
 constexpr int kTwN = 2048;          // twiddle table size (largest FFT length)
 
 // Control words (int) and scalars (double) of a solve.
+// C_OVER: the last regrid found more active nodes (C_NEED) than the solve's
+// capacity; the solve is frozen until it is moved to a larger arena.
 enum Ctrl : int { C_MEFF = 0, C_DONE = 1, C_STATUS = 2, C_CNT0 = 4, C_CNT1 = 5, C_CNT2 = 6,
-                  C_CNT3 = 7, C_NCTRL = 16 };
+                  C_CNT3 = 7, C_OVER = 8, C_NEED = 9, C_NCTRL = 16 };
+constexpr int kStatusCapacity = 7;   // the status word's value for MRA_E_CAPACITY
 enum Scal : int { S_BETA = 0, S_INV = 1, S_UMAX = 3, S_T = 4, S_EVALS = 5, S_STEPS = 6,
                   S_THETA = 7, S_COND = 8, S_NSCAL = 16 };
 
@@ -38,22 +41,23 @@ struct SolveDev {
   int adjacent_zone;
   int smag_mode;
   int tile, ntx;            // stencil tile edge and tiles per side
+  int cap;                  // capacity: length of the active-value arrays and basis vectors (<= Nf)
   double h, length, eps, dt;
   double nu0, cs, s0, mu;
   // active set
   uint8_t* mask;            // [Nf] packed
-  int32_t* index_packed;    // [Nf]
-  int32_t* index_fine;      // [Nf]
+  int32_t* index_packed;    // [cap]
+  int32_t* index_fine;      // [cap]
   int32_t* rank;            // [Nf] dense: active position or -1
   int32_t* tile_count;      // [ntiles] active nodes per stencil tile
   int64_t* n_active;        // device scalar
   int32_t* block_off;       // [nscan] compaction block counts -> offsets
   unsigned long long* umax; // bits of max|u| (non-negative doubles order as integers)
   // Krylov (FP64 arithmetic)
-  double* omega;            // [Nf] active values
-  double* V;                // [(m+1)][Nf] basis in FP64 (null when stored in FP32)
-  float* V32;               // [(m+1)][Nf] basis in FP32, precision MRA_FP32 only (else null)
-  double* w;                // [Nf]
+  double* omega;            // [cap] active values
+  double* V;                // [(m+1)][cap] basis in FP64 (null when stored in FP32)
+  float* V32;               // [(m+1)][cap] basis in FP32, precision MRA_FP32 only (else null)
+  double* w;                // [cap]
   double* H;                // [(m+1)][m]
   double* hpart;            // [2][kMaxM+1] first-pass Gram-Schmidt coefficients, by column parity
   double* y;                // [kMaxM + 1]
@@ -72,11 +76,12 @@ struct SolveDev {
   void* spec2;              // the v spectrum, same shape
   double* vel64;            // FP64 velocity [2][Nf] of dense64 (diagnostics), and of res64
   double* res64;            // FP32-bulk solves: Pi(omega) in FP64 for the residual [Nf] (it
-                            // shares the Krylov basis storage, which a step fills only later)
+                            // shares the Krylov basis storage, which a step fills only later,
+                            // when that holds Nf values)
   double* dense64;          // FP64 regrid field [Nf]; F(omega_n) during Newton iterations
   double* packed64;         // FP64 packed pyramid [Nf]; omega_n during Newton iterations
-  double* out_rhs;          // residual at the active nodes [Nf]
-  double* out_jvp;          // J v at the active nodes [Nf]
+  double* out_rhs;          // residual at the active nodes [cap]
+  double* out_jvp;          // J v at the active nodes [cap]
   const double* vin;        // active vector scattered by src 2 of the scatter
   double* diag;             // [N][4] per-row diagnostic partial sums
   uint8_t* lam;             // level-adapted evaluation: local level of each active node [Nf]

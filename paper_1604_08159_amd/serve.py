@@ -3,9 +3,9 @@
 Host-side orchestration only: every step of every solve runs in the
 library's kernels through solve_batch.  Requests (initial vortices, grid,
 Reynolds number, step count) arrive over time; a request is admitted as soon
-as its arena fits in the HBM budget (footprint from mra_solve_footprint) and
-stays resident -- active set, Krylov basis, dense work fields -- until its
-last step.  Resident solves of equal (J, p, m) form a group with a stream of
+as its arena fits in the HBM budget (footprint from mra_solve_footprint_cap,
+for a capacity of N^2 nodes or a set fraction of them) and stays resident --
+active set, Krylov basis, dense work fields -- until its last step.  Resident solves of equal (J, p, m) form a group with a stream of
 its own; a group advances in rounds of a few steps (one solve_batch call, so
 its solves share every kernel launch and a captured step graph), and groups
 run independently of each other: there is no barrier across groups.  The
@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import math
 import time
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
@@ -69,8 +70,19 @@ class Server:
 
     def __init__(self, hbm_budget: int, prec: int = MRA_MIXED, round_steps: int = 20,
                  device: str = "cuda:0", keep_results: bool = False,
-                 progress: Optional[Callable[[int, int, int], None]] = None):
+                 progress: Optional[Callable[[int, int, int], None]] = None,
+                 capacity_fraction: Optional[float] = None):
+        """capacity_fraction: size each solve's active-length arrays and Krylov
+        basis for that fraction of its N^2 nodes (None: N^2).  A solve whose
+        active set outgrows its capacity is moved to a larger arena when its
+        round ends, and then continues exactly as with full capacity; the
+        move may take the bytes in use above the budget (the solve cannot go
+        on in its old arena), and admission then waits until they fall below
+        it."""
         self.budget = int(hbm_budget)
+        self.cap_frac = capacity_fraction
+        self.peak_used = 0
+        self.migrations = 0
         self.progress = progress          # called after each round: (done, resident, waiting)
         self.prec = prec
         self.round_steps = round_steps
@@ -80,8 +92,14 @@ class Server:
         self.used = 0
         self.live: Dict[int, Tuple[Solve, Request, Record, int]] = {}   # rid -> (solve, req, rec, steps done)
 
+    def capacity(self, r: Request) -> int:
+        if not self.cap_frac:
+            return 0
+        nf = 1 << (2 * r.J)
+        return min(nf, max(4096, int(math.ceil(self.cap_frac * nf))))
+
     def footprint(self, r: Request) -> int:
-        return solve_footprint(grid_desc(r.J, r.p, r.eps), self.prec, r.m)
+        return solve_footprint(grid_desc(r.J, r.p, r.eps), self.prec, r.m, self.capacity(r))
 
     def _stream(self, r: Request) -> torch.cuda.Stream:
         key = (r.J, r.p, r.m)
@@ -96,9 +114,11 @@ class Server:
             # host does not wait for a round of that group still in flight
             host = torch.from_numpy(r.omega0).pin_memory()
             w0 = host.to(self.dev, non_blocking=True)
-            s = Solve(grid_desc(r.J, r.p, r.eps), flow_desc(r.nu0, r.cs), self.prec, r.m, r.dt, w0, stream=st)
+            s = Solve(grid_desc(r.J, r.p, r.eps), flow_desc(r.nu0, r.cs), self.prec, r.m, r.dt, w0, stream=st,
+                      capacity=self.capacity(r))
         s._staging = (host, w0)          # alive until the copy and the init have run
         self.used += s.nbytes
+        self.peak_used = max(self.peak_used, self.used)
         rec.admitted = now
         self.live[r.rid] = (s, r, rec, 0)
 
@@ -152,7 +172,18 @@ class Server:
                 progressed = True
                 for i in rids:
                     s, r, rec, d = self.live[i]
-                    self.live[i] = (s, r, rec, d + k)
+                    if s.capacity < s.N * s.N:
+                        # a solve that outgrew its capacity froze during the
+                        # round: move it, and count the steps it really took
+                        before = s.nbytes
+                        if s.fit(stream=self.streams[key]):
+                            self.migrations += 1
+                            self.used += s.nbytes - before
+                            self.peak_used = max(self.peak_used, self.used)
+                        d = s.steps_done(stream=self.streams[key])
+                    else:
+                        d += k
+                    self.live[i] = (s, r, rec, d)
                 for i in [i for i in rids if self.live[i][3] >= self.live[i][1].steps]:
                     done.append(self._retire(i, now()))
             # admission: FIFO, while the head fits in the remaining budget
@@ -174,7 +205,7 @@ class Server:
                     continue
                 k = min(self.round_steps, min(self.live[i][1].steps - self.live[i][3] for i in rids))
                 st = self.streams[key]
-                solve_batch([self.live[i][0] for i in rids], [k] * len(rids), stream=st)
+                solve_batch([self.live[i][0] for i in rids], [k] * len(rids), stream=st, fit=False)
                 ev = self._event()
                 ev.record(st)
                 inflight[key] = (ev, list(rids), k)

@@ -146,3 +146,38 @@ def test_noalloc_transform_host_checks(lib):
     assert lib.mra_transform_noalloc(C.byref(_grid(11, 3)), 2, 2, buf, buf, buf, None, buf, buf, None) == 2
     assert lib.mra_transform_noalloc(C.byref(_grid(6, 2)), 0, 1, None, None, None, None, None, None, None) == 1
     assert lib.mra_transform_noalloc(C.byref(_grid(6, 2)), 0, 7, buf, buf, None, None, None, None, None) == 1
+
+
+def test_capacity_footprint_and_checks(lib):
+    """The arena of a solve sized for `capacity` active nodes: the active-length
+    arrays and the Krylov basis shrink with it, the node-indexed fields do
+    not; 0 means N^2; out-of-range capacities are refused before anything is
+    allocated or launched."""
+    n, full, zero = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    g = _grid(9, 2)
+    nf = 512 * 512
+    assert lib.mra_solve_footprint(C.byref(g), 2, 20, C.byref(full)) == 0
+    assert lib.mra_solve_footprint_cap(C.byref(g), 2, 20, 0, C.byref(zero)) == 0
+    assert zero.value == full.value
+    assert lib.mra_solve_footprint_cap(C.byref(g), 2, 20, nf, C.byref(n)) == 0 and n.value == full.value
+    sizes = []
+    for cap in (16, 4096, 20000, 65536, nf // 2):
+        assert lib.mra_solve_footprint_cap(C.byref(g), 2, 20, cap, C.byref(n)) == 0
+        sizes.append(n.value)
+    assert sizes == sorted(sizes) and sizes[-1] < full.value
+    # per active node: FP64 value, two int32 indices, FP64 w, m + 1 FP64 basis
+    # entries and the adapted evaluation's level byte (within the 256-byte
+    # alignment of each array)
+    per_node = 8 + 4 + 4 + 8 + 21 * 8 + 1
+    assert abs((sizes[3] - sizes[2]) - per_node * (65536 - 20000)) <= 16 * 256
+    # a small capacity takes the residual's FP64 prolongation out of the basis
+    assert lib.mra_solve_footprint_cap(C.byref(g), 0, 20, 4096, C.byref(n)) == 0
+    assert lib.mra_solve_footprint_cap(C.byref(g), 2, 20, 15, C.byref(n)) == 2       # below the coarsest mesh
+    assert lib.mra_solve_footprint_cap(C.byref(g), 2, 20, nf + 1, C.byref(n)) == 2   # above N^2
+    assert lib.mra_solve_footprint_cap(C.byref(g), 2, 20, -5, C.byref(n)) == 2
+    assert lib.mra_solve_capacity(None, C.byref(C.c_int64()), C.byref(C.c_int64()), C.byref(C.c_int32()),
+                                  None) == 1
+    assert lib.mra_solve_migrate(None, 4096, None, 0, None) == 1
+    assert lib.mra_solve_init_cap(C.byref(g), None, 2, 20, 0.01, None, 4096, None, 0, None,
+                                  C.byref(C.c_void_p()), None) != 0
+    assert lib.mra_status_str(7) == b"active set exceeds the solve's capacity"

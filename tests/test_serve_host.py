@@ -17,8 +17,10 @@ class FakeSolve:
     bytes_live = 0
     peak_bytes = 0
 
-    def __init__(self, g, f, prec, m, dt, w0, stream=None):
+    def __init__(self, g, f, prec, m, dt, w0, stream=None, capacity=0):
         self.J, self.m = g.J, m
+        self.N = 1 << g.J
+        self.capacity = self.N * self.N
         self.nbytes = FOOTPRINT[g.J]
         self.steps = 0
         FakeSolve.live += 1
@@ -41,7 +43,7 @@ FOOTPRINT = {6: 100, 7: 400, 8: 1600}
 BATCHES = []
 
 
-def fake_solve_batch(solves, nsteps, stream=None):
+def fake_solve_batch(solves, nsteps, stream=None, fit=True):
     assert len({s.J for s in solves}) == 1            # one launch configuration per batch
     BATCHES.append((solves[0].J, len(solves), nsteps[0]))
     for s, k in zip(solves, nsteps):
@@ -69,7 +71,7 @@ def fakes(monkeypatch):
     BATCHES.clear()
     monkeypatch.setattr(serve, "Solve", FakeSolve)
     monkeypatch.setattr(serve, "solve_batch", fake_solve_batch)
-    monkeypatch.setattr(serve, "solve_footprint", lambda g, prec, m: FOOTPRINT[g.J])
+    monkeypatch.setattr(serve, "solve_footprint", lambda g, prec, m, capacity=0: FOOTPRINT[g.J])
     monkeypatch.setattr(serve.torch.cuda, "Stream", lambda device=None: FakeStream())
     monkeypatch.setattr(serve.torch.cuda, "stream", lambda st: contextlib.nullcontext())
     monkeypatch.setattr(serve.torch, "from_numpy", lambda a: a)          # host arrays stay put
@@ -161,3 +163,59 @@ def test_groups_advance_without_a_barrier(fakes, monkeypatch):
     j6 = [b for b in BATCHES if b[0] == 6]
     assert sum(k for _, n, k in j6 if n >= 1) >= 60 and BATCHES.index((8, 1, 20)) < BATCHES.index(j6[-1])
     assert all(r.status == 0 for r in recs) and FakeSolve.live == 0
+
+
+def test_capacity_sized_solves_refit_and_finish(fakes, monkeypatch):
+    """With capacity_fraction the server admits by the smaller footprint; a
+    solve that outgrows its capacity freezes partway through a round (fewer
+    steps done than the round asked for), is moved to a larger arena when the
+    round ends (bytes in use updated, migration counted), and still runs
+    exactly its steps."""
+    class CapSolve(FakeSolve):
+        def __init__(self, g, f, prec, m, dt, w0, stream=None, capacity=0):
+            super().__init__(g, f, prec, m, dt, w0, stream)
+            self.capacity = capacity or self.N * self.N
+            self.nbytes_full = self.nbytes
+            FakeSolve.bytes_live -= self.nbytes
+            self.nbytes = self.nbytes // 4 if self.capacity < self.N * self.N else self.nbytes
+            FakeSolve.bytes_live += self.nbytes
+            self.freeze_at = 7 if self.J == 7 else None      # the J = 7 solves outgrow their capacity
+            self.frozen = False
+
+        def fit(self, stream=None):
+            if not self.frozen:
+                return False
+            FakeSolve.bytes_live += self.nbytes_full - self.nbytes
+            FakeSolve.peak_bytes = max(FakeSolve.peak_bytes, FakeSolve.bytes_live)
+            self.nbytes, self.capacity, self.frozen, self.freeze_at = self.nbytes_full, self.N * self.N, False, None
+            return True
+
+        def steps_done(self, stream=None):
+            return self.steps
+
+    def cap_batch(solves, nsteps, stream=None, fit=True):
+        assert not fit                                     # the server refits at the end of a round
+        BATCHES.append((solves[0].J, len(solves), nsteps[0]))
+        for s, k in zip(solves, nsteps):
+            if s.frozen:
+                continue
+            if s.freeze_at is not None and s.steps + k > s.freeze_at:
+                s.steps, s.frozen = s.freeze_at, True
+            else:
+                s.steps += k
+
+    monkeypatch.setattr(serve, "Solve", CapSolve)
+    monkeypatch.setattr(serve, "solve_batch", cap_batch)
+    monkeypatch.setattr(serve, "solve_footprint",
+                        lambda g, prec, m, capacity=0: FOOTPRINT[g.J] // (4 if capacity else 1))
+    reqs = [_req(0, 0.0, 7, 30), _req(1, 0.0, 6, 25), _req(2, 0.0, 7, 12), _req(3, 0.0, 8, 10)]
+    srv = serve.Server(hbm_budget=1200, round_steps=10, device="cpu", capacity_fraction=0.25)
+    recs = {r.rid: r for r in srv.run(reqs, realtime=False)}
+    assert all(r.status == 0 for r in recs.values())
+    assert all(recs[r.rid].evals == 21.0 * 10 * r.steps for r in reqs)     # exactly its steps
+    assert srv.migrations == 2                                              # both J = 7 solves
+    # admitted at a quarter of 1600 + 400 + 400 + 100 bytes, all resident at once
+    assert FakeSolve.peak >= 3 and srv.used == 0 and FakeSolve.live == 0
+    # admission keeps to the budget; a refit may take the bytes in use above it
+    # (the solve cannot go on in its old arena) by at most what the refits added
+    assert srv.peak_used <= 1200 + 2 * (400 - 100)
