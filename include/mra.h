@@ -105,7 +105,7 @@ typedef struct {
   int32_t* index_packed;     /* [capacity], first N_a valid                      */
   int32_t* index_fine;       /* [capacity], first N_a valid                      */
   int64_t* n_active;         /* device scalar (0 while the solve is frozen)      */
-  void* krylov_V;            /* [(m+1)][capacity] Arnoldi basis: double, or float for
+  void* krylov_V;            /* [(m+1)][basis_stride] Arnoldi basis: double, or float for
                                 precision MRA_FP32 (sums over it are FP64); after
                                 a step rows 0 .. m_eff-1 hold the orthonormal
                                 basis, the next row a work vector              */
@@ -116,6 +116,8 @@ typedef struct {
   int32_t* control;          /* [16] int: [0] m_eff, [1] done, [2] status, [8] 1
                                 while frozen, [9] the N_a a frozen regrid found  */
   int64_t capacity;          /* entries of the active-length arrays             */
+  int64_t basis_stride;      /* elements from one basis vector to the next
+                                (capacity plus a padding)                       */
 } mra_solve_ptrs;
 
 const char* mra_status_str(int32_t status);

@@ -34,7 +34,7 @@ class SolvePtrs(C.Structure):
     _fields_ = [("omega_active", C.c_void_p), ("mask", C.c_void_p), ("index_packed", C.c_void_p),
                 ("index_fine", C.c_void_p), ("n_active", C.c_void_p), ("krylov_V", C.c_void_p),
                 ("hessenberg", C.c_void_p), ("scalars", C.c_void_p), ("control", C.c_void_p),
-                ("capacity", C.c_int64)]
+                ("capacity", C.c_int64), ("basis_stride", C.c_int64)]
 
 
 EXPORTS = {

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   if (s.ctrl[C_DONE]) return;
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
-  const size_t Nf = (size_t)s.cap;   // basis stride
+  const size_t Nf = (size_t)s.vs;   // basis stride
   auto* W = glb(s.w);
   const auto* V = glb(vbasis<TV>(s));
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
     for (int r = threadIdx.x; r <= j; r += blockDim.x) hc[r] = ((r < j ? ga[r] : sc[1]) - u[r]) * sc[2];
   }
   const double ia = sc[2], kap = sc[1];
-  const size_t Nf = (size_t)s.cap;   // basis stride
+  const size_t Nf = (size_t)s.vs;   // basis stride
   const auto* W = glb(s.w);
   auto* V = glb(vbasis<TV>(s));
   auto* Vj = V + (size_t)j * Nf;
@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(256) k_update(Batch b, int mode) {
     s.scal[S_EVALS] += (double)(1 + k) * (double)na;
   }
   if (k <= 0) return;
-  const size_t Nf = (size_t)s.cap;   // basis stride
+  const size_t Nf = (size_t)s.vs;   // basis stride
   __shared__ double yy[kMaxM + 1];
   const double f = mode == 0 ? s.dt * s.scal[S_BETA] : 1.0;
   for (int i = threadIdx.x; i < k; i += blockDim.x) yy[i] = f * s.y[i];

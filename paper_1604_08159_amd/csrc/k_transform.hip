@@ -91,8 +91,8 @@ __global__ void __launch_bounds__(1024) k_prolong_coarse(Batch b, int target, in
     inv = first_scale(s, 0);
     if (threadIdx.x == 0) s.scal[S_INV] = inv;
   }
-  double* Vd = s.V ? s.V + (size_t)j * s.cap : nullptr;
-  float* Vf = s.V32 ? s.V32 + (size_t)j * s.cap : nullptr;
+  double* Vd = s.V ? s.V + (size_t)j * s.vs : nullptr;
+  float* Vf = s.V32 ? s.V32 + (size_t)j * s.vs : nullptr;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     const int fi = packed_to_fine(i, J, j0, nullptr);
     const int sub = ((fi >> J) / S) * n + (fi & (s.N - 1)) / S;
@@ -339,8 +339,8 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
   const int t = MRA_BX(b);
   const int x0 = (t % NTX) * B, y0 = (t / NTX) * B;
   T* f = dense_target<T>(s, target);
-  double* Vd = s.V ? s.V + (size_t)j * s.cap : nullptr;      // V_j, FP64 basis
-  float* Vf = s.V32 ? s.V32 + (size_t)j * s.cap : nullptr;   // V_j, FP32 basis
+  double* Vd = s.V ? s.V + (size_t)j * s.vs : nullptr;      // V_j, FP64 basis
+  float* Vf = s.V32 ? s.V32 + (size_t)j * s.vs : nullptr;   // V_j, FP32 basis
   const int pox = lat_origin<J, P, J0>(x0), poy = lat_origin<J, P, J0>(y0);
   // the coarsest lattice (all active, at most 256 nodes): rank and raw value
   // of this thread's node are fetched while the scale is being reduced

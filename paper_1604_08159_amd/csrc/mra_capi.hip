@@ -94,7 +94,11 @@ int prec_bulk(int32_t prec) { return prec == MRA_FP64 ? 0 : 1; }
 static std::atomic<int> g_tile_set[kMaxJ + 1][2][2];
 
 
-// Simple bump allocator over a caller buffer (null base = size query).
+// Simple bump allocator over a caller buffer (null base = size query).  Each
+// array is 256-byte aligned and followed by 4 KB, so that arrays of
+// power-of-two size do not all start on the same DRAM channel (the stencils
+// read six N^2 fields at the same node).
+constexpr size_t kStagger = 4096;
 struct Layout {
   char* base;
   size_t off = 0;
@@ -103,7 +107,7 @@ struct Layout {
   T* take(size_t count) {
     off = (off + 255) & ~size_t(255);
     T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += count * sizeof(T);
+    off += count * sizeof(T) + kStagger;
     return p;
   }
 };
@@ -120,6 +124,7 @@ void fill_geometry(SolveDev& s, const mra_grid_desc* g, int32_t prec) {
   s.tile = tile_choice(s.J, s.p, s.prec);
   s.ntx = s.N / s.tile;
   s.cap = s.N * s.N;
+  s.vs = s.cap + kBasisPad;
   s.length = g->length;
   s.h = g->length / s.N;
   s.eps = g->eps;
@@ -199,8 +204,9 @@ void solve_layout(Layout& L, SolveDev& s) {
   s.omega = L.take<double>(cap);
   s.V = nullptr;
   s.V32 = nullptr;
-  if (s.vb32) s.V32 = L.take<float>((size_t)(s.m + 1) * cap);
-  else s.V = L.take<double>((size_t)(s.m + 1) * cap);
+  s.vs = s.cap + kBasisPad;
+  if (s.vb32) s.V32 = L.take<float>((size_t)(s.m + 1) * s.vs);
+  else s.V = L.take<double>((size_t)(s.m + 1) * s.vs);
   s.w = L.take<double>(cap);
   s.H = L.take<double>((size_t)(s.m + 1) * s.m);
   s.hpart = L.take<double>(2 * (kMaxM + 1));
@@ -227,7 +233,7 @@ void solve_layout(Layout& L, SolveDev& s) {
   // after the residual (V_0 = F / beta is written by the first product's Pi),
   // when that holds N^2 doubles; else in a buffer of its own
   if (s.prec != 0) {
-    const size_t vbytes = (size_t)(s.m + 1) * cap * (s.vb32 ? 4 : 8);
+    const size_t vbytes = (size_t)(s.m + 1) * s.vs * (s.vb32 ? 4 : 8);
     s.res64 = vbytes >= Nf * 8 ? (s.V ? s.V : reinterpret_cast<double*>(s.V32)) : L.take<double>(Nf);
   }
 }
@@ -1079,6 +1085,7 @@ int32_t mra_solve_ptrs_get(mra_solve h, mra_solve_ptrs* out) {
   out->scalars = s.scal;
   out->control = s.ctrl;
   out->capacity = s.cap;
+  out->basis_stride = s.vs;
   return MRA_OK;
 }
 

@@ -29,6 +29,12 @@ constexpr int kTwN = 2048;          // twiddle table size (largest FFT length)
 enum Ctrl : int { C_MEFF = 0, C_DONE = 1, C_STATUS = 2, C_CNT0 = 4, C_CNT1 = 5, C_CNT2 = 6,
                   C_CNT3 = 7, C_OVER = 8, C_NEED = 9, C_NCTRL = 16 };
 constexpr int kStatusCapacity = 7;   // the status word's value for MRA_E_CAPACITY
+// Elements between consecutive basis vectors beyond the capacity: vectors of
+// a power-of-two length would all start on the same DRAM channel and bank,
+// and the Gram-Schmidt reads up to m + 1 of them at the same offset at once.
+// 4 KB of FP64 (a 2 x 2048^2 step: 23.14 -> 22.40 ms; 2 KB and 12 KB within
+// 0.5% of it).
+constexpr int kBasisPad = 512;
 enum Scal : int { S_BETA = 0, S_INV = 1, S_UMAX = 3, S_T = 4, S_EVALS = 5, S_STEPS = 6,
                   S_THETA = 7, S_COND = 8, S_NSCAL = 16 };
 
@@ -42,6 +48,7 @@ struct SolveDev {
   int smag_mode;
   int tile, ntx;            // stencil tile edge and tiles per side
   int cap;                  // capacity: length of the active-value arrays and basis vectors (<= Nf)
+  int vs;                   // stride of the basis vectors (cap, padded: kBasisPad)
   double h, length, eps, dt;
   double nu0, cs, s0, mu;
   // active set
@@ -55,8 +62,8 @@ struct SolveDev {
   unsigned long long* umax; // bits of max|u| (non-negative doubles order as integers)
   // Krylov (FP64 arithmetic)
   double* omega;            // [cap] active values
-  double* V;                // [(m+1)][cap] basis in FP64 (null when stored in FP32)
-  float* V32;               // [(m+1)][cap] basis in FP32, precision MRA_FP32 only (else null)
+  double* V;                // [(m+1)][vs] basis in FP64 (null when stored in FP32)
+  float* V32;               // [(m+1)][vs] basis in FP32, precision MRA_FP32 only (else null)
   double* w;                // [cap]
   double* H;                // [(m+1)][m]
   double* hpart;            // [2][kMaxM+1] first-pass Gram-Schmidt coefficients, by column parity

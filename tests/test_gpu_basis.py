@@ -63,7 +63,8 @@ def test_basis_orthonormal(M, case, prec):
     assert ctrl[2] == 0 and k == m_                        # no breakdown at these sizes
     nf = s.N * s.N
     vdt = torch.float32 if prec == "fp32" else torch.float64     # MRA_FP32 stores the basis in FP32
-    V = s._arena_view(p.krylov_V, (m_ + 1) * nf, vdt).view(m_ + 1, nf)[:k, :na].cpu().numpy().astype(np.float64)
+    vs = p.basis_stride
+    V = s._arena_view(p.krylov_V, (m_ + 1) * vs, vdt).view(m_ + 1, vs)[:k, :na].cpu().numpy().astype(np.float64)
     G = V @ V.T
     err = np.abs(G - np.eye(k)).max()
     print(f"  N_a {na}, max |V^T V - I| = {err:.2e}")
