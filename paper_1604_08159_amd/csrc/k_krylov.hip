@@ -38,27 +38,30 @@ namespace mra {
 // of the basis holds r_j, the residual of the first pass of column j - 1 (not
 // normalised and not yet reorthogonalised; for j = 0 the normalised v_0), and
 // the product w = A r_j is taken of it.  Column j:
-//   stage 1 (k_gs_dot)   g = V_{<j}^T w, c = r_j^T w, ||w||^2;
-//   stage 2 (k_gs_update), with s = V_{<j}^T r_j and ||r_j||^2 from the
-//     previous column's stage 2:
+//   stage 1 (k_gs_dot)   g = V_{<j}^T w, c = r_j^T w, ||w||^2, and
+//     s = V_{<j}^T r_j, ||r_j||^2;
+//   stage 2 (k_gs_update):
 //       alpha = ||r_j - V s|| = sqrt(||r_j||^2 - ||s||^2)      (Pythagoras)
 //       column j - 1 of H: h^(j-1) + s, and H[j][j-1] = alpha     (final)
 //       v_j = (r_j - V s) / alpha
 //       A v_j = (w - V_{<=j} u) / alpha,  u = H[0..j][0..j-1] s   (Arnoldi)
 //       h^(j) = V_{<=j}^T A v_j: (g_i - u_i) / alpha for i < j,
 //               (kappa - u_j) / alpha at j, kappa = (c - s^T g) / alpha
-//       r_{j+1} = A v_j - V_{<=j} h^(j) = (w - V g - kappa v_j) / alpha
-//     and on the fly the partials of V_{<=j}^T r_{j+1} and ||r_{j+1}||^2;
-//   after the last column, k_gs_last ends column m - 1 from those partials.
+//       r_{j+1} = A v_j - V_{<=j} h^(j) = (w - V g - kappa v_j) / alpha;
+//   the last column's stage 2 also sums V_{<m}^T r_m and ||r_m||^2 on the fly
+//   (r_m is not stored), and k_gs_last ends column m - 1 from them.
 // A breakdown of column j - 1 (alpha <= 1e-13 ||A v_{j-1}||, with
 // ||A v_{j-1}||^2 = ||h^(j-1)||^2 + ||r_j||^2) or a non-finite value ends the
 // basis at column j's stage 2 (m_eff = j).  The oracle's Arnoldi uses
 // modified Gram-Schmidt; in exact arithmetic the two give the same basis and
 // Hessenberg matrix.
 //
-// Partials: stage 1 writes buffer 0; stage 2 of column j reads buffer
-// 1 + ((j - 1) & 1) and writes 1 + (j & 1), so no kernel overwrites partials
-// that a block of the same kernel is still reading.  The first-pass
+// The second-pass sums of r_j (V_{<j}^T r_j, ||r_j||^2) are taken by column
+// j's stage 1, which reads V_{<j} and r_j for its own sums anyway; stage 2
+// then holds no sums of its own (except in the last column, for r_m).
+// Partials: stage 1 writes buffers 0 and 1, stage 2 reads them, the last
+// column's stage 2 writes buffer 2 for k_gs_last; no kernel overwrites
+// partials that a block of the same kernel is still reading.  The first-pass
 // coefficients h^(j) wait in hpart slot j & 1 until the next column ends them.
 
 // ||F||^2 partials (buffer 1).
@@ -76,7 +79,9 @@ __global__ void __launch_bounds__(256) k_norm0(Batch b) {
   }
 }
 
-// Stage 1: V_{<=j}^T w (slot j holding r_j) and ||w||^2 partials (buffer 0).
+// Stage 1: V_{<=j}^T w (slot j holding r_j) and ||w||^2 partials (buffer 0)
+// and, for j > 0, the second-pass sums of r_j, V_{<j}^T r_j and ||r_j||^2
+// (buffer 1), from the same loads.
 template <typename TV, int MJ, int JC>
 __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
@@ -89,26 +94,42 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   const auto* V = glb(vbasis<TV>(s));
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
-    double acc[MJ + 1];
+    double acc[MJ + 1], acs[MJ + 1];
 #pragma unroll
-    for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
+    for (int i = 0; i <= MJ; ++i) acc[i] = acs[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
       const double wk = W[k];
       TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) v[i] = V[i * Nf + k];
+      double rj = 0.0;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i == j) rj = (double)v[i];
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
         if (i <= j) acc[i] += (double)v[i] * wk;
       acc[MJ] += wk * wk;
+#pragma unroll
+      for (int i = 0; i < MJ; ++i)
+        if (i < j) acs[i] += (double)v[i] * rj;
+      acs[MJ] += rj * rj;
     }
-    // slot layout: g[0 .. j - 1], c at j, ||w||^2 at j + 1 (static register indices)
+    // slot layouts: g[0 .. j - 1], c at j, ||w||^2 at j + 1; s[0 .. j - 1],
+    // ||r_j||^2 at j (static register indices)
 #pragma unroll
     for (int i = 0; i < MJ; ++i)
       if (i == j + 1) acc[i] = acc[MJ];
+#pragma unroll
+    for (int i = 0; i < MJ; ++i)
+      if (i == j) acs[i] = acs[MJ];
     block_sums_store<MJ + 1>(acc, j + 2, part_buf(s, 0) + (size_t)ch * (kMaxM + 2));
     __syncthreads();
+    if (j > 0) {
+      block_sums_store<MJ + 1>(acs, j + 1, part_buf(s, 1) + (size_t)ch * (kMaxM + 2));
+      __syncthreads();
+    }
   }
 }
 
@@ -150,8 +171,10 @@ __device__ inline void write_column(const SolveDev& s, int jj, const double* sb,
   }
 }
 
-// Stage 2 (see above).
-template <typename TV, int MJ, int JC>
+// Stage 2 (see above).  ACC: the last column, which also sums the
+// second-pass partials of r_m for k_gs_last (buffer 2); the other columns'
+// r_{j+1} get theirs from the next column's stage 1.
+template <typename TV, int MJ, int JC, bool ACC>
 __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
   const int j = JC >= 0 ? JC : jrt;   // JC >= 0: the column is a compile-time constant
   const SolveDev& s = MRA_SOLVE(b);
@@ -172,10 +195,10 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
     Hs[q] = cidx < j - 1 ? s.H[r * m + cidx] : 0.0;
   }
   if (j > 0 && 2 * j + 3 <= 64) {
-    reduce_partials2(part_buf(s, 0), j + 2, ga, part_buf(s, 1 + ((j + 1) & 1)), j + 1, sb, nb);
+    reduce_partials2(part_buf(s, 0), j + 2, ga, part_buf(s, 1), j + 1, sb, nb);
   } else {
     reduce_partials<32>(part_buf(s, 0), nb, j + 2, ga);
-    if (j > 0) reduce_partials<32>(part_buf(s, 1 + ((j + 1) & 1)), nb, j + 1, sb);
+    if (j > 0) reduce_partials<32>(part_buf(s, 1), nb, j + 1, sb);
   }
   if (threadIdx.x == 0) {
     double al = 1.0;
@@ -229,13 +252,13 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
   const bool store_next = j + 1 < m;
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
-    double acc[MJ + 1];
+    double acc[ACC ? MJ + 1 : 1];
 #pragma unroll
-    for (int i = 0; i <= MJ; ++i) acc[i] = 0.0;
+    for (int i = 0; i < (ACC ? MJ + 1 : 1); ++i) acc[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
       // the coefficients sb, ga are read from LDS in every trip: held in
       // registers across the loop they would take 4 more per basis vector
-      // beside the loaded entries and the sums, and cut the waves per SIMD
+      // beside the loaded entries, and cut the waves per SIMD
       asm volatile("" ::: "memory");
       const double wk = W[k];
       TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
@@ -262,20 +285,24 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
       const double rn = (double)rns;
       if (j > 0) Vj[k] = vjs;
       if (store_next) Vn[k] = rns;
+      if constexpr (ACC) {
 #pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i < j) acc[i] += (double)v[i] * rn;
+        for (int i = 0; i < MJ; ++i)
+          if (i < j) acc[i] += (double)v[i] * rn;
 #pragma unroll
-      for (int i = 0; i < MJ; ++i)
-        if (i == j) acc[i] += vj * rn;
-      acc[MJ] += rn * rn;
+        for (int i = 0; i < MJ; ++i)
+          if (i == j) acc[i] += vj * rn;
+        acc[MJ] += rn * rn;
+      }
     }
-    // slot layout: V_{<=j}^T r_{j+1} at 0 .. j, ||r_{j+1}||^2 at j + 1
+    if constexpr (ACC) {
+      // slot layout: V_{<=j}^T r_{j+1} at 0 .. j, ||r_{j+1}||^2 at j + 1
 #pragma unroll
-    for (int i = 0; i < MJ; ++i)
-      if (i == j + 1) acc[i] = acc[MJ];
-    block_sums_store<MJ + 1>(acc, j + 2, part_buf(s, 1 + (j & 1)) + (size_t)ch * (kMaxM + 2));
-    __syncthreads();
+      for (int i = 0; i < MJ; ++i)
+        if (i == j + 1) acc[i] = acc[MJ];
+      block_sums_store<MJ + 1>(acc, j + 2, part_buf(s, 2) + (size_t)ch * (kMaxM + 2));
+      __syncthreads();
+    }
   }
 }
 
@@ -290,7 +317,7 @@ __global__ void __launch_bounds__(256) k_gs_last(Batch b) {
   __shared__ double sb[kMaxM + 2];
   __shared__ double al_sh;
   __shared__ int brk_sh, bad_sh;
-  reduce_partials<32>(part_buf(s, 1 + ((jj + 1) & 1)), nb, jj + 1, sb);
+  reduce_partials<32>(part_buf(s, 2), nb, jj + 1, sb);
   if (threadIdx.x == 0) {
     bool brk, bad;
     al_sh = end_column(s, jj, sb, &brk, &bad);
@@ -322,9 +349,10 @@ hipError_t launch_norm0(const Batch& b, const LaunchCfg& c, hipStream_t st) {
 }
 
 template <typename TV, int MJ, int JC>
-static void arnoldi_mj(const Batch& b, dim3 g, int j, hipStream_t st) {
+static void arnoldi_mj(const Batch& b, dim3 g, int j, bool last, hipStream_t st) {
   hipLaunchKernelGGL((k_gs_dot<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
-  hipLaunchKernelGGL((k_gs_update<TV, MJ, JC>), g, dim3(256), 0, st, b, j);
+  if (last) hipLaunchKernelGGL((k_gs_update<TV, MJ, JC, true>), g, dim3(256), 0, st, b, j);
+  else hipLaunchKernelGGL((k_gs_update<TV, MJ, JC, false>), g, dim3(256), 0, st, b, j);
 }
 
 // Columns j < kFixedCols run kernels instantiated for that column (exactly
@@ -332,15 +360,17 @@ static void arnoldi_mj(const Batch& b, dim3 g, int j, hipStream_t st) {
 // smallest register bucket holding m vectors with a run-time column.
 constexpr int kFixedCols = 24;
 template <typename TV, int... Js>
-static void arnoldi_fixed(const Batch& b, dim3 g, int j, hipStream_t st, std::integer_sequence<int, Js...>) {
-  (void)((j == Js ? (arnoldi_mj<TV, Js + 1, Js>(b, g, j, st), true) : false) || ...);
+static void arnoldi_fixed(const Batch& b, dim3 g, int j, bool last, hipStream_t st,
+                          std::integer_sequence<int, Js...>) {
+  (void)((j == Js ? (arnoldi_mj<TV, Js + 1, Js>(b, g, j, last, st), true) : false) || ...);
 }
 
 template <typename TV>
 static void arnoldi_t(const Batch& b, const LaunchCfg& c, dim3 g, int j, hipStream_t st) {
-  if (j < kFixedCols) arnoldi_fixed<TV>(b, g, j, st, std::make_integer_sequence<int, kFixedCols>{});
-  else if (c.m <= 32) arnoldi_mj<TV, 32, -1>(b, g, j, st);
-  else arnoldi_mj<TV, 48, -1>(b, g, j, st);
+  const bool last = j == c.m - 1;
+  if (j < kFixedCols) arnoldi_fixed<TV>(b, g, j, last, st, std::make_integer_sequence<int, kFixedCols>{});
+  else if (c.m <= 32) arnoldi_mj<TV, 32, -1>(b, g, j, last, st);
+  else arnoldi_mj<TV, 48, -1>(b, g, j, last, st);
 }
 
 hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t st) {
