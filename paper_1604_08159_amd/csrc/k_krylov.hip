@@ -356,9 +356,9 @@ static void arnoldi_mj(const Batch& b, dim3 g, int j, bool last, hipStream_t st)
 }
 
 // Columns j < kFixedCols run kernels instantiated for that column (exactly
-// j + 1 basis vectors, no per-vector predicates); later columns use the
-// smallest register bucket holding m vectors with a run-time column.
-constexpr int kFixedCols = 24;
+// j + 1 basis vectors, no per-vector predicates); later columns (m > 32) use
+// a register bucket of 48 vectors with a run-time column.
+constexpr int kFixedCols = 32;
 template <typename TV, int... Js>
 static void arnoldi_fixed(const Batch& b, dim3 g, int j, bool last, hipStream_t st,
                           std::integer_sequence<int, Js...>) {
@@ -369,7 +369,6 @@ template <typename TV>
 static void arnoldi_t(const Batch& b, const LaunchCfg& c, dim3 g, int j, hipStream_t st) {
   const bool last = j == c.m - 1;
   if (j < kFixedCols) arnoldi_fixed<TV>(b, g, j, last, st, std::make_integer_sequence<int, kFixedCols>{});
-  else if (c.m <= 32) arnoldi_mj<TV, 32, -1>(b, g, j, last, st);
   else arnoldi_mj<TV, 48, -1>(b, g, j, last, st);
 }
 
