@@ -177,33 +177,104 @@ __device__ inline int lat_origin(int x0) {
 // get the x-prediction of the y-predictions, the canonical order, and every
 // y-prediction is computed once per column instead of once per neighbour.
 // Active nodes then take their value.
-// Ranks of this thread's nodes of level L that are new at L (-1 for the
-// nodes of coarser levels and for slots past the lattice).
+//
+// Work is dealt in pairs: a node on the coarse lattice and the predicted node
+// after it (two rows of one column in pass 1, two columns of one row in pass
+// 2).  Both come from one window of 2P coarse values, the sample being the
+// window's entry P - 1, so no lane branches on parity and a pair costs one
+// window of loads.
+//
+// Pair geometry of level L along one axis: the level-L lattice starts at o
+// (n nodes, spacing SV), the level-(L - 1) lattice at po (pn nodes, spacing
+// 2 SV), and D = (o - po) / SV.  Pair jj holds lattice nodes 2 jj - e and
+// 2 jj + 1 - e (e = D & 1) and coarse node (D >> 1) + jj.  Where 2 SV <= B
+// every tile origin is a multiple of 2 SV, so D is a compile-time constant and
+// the pairs cover the lattice exactly; on coarser levels D varies with the
+// tile and one more pair is dealt.  A pair member outside the lattice (node
+// -1 or n) is computed from in-buffer values and lands in a padding column or
+// row that nothing reads as a value: lattice rows hold columns -1 .. n + 1
+// (stride n + 3) and P + 2 spare rows for the windows of such members; rows
+// of `half` hold the coarse columns and the reach of such a window (stride
+// pn + P + 1), and rows -1 .. n + 1.
+template <int J, int P, int L, int B> struct Lvl {
+  static constexpr int SH = J - L, SV = 1 << SH;
+  static constexpr int n = lat_count(J, P, B, 0, L), pn = lat_count(J, P, B, 0, L - 1);
+  static constexpr bool FIX = 2 * SV <= B;
+  static constexpr int D0 = (lat_floor(-lat_halo(J, P, L), SH) - lat_floor(-lat_halo(J, P, L - 1), SH + 1)) >> SH;
+  static constexpr int np = FIX ? ((D0 + n - 1) >> 1) - (D0 >> 1) + 1 : n / 2 + 1;
+  static constexpr int RS = n + 3, RSP = pn + 3, RH = pn + P + 1;
+};
+template <int J, int P, int L, int B>
+__device__ __forceinline__ int lvl_d(int x0) {
+  using G = Lvl<J, P, L, B>;
+  if constexpr (G::FIX) return G::D0;
+  else return (lat_origin<J, P, L>(x0) - lat_origin<J, P, L - 1>(x0)) >> G::SH;
+}
+// coarsest swept lattice (every node of it active) and the LDS of the sweep:
+// two lattice buffers (levels J0 .. J - 1; level J goes straight to the
+// output) and the half-predicted lattice of each level
+template <int P> constexpr int pi_j0() { return P == 2 ? 2 : 3; }
+template <int J, int P, int TB> constexpr int pi_buf_len() {
+  constexpr int B = (1 << J) < TB ? (1 << J) : TB;
+  int m = 1;
+  for (int l = pi_j0<P>(); l < J; ++l) {
+    const int n = lat_count(J, P, B, 0, l), len = (n + P + 2) * (n + 3);
+    m = len > m ? len : m;
+  }
+  return m;
+}
+template <int J, int P, int TB> constexpr int pi_half_len() {
+  constexpr int B = (1 << J) < TB ? (1 << J) : TB;
+  int m = 1;
+  for (int L = pi_j0<P>() + 1; L <= J; ++L) {
+    const int len = (lat_count(J, P, B, 0, L) + 3) * (lat_count(J, P, B, 0, L - 1) + P + 1);
+    m = len > m ? len : m;
+  }
+  return m;
+}
+// pass-2 pairs of level L per thread
+template <int J, int P, int L, int TB, int NT>
+__host__ __device__ constexpr int pair_slots() {
+  using G = Lvl<J, P, L, ((1 << J) < TB ? (1 << J) : TB)>;
+  return (G::n * G::np + NT - 1) / NT;
+}
+
+template <typename T> using vec2 = T __attribute__((ext_vector_type(2)));
+
+// Ranks of the two nodes of each of this thread's pass-2 pairs of level L (-1
+// for a node of a coarser level, a node outside the lattice, a slot past the
+// pairs).
 template <int S> struct Ranks {
-  int k[S];
+  int c[S], p[S];
 };
 template <int J, int P, int L, int TB, int NT>
-__host__ __device__ constexpr int lat_slots() {
-  constexpr int B = (1 << J) < TB ? (1 << J) : TB;
-  constexpr int n = lat_count(J, P, B, 0, L);
-  return (n * n + NT - 1) / NT;
-}
-template <int J, int P, int L, int TB, int NT>
-__device__ __forceinline__ Ranks<lat_slots<J, P, L, TB, NT>()> level_ranks(const SolveDev& s, int x0, int y0) {
+__device__ __forceinline__ Ranks<pair_slots<J, P, L, TB, NT>()> level_ranks(const SolveDev& s, int x0, int y0) {
   constexpr int N = 1 << J, NM = N - 1, B = N < TB ? N : TB;
-  constexpr int SH = J - L, SV = 1 << SH;
-  constexpr int n = lat_count(J, P, B, 0, L), NN = n * n, SLOTS = lat_slots<J, P, L, TB, NT>();
+  using G = Lvl<J, P, L, B>;
+  constexpr int NQ = G::n * G::np, S = pair_slots<J, P, L, TB, NT>();
   const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
+  const int ex = lvl_d<J, P, L, B>(x0) & 1;
   const auto* __restrict__ rank = glb(s.rank);
-  Ranks<SLOTS> r;
+  Ranks<S> r;
 #pragma unroll
-  for (int i = 0; i < SLOTS; ++i) {
+  for (int i = 0; i < S; ++i) {
     const int q = threadIdx.x + NT * i;
-    r.k[i] = -1;
-    if (q < NN) {
-      const int iy = q / n, ix = q - iy * n;
-      const int x = ox + (ix << SH), y = oy + (iy << SH);
-      if ((x | y) & SV) r.k[i] = rank[(y & NM) * N + (x & NM)];
+    r.c[i] = -1;
+    r.p[i] = -1;
+    if (NQ % NT == 0 || i + 1 < S || q < NQ) {
+      const int iy = q / G::np, jj = q - iy * G::np;
+      const int ixc = 2 * jj - ex;
+      const int y = oy + (iy << G::SH), xc = ox + (ixc << G::SH);
+      const int row = (y & NM) * N;
+      if constexpr (L == J) {
+        // the finest pair is two neighbours inside the tile, the first at an even x
+        const vec2<int> kk = *glb(reinterpret_cast<const vec2<int>*>(s.rank + row + xc));
+        r.c[i] = (y & 1) ? kk.x : -1;
+        r.p[i] = kk.y;
+      } else {
+        if ((y & G::SV) && ixc >= 0 && ixc < G::n) r.c[i] = rank[row + (xc & NM)];
+        if (ixc + 1 < G::n) r.p[i] = rank[row + ((xc + G::SV) & NM)];
+      }
     }
   }
   return r;
@@ -212,8 +283,8 @@ __device__ __forceinline__ Ranks<lat_slots<J, P, L, TB, NT>()> level_ranks(const
 // Raw source values of a level's new active nodes (before the first basis
 // vector's scale is applied): FP64, or FP32 for a basis stored in FP32.
 template <int S, bool FB> struct RawVals {
-  double d[S];
-  float f[FB ? S : 1];
+  double c[S], p[S];
+  float fc[FB ? S : 1], fp[FB ? S : 1];
 };
 template <int S, bool FB>
 __device__ __forceinline__ RawVals<S, FB> level_values(const SolveDev& s, const Ranks<S>& kr, int src,
@@ -223,99 +294,129 @@ __device__ __forceinline__ RawVals<S, FB> level_values(const SolveDev& s, const 
     // loaded raw: a conversion next to the load would wait for each in turn
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      rv.f[i] = 0.0f;
-      if (kr.k[i] >= 0) rv.f[i] = glb(Vf)[kr.k[i]];
+      rv.fc[i] = 0.0f;
+      rv.fp[i] = 0.0f;
+      if (kr.c[i] >= 0) rv.fc[i] = glb(Vf)[kr.c[i]];
+      if (kr.p[i] >= 0) rv.fp[i] = glb(Vf)[kr.p[i]];
     }
   } else {
     const double* base = src == 0 ? s.omega : (src == 2 ? s.vin : (src == 3 ? Vd : s.w));
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      rv.d[i] = 0.0;
-      if (kr.k[i] >= 0) rv.d[i] = glb(base)[kr.k[i]];
+      rv.c[i] = 0.0;
+      rv.p[i] = 0.0;
+      if (kr.c[i] >= 0) rv.c[i] = glb(base)[kr.c[i]];
+      if (kr.p[i] >= 0) rv.p[i] = glb(base)[kr.p[i]];
     }
   }
   return rv;
 }
 
+
 // The sweep keeps two levels of loads in flight: at level L the values of
 // level L + 1 (whose ranks arrived during level L - 1) and the ranks of level
 // L + 2 are issued before L's passes, so no global load sits on the path
 // between two levels.  kin, vin: ranks and raw values of level L; kn1: ranks
-// of level L + 1.
+// of level L + 1.  inv is uniform over the block (1 / beta for src 1).
 template <int J, int L> constexpr int lvl_cap() { return L < J ? L : J; }
 template <int P, typename T, int J, int L, bool FB, int TB, int NT>
-__device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[TB * TB], T* half, int cur, int x0,
-                                                 int y0, int src, double inv, double* Vd, float* Vf, T* f,
-                                                 const Ranks<lat_slots<J, P, L, TB, NT>()>& kin,
-                                                 const RawVals<lat_slots<J, P, L, TB, NT>(), FB>& vin,
-                                                 const Ranks<lat_slots<J, P, lvl_cap<J, L + 1>(), TB, NT>()>& kn1) {
+__device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[pi_buf_len<J, P, TB>()], T* half,
+                                                 int cur, int x0, int y0, int src, double inv, double* Vd, float* Vf,
+                                                 T* f, const Ranks<pair_slots<J, P, L, TB, NT>()>& kin,
+                                                 const RawVals<pair_slots<J, P, L, TB, NT>(), FB>& vin,
+                                                 const Ranks<pair_slots<J, P, lvl_cap<J, L + 1>(), TB, NT>()>& kn1) {
 #pragma clang fp contract(off)
   constexpr int N = 1 << J, B = N < TB ? N : TB;
-  constexpr int SH = J - L, SV = 1 << SH;  // node spacing of level L (fine units)
-  constexpr int n = lat_count(J, P, B, 0, L), pn = lat_count(J, P, B, 0, L - 1);
-  constexpr int NN = n * n, SLOTS = lat_slots<J, P, L, TB, NT>();
-  constexpr int NH = n * pn;
-  static_assert(NN <= TB * TB && SLOTS <= 16, "lattice of one level exceeds the tile buffer");
-  static_assert(NH <= TB * TB, "half-predicted lattice exceeds its buffer");
-  const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
-  const int pox = lat_origin<J, P, L - 1>(x0), poy = lat_origin<J, P, L - 1>(y0);
+  using G = Lvl<J, P, L, B>;
+  constexpr int SH = G::SH, SV = G::SV, n = G::n, pn = G::pn, np = G::np;
+  constexpr int RS = G::RS, RSP = G::RSP, RH = G::RH;
+  constexpr int N1 = np * pn, S1 = (N1 + NT - 1) / NT;               // pass 1: (row pair, coarse column)
+  constexpr int N2 = n * np, S2 = pair_slots<J, P, L, TB, NT>();     // pass 2: (row, column pair)
+  static_assert(S2 <= 16, "too many pairs of one level per thread");
+  static_assert(L == J || (n + P + 2) * RS <= pi_buf_len<J, P, TB>(), "lattice of one level exceeds its buffer");
+  static_assert((n + 3) * RH <= pi_half_len<J, P, TB>(), "half-predicted lattice exceeds its buffer");
+  static_assert(L < J || (G::FIX && (G::D0 & 1) == 0 && 2 * np == n), "finest pairs are neighbours in the tile");
   const T* prev = buf[cur];
   T* nxt = buf[cur ^ 1];
   constexpr int L1 = lvl_cap<J, L + 1>(), L2 = lvl_cap<J, L + 2>();
-  RawVals<lat_slots<J, P, L1, TB, NT>(), FB> vn1;
-  Ranks<lat_slots<J, P, L2, TB, NT>()> kn2;
-  if constexpr (L < J) vn1 = level_values<lat_slots<J, P, L1, TB, NT>(), FB>(s, kn1, src, Vd, Vf);
+  RawVals<pair_slots<J, P, L1, TB, NT>(), FB> vn1;
+  Ranks<pair_slots<J, P, L2, TB, NT>()> kn2;
+  if constexpr (L < J) vn1 = level_values<pair_slots<J, P, L1, TB, NT>(), FB>(s, kn1, src, Vd, Vf);
   if constexpr (L + 1 < J) kn2 = level_ranks<J, P, L2, TB, NT>(s, x0, y0);
-  // pass 1: level-L rows of the level-(L - 1) columns
-  for (int q = threadIdx.x; q < NH; q += NT) {
-    const int iy = q / pn, c = q - iy * pn;
-    const int dy = oy + (iy << SH) - poy;
-    T v;
-    if ((dy & SV) == 0) {
-      v = prev[(dy >> (SH + 1)) * pn + c];
-    } else {
-      const int bb = ((dy - SV) >> (SH + 1)) - (P - 1);
-      T cc[2 * P];
+  // pass 1: a sample row and a y-predicted row of one coarse column
+  {
+    const int dy = lvl_d<J, P, L, B>(y0);
+    const int jr0 = (dy >> 1) - (P - 1), ey = dy & 1;
 #pragma unroll
-      for (int o = 0; o < 2 * P; ++o) cc[o] = prev[(bb + o) * pn + c];
-      v = dd_pred<P, T>(cc);
-    }
-    half[q] = v;
-  }
-  __syncthreads();
-  // pass 2: every node of level L from its row of `half`
-#pragma unroll
-  for (int i = 0; i < SLOTS; ++i) {
-    const int q = threadIdx.x + NT * i;
-    if (q < NN) {
-      const int iy = q / n, ix = q - iy * n;
-      const int x = ox + (ix << SH), y = oy + (iy << SH);
-      const T* row = half + iy * pn;
-      const int dx = x - pox;
-      T v;
-      if ((dx & SV) == 0) {
-        v = row[dx >> (SH + 1)];
-      } else {
-        const int a = ((dx - SV) >> (SH + 1)) - (P - 1);
+    for (int i = 0; i < S1; ++i) {
+      const int q = threadIdx.x + NT * i;
+      if (N1 % NT == 0 || i + 1 < S1 || q < N1) {
+        const int rp = q / pn, c = q - rp * pn;
+        const T* w = prev + (jr0 + rp) * RSP + c + 1;
         T cc[2 * P];
 #pragma unroll
-        for (int o = 0; o < 2 * P; ++o) cc[o] = row[a + o];
-        v = dd_pred<P, T>(cc);
+        for (int o = 0; o < 2 * P; ++o) cc[o] = w[o * RSP];
+        T* h = half + (2 * rp - ey + 1) * RH + c;
+        h[0] = cc[P - 1];
+        h[RH] = dd_pred<P, T>(cc);
       }
-      if (kin.k[i] >= 0) {
-        if (FB && src == 3) {
-          v = (T)vin.f[i];
-        } else {
-          const double av = src == 1 ? (inv == 0.0 ? 0.0 : vin.d[i] * inv) : vin.d[i];
-          v = (T)av;
-          if (src == 1 && inv != 0.0 && x >= x0 && x < x0 + B && y >= y0 && y < y0 + B) {
-            if constexpr (FB) glb(Vf)[kin.k[i]] = (float)av;
-            else glb(Vd)[kin.k[i]] = av;
+    }
+  }
+  __syncthreads();
+  // pass 2: a sample and an x-predicted node of one level-L row
+  const int dx = lvl_d<J, P, L, B>(x0);
+  const int jc0 = (dx >> 1) - (P - 1), ex = dx & 1;
+  const bool s1 = src == 1, keep = s1 && inv != 0.0;
+  const bool fsrc = FB && src == 3;
+#pragma unroll
+  for (int i = 0; i < S2; ++i) {
+    const int q = threadIdx.x + NT * i;
+    if (N2 % NT == 0 || i + 1 < S2 || q < N2) {
+      const int iy = q / np, jj = q - iy * np;
+      const T* w = half + (iy + 1) * RH + jc0 + jj;
+      T cc[2 * P];
+#pragma unroll
+      for (int o = 0; o < 2 * P; ++o) cc[o] = w[o];
+      T vc = cc[P - 1], vp = dd_pred<P, T>(cc);
+      const int ixc = 2 * jj - ex;
+      // active nodes take their value
+      T ac, ap;
+      if (fsrc) {
+        ac = (T)vin.fc[i];
+        ap = (T)vin.fp[i];
+      } else {
+        double dc = vin.c[i], dp = vin.p[i];
+        if (s1) {
+          dc = inv == 0.0 ? 0.0 : dc * inv;
+          dp = inv == 0.0 ? 0.0 : dp * inv;
+        }
+        ac = (T)dc;
+        ap = (T)dp;
+        if (keep) {
+          // the first basis vector, at this tile's own nodes
+          const int ox = lat_origin<J, P, L>(x0), oy = lat_origin<J, P, L>(y0);
+          const int y = oy + (iy << SH), xc = ox + (ixc << SH), xp = xc + SV;
+          const bool rin = y >= y0 && y < y0 + B;
+          if (kin.c[i] >= 0 && rin && xc >= x0 && xc < x0 + B) {
+            if constexpr (FB) glb(Vf)[kin.c[i]] = (float)dc;
+            else glb(Vd)[kin.c[i]] = dc;
+          }
+          if (kin.p[i] >= 0 && rin && xp >= x0 && xp < x0 + B) {
+            if constexpr (FB) glb(Vf)[kin.p[i]] = (float)dp;
+            else glb(Vd)[kin.p[i]] = dp;
           }
         }
       }
-      if constexpr (L == J) glb(f)[(y0 + q / B) * N + x0 + (q % B)] = v;   // finest lattice = the tile
-      else nxt[q] = v;
+      vc = kin.c[i] >= 0 ? ac : vc;
+      vp = kin.p[i] >= 0 ? ap : vp;
+      if constexpr (L == J) {
+        // finest lattice = the tile; the pair is two neighbours, the first at an even x
+        *glb(reinterpret_cast<vec2<T>*>(f + (y0 + iy) * N + x0 + ixc)) = vec2<T>{vc, vp};
+      } else {
+        T* o = nxt + iy * RS + ixc + 1;
+        o[0] = vc;
+        o[1] = vp;
+      }
     }
   }
   if constexpr (L < J) {
@@ -325,16 +426,24 @@ __device__ __forceinline__ void prolong_level_ct(const SolveDev& s, T (*buf)[TB 
   }
 }
 
+// 1 / beta of the first basis vector, the same in every lane
+__device__ inline double lane_uniform(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <int P, typename T, int J, bool FB, int TB = pi_tile<T>(), int NT = pi_threads<T>()>
 __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int src, int j) {
 #pragma clang fp contract(off)
   constexpr int N = 1 << J, NM = N - 1, B = N < TB ? N : TB, NTX = N / B;
-  constexpr int J0 = P == 2 ? 2 : 3;
-  constexpr int pn = lat_count(J, P, B, 0, J0), SH0 = J - J0;
+  constexpr int J0 = pi_j0<P>();
+  constexpr int pn = lat_count(J, P, B, 0, J0), SH0 = J - J0, RS0 = pn + 3;
   static_assert(pn * pn <= NT, "coarsest lattice exceeds one node per thread");
   static_assert(lat_count(J, P, B, 0, J) == B, "finest lattice is the tile");
-  __shared__ T buf[2][TB * TB];
-  __shared__ T half[TB * TB];
+  __shared__ T buf[2][pi_buf_len<J, P, TB>()];
+  __shared__ T half[pi_half_len<J, P, TB>()];
   const SolveDev& s = MRA_SOLVE(b);
   const int t = MRA_BX(b);
   const int x0 = (t % NTX) * B, y0 = (t / NTX) * B;
@@ -345,15 +454,16 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
   // the coarsest lattice (all active, at most 256 nodes): rank and raw value
   // of this thread's node are fetched while the scale is being reduced
   const bool has0 = (int)threadIdx.x < pn * pn;
-  int x0n = 0, y0n = 0, k0n = 0;
+  int x0n = 0, y0n = 0, k0n = 0, q0 = 0;
   double raw = 0.0;
   // the first two swept levels' ranks, in flight meanwhile
   const auto k1 = level_ranks<J, P, J0 + 1, TB, NT>(s, x0, y0);
-  Ranks<lat_slots<J, P, lvl_cap<J, J0 + 2>(), TB, NT>()> k2;
+  Ranks<pair_slots<J, P, lvl_cap<J, J0 + 2>(), TB, NT>()> k2;
   if constexpr (J0 + 1 < J) k2 = level_ranks<J, P, J0 + 2, TB, NT>(s, x0, y0);
   if (has0) {
     const int q = threadIdx.x;
     const int iy = q / pn, ix = q - iy * pn;
+    q0 = iy * RS0 + ix + 1;
     x0n = pox + (ix << SH0);
     y0n = poy + (iy << SH0);
     k0n = glb(s.rank)[(y0n & NM) * N + (x0n & NM)];
@@ -361,7 +471,7 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
                    : (src == 2 ? glb(s.vin)[k0n]
                                : (src == 3 ? (FB ? (double)glb(Vf)[k0n] : glb(Vd)[k0n]) : glb(s.w)[k0n]));
   }
-  const double inv = src == 1 ? first_scale(s, t) : 0.0;
+  const double inv = src == 1 ? lane_uniform(first_scale(s, t)) : 0.0;
   if (has0) {
     double a = raw;
     if (src == 1) {
@@ -371,9 +481,9 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
         else glb(Vd)[k0n] = a;
       }
     }
-    buf[0][threadIdx.x] = (T)a;
+    buf[0][q0] = (T)a;
   }
-  const auto v1 = level_values<lat_slots<J, P, J0 + 1, TB, NT>(), FB>(s, k1, src, Vd, Vf);
+  const auto v1 = level_values<pair_slots<J, P, J0 + 1, TB, NT>(), FB>(s, k1, src, Vd, Vf);
   __syncthreads();
   prolong_level_ct<P, T, J, J0 + 1, FB, TB, NT>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f, k1, v1, k2);
 }
