@@ -90,19 +90,21 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
   const int na = (int)*s.n_active;
   const int nb = nchunks(na);
   const size_t Nf = (size_t)s.vs;   // basis stride
-  auto* W = glb(s.w);
-  const auto* V = glb(vbasis<TV>(s));
+  const unsigned vst = (unsigned)(Nf * sizeof(TV));
+  const auto rV = buf_rsrc(vbasis<TV>(s), (size_t)(s.m + 1) * Nf * sizeof(TV));
+  const auto rW = buf_rsrc(s.w, (size_t)s.cap * sizeof(double));
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
     double acc[MJ + 1], acs[MJ + 1];
 #pragma unroll
     for (int i = 0; i <= MJ; ++i) acc[i] = acs[i] = 0.0;
     for (int k = c.lo + (int)threadIdx.x; k < c.hi; k += blockDim.x) {
-      const double wk = W[k];
+      const double wk = buf_ld<double>(rW, (unsigned)k * 8u, 0u);
+      const unsigned ko = (unsigned)k * (unsigned)sizeof(TV);
       TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) v[i] = V[i * Nf + k];
+        if (i <= j) v[i] = buf_ld<TV>(rV, ko, (unsigned)i * vst);
       double rj = 0.0;
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
@@ -136,15 +138,21 @@ __global__ void __launch_bounds__(256) k_gs_dot(Batch b, int jrt) {
 // The end of column jj - 1 from the partials of V_{<jj}^T r_jj and
 // ||r_jj||^2 (in sb, ||r_jj||^2 at jj) and its first-pass coefficients
 // (hpart slot (jj - 1) & 1): alpha, and the breakdown and non-finite tests
-// against ||A v_{jj-1}||.  Thread 0; *brk when the basis ends at column
-// jj - 1, *bad when a value is not finite.
+// against ||A v_{jj-1}||.  Called by the first wavefront (lane i takes term i
+// of both sums; jj <= kMaxM + 1 <= 64), every lane gets the result; *brk when
+// the basis ends at column jj - 1, *bad when a value is not finite.
 __device__ inline double end_column(const SolveDev& s, int jj, const double* sb, bool* brk, bool* bad) {
+  static_assert(kMaxM + 1 <= 64, "one lane per coefficient");
   const double* hp = s.hpart + (size_t)((jj - 1) & 1) * (kMaxM + 1);
+  const int lane = threadIdx.x & 63;
   double ss = 0.0, hh = 0.0;
-  for (int i = 0; i < jj; ++i) {
-    ss += sb[i] * sb[i];
-    hh += hp[i] * hp[i];
+  if (lane < jj) {
+    const double a = sb[lane], h = hp[lane];
+    ss = a * a;
+    hh = h * h;
   }
+  ss = wave_sum(ss);
+  hh = wave_sum(hh);
   const double a = sb[jj];
   *bad = !isfinite(a) || !isfinite(ss) || !isfinite(hh);
   const double al = *bad ? 0.0 : sqrt(fmax(a - ss, 0.0));
@@ -183,6 +191,11 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
   const int nb = nchunks(na);
   if ((int)MRA_BX(b) >= nb) return;
   const int m = s.m;
+  // the buffer resources, formed while every value they take is uniform
+  const size_t Nf = (size_t)s.vs;   // basis stride
+  const unsigned vst = (unsigned)(Nf * sizeof(TV));
+  const auto rV = buf_rsrc(vbasis<TV>(s), (size_t)(m + 1) * Nf * sizeof(TV));
+  const auto rW = buf_rsrc(s.w, (size_t)s.cap * sizeof(double));
   __shared__ double ga[kMaxM + 2];               // g[0 .. j - 1], c, ||w||^2
   __shared__ double sb[kMaxM + 2];               // s[0 .. j - 1], ||r_j||^2
   __shared__ double Hs[(kMaxM + 1) * kMaxM];     // H[0..j][0..j-1], column j - 1 made final
@@ -200,15 +213,17 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
     reduce_partials<32>(part_buf(s, 0), nb, j + 2, ga);
     if (j > 0) reduce_partials<32>(part_buf(s, 1), nb, j + 1, sb);
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     double al = 1.0;
     bool brk = false, bad = false;
     if (j > 0) al = end_column(s, j, sb, &brk, &bad);
-    bad |= !isfinite(ga[j + 1]);        // the product of r_j
-    sc[0] = al;
-    sc[2] = al > 0.0 ? 1.0 / al : 0.0;
-    brk_sh = brk || bad;
-    bad_sh = bad;
+    if (threadIdx.x == 0) {
+      bad |= !isfinite(ga[j + 1]);        // the product of r_j
+      sc[0] = al;
+      sc[2] = al > 0.0 ? 1.0 / al : 0.0;
+      brk_sh = brk || bad;
+      bad_sh = bad;
+    }
   }
   __syncthreads();
   if (MRA_BX(b) == 0) {
@@ -228,14 +243,17 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
   }
   __syncthreads();
   for (int r = threadIdx.x; r <= j; r += blockDim.x) {
+    // row r of the Hessenberg H[0..j][0..j-1] starts at column r - 1
     double t = 0.0;
-    for (int i = r > 0 ? r - 1 : 0; i < j; ++i) t += Hs[r * j + i] * sb[i];
+#pragma unroll
+    for (int i = 0; i < MJ; ++i)
+      if (i + 1 >= r && i < j) t += Hs[r * j + i] * sb[i];
     u[r] = t;
   }
-  if (threadIdx.x == 0) {
-    double sg = 0.0;
-    for (int i = 0; i < j; ++i) sg += sb[i] * ga[i];
-    sc[1] = (ga[j] - sg) * sc[2];
+  if (threadIdx.x >= 64 && threadIdx.x < 128) {
+    const int lane = threadIdx.x - 64;
+    const double sg = wave_sum(lane < j ? sb[lane] * ga[lane] : 0.0);
+    if (lane == 0) sc[1] = (ga[j] - sg) * sc[2];
   }
   __syncthreads();
   // first-pass coefficients of column j, kept until the next column ends it
@@ -244,11 +262,6 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
     for (int r = threadIdx.x; r <= j; r += blockDim.x) hc[r] = ((r < j ? ga[r] : sc[1]) - u[r]) * sc[2];
   }
   const double ia = sc[2], kap = sc[1];
-  const size_t Nf = (size_t)s.vs;   // basis stride
-  const auto* W = glb(s.w);
-  auto* V = glb(vbasis<TV>(s));
-  auto* Vj = V + (size_t)j * Nf;
-  auto* Vn = V + (size_t)(j + 1) * Nf;
   const bool store_next = j + 1 < m;
   for (int ch = MRA_BX(b); ch < nb; ch += MRA_GX(b)) {
     const Chunk c = chunk_of(na, ch);
@@ -260,11 +273,12 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
       // registers across the loop they would take 4 more per basis vector
       // beside the loaded entries, and cut the waves per SIMD
       asm volatile("" ::: "memory");
-      const double wk = W[k];
+      const double wk = buf_ld<double>(rW, (unsigned)k * 8u, 0u);
+      const unsigned ko = (unsigned)k * (unsigned)sizeof(TV);
       TV v[MJ];   // raw loads: a conversion here would wait for each load in turn
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
-        if (i <= j) v[i] = V[i * Nf + k];
+        if (i <= j) v[i] = buf_ld<TV>(rV, ko, (unsigned)i * vst);
       double rj = 0.0;
 #pragma unroll
       for (int i = 0; i < MJ; ++i)
@@ -283,8 +297,8 @@ __global__ void __launch_bounds__(256) k_gs_update(Batch b, int jrt) {
       q -= kap * vj;
       const TV rns = (TV)(q * ia);
       const double rn = (double)rns;
-      if (j > 0) Vj[k] = vjs;
-      if (store_next) Vn[k] = rns;
+      if (j > 0) buf_st<TV>(rV, ko, (unsigned)j * vst, vjs);
+      if (store_next) buf_st<TV>(rV, ko, (unsigned)(j + 1) * vst, rns);
       if constexpr (ACC) {
 #pragma unroll
         for (int i = 0; i < MJ; ++i)
@@ -318,11 +332,14 @@ __global__ void __launch_bounds__(256) k_gs_last(Batch b) {
   __shared__ double al_sh;
   __shared__ int brk_sh, bad_sh;
   reduce_partials<32>(part_buf(s, 2), nb, jj + 1, sb);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     bool brk, bad;
-    al_sh = end_column(s, jj, sb, &brk, &bad);
-    brk_sh = brk;
-    bad_sh = bad;
+    const double al = end_column(s, jj, sb, &brk, &bad);
+    if (threadIdx.x == 0) {
+      al_sh = al;
+      brk_sh = brk;
+      bad_sh = bad;
+    }
   }
   __syncthreads();
   write_column(s, jj, sb, al_sh, brk_sh, bad_sh);

@@ -235,6 +235,34 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
+// Vector memory through a buffer resource.  Element k of vector i of a basis
+// (stride `stride` bytes) is at byte i * stride + k * sizeof(T): the vector's
+// offset is a scalar register and the element's offset one vector register
+// shared by every vector, so a loop over the basis spends no address
+// arithmetic per vector and no register pair per address.  The resource
+// covers `bytes` (below 2 GiB for every basis: (kMaxM + 1) vectors of at most
+// 2^22 + kBasisPad doubles); an access past it reads zero and writes nothing.
+constexpr int kBufWord3 = 0x00020000;   // 32-bit data format, no swizzle, no stride
+static_assert((long long)(kMaxM + 1) * ((1 << 22) + kBasisPad) * 8 < (1ll << 31), "basis exceeds a buffer resource");
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, T v) {
+  if constexpr (sizeof(T) == 8) {
+    using R = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(R, v), r, voff, soff, 0);
+  } else {
+    using R = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(R, v), r, voff, soff, 0);
+  }
+}
+
 // The Krylov basis is stored in FP64, or in FP32 for solves of precision
 // MRA_FP32 (every sum over it stays FP64 either way; the FP32 products take
 // the basis vectors rounded to FP32 in both cases).
