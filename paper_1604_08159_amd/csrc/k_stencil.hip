@@ -73,6 +73,20 @@ struct Region {
       }
     }
   }
+  // the same through a buffer resource over an N x N field, N = 2^J: one
+  // offset register per element and no 64-bit address
+  __device__ inline void fetch_buf(__amdgpu_buffer_rsrc_t rs, int x0, int y0, int J) {
+    const int nm = (1 << J) - 1;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      if (q < W * W) {
+        const int r = q / W, c = q - r * W;
+        const unsigned f = ((unsigned)((y0 + r) & nm) << J) + (unsigned)((x0 + c) & nm);
+        v[i] = buf_ld<T>(rs, f * (unsigned)sizeof(T), 0u);
+      }
+    }
+  }
   __device__ inline void put(T* dst) const {
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -300,7 +314,12 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   using G = Geo<P>;
   extern __shared__ unsigned char smem[];
   const SolveDev& s = MRA_SOLVE(b);
-  const int N = s.N, ntx = s.ntx, nm = N - 1;
+  const int N = s.N, J = s.J, ntx = s.ntx, nm = N - 1;
+  // the fields through buffer resources (N x N each, formed while uniform)
+  const size_t fbytes = (size_t)N * N * sizeof(T);
+  const auto rU = buf_rsrc(s.u, fbytes), rV = buf_rsrc(s.v, fbytes), rW = buf_rsrc(s.wt, fbytes);
+  const auto rVt = buf_rsrc(s.vt, fbytes), rNu = buf_rsrc(s.nu, fbytes), rUv = buf_rsrc(s.uv, fbytes);
+  const auto rVv = buf_rsrc(s.vv, fbytes), rR = buf_rsrc(s.rank, (size_t)N * N * sizeof(int));
   const int tile = tile_of_block(MRA_BX(b), ntx * ntx, b.n);
   const int done = s.ctrl[C_DONE], cnt = s.tile_count[tile];
   if (done || cnt == 0) return;
@@ -321,11 +340,6 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
   T* np = wl + Ww * Ww;
   T* cp = np + Wn * Wn;
   const bool ex = EX && s.smag_mode == 2;
-  const T* gu = reinterpret_cast<const T*>(s.u);
-  const T* gv = reinterpret_cast<const T*>(s.v);
-  const T* guv = reinterpret_cast<const T*>(s.uv);
-  const T* gvv = reinterpret_cast<const T*>(s.vv);
-  const T* gw = reinterpret_cast<const T*>(s.wt);
   T ur[NQ], vr[NQ], wr[NQ], uvr[EX ? NQ : 1], vvr[EX ? NQ : 1];
   int kr[NO];
 #pragma unroll
@@ -333,26 +347,28 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
     const int q = threadIdx.x + 256 * i;
     if (q < Ww * Ww) {
       const int r = q / Ww, c = q - r * Ww;
-      const int f = ((y0 - G::R1 + r) & nm) * N + ((x0 - G::R1 + c) & nm);
-      ur[i] = gu[f];
-      vr[i] = gv[f];
-      wr[i] = gw[f];
+      const unsigned f = ((unsigned)((y0 - G::R1 + r) & nm) << J) + (unsigned)((x0 - G::R1 + c) & nm);
+      const unsigned fo = f * (unsigned)sizeof(T);
+      ur[i] = buf_ld<T>(rU, fo, 0u);
+      vr[i] = buf_ld<T>(rV, fo, 0u);
+      wr[i] = buf_ld<T>(rW, fo, 0u);
       if constexpr (EX) {
-        uvr[i] = guv[f];
-        vvr[i] = gvv[f];
+        uvr[i] = buf_ld<T>(rUv, fo, 0u);
+        vvr[i] = buf_ld<T>(rVv, fo, 0u);
       }
     }
   }
 #pragma unroll
   for (int i = 0; i < NO; ++i) {
     const int q = threadIdx.x + 256 * i;
-    kr[i] = q < TS * TS ? s.rank[(y0 + q / TS) * N + x0 + (q % TS)] : -1;
+    const unsigned f = ((unsigned)(y0 + q / TS) << J) + (unsigned)(x0 + (q % TS));
+    kr[i] = q < TS * TS ? buf_ld<int>(rR, f * 4u, 0u) : -1;
   }
   {
-    Region<Ww, T> rvt;
     Region<Wn, T> rnu;
-    rvt.fetch(reinterpret_cast<const T*>(s.vt), x0 - G::R1, y0 - G::R1, N);
-    rnu.fetch(reinterpret_cast<const T*>(s.nu), x0 - P, y0 - P, N);
+    Region<Ww, T> rvt;
+    rvt.fetch_buf(rVt, x0 - G::R1, y0 - G::R1, J);
+    rnu.fetch_buf(rNu, x0 - P, y0 - P, J);
     if constexpr (EX) {
       if (ex) {
         Region<Wn, T> rnp;
@@ -363,7 +379,7 @@ __global__ void __launch_bounds__(256) k_jvp(Batch b) {
       rnu.put(nu);
     } else {
       Region<Ww, T> rps;
-      rps.fetch(guv, x0 - G::R1, y0 - G::R1, N);
+      rps.fetch_buf(rUv, x0 - G::R1, y0 - G::R1, J);
       rvt.put(vt);
       rnu.put(nu);
       rps.put(ps);
