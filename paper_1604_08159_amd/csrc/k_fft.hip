@@ -472,7 +472,10 @@ __global__ void __launch_bounds__(NT) k_fft_rows_inv(Batch b, int src) {
   extern __shared__ unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
   const SolveDev& s = MRA_SOLVE(b);
-  const int y0 = MRA_BX(b) * R;
+  // row blocks in XCD-aware order: the blocks that read the two 64-byte
+  // halves of a 128-byte line of the transposed spectrum share an L2 (the
+  // forward pass, which writes such halves, measured slower in this order)
+  const int y0 = tile_of_block(MRA_BX(b), N / R, b.n) * R;
   constexpr int twN = kTwN / N;
   constexpr int NP = (M / 2 + 1) * R, PP = (NP + NT - 1) / NT;
   TwSet<T, G::LGM, 0> ts;

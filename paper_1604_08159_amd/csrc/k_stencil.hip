@@ -96,17 +96,6 @@ struct Region {
   }
 };
 
-// XCD-aware tile order.  Block L of a batch of n solves runs on XCD L % 8
-// and serves solve L % n as its block L / n, so one solve's blocks are spread
-// over nx = 8 / gcd(n, 8) XCDs, its block bx landing on XCD group bx % nx.
-// Give each of those XCDs a contiguous run of tiles so that shared halos stay
-// in its L2 (nx = 1: plain order).
-__device__ inline int tile_of_block(int bid, int ntiles, int nbatch) {
-  int g = nbatch & 7;
-  const int nx = g == 0 ? 1 : (g == 4 ? 2 : (g == 2 || g == 6 ? 4 : 8));
-  if (nx == 1 || ntiles % nx != 0) return bid;
-  return (bid % nx) * (ntiles / nx) + bid / nx;
-}
 
 template <int P> struct Geo {
   static constexpr int R1 = 2 * P - 2;   // D1 reach

@@ -109,6 +109,18 @@ struct Batch {
 #define MRA_GX(b) ((int)(gridDim.x / (b).n))
 
 // ------------------------------------------------------------------ helpers
+// XCD-aware order of tiles (or row blocks).  Block L of a batch of n solves
+// runs on XCD L % 8 and serves solve L % n as its block L / n, so one solve's
+// blocks are spread over nx = 8 / gcd(n, 8) XCDs, its block bx landing on XCD
+// group bx % nx.  Give each of those XCDs a contiguous run of tiles so that
+// shared halos (or shared cache lines) stay in its L2 (nx = 1: plain order).
+__device__ inline int tile_of_block(int bid, int ntiles, int nbatch) {
+  int g = nbatch & 7;
+  const int nx = g == 0 ? 1 : (g == 4 ? 2 : (g == 2 || g == 6 ? 4 : 8));
+  if (nx == 1 || ntiles % nx != 0) return bid;
+  return (bid % nx) * (ntiles / nx) + bid / nx;
+}
+
 __host__ __device__ inline int ilog2(unsigned v) { return 31 - __builtin_clz(v); }
 __host__ __device__ inline int ntz(unsigned v) { return __builtin_ctz(v); }
 
