@@ -445,7 +445,9 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
   __shared__ T buf[2][pi_buf_len<J, P, TB>()];
   __shared__ T half[pi_half_len<J, P, TB>()];
   const SolveDev& s = MRA_SOLVE(b);
-  const int t = MRA_BX(b);
+  // tiles in XCD-aware order: neighbours, which read each other's halo ranks
+  // and values, share an L2
+  const int t = tile_of_block(MRA_BX(b), NTX * NTX, b.n);
   const int x0 = (t % NTX) * B, y0 = (t / NTX) * B;
   T* f = dense_target<T>(s, target);
   double* Vd = s.V ? s.V + (size_t)j * s.vs : nullptr;      // V_j, FP64 basis
