@@ -191,11 +191,11 @@ __device__ inline int lat_origin(int x0) {
 // every tile origin is a multiple of 2 SV, so D is a compile-time constant and
 // the pairs cover the lattice exactly; on coarser levels D varies with the
 // tile and one more pair is dealt.  A pair member outside the lattice (node
-// -1 or n) is computed from in-buffer values and lands in a padding column or
-// row that nothing reads as a value: lattice rows hold columns -1 .. n + 1
-// (stride n + 3) and P + 2 spare rows for the windows of such members; rows
-// of `half` hold the coarse columns and the reach of such a window (stride
-// pn + P + 1), and rows -1 .. n + 1.
+// -1, n or n + 1) is computed from in-buffer values and lands in a padding
+// column or row that nothing reads as a value: lattice rows hold columns
+// -1 .. n + 1 (stride n + 3) and P + 2 spare rows for the windows of such
+// members; rows of `half` hold the coarse columns and the reach of such a
+// window (stride pn + P + 1), and rows -1 .. n + 1.
 template <int J, int P, int L, int B> struct Lvl {
   static constexpr int SH = J - L, SV = 1 << SH;
   static constexpr int n = lat_count(J, P, B, 0, L), pn = lat_count(J, P, B, 0, L - 1);
