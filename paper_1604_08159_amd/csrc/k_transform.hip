@@ -473,6 +473,22 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
                    : (src == 2 ? glb(s.vin)[k0n]
                                : (src == 3 ? (FB ? (double)glb(Vf)[k0n] : glb(Vd)[k0n]) : glb(s.w)[k0n]));
   }
+  // A tile whose every node is active needs no sweep: each node takes its own
+  // value.  Its stencil tiles (edge s.tile, dividing B) are then full.  On
+  // grids of 1024^2 and up where most nodes are active, their counts are
+  // loaded once the sweep's first loads are out and read after its first
+  // barrier; elsewhere no tile is checked (on smaller grids the check's code
+  // cost the sparse sweep more than it saved).
+  constexpr bool kFullPath = J >= 10;
+  __shared__ int tfull[kFullPath ? 64 : 1];
+  const int ts = s.tile, nq = ts > 0 && B % ts == 0 ? B / ts : 0;
+  bool cand = false;
+  if constexpr (kFullPath) cand = nq > 0 && nq * nq <= 64 && 2 * *s.n_active > (int64_t)N * N;
+  int tcv = 0;
+  if (cand && (int)threadIdx.x < nq * nq) {
+    const int a = threadIdx.x / nq, c = threadIdx.x - a * nq;
+    tcv = glb(s.tile_count)[(y0 / ts + a) * s.ntx + x0 / ts + c];
+  }
   const double inv = src == 1 ? lane_uniform(first_scale(s, t)) : 0.0;
   if (has0) {
     double a = raw;
@@ -486,7 +502,38 @@ __global__ void __launch_bounds__(NT) k_prolong_tiles(Batch b, int target, int s
     buf[0][q0] = (T)a;
   }
   const auto v1 = level_values<pair_slots<J, P, J0 + 1, TB, NT>(), FB>(s, k1, src, Vd, Vf);
+  if (cand && (int)threadIdx.x < nq * nq) tfull[threadIdx.x] = tcv == ts * ts;
   __syncthreads();
+  bool full = cand;
+  for (int i = 0; i < nq * nq && full; ++i) full = tfull[i] != 0;
+  if (kFullPath && full) {
+    // every rank, then every value, then the stores: a store between them
+    // would order each load after it (the pointers may alias)
+    constexpr int PT = (B * B + NT - 1) / NT;
+    const auto* rank = glb(s.rank);
+    const int nmine = (B * B - (int)threadIdx.x + NT - 1) / NT;   // nodes of this thread
+    int fi[PT], kk[PT];
+    double a[PT];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int i = threadIdx.x + u * NT;
+      fi[u] = (y0 + i / B) * N + x0 + i % B;
+      if (u < nmine) kk[u] = rank[fi[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < PT; ++u)
+      if (u < nmine) a[u] = (FB && src == 3) ? (double)glb(Vf)[kk[u]] : active_value(s, src, kk[u], inv, Vd);
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      if (u >= nmine) break;
+      if (src == 1 && inv != 0.0) {
+        if constexpr (FB) glb(Vf)[kk[u]] = (float)a[u];
+        else glb(Vd)[kk[u]] = a[u];
+      }
+      glb(f)[fi[u]] = (T)a[u];
+    }
+    return;
+  }
   prolong_level_ct<P, T, J, J0 + 1, FB, TB, NT>(s, buf, half, 0, x0, y0, src, inv, Vd, Vf, f, k1, v1, k2);
 }
 

@@ -105,12 +105,14 @@ def _active_inputs(u, J, p, eps):
 
 @pytest.mark.parametrize("p,J,eps", [(2, 5, 1e-3), (2, 8, 1e-4), (3, 7, 1e-3), (2, 6, 0.0), (2, 9, 1e-4),
                                      (3, 9, 1e-3), (2, 10, 1e-3), (3, 8, 0.0), (2, 11, 1e-3), (3, 11, 1e-3),
-                                     (3, 11, 1e-2)])
+                                     (3, 11, 1e-2), (2, 10, 0.0), (3, 11, 3e-4)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_prolong(M, p, J, eps, prec):
     """Pi at every node against the oracle: FP64 bit-exact, FP32 within 2e-6
     of the scale.  J = 11 takes the largest grid, where the coarse levels'
-    pair offsets vary from tile to tile."""
+    pair offsets vary from tile to tile; (2, 10, 0) and (3, 11, 3e-4) have
+    more than half of the nodes active, where tiles whose every node is active
+    skip the level sweep (all of them at eps = 0, some at 3e-4)."""
     N = 1 << J
     u = _field(N, 4)
     mask, ip, fi = _active_inputs(u, J, p, eps)
