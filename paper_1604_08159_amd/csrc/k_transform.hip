@@ -654,18 +654,18 @@ hipError_t launch_reset_max(const Batch& b, hipStream_t st) {
 }
 
 // src: 0 -> dense64 (double), 1 -> wt (T).  dst: 0 -> packed64 (double),
-// 1 -> spec reinterpreted as a packed T array.
+// 1 -> spec reinterpreted as a packed T array.  One thread per packed node
+// below nlim (the levels below those of k_forward_tiles).
 template <int P, typename T>
-__global__ void __launch_bounds__(256) k_forward(Batch b, int src, int dst) {
+__global__ void __launch_bounds__(256) k_forward(Batch b, int src, int dst, int nlim) {
 #pragma clang fp contract(off)
   const SolveDev& s = MRA_SOLVE(b);
   const auto* f = glb(src == 0 ? reinterpret_cast<const T*>(s.dense64) : reinterpret_cast<const T*>(s.wt));
   auto* out = glb(dst == 0 ? reinterpret_cast<T*>(s.packed64) : reinterpret_cast<T*>(s.spec));
   const int J = s.J, j0 = s.j0, N = s.N;
-  const int Nf = N * N;
   const int i = MRA_BX(b) * blockDim.x + threadIdx.x;
   double am = 0.0;
-  if (i < Nf) {
+  if (i < nlim) {
     int l;
     const int fi = packed_to_fine(i, J, j0, &l);
     const T val = f[fi];
@@ -683,18 +683,121 @@ __global__ void __launch_bounds__(256) k_forward(Batch b, int src, int dst) {
   }
 }
 
-hipError_t launch_forward(const Batch& b, const LaunchCfg& c, int src, int dst, hipStream_t st) {
-  const int nf = 1 << (2 * c.J);
-  dim3 g(((nf + 255) / 256) * b.n);
-  const bool dbl = src == 0 || c.prec == 0;
-  if (dbl) {
-    if (c.p == 2) hipLaunchKernelGGL((k_forward<2, double>), g, dim3(256), 0, st, b, src, dst);
-    else hipLaunchKernelGGL((k_forward<3, double>), g, dim3(256), 0, st, b, src, dst);
-  } else {
-    if (c.p == 2) hipLaunchKernelGGL((k_forward<2, float>), g, dim3(256), 0, st, b, src, dst);
-    else hipLaunchKernelGGL((k_forward<3, float>), g, dim3(256), 0, st, b, src, dst);
+// The three finest levels (98% of the nodes), tile by tile: the dense field
+// of a TS x TS tile and the reach of its predictions (H = (2P - 1) 2^(J - LT)
+// for the coarsest of those levels, LT) is staged in LDS once, and every node
+// of the tile at a level >= LT takes its detail from there, with the
+// arithmetic of predict_node (a node's parity from its global coordinates,
+// its neighbours at the same offsets in the tile's window).  The max |f| is
+// taken over every node of the tile.
+template <int P> constexpr int fwd_lt(int J) {
+  return J - 2 > pi_j0<P>() + 1 ? J - 2 : pi_j0<P>() + 1;
+}
+template <int P, typename T, int J>
+__global__ void __launch_bounds__(256) k_forward_tiles(Batch b, int src, int dst) {
+#pragma clang fp contract(off)
+  constexpr int N = 1 << J, NM = N - 1, J0 = pi_j0<P>(), LT = fwd_lt<P>(J);
+  constexpr int TS = N < 32 ? N : 32, NTX = N / TS;
+  constexpr int H = (2 * P - 1) << (J - LT), W = TS + 2 * H;
+  __shared__ T reg[W * W];
+  const SolveDev& s = MRA_SOLVE(b);
+  const auto* f = glb(src == 0 ? reinterpret_cast<const T*>(s.dense64) : reinterpret_cast<const T*>(s.wt));
+  auto* out = glb(dst == 0 ? reinterpret_cast<T*>(s.packed64) : reinterpret_cast<T*>(s.spec));
+  const int t = tile_of_block(MRA_BX(b), NTX * NTX, b.n);
+  const int x0 = (t % NTX) * TS, y0 = (t / NTX) * TS;
+  constexpr int NR = (W * W + 255) / 256;
+  T v[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    if (q < W * W) {
+      const int r = q / W, c = q - r * W;
+      v[i] = f[((y0 - H + r) & NM) * N + ((x0 - H + c) & NM)];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    if (q < W * W) reg[q] = v[i];
+  }
+  __syncthreads();
+  double am = 0.0;
+  for (int q = threadIdx.x; q < TS * TS; q += 256) {
+    const int ly = q / TS, lx = q - ly * TS;
+    const int x = x0 + lx, y = y0 + ly;
+    const int cx = lx + H, cy = ly + H;
+    const T val = reg[cy * W + cx];
+    am = fmax(am, isfinite((double)val) ? fabs((double)val) : __builtin_huge_val());
+    const int xy = x | y;
+    const int l = xy == 0 ? J0 : (J - ntz((unsigned)xy) > J0 ? J - ntz((unsigned)xy) : J0);
+    if (l < LT) continue;
+    // predict_node's arithmetic on the window (same neighbours, same order)
+    const int sv = 1 << (J - l), S = 2 * sv;
+    const bool ox = (x & sv) != 0, oy = (y & sv) != 0;
+    T c[2 * P];
+    T pred;
+    if (ox && !oy) {
+      const int a = cx - sv - (P - 1) * S;
+#pragma unroll
+      for (int o = 0; o < 2 * P; ++o) c[o] = reg[cy * W + a + o * S];
+      pred = dd_pred<P, T>(c);
+    } else if (oy && !ox) {
+      const int a = cy - sv - (P - 1) * S;
+#pragma unroll
+      for (int o = 0; o < 2 * P; ++o) c[o] = reg[(a + o * S) * W + cx];
+      pred = dd_pred<P, T>(c);
+    } else {
+      T py[2 * P];
+      const int ax = cx - sv - (P - 1) * S, ay = cy - sv - (P - 1) * S;
+#pragma unroll
+      for (int o2 = 0; o2 < 2 * P; ++o2) {
+#pragma unroll
+        for (int o = 0; o < 2 * P; ++o) c[o] = reg[(ay + o * S) * W + ax + o2 * S];
+        py[o2] = dd_pred<P, T>(c);
+      }
+      pred = dd_pred<P, T>(py);
+    }
+    out[fine_to_packed(x, y, l, J, J0)] = val - pred;
+  }
+  __shared__ double red[4];
+  am = warp_max(am);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = am;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(s.umax, (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+template <int P, typename T>
+static hipError_t forward_p(const Batch& b, int J, int src, int dst, hipStream_t st) {
+  const int j0 = pi_j0<P>();
+  if (J <= j0 || J > 11) return hipErrorInvalidValue;
+  // coarse levels: one thread per packed node below level LT
+  const int lt = J - 2 > j0 + 1 ? J - 2 : j0 + 1;
+  const int nlim = 1 << (2 * (lt - 1));
+  hipLaunchKernelGGL((k_forward<P, T>), dim3(((nlim + 255) / 256) * b.n), dim3(256), 0, st, b, src, dst, nlim);
+  const int N = 1 << J, TS = N < 32 ? N : 32;
+  const dim3 g((N / TS) * (N / TS) * b.n);
+  switch (J) {
+    case 3: if constexpr (P == 2) { hipLaunchKernelGGL((k_forward_tiles<P, T, 3>), g, dim3(256), 0, st, b, src, dst); break; } return hipErrorInvalidValue;
+    case 4: hipLaunchKernelGGL((k_forward_tiles<P, T, 4>), g, dim3(256), 0, st, b, src, dst); break;
+    case 5: hipLaunchKernelGGL((k_forward_tiles<P, T, 5>), g, dim3(256), 0, st, b, src, dst); break;
+    case 6: hipLaunchKernelGGL((k_forward_tiles<P, T, 6>), g, dim3(256), 0, st, b, src, dst); break;
+    case 7: hipLaunchKernelGGL((k_forward_tiles<P, T, 7>), g, dim3(256), 0, st, b, src, dst); break;
+    case 8: hipLaunchKernelGGL((k_forward_tiles<P, T, 8>), g, dim3(256), 0, st, b, src, dst); break;
+    case 9: hipLaunchKernelGGL((k_forward_tiles<P, T, 9>), g, dim3(256), 0, st, b, src, dst); break;
+    case 10: hipLaunchKernelGGL((k_forward_tiles<P, T, 10>), g, dim3(256), 0, st, b, src, dst); break;
+    case 11: hipLaunchKernelGGL((k_forward_tiles<P, T, 11>), g, dim3(256), 0, st, b, src, dst); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_forward(const Batch& b, const LaunchCfg& c, int src, int dst, hipStream_t st) {
+  const bool dbl = src == 0 || c.prec == 0;
+  if (dbl) return c.p == 2 ? forward_p<2, double>(b, c.J, src, dst, st) : forward_p<3, double>(b, c.J, src, dst, st);
+  return c.p == 2 ? forward_p<2, float>(b, c.J, src, dst, st) : forward_p<3, float>(b, c.J, src, dst, st);
 }
 
 // ---------------------------------------------------------------- threshold
