@@ -404,10 +404,14 @@ hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t
 // polynomial: ||A/2^s||_1 <= 1/2 bounds the truncation by 1e-22 relative.
 constexpr int kTaylor = 18;
 
+// C = A B (K x K, LDS).  The sum over l keeps its order; unrolled, the LDS
+// loads of eight terms are issued before their products, so a term no longer
+// waits for its own loads.
 __device__ void mat_mul(const double* A, const double* B, double* C, int K) {
   for (int q = threadIdx.x; q < K * K; q += blockDim.x) {
     const int i = q / K, j = q - i * K;
     double t = 0.0;
+#pragma unroll 8
     for (int l = 0; l < K; ++l) t += A[i * K + l] * B[l * K + j];
     C[q] = t;
   }
