@@ -77,6 +77,34 @@ def test_basis_orthonormal(M, case, prec):
     s.close()
 
 
+def test_basis_orthonormal_largest(M):
+    """The largest grid and the largest Krylov dimension (m = 47): the basis
+    then spans its whole buffer resource, and columns 32 .. 46 run the
+    run-time-column kernels."""
+    pb = dataclasses.replace(W.three_vortex(), noise_seed=37440)
+    m_ = 47
+    s = M.Solve(M.grid_desc(pb.J, pb.p, pb.eps), M.flow_desc(pb.nu0, pb.cs), M.MRA_MIXED, m_, pb.dt,
+                torch.from_numpy(W.initial_field(pb)).to(DEV))
+    print(f"three-vortex 2048^2 mixed: 2 steps, m = {m_}", flush=True)
+    s.step(1)
+    p = s.ptrs()
+    torch.cuda.synchronize()
+    na = int(s._arena_view(p.n_active, 1, torch.int64).item())
+    s.step(1)
+    torch.cuda.synchronize()
+    ctrl = s._arena_view(p.control, 16, torch.int32).cpu().numpy()
+    k = int(ctrl[0])
+    assert ctrl[2] == 0 and k == m_
+    vs = p.basis_stride
+    V = s._arena_view(p.krylov_V, (m_ + 1) * vs, torch.float64).view(m_ + 1, vs)[:k, :na].cpu().numpy()
+    err = np.abs(V @ V.T - np.eye(k)).max()
+    print(f"  N_a {na}, max |V^T V - I| = {err:.2e}")
+    assert err <= 1e-12
+    H = s._arena_view(p.hessenberg, (m_ + 1) * m_, torch.float64).view(m_ + 1, m_).cpu().numpy()
+    assert np.all(np.isfinite(H[:k + 1, :k])) and np.all(np.array([H[j + 1, j] for j in range(k)]) > 0)
+    s.close()
+
+
 def test_fp32_basis_steps_match_oracle(M):
     """Two steps of a 512^2 Fujiwhara solve with the basis stored in FP32
     against the FP64 oracle, at the mixed-precision bar (1e-5 relative L2)."""
