@@ -1,5 +1,5 @@
 """The Arnoldi basis the GPU builds is orthonormal over the active set, at
-full size and in both precisions.  This holds at any size and for every
+full size and in every precision.  This holds at any size and for every
 column: each column's second Gram-Schmidt pass is taken in the next column's
 reads of the basis, and the last column's from the partial sums of its own
 update, so every stored vector must be orthogonal to rounding level.  The
@@ -34,6 +34,9 @@ def M():
 CASES = {
     "fujiwhara512": lambda: W.fujiwhara_pair(1000),
     "three256_noise": lambda: W.three_vortex(J=8),
+    # 1024^2 with noise: nearly every node active, so the prolongation's
+    # full-tile path writes and reads the basis in all three precisions
+    "three1024_noise": lambda: W.three_vortex(J=10),
 }
 
 
