@@ -181,3 +181,18 @@ def test_capacity_footprint_and_checks(lib):
     assert lib.mra_solve_init_cap(C.byref(g), None, 2, 20, 0.01, None, 4096, None, 0, None,
                                   C.byref(C.c_void_p()), None) != 0
     assert lib.mra_status_str(7) == b"active set exceeds the solve's capacity"
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library every entry of the binding raises: there is
+    no CPU path behind it."""
+    import paper_1604_08159_amd as m
+    from paper_1604_08159_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libmra.so"))
+    monkeypatch.setattr(m, "_LIB", None)
+    with pytest.raises(ImportError):
+        _lib.load()
+    with pytest.raises(ImportError):
+        m.lib()
+    with pytest.raises(ImportError):
+        m.solve_footprint(m.grid_desc(7, 2, 1e-4), m.MRA_FP64, 10)
