@@ -402,7 +402,19 @@ hipError_t launch_arnoldi(const Batch& b, const LaunchCfg& c, int j, hipStream_t
 // y = phi_1(dt H_k) e_1 = last column of exp([[dt H_k, e_1], [0, 0]]) (first
 // k entries), k = m_eff.  exp by scaling and squaring of a degree-18 Taylor
 // polynomial: ||A/2^s||_1 <= 1/2 bounds the truncation by 1e-22 relative.
+// The polynomial is evaluated in the Paterson-Stockmeyer form (Paterson and
+// Stockmeyer 1973): with X = A^3 and B_k = c_3k I + c_3k+1 A + c_3k+2 A^2,
+// p(A) = B_0 + X (B_1 + X (B_2 + X (B_3 + X (B_4 + X (B_5 + c_18 X))))),
+// seven matrix products (A^2, A^3 and five in X) instead of Horner's 17.
 constexpr int kTaylor = 18;
+struct TaylorCoef {
+  double c[kTaylor + 1];
+  constexpr TaylorCoef() : c() {
+    c[0] = 1.0;
+    for (int i = 1; i <= kTaylor; ++i) c[i] = c[i - 1] / i;
+  }
+};
+static_assert(kTaylor == 18, "the evaluation below is written for degree 3 * 6");
 
 // C = A B (K x K, LDS).  The sum over l keeps its order; unrolled, the LDS
 // loads of eight terms are issued before their products, so a term no longer
@@ -424,6 +436,8 @@ __global__ void __launch_bounds__(256) k_phi1(Batch b) {
   if (k <= 0) return;
   const int K = k + 1, m = s.m;
   __shared__ double A[(kMaxM + 1) * (kMaxM + 1)];
+  __shared__ double A2[(kMaxM + 1) * (kMaxM + 1)];
+  __shared__ double X[(kMaxM + 1) * (kMaxM + 1)];
   __shared__ double Pm[(kMaxM + 1) * (kMaxM + 1)];
   __shared__ double Tm[(kMaxM + 1) * (kMaxM + 1)];
   __shared__ double colsum[kMaxM + 1];
@@ -453,18 +467,23 @@ __global__ void __launch_bounds__(256) k_phi1(Batch b) {
   }
   __syncthreads();
   const double scale = ldexp(1.0, -sc);
+  for (int q = threadIdx.x; q < K * K; q += blockDim.x) A[q] *= scale;
+  __syncthreads();
+  constexpr TaylorCoef tc;
+  mat_mul(A, A, A2, K);
+  mat_mul(A2, A, X, K);
+  // Pm = B_5 + c_18 X, then Pm = B_k + X Pm for k = 4 .. 0
   for (int q = threadIdx.x; q < K * K; q += blockDim.x) {
-    A[q] *= scale;
     const int i = q / K, j = q - i * K;
-    Pm[q] = (i == j ? 1.0 : 0.0) + A[q] / kTaylor;
+    Pm[q] = (i == j ? tc.c[15] : 0.0) + tc.c[16] * A[q] + tc.c[17] * A2[q] + tc.c[18] * X[q];
   }
   __syncthreads();
-  for (int d = kTaylor - 1; d >= 1; --d) {
-    mat_mul(A, Pm, Tm, K);
-    const double inv = 1.0 / d;
+  for (int kb = 4; kb >= 0; --kb) {
+    mat_mul(X, Pm, Tm, K);
+    const double c0 = tc.c[3 * kb], c1 = tc.c[3 * kb + 1], c2 = tc.c[3 * kb + 2];
     for (int q = threadIdx.x; q < K * K; q += blockDim.x) {
       const int i = q / K, j = q - i * K;
-      Pm[q] = (i == j ? 1.0 : 0.0) + Tm[q] * inv;
+      Pm[q] = (i == j ? c0 : 0.0) + c1 * A[q] + c2 * A2[q] + Tm[q];
     }
     __syncthreads();
   }
