@@ -401,6 +401,7 @@ def ensemble_leg(args, with_cpu: bool = True) -> dict:
         s.close()
         log(f"fp64 per-solve J={J}: {per_step[J] * 1e3:.2f} ms/step")
     fp64_total = sum(per_step[pb.J] * pb.steps for pb in probs)
+    accuracy = ensemble_accuracy(m, W, probs)
     cpu = ensemble_cpu_baseline(probs) if with_cpu else None
     out = ({"workload": f"ensemble of {len(probs)} two-vortex solves, finest 128^2..1024^2, "
                                   f"{args.ens_steps} steps each, mixed precision, one GPU",
@@ -410,10 +411,43 @@ def ensemble_leg(args, with_cpu: bool = True) -> dict:
                                              "sec_per_step_by_J": per_step,
                                              "note": "one warmed solve per size timed over 8 steps, "
                                                      "applied to every solve's step count"},
+                      "accuracy_vs_fp64_gpu": accuracy,
                       "autotune": tuned, "capacity_sized": cap_rec,
                       "cpu_baseline": cpu})
     untune_tiles(tuned)
     return out
+
+
+def ensemble_accuracy(m, W, probs) -> dict:
+    """The first solve of each grid size of the ensemble over its full step
+    count, mixed precision (the tiles the ensemble ran with) against the FP64
+    GPU path on the same problem: vorticity, energy and enstrophy, and the
+    active sets."""
+    import torch
+    rows = {}
+    worst = 0.0
+    for J in sorted({pb.J for pb in probs}):
+        pb = next(q for q in probs if q.J == J)
+        st = torch.cuda.Stream()
+        res = {}
+        for name, prec in (("fp64", m.MRA_FP64), ("mixed", m.MRA_MIXED)):
+            with torch.cuda.stream(st):
+                s = m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m, pb.dt,
+                            torch.from_numpy(W.initial_field(pb)).cuda(), stream=st)
+            s.step(pb.steps, stream=st)
+            dense, diag = s.read(stream=st)
+            _, mask, _, _ = s.active_set()
+            res[name] = (dense.cpu().numpy(), diag, mask.cpu().numpy())
+            s.close()
+        a, da, ma = res["fp64"]
+        b, db, mb = res["mixed"]
+        row = {"steps": pb.steps, "eps": pb.eps, **compare_fields(a, b, da, db),
+               "mask_flips": int((ma != mb).sum()), "n_active_fp64": int(da["n_active"])}
+        worst = max(worst, row["rel_l2_vorticity"], row["rel_energy"], row["rel_enstrophy"])
+        rows[str(1 << J)] = row
+        log(f"ensemble accuracy {1 << J}^2: rel L2 {row['rel_l2_vorticity']:.2e}, flips {row['mask_flips']}")
+    return {"by_finest_size": rows, "worst": worst, "tolerance": 1e-5, "within": worst <= 1e-5,
+            "note": "the first solve of each size, its full step count, mixed against FP64 on the GPU"}
 
 
 def run_ensemble(args) -> int:
