@@ -25,7 +25,8 @@ in the same JSON line:
                   residual and product against the oracle;
   sub-records     the 512^2 Fujiwhara batch of 24 (with its accuracy against
                   the oracle after the timed steps and its 2000-step drift),
-                  the 256-solve ensemble (solves/s against the FP64 per-solve
+                  the 2048^2 configuration's 5000-step drift (mixed against
+                  FP64, beside a perturbed FP64 run), the 256-solve ensemble (solves/s against the FP64 per-solve
                   GPU path and the oracle), and the serving configuration's
                   request mix (p50 / p99 latency at 70% of capacity).
 
@@ -1042,6 +1043,61 @@ def adapted_leg(args, m, W, dev) -> dict:
     return out
 
 
+def run_drift_three(args) -> int:
+    import torch
+    import workloads as W
+    import paper_1604_08159_amd as m
+    print(json.dumps(drift_three_leg(m, W, torch.device("cuda:0"), args.long_steps3)))
+    return 0
+
+
+def drift_three_leg(m, W, dev, steps: int) -> dict:
+    """The three-vortex 2048^2 configuration over its full length for noise
+    seed 37440: one solve in mixed precision against one in FP64, both on the
+    GPU, and beside it an FP64 solve whose initial field carries relative
+    white noise of 1e-10 against the same FP64 run (the threshold's own
+    sensitivity), compared every 100 steps up to step 1000 and every 500
+    after (vorticity, energy, enstrophy, mask flips)."""
+    import torch
+    pb = W.three_vortex()
+    w0 = W.initial_field(pb)
+    w0p = w0 * (1.0 + 1e-10 * np.random.default_rng(7).standard_normal(w0.shape))
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        mk = lambda prec, w: m.Solve(m.grid_desc(pb.J, pb.p, pb.eps), m.flow_desc(pb.nu0, pb.cs), prec, pb.m,
+                                     pb.dt, torch.from_numpy(w).to(dev), stream=stream)
+        runs = {"fp64": mk(m.MRA_FP64, w0), "mixed": mk(m.MRA_MIXED, w0), "perturbed_fp64": mk(m.MRA_FP64, w0p)}
+    t0 = time.perf_counter()
+    curve, done = [], 0
+    first_flip = {"mixed": None, "perturbed_fp64": None}
+    while done < steps:
+        k = min(100 if done < 1000 else 500, steps - done)
+        m.solve_batch(list(runs.values()), [k] * len(runs), stream=stream)
+        done += k
+        got = {}
+        for name, sv in runs.items():
+            dense, diag = sv.read(stream=stream)
+            got[name] = (dense.cpu().numpy(), diag, sv.active_set()[1].cpu().numpy())
+        a, da, ma = got["fp64"]
+        row = {"step": done, "n_active_fp64": int(da["n_active"])}
+        for name in ("mixed", "perturbed_fp64"):
+            b, db, mb = got[name]
+            row[name] = {**compare_fields(a, b, da, db), "mask_flips": int((ma != mb).sum())}
+            if row[name]["mask_flips"] and first_flip[name] is None:
+                first_flip[name] = done
+        curve.append(row)
+        log(f"step {done}: mixed {row['mixed']['rel_l2_vorticity']:.2e} ({row['mixed']['mask_flips']} flips), "
+            f"perturbed FP64 {row['perturbed_fp64']['rel_l2_vorticity']:.2e} "
+            f"({row['perturbed_fp64']['mask_flips']} flips), N_a {row['n_active_fp64']} "
+            f"({time.perf_counter() - t0:.0f} s)")
+    for sv in runs.values():
+        sv.close()
+    return {"workload": f"three vortices Re=37440 + noise (seed 37440), 2048^2, 6-point DD, m=30, dt=0.002, "
+                        f"{steps} steps; mixed against FP64 on the GPU",
+            "reference": "the FP64 GPU path", "final": curve[-1], "first_flip_by": first_flip, "tolerance": 1e-5,
+            "curve": curve, "seconds": time.perf_counter() - t0}
+
+
 def drift_leg(m, W, dev, steps: int, every: int = 100) -> dict:
     """Mixed precision against FP64 over the Fujiwhara configuration's full
     length for one seed, both on the GPU (the FP64 GPU path is pinned to the
@@ -1179,6 +1235,8 @@ def run_default(args) -> int:
             out["fujiwhara512"] = pair_leg(args, m, W, dev, tmp.name, r2)
         out["drift_fujiwhara512"] = drift_leg(m, W, dev, args.long_steps)
         log("drift leg done")
+        out["drift_three2048"] = drift_three_leg(m, W, dev, args.long_steps3)
+        log("2048^2 drift leg done")
         out["adapted_fujiwhara512"] = adapted_leg(args, m, W, dev)
         log("adapted leg done")
         out["ensemble"] = ensemble_leg(args, not args.no_cpu)
@@ -1194,7 +1252,7 @@ def run_default(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["default", "fujiwhara", "adapted", "ensemble", "serving", "vapor", "three2048",
-                                           "longrun", "implicit", "families", "serving_spec", "condensation"],
+                                           "longrun", "implicit", "families", "serving_spec", "condensation", "drift_three"],
                     default="default",
                     help="default: the three-vortex 2048^2 headline with every sub-record")
     ap.add_argument("--no-sub", action="store_true", help="default workload: the headline only")
@@ -1208,6 +1266,7 @@ def main() -> int:
     ap.add_argument("--prec3", choices=["mixed", "fp32"], default="mixed",
                     help="three2048: fp32 stores the Krylov basis in FP32")
     ap.add_argument("--long-steps", type=int, default=2000)
+    ap.add_argument("--long-steps3", type=int, default=5000, help="drift_three: steps of the 2048^2 run")
     ap.add_argument("--fam-steps", type=int, default=0, help="0: up to 37.5 h")
     ap.add_argument("--spec-requests", type=int, default=24)
     ap.add_argument("--theta", type=float, default=0.5)
@@ -1251,6 +1310,8 @@ def main() -> int:
         return run_families(args)
     if args.workload == "implicit":
         return run_implicit(args)
+    if args.workload == "drift_three":
+        return run_drift_three(args)
     if args.workload == "longrun":
         return run_longrun(args)
 
