@@ -1047,19 +1047,22 @@ def run_drift_three(args) -> int:
     import torch
     import workloads as W
     import paper_1604_08159_amd as m
-    print(json.dumps(drift_three_leg(m, W, torch.device("cuda:0"), args.long_steps3)))
+    print(json.dumps(drift_three_leg(m, W, torch.device("cuda:0"), args.long_steps3, args.noise3)))
     return 0
 
 
-def drift_three_leg(m, W, dev, steps: int) -> dict:
+def drift_three_leg(m, W, dev, steps: int, noise_amp: float = None) -> dict:
     """The three-vortex 2048^2 configuration over its full length for noise
     seed 37440: one solve in mixed precision against one in FP64, both on the
     GPU, and beside it an FP64 solve whose initial field carries relative
     white noise of 1e-10 against the same FP64 run (the threshold's own
     sensitivity), compared every 100 steps up to step 1000 and every 500
     after (vorticity, energy, enstrophy, mask flips)."""
+    import dataclasses
     import torch
     pb = W.three_vortex()
+    if noise_amp is not None:
+        pb = dataclasses.replace(pb, noise_amp=noise_amp)
     w0 = W.initial_field(pb)
     w0p = w0 * (1.0 + 1e-10 * np.random.default_rng(7).standard_normal(w0.shape))
     stream = torch.cuda.Stream(device=dev)
@@ -1092,8 +1095,8 @@ def drift_three_leg(m, W, dev, steps: int) -> dict:
             f"({time.perf_counter() - t0:.0f} s)")
     for sv in runs.values():
         sv.close()
-    return {"workload": f"three vortices Re=37440 + noise (seed 37440), 2048^2, 6-point DD, m=30, dt=0.002, "
-                        f"{steps} steps; mixed against FP64 on the GPU",
+    return {"workload": f"three vortices Re=37440 + noise of amplitude {pb.noise_amp:g} (seed 37440), 2048^2, "
+                        f"6-point DD, m=30, dt=0.002, {steps} steps; mixed against FP64 on the GPU",
             "reference": "the FP64 GPU path", "final": curve[-1], "first_flip_by": first_flip, "tolerance": 1e-5,
             "curve": curve, "seconds": time.perf_counter() - t0}
 
@@ -1267,6 +1270,7 @@ def main() -> int:
                     help="three2048: fp32 stores the Krylov basis in FP32")
     ap.add_argument("--long-steps", type=int, default=2000)
     ap.add_argument("--long-steps3", type=int, default=5000, help="drift_three: steps of the 2048^2 run")
+    ap.add_argument("--noise3", type=float, default=None, help="drift_three: noise amplitude in place of 1e-3")
     ap.add_argument("--fam-steps", type=int, default=0, help="0: up to 37.5 h")
     ap.add_argument("--spec-requests", type=int, default=24)
     ap.add_argument("--theta", type=float, default=0.5)
