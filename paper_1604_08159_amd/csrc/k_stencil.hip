@@ -122,8 +122,8 @@ __host__ __device__ inline size_t jvp_lds_elems(int TS, bool exact = false) {
 // the bulk fields, which the Jacobian-vector products of the step read.
 // FIELDS: only the fields (nu_e, and with R64 the FP32 copies and nu_e in FP64
 // in dense64), no residual: the level-adapted residual follows.
-template <int P, typename T, int TS, bool R64 = false, bool FIELDS = false>
-__global__ void __launch_bounds__(256) k_rhs(Batch b) {
+template <int P, typename T, int TS, bool R64 = false, bool FIELDS = false, int NT = 256>
+__global__ void __launch_bounds__(NT) k_rhs(Batch b) {
   static_assert(!R64 || sizeof(T) == 8, "the FP32-bulk residual runs in FP64");
   using G = Geo<P>;
   using TB = typename std::conditional<R64, float, T>::type;   // bulk field type
@@ -142,8 +142,8 @@ __global__ void __launch_bounds__(256) k_rhs(Batch b) {
     const T* gu = R64 ? reinterpret_cast<const T*>(s.vel64) : reinterpret_cast<const T*>(s.u);
     const T* gv = R64 ? reinterpret_cast<const T*>(s.vel64 + (size_t)N * N) : reinterpret_cast<const T*>(s.v);
     const T* gw = R64 ? reinterpret_cast<const T*>(s.res64) : reinterpret_cast<const T*>(s.wt);
-    Region<Wu, T> ru, rv;
-    Region<Ww, T> rw;
+    Region<Wu, T, NT> ru, rv;
+    Region<Ww, T, NT> rw;
     ru.fetch(gu, x0 - G::HU, y0 - G::HU, N);
     rv.fetch(gv, x0 - G::HU, y0 - G::HU, N);
     rw.fetch(gw, x0 - G::R1, y0 - G::R1, N);
@@ -579,8 +579,13 @@ template <int P, typename T, int TS, bool FIELDS>
 static void rhs_launch(const Batch& b, int nt, hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
     // FP32 bulk fields: the residual itself runs in FP64 (k_rhs R64)
+    // on grids of 2048^2 and up, 1024 threads: the LDS of the FP64 tiles
+    // holds two blocks per CU, 32 wavefronts against 8 with 256 threads
     const size_t lds = rhs_lds_elems<P, double>(TS) * sizeof(double);
-    hipLaunchKernelGGL((k_rhs<P, double, TS, true, FIELDS>), dim3((nt) * b.n), dim3(256), lds, st, b);
+    if (nt * TS * TS >= (1 << 22))
+      hipLaunchKernelGGL((k_rhs<P, double, TS, true, FIELDS, 1024>), dim3((nt) * b.n), dim3(1024), lds, st, b);
+    else
+      hipLaunchKernelGGL((k_rhs<P, double, TS, true, FIELDS>), dim3((nt) * b.n), dim3(256), lds, st, b);
   } else {
     const size_t lds = rhs_lds_elems<P, T>(TS) * sizeof(T);
     hipLaunchKernelGGL((k_rhs<P, T, TS, false, FIELDS>), dim3((nt) * b.n), dim3(256), lds, st, b);
